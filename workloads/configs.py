@@ -1,0 +1,97 @@
+"""Named synthetic workloads: pencil, target window, contours and solver sizes.
+
+Windows for the constant-coefficient pencils are placed at midpoints of
+spectral gaps using the separable closed form of the discrete spectrum (the
+1D linear-FEM eigenvalues and, for tensor-product Q1 elements, their sums);
+this only chooses inputs and is not part of the solve.  Contours are circles
+built from intervals as the paper does (Sec. 4.2: centre at the interval
+midpoint, radius (1 + alpha) times the half-width).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import pencils
+
+
+@dataclass
+class Workload:
+    name: str
+    A: object
+    B: object
+    contours: np.ndarray          # (K, 4): centre, radius, keep_lo, keep_hi
+    n_nodes: int
+    moments: int
+    block: int
+    seed: int
+    tol: float = 1e-8
+    window: tuple = (0.0, 0.0)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.A.shape[0]
+
+
+def line_eigs(m: int) -> np.ndarray:
+    """Discrete spectrum of the 1D linear-FEM pencil on m interior nodes, ascending."""
+    h = 1.0 / (m + 1)
+    th = np.arange(1, m + 1) * np.pi / (m + 1)
+    return 12.0 / h ** 2 * np.sin(th / 2) ** 2 / (2.0 + np.cos(th))
+
+
+def q1_2d_eigs(nx: int, ny: int) -> np.ndarray:
+    """Discrete spectrum of the constant-coefficient Q1 pencil, ascending."""
+    return np.sort((line_eigs(nx)[None, :] + line_eigs(ny)[:, None]).ravel())
+
+
+def gap_window(eigs: np.ndarray, first: int, last: int):
+    """Window holding sorted eigenvalues first..last (1-based, inclusive), ends at gap midpoints."""
+    lo = 0.5 * (eigs[first - 2] + eigs[first - 1])
+    hi = 0.5 * (eigs[last - 1] + eigs[last])
+    return float(lo), float(hi)
+
+
+def uniform_contours(lo: float, hi: float, k: int, alpha: float) -> np.ndarray:
+    """Split [lo, hi) into k equal keep windows, one circle per window."""
+    cuts = np.linspace(lo, hi, k + 1)
+    out = np.zeros((k, 4))
+    for i in range(k):
+        s, e = cuts[i], cuts[i + 1]
+        out[i] = [(s + e) / 2, (1 + alpha) * (e - s) / 2, s, e]
+    return out
+
+
+def config_fem1d(n: int = 2000, first: int = 101, last: int = 120, n_nodes: int = 16,
+                 moments: int = 4, block: int = 16, seed: int = 1001) -> Workload:
+    """1D linear-FEM pencil, one circle whose diameter is the gap-to-gap window."""
+    A, B = pencils.fem1d(n)
+    lo, hi = gap_window(line_eigs(n), first, last)
+    cont = uniform_contours(lo, hi, 1, 0.0)
+    return Workload(f"fem1d_n{n}", A, B, cont, n_nodes, moments, block, seed, window=(lo, hi),
+                    meta={"first": first, "last": last})
+
+
+def config_q1_2d(nx: int = 300, ny: int = 300, first: int = 1001, last: int = 1199, k: int = 4,
+                 alpha: float = 0.1, n_nodes: int = 32, moments: int = 4, block: int = 64,
+                 seed: int = 1002) -> Workload:
+    """Constant-coefficient Q1 pencil, gap-to-gap window split into k uniform circles."""
+    A, B = pencils.q1_2d(nx, ny)
+    lo, hi = gap_window(q1_2d_eigs(nx, ny), first, last)
+    cont = uniform_contours(lo, hi, k, alpha)
+    return Workload(f"q1_2d_{nx}x{ny}", A, B, cont, n_nodes, moments, block, seed, window=(lo, hi),
+                    meta={"first": first, "last": last})
+
+
+# The two headline configurations: a 1D linear-FEM pencil (n = 2000, the
+# eigenvalues 101..120, one circle, 16 nodes, 4 moments, 16 right-hand sides)
+# and a 300 x 300 Q1 pencil (n = 90000, eigenvalues 1001..1199 split over four
+# uniform circles, 32 nodes, 4 moments, 64 right-hand sides).
+def fem1d_2000() -> Workload:
+    return config_fem1d()
+
+
+def q1_2d_300() -> Workload:
+    return config_q1_2d()
