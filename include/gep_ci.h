@@ -1,0 +1,200 @@
+/*
+ * gep_ci.h -- C ABI of the MI355X (gfx950) contour-integral eigensolver.
+ *
+ * Computes every eigenpair (lambda, x) of a sparse real symmetric pencil
+ * A x = lambda B x, B symmetric positive definite (paper Sec. 3.1, Eq. GEP),
+ * whose eigenvalue lies in the keep window of one of the given circular
+ * contours.  The method is the moment-based CI pipeline of the paper's
+ * Appendix "Numerical Implementation of CI Methods" (quadrature equation,
+ * Alg. "Standard CI pipeline with contour partitioning and
+ * orthogonalization", moment matrices S_m):
+ *
+ *   V (n x L, real Gaussian) -> for each circle and each trapezoid node z_j
+ *   in the upper half plane: solve (z_j B - A) Y_j = B V (Jacobi-
+ *   preconditioned COCG, all nodes x right-hand sides batched) ->
+ *   S_m = sum_j 2 Re(w_j zeta_j^m Y_j) -> B-orthonormal basis Q (SVQB then a
+ *   Cholesky pass) -> Rayleigh-Ritz on Q^T A Q, Q^T B Q -> Ritz vectors,
+ *   residuals, keep-window selection, merge across contours.
+ *
+ * Conventions shared by all entry points:
+ *  - Return value: 0 on success, a negative GEP_E* code on error (nothing
+ *    is returned in *out), or a positive GEP_W* warning code (the result is
+ *    valid but flagged).  gep_strerror() names a code; gep_last_error()
+ *    gives the calling thread's last detailed message.
+ *  - Inputs are borrowed: read during the call only, never retained or
+ *    written.  Results are library-owned until the matching *_free call.
+ *  - Pointers marked "host or device" follow gep_opts.inputs_on_device.
+ *  - The library allocates its own device memory (hipMalloc) and runs all
+ *    GPU work on gep_opts.stream; the call returns after that work is done.
+ *  - One GPU (the current HIP device).  Calls on different streams may run
+ *    concurrently; calls are not re-entrant on the same stream.
+ */
+#ifndef GEP_CI_H
+#define GEP_CI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define GEP_OK 0
+#define GEP_EINVAL (-1)     /* bad argument: NULL pointer, n <= 0, odd or < 2 nodes,
+                               moments/block < 1, tol <= 0, radius <= 0, keep window
+                               outside the circle's real diameter, NaN/Inf values,
+                               unsorted or out-of-range column indices, nnz >= 2^31 */
+#define GEP_ENOTSYM (-2)    /* A or B not symmetric (|a_ij - a_ji| > 1e-12 max|a|) */
+#define GEP_ENOTSPD (-3)    /* B has a non-positive diagonal entry, or a reduced
+                               B-Gram matrix lost positive definiteness */
+#define GEP_ENOMEM (-4)     /* not even one contour fits in device memory */
+#define GEP_EDEVICE (-5)    /* a HIP runtime call failed (see gep_last_error) */
+#define GEP_WNOCONV 1       /* some kept pairs have residual > tol after refinement;
+                               they are returned with converged = 0 */
+#define GEP_WSATURATED 2    /* some contour's subspace is saturated (its weakest
+                               moment direction keeps weight > 1e-3 of the
+                               strongest): eigenvalues may be missed; split the
+                               contour or raise block*moments */
+
+/* ---- precision of the shifted solves --------------------------------- */
+#define GEP_FP64 0          /* FP64 complex COCG throughout */
+#define GEP_MIXED 1         /* FP32 complex COCG with FP64 residual replacement;
+                               orthonormalisation, Rayleigh-Ritz and residuals FP64 */
+
+/* Sparse matrix in CSR form, both triangles stored, column indices sorted
+ * ascending within each row, 0-based.  rowptr has n+1 entries. */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    const int64_t* rowptr;   /* host or device */
+    const int32_t* colind;   /* host or device */
+    const double* val;       /* host or device */
+} gep_csr;
+
+/* Circle |z - center| = radius; eigenvalues in [keep_lo, keep_hi) are kept
+ * from this contour.  Requires center - radius <= keep_lo < keep_hi <=
+ * center + radius (paper Sec. 4.2: circle from an interval with inflation). */
+typedef struct {
+    double center;
+    double radius;
+    double keep_lo;
+    double keep_hi;
+} gep_contour;
+
+typedef struct {
+    uint64_t seed;          /* seed of the counter-based Gaussian block V
+                               (SplitMix64 + Box-Muller, column-major counters) */
+    int precision;          /* GEP_FP64 (default) or GEP_MIXED */
+    int max_refine;         /* FEAST-type refinement passes when a kept pair
+                               misses tol (default 1) */
+    double solve_tol;       /* per-column COCG stop ||r||/||b|| (default 1e-9) */
+    int max_iter;           /* COCG iteration cap (default 100000) */
+    int check_every;        /* iterations between convergence read-backs (default 16) */
+    void* stream;           /* hipStream_t, NULL = default stream */
+    int inputs_on_device;   /* 1: gep_csr arrays and rhs are device pointers */
+    const double* rhs;      /* optional V, n x block, column-major, host or device;
+                               NULL = draw V from seed */
+    double mem_limit_bytes; /* device-memory budget for one wave of contours;
+                               0 = 85% of free memory */
+    int timing;             /* 1: time every kernel class with HIP events */
+} gep_opts;
+
+typedef struct gep_result gep_result;
+
+/* Fill *opts with the defaults listed above. */
+void gep_opts_default(gep_opts* opts);
+
+/* Solve one pencil over n_contours circles (Alg. "Standard CI pipeline").
+ * n_nodes: trapezoid nodes per circle N (even, >= 2); only the N/2 nodes in
+ * the upper half plane are solved (conjugate symmetry of a real pencil).
+ * moments: M >= 1.  block: L >= 1 right-hand sides.  tol: residual
+ * threshold ||Ax - lambda Bx||_2 / (||A||_inf ||x||_2) for acceptance.
+ * On success *out holds the merged, ascending eigenpairs. */
+int gep_ci_solve(const gep_csr* A, const gep_csr* B, const gep_contour* contours,
+                 int n_contours, int n_nodes, int moments, int block, double tol,
+                 const gep_opts* opts, gep_result** out);
+
+/* Number m of returned eigenpairs and the problem size n. */
+int gep_result_count(const gep_result* res, int64_t* m, int64_t* n);
+
+/* Copy results to caller-owned HOST buffers (any may be NULL):
+ * evals[m] ascending; evecs n x m column-major, B-normalised, largest-|.|
+ * entry positive; resid[m]; contour_id[m]; converged[m] (1 if resid <= tol). */
+int gep_result_copy(const gep_result* res, double* evals, double* evecs, double* resid,
+                    int32_t* contour_id, uint8_t* converged);
+
+/* JSON statistics (iterations, passes, ranks, per-phase times, bytes) into
+ * json[cap]; *needed receives the full length including the terminator. */
+int gep_result_stats(const gep_result* res, char* json, size_t cap, size_t* needed);
+
+void gep_result_free(gep_result* res);
+
+const char* gep_strerror(int status);
+const char* gep_last_error(void);
+
+/* ---- component entry points (kernel-level checks and measurement) -----
+ * These expose single steps of the hot path on caller-owned DEVICE buffers.
+ * Work is enqueued on `stream` (NULL = default stream) and the stream is
+ * synchronised before the call returns.  Errors as above. */
+
+typedef struct gep_pencil gep_pencil;
+
+/* Validate and pack A, B into the device format (union pattern, interleaved
+ * (a_ij, b_ij) values, diagonals, ||A||_inf).  Inputs host or device per
+ * inputs_on_device. */
+int gep_pencil_create(const gep_csr* A, const gep_csr* B, int inputs_on_device, void* stream,
+                      gep_pencil** out);
+void gep_pencil_free(gep_pencil* p);
+/* n, nnz of the packed union pattern, and ||A||_inf. */
+int gep_pencil_info(const gep_pencil* p, int64_t* n, int64_t* nnz, double* a_inf);
+
+/* gep_ci_solve on an already packed pencil (same arguments and results);
+ * opts->inputs_on_device then only concerns opts->rhs. */
+int gep_ci_solve_pencil(gep_pencil* p, const gep_contour* contours, int n_contours, int n_nodes,
+                        int moments, int block, double tol, const gep_opts* opts,
+                        gep_result** out);
+
+/* Shifted complex SpMM, Y[:, c] = z_c B X[:, c] - A X[:, c] (quadrature
+ * equation's operator), FP64 complex, on the tiled layout: column c of an
+ * n x W multivector lives at element ((c / 64) * n + i) * 64 + c % 64,
+ * each element an interleaved (re, im) double pair; W a multiple of 64.
+ * shifts: W interleaved complex doubles.  pq (optional, W complex doubles):
+ * receives sum_i X[i,c] Y[i,c] (bilinear, no conjugation). */
+int gep_spmm_shifted(const gep_pencil* p, const double* shifts, const double* X, double* Y,
+                     int64_t W, double* pq, void* stream);
+
+/* FP32 complex variant of gep_spmm_shifted (shifts stay FP64 complex). */
+int gep_spmm_shifted_f32(const gep_pencil* p, const double* shifts, const float* X, float* Y,
+                         int64_t W, void* stream);
+
+/* Real multivector products on row-major n x k blocks (leading dim ld >= k):
+ * YA = A X and/or YB = B X (either output may be NULL). */
+int gep_spmm_real(const gep_pencil* p, const double* X, int64_t k, int64_t ld, double* YA,
+                  double* YB, void* stream);
+
+/* G = X^T Y for row-major X (n x k1, ld1) and Y (n x k2, ld2), G row-major
+ * k1 x k2, FP64 MFMA with split-K over n.  Deterministic. */
+int gep_gram(const double* X, int64_t ld1, const double* Y, int64_t ld2, int64_t n, int64_t k1,
+             int64_t k2, double* G, void* stream);
+
+/* C = X T for row-major X (n x k, ldx), T (k x m, row-major, ldt), C (n x m, ldc);
+ * FP64 MFMA. */
+int gep_gemm_tall(const double* X, int64_t ldx, const double* T, int64_t ldt, int64_t n, int64_t k,
+                  int64_t m, double* C, int64_t ldc, void* stream);
+
+/* Symmetric eigen-decomposition of `batch` k x k row-major matrices (cyclic
+ * Jacobi, parallel ordering, one work-group per matrix): eigenvalues
+ * ascending into w[batch*k], orthonormal eigenvectors as columns of
+ * V[batch*k*k] (row-major).  A is overwritten. */
+int gep_sym_eig(double* A, double* w, double* V, int64_t k, int batch, void* stream);
+
+/* Counter-based Gaussian block (the V of the solve): row-major n x L with
+ * V[i*L + l] = entry at counter l*n + i of the SplitMix64 + Box-Muller
+ * stream of `seed`. */
+int gep_gaussian_block(uint64_t seed, int64_t n, int64_t L, double* V, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GEP_CI_H */

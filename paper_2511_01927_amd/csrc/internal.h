@@ -1,0 +1,143 @@
+// Internal declarations shared by the host orchestrator and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+namespace gep {
+
+// One wavefront covers 64 columns of a multivector tile.
+constexpr int kTile = 64;
+// Work-group size of the streaming kernels: 4 wavefronts.
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / kTile;
+
+void set_error(const std::string& msg);
+
+// Device-resident packed pencil: union CSR pattern with interleaved (a, b).
+struct DevPencil {
+    int64_t n = 0, nnz = 0;
+    int32_t* rowptr = nullptr;  // n + 1
+    int32_t* colind = nullptr;  // nnz
+    double2* ab = nullptr;      // nnz (a_ij, b_ij)
+    float2* ab32 = nullptr;     // nnz FP32 copy (mixed precision)
+    double* dA = nullptr;       // diag(A)
+    double* dB = nullptr;       // diag(B)
+    double a_inf = 0.0;         // max absolute row sum of A
+    int max_row_nnz = 0;
+};
+
+// XCD-aware remap of a flat work-group id: the hardware deals work-groups
+// round-robin over the 8 XCDs; this gives each XCD a contiguous range of
+// logical ids so neighbouring rows of one column tile share an L2.
+__device__ inline int xcd_logical(int b, int grid) {
+    const int per = grid >> 3;   // grid is always padded to a multiple of 8
+    return (b & 7) * per + (b >> 3);
+}
+
+inline int pad8(int g) { return (g + 7) & ~7; }
+
+// ---- launchers (all enqueue on `s`, return hipError_t) -------------------
+// complex FP64 shifted SpMM over active tiles (tiled layout), optional
+// bilinear dot partials [tile][nrb][64].
+hipError_t launch_spmm_c64(const DevPencil& P, const double2* shifts, const double2* X,
+                           double2* Y, const int32_t* tiles, const int32_t* n_active,
+                           int n_active_host, int nrb, double2* partial, hipStream_t s);
+hipError_t launch_spmm_c32(const DevPencil& P, const double2* shifts, const float2* X, float2* Y,
+                           const int32_t* tiles, const int32_t* n_active, int n_active_host,
+                           int nrb, double2* partial, hipStream_t s);
+hipError_t launch_spmm_real(const DevPencil& P, const double* X, int64_t k, int64_t ld,
+                            double* YA, double* YB, hipStream_t s);
+
+// COCG pieces, FP64 (cocg.hip)
+struct CocgState {
+    int64_t n = 0;
+    int ntiles = 0;          // W / 64
+    double2* x = nullptr;    // tiled n x W
+    double2* r = nullptr;
+    double2* p = nullptr;
+    double2* q = nullptr;
+    double2* shifts = nullptr;   // [W]
+    int32_t* bcol = nullptr;     // [W] column of the B V block feeding column c (-1: none)
+    double2* rho = nullptr;      // [W]
+    double2* alpha = nullptr;    // [W]
+    double2* beta = nullptr;     // [W]
+    double* bb = nullptr;        // [W] ||b||^2
+    double* rr = nullptr;        // [W] ||r||^2
+    int32_t* active = nullptr;   // [W]
+    int32_t* iters = nullptr;    // [W]
+    int32_t* tile_active = nullptr;  // [ntiles]
+    int32_t* tiles = nullptr;        // [ntiles] compacted active list
+    int32_t* counts = nullptr;       // [2]: active tiles, active columns
+    double2* part_c = nullptr;       // [ntiles][nrb_max][64]
+    double* part_r = nullptr;        // [ntiles][nrb_max][64]
+    int nrb_max = 0;
+    // mixed precision (FP32 recurrence, FP64 true residual / solution)
+    float2* x32 = nullptr;
+    float2* r32 = nullptr;
+    float2* p32 = nullptr;
+    float2* q32 = nullptr;
+};
+
+hipError_t cocg_init(const DevPencil& P, CocgState& S, const double* BV, int64_t ldbv, int nrb,
+                     hipStream_t s);
+hipError_t cocg_reduce_alpha(CocgState& S, int n_active_host, int nrb, hipStream_t s);
+hipError_t cocg_update(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
+                       hipStream_t s);
+hipError_t cocg_reduce_beta(CocgState& S, int n_active_host, int nrb, double tol2, int max_iter,
+                            hipStream_t s);
+hipError_t cocg_compact(CocgState& S, hipStream_t s);
+hipError_t cocg_direction(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
+                          hipStream_t s);
+// mixed precision
+hipError_t cocg32_init(const DevPencil& P, CocgState& S, const double* BV, int64_t ldbv, int nrb,
+                       hipStream_t s);
+hipError_t cocg32_update(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
+                         hipStream_t s);
+hipError_t cocg32_direction(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
+                            hipStream_t s);
+hipError_t cocg32_replace(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
+                          hipStream_t s);
+
+// moments: S_k[i][m*L + l] = sum_j Re(coef[k][j][m] * x[col(k,j,l)][i])
+hipError_t launch_moments(const double2* X, int64_t n, int K, int NH, int L, int M,
+                          const double2* coef, double* S, hipStream_t s);
+hipError_t launch_moments_f32(const float2* X, int64_t n, int K, int NH, int L, int M,
+                              const double2* coef, double* S, hipStream_t s);
+
+// RNG
+hipError_t launch_gaussian(uint64_t seed, int64_t n, int64_t L, double* V, hipStream_t s);
+
+// dense (gemm.hip / dense.hip)
+hipError_t launch_gram(const double* X, int64_t ld1, const double* Y, int64_t ld2, int64_t n,
+                       int64_t k1, int64_t k2, double* G, double* work, size_t work_elems,
+                       hipStream_t s);
+size_t gram_work_elems(int64_t n, int64_t k1, int64_t k2);
+hipError_t launch_gemm_tall(const double* X, int64_t ldx, const double* T, int64_t ldt, int64_t n,
+                            int64_t k, int64_t m, double* C, int64_t ldc, hipStream_t s);
+hipError_t launch_sym_eig(double* A, double* w, double* V, int64_t k, int batch, double* work,
+                          hipStream_t s);
+// Cholesky of k x k SPD matrices; writes L^-T (upper) into LinvT; status[b] = 0 ok,
+// j+1 if pivot j failed.
+hipError_t launch_chol_inv(const double* G, double* LinvT, int64_t k, int batch, double* work,
+                           int32_t* status, hipStream_t s);
+// C = op(A) op(B) for k x k row-major small matrices (ta/tb transpose flags).
+hipError_t launch_small_gemm(const double* A, int ta, const double* B, int tb, double* C,
+                             int64_t m, int64_t n, int64_t kk, int64_t lda, int64_t ldb,
+                             int64_t ldc, hipStream_t s);
+hipError_t launch_symmetrise(double* A, int64_t k, hipStream_t s);
+// SVQB scaling: T[i][j] = U[i][k-r+j] / sqrt(w[k-r+j]), i < k, j < r
+hipError_t launch_svqb_scale(const double* U, const double* w, int64_t k, int64_t r, double* T,
+                             hipStream_t s);
+// residual norms for row-major n x k blocks: num[j] = ||AX_j - th_j BX_j||, den[j] = ||X_j||
+hipError_t launch_resid_norms(const double* AX, const double* BX, const double* X,
+                              const double* theta, int64_t n, int64_t k, double* num, double* den,
+                              double* work, hipStream_t s);
+// gather selected columns of row-major X (n x k) into column-major out (n x m),
+// sign-normalised (largest-|.| entry positive, lowest index on ties)
+hipError_t launch_gather_cols(const double* X, int64_t n, int64_t k, const int32_t* sel, int m,
+                              double* out, hipStream_t s);
+
+}  // namespace gep

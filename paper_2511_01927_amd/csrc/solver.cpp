@@ -1,0 +1,1119 @@
+// Host orchestrator and C ABI of the contour-integral eigensolver.
+//
+// Pipeline per wave of contours (paper Appendix, Alg. "Standard CI pipeline
+// with contour partitioning and orthogonalization", moment matrices S_m):
+//   pack pencil -> V, B V -> batched COCG over (contour, node, rhs) columns
+//   -> moments -> SVQB + Cholesky B-orthonormalisation -> Rayleigh-Ritz ->
+//   residuals -> keep-window selection -> optional FEAST-type refinement ->
+//   merge.  All arithmetic on the pencil-sized data runs in the HIP kernels
+//   of this library; the host validates, plans memory, launches, and makes
+//   the O(r)-sized decisions (rank cut, window selection, merge).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/gep_ci.h"
+#include "internal.h"
+
+namespace gep {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+struct Fail {
+    int code;
+};
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                 \
+            throw Fail{GEP_EDEVICE};                                                      \
+        }                                                                                 \
+    } while (0)
+
+[[noreturn]] static void fail(int code, const std::string& msg) {
+    set_error(msg);
+    throw Fail{code};
+}
+
+// RAII device buffer
+template <typename T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    explicit DBuf(size_t count) { alloc(count); }
+    void alloc(size_t count) {
+        release();
+        n = count;
+        if (count) {
+            hipError_t e = hipMalloc(&p, count * sizeof(T));
+            if (e != hipSuccess) {
+                p = nullptr;
+                (void)hipGetLastError();
+                fail(e == hipErrorOutOfMemory ? GEP_ENOMEM : GEP_EDEVICE,
+                     "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed: " +
+                         hipGetErrorString(e));
+            }
+        }
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    ~DBuf() { release(); }
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    T* get() const { return p; }
+};
+
+// Host copy of the packed pencil (needed for validation and the merge).
+struct HostPencil {
+    int64_t n = 0, nnz = 0;
+    std::vector<int32_t> rowptr, colind;
+    std::vector<double> a, b;
+    std::vector<double> dA, dB;
+    double a_inf = 0.0;
+    int max_row = 0;
+};
+
+// ---- per-kernel-class timing with HIP events -----------------------------
+struct Timer {
+    bool on = false;
+    hipStream_t s = nullptr;
+    struct Rec {
+        int cls;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    static constexpr int kClasses = 8;
+    double ms[kClasses] = {0};
+    long count[kClasses] = {0};
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        return e;
+    }
+    int open_cls = -1;
+    hipEvent_t open_a = nullptr;
+    void begin(int cls) {
+        if (!on) return;
+        open_cls = cls;
+        open_a = get();
+        HIPCHK(hipEventRecord(open_a, s));
+    }
+    void end() {
+        if (!on) return;
+        hipEvent_t b = get();
+        HIPCHK(hipEventRecord(b, s));
+        pending.push_back({open_cls, open_a, b});
+    }
+    // call after a stream synchronisation
+    void flush() {
+        for (auto& r : pending) {
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+            ms[r.cls] += t;
+            count[r.cls] += 1;
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        pending.clear();
+    }
+    ~Timer() {
+        for (auto& r : pending) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+enum { T_SPMM = 0, T_UPDATE, T_DIRECTION, T_REDUCE, T_MOMENTS, T_GRAM, T_GEMM, T_DENSE };
+static const char* kTimerNames[Timer::kClasses] = {"spmm_shifted", "cocg_update", "cocg_direction",
+                                                   "cocg_reduce", "moments", "gram",
+                                                   "gemm_tall", "dense_small"};
+
+}  // namespace gep
+
+using namespace gep;
+
+struct gep_pencil {
+    HostPencil h;
+    DevPencil d;
+    std::vector<void*> owned;
+    ~gep_pencil() {
+        for (void* p : owned) (void)hipFree(p);
+    }
+};
+
+struct gep_result {
+    int64_t n = 0, m = 0;
+    std::vector<double> evals, evecs, resid;
+    std::vector<int32_t> cid;
+    std::vector<uint8_t> conv;
+    std::string stats;
+};
+
+namespace gep {
+
+// ---- validation and packing ---------------------------------------------
+static void fetch_csr(const gep_csr* M, bool on_dev, std::vector<int64_t>& rp,
+                      std::vector<int32_t>& ci, std::vector<double>& v, const char* name) {
+    if (!M || !M->rowptr || !M->colind || !M->val) fail(GEP_EINVAL, std::string(name) + ": NULL pointer");
+    if (M->n <= 0 || M->nnz < 0) fail(GEP_EINVAL, std::string(name) + ": n <= 0 or nnz < 0");
+    if (M->n >= (1ll << 31) - 1 || M->nnz >= (1ll << 31) - 1)
+        fail(GEP_EINVAL, std::string(name) + ": n or nnz >= 2^31");
+    rp.resize(M->n + 1);
+    ci.resize(M->nnz);
+    v.resize(M->nnz);
+    if (on_dev) {
+        HIPCHK(hipMemcpy(rp.data(), M->rowptr, sizeof(int64_t) * (M->n + 1), hipMemcpyDeviceToHost));
+        if (M->nnz) {
+            HIPCHK(hipMemcpy(ci.data(), M->colind, sizeof(int32_t) * M->nnz, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(v.data(), M->val, sizeof(double) * M->nnz, hipMemcpyDeviceToHost));
+        }
+    } else {
+        std::memcpy(rp.data(), M->rowptr, sizeof(int64_t) * (M->n + 1));
+        if (M->nnz) {
+            std::memcpy(ci.data(), M->colind, sizeof(int32_t) * M->nnz);
+            std::memcpy(v.data(), M->val, sizeof(double) * M->nnz);
+        }
+    }
+    if (rp[0] != 0 || rp[M->n] != M->nnz) fail(GEP_EINVAL, std::string(name) + ": rowptr ends wrong");
+    for (int64_t i = 0; i < M->n; ++i) {
+        if (rp[i + 1] < rp[i]) fail(GEP_EINVAL, std::string(name) + ": rowptr not monotone");
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+            if (ci[e] < 0 || ci[e] >= M->n) fail(GEP_EINVAL, std::string(name) + ": column index out of range");
+            if (e > rp[i] && ci[e] <= ci[e - 1])
+                fail(GEP_EINVAL, std::string(name) + ": column indices not strictly ascending");
+            if (!std::isfinite(v[e])) fail(GEP_EINVAL, std::string(name) + ": non-finite value");
+        }
+    }
+}
+
+static double csr_get(const std::vector<int64_t>& rp, const std::vector<int32_t>& ci,
+                      const std::vector<double>& v, int64_t i, int32_t j) {
+    auto b = ci.begin() + rp[i], e = ci.begin() + rp[i + 1];
+    auto it = std::lower_bound(b, e, j);
+    if (it != e && *it == j) return v[it - ci.begin()];
+    return 0.0;
+}
+
+static void check_sym(const std::vector<int64_t>& rp, const std::vector<int32_t>& ci,
+                      const std::vector<double>& v, int64_t n, const char* name) {
+    double amax = 0.0;
+    for (double x : v) amax = std::max(amax, std::fabs(x));
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+            const double t = csr_get(rp, ci, v, ci[e], (int32_t)i);
+            if (std::fabs(v[e] - t) > 1e-12 * amax)
+                fail(GEP_ENOTSYM, std::string(name) + " is not symmetric at (" + std::to_string(i) +
+                                      "," + std::to_string(ci[e]) + ")");
+        }
+}
+
+static void pack(const gep_csr* A, const gep_csr* B, bool on_dev, HostPencil& H) {
+    std::vector<int64_t> ra, rb;
+    std::vector<int32_t> ca, cb;
+    std::vector<double> va, vb;
+    fetch_csr(A, on_dev, ra, ca, va, "A");
+    fetch_csr(B, on_dev, rb, cb, vb, "B");
+    if (A->n != B->n) fail(GEP_EINVAL, "A and B differ in size");
+    const int64_t n = A->n;
+    check_sym(ra, ca, va, n, "A");
+    check_sym(rb, cb, vb, n, "B");
+    H.n = n;
+    H.rowptr.assign(n + 1, 0);
+    H.colind.clear();
+    H.a.clear();
+    H.b.clear();
+    H.dA.assign(n, 0.0);
+    H.dB.assign(n, 0.0);
+    H.a_inf = 0.0;
+    H.max_row = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t ea = ra[i], eb = rb[i];
+        double rowsum = 0.0;
+        while (ea < ra[i + 1] || eb < rb[i + 1]) {
+            const int32_t ja = ea < ra[i + 1] ? ca[ea] : INT32_MAX;
+            const int32_t jb = eb < rb[i + 1] ? cb[eb] : INT32_MAX;
+            const int32_t j = std::min(ja, jb);
+            const double av = (ja == j) ? va[ea++] : 0.0;
+            const double bv = (jb == j) ? vb[eb++] : 0.0;
+            H.colind.push_back(j);
+            H.a.push_back(av);
+            H.b.push_back(bv);
+            rowsum += std::fabs(av);
+            if (j == i) {
+                H.dA[i] = av;
+                H.dB[i] = bv;
+            }
+        }
+        H.rowptr[i + 1] = (int32_t)H.colind.size();
+        H.max_row = std::max(H.max_row, H.rowptr[i + 1] - H.rowptr[i]);
+        H.a_inf = std::max(H.a_inf, rowsum);
+        if (!(H.dB[i] > 0.0)) fail(GEP_ENOTSPD, "B has a non-positive diagonal entry at row " + std::to_string(i));
+    }
+    H.nnz = (int64_t)H.colind.size();
+    if (H.nnz >= (1ll << 31) - 1) fail(GEP_EINVAL, "union pattern nnz >= 2^31");
+}
+
+static void upload(const HostPencil& H, gep_pencil* P) {
+    DevPencil& D = P->d;
+    D.n = H.n;
+    D.nnz = H.nnz;
+    D.a_inf = H.a_inf;
+    D.max_row_nnz = H.max_row;
+    auto dalloc = [&](size_t bytes) {
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 16));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(e == hipErrorOutOfMemory ? GEP_ENOMEM : GEP_EDEVICE,
+                 std::string("hipMalloc failed while packing the pencil: ") + hipGetErrorString(e));
+        }
+        P->owned.push_back(p);
+        return p;
+    };
+    D.rowptr = (int32_t*)dalloc(sizeof(int32_t) * (H.n + 1));
+    D.colind = (int32_t*)dalloc(sizeof(int32_t) * H.nnz);
+    D.ab = (double2*)dalloc(sizeof(double2) * H.nnz);
+    D.ab32 = (float2*)dalloc(sizeof(float2) * H.nnz);
+    D.dA = (double*)dalloc(sizeof(double) * H.n);
+    D.dB = (double*)dalloc(sizeof(double) * H.n);
+    std::vector<double2> ab(H.nnz);
+    std::vector<float2> ab32(H.nnz);
+    for (int64_t e = 0; e < H.nnz; ++e) {
+        ab[e] = make_double2(H.a[e], H.b[e]);
+        ab32[e] = make_float2((float)H.a[e], (float)H.b[e]);
+    }
+    HIPCHK(hipMemcpy(D.rowptr, H.rowptr.data(), sizeof(int32_t) * (H.n + 1), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(D.colind, H.colind.data(), sizeof(int32_t) * H.nnz, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(D.ab, ab.data(), sizeof(double2) * H.nnz, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(D.ab32, ab32.data(), sizeof(float2) * H.nnz, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(D.dA, H.dA.data(), sizeof(double) * H.n, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(D.dB, H.dB.data(), sizeof(double) * H.n, hipMemcpyHostToDevice));
+}
+
+// ---- solve ----------------------------------------------------------------
+struct SolveCfg {
+    int N = 0, NH = 0, M = 0, L = 0;
+    double tol = 1e-8;
+    gep_opts o;
+};
+
+struct ContourOut {
+    int id = 0;
+    int passes = 0;
+    std::vector<int> rank;
+    bool saturated = false;
+    double smin_ratio = 0.0;
+    std::vector<double> theta, rho;   // all Ritz pairs of the last pass
+    std::shared_ptr<DBuf<double>> X;  // n x r row-major Ritz vectors of the last pass
+    int r = 0;
+    long iters_max = 0;
+    double iters_mean = 0.0;
+};
+
+struct Stats {
+    long cocg_iters = 0;          // iterations of the COCG loop (all passes)
+    long tile_iters = 0;          // sum over tiles of iterations run
+    long spmm_launches = 0;
+    double spmm_alg_bytes = 0.0;  // algorithmic bytes of all shifted SpMM launches
+    double update_alg_bytes = 0.0;
+    double direction_alg_bytes = 0.0;
+    long columns = 0;
+    int waves = 0;
+    std::vector<double> phase_ms;
+};
+
+static void choose_nrb(int64_t n, int n_active, int nrb_max, int& nrb) {
+    int v = (4096 + n_active - 1) / std::max(1, n_active);
+    v = std::max(1, std::min(v, nrb_max));
+    nrb = v;
+}
+
+class Solver {
+   public:
+    Solver(gep_pencil* P, const SolveCfg& c) : P_(P), c_(c) {
+        s_ = (hipStream_t)c.o.stream;
+        tm_.on = c.o.timing != 0;
+        tm_.s = s_;
+        HIPCHK(hipHostMalloc((void**)&counts_h_, sizeof(int32_t) * 4, 0));
+    }
+    ~Solver() {
+        if (counts_h_) (void)hipHostFree(counts_h_);
+    }
+
+    // One pass of the pipeline for a set of contours sharing (L, M).
+    // BV: row-major n x ldbv; column feeding (contour slot k, rhs l) is
+    // bv_col(k, l) = shared ? l : k*L + l.
+    void run_pass(const std::vector<gep_contour>& cs, const std::vector<int>& ids,
+                  const double* BV, int64_t ldbv, bool shared, int L, int M,
+                  std::vector<ContourOut>& out) {
+        const int K = (int)cs.size();
+        const int NH = c_.NH;
+        const int64_t n = P_->d.n;
+        const int64_t W = (int64_t)K * NH * L;
+        const int ntiles = (int)((W + kTile - 1) / kTile);
+        const int64_t Wp = (int64_t)ntiles * kTile;
+        stats_.columns += W;
+        // per-column metadata
+        std::vector<double2> shifts(Wp, make_double2(0.0, 1.0));
+        std::vector<int32_t> bcol(Wp, -1);
+        std::vector<double2> coef((size_t)K * NH * M);
+        for (int k = 0; k < K; ++k) {
+            const double c = cs[k].center, R = cs[k].radius;
+            for (int j = 0; j < NH; ++j) {
+                const double th = M_PI * (2.0 * (j + 1) - 1.0) / c_.N;
+                const std::complex<double> zeta(std::cos(th), std::sin(th));
+                const std::complex<double> z = c + R * zeta;
+                const std::complex<double> w = R * zeta / (double)c_.N;
+                std::complex<double> zm(1.0, 0.0);
+                for (int m = 0; m < M; ++m) {
+                    const std::complex<double> cf = 2.0 * w * zm;
+                    coef[((size_t)k * NH + j) * M + m] = make_double2(cf.real(), cf.imag());
+                    zm *= zeta;
+                }
+                for (int l = 0; l < L; ++l) {
+                    const int64_t col = ((int64_t)k * NH + j) * L + l;
+                    shifts[col] = make_double2(z.real(), z.imag());
+                    bcol[col] = shared ? l : k * L + l;
+                }
+            }
+        }
+        CocgState S;
+        S.n = n;
+        S.ntiles = ntiles;
+        S.nrb_max = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 31) / 32));
+        const size_t mv = (size_t)n * Wp;
+        DBuf<double2> x(mv), r(mv), p(mv), q(mv);
+        DBuf<double2> d_shifts(Wp), rho(Wp), alpha(Wp), beta(Wp);
+        DBuf<int32_t> d_bcol(Wp), active(Wp), iters(Wp), tile_active(ntiles), tiles(ntiles), counts(4);
+        DBuf<double> bb(Wp), rr(Wp);
+        DBuf<double2> part_c((size_t)ntiles * S.nrb_max * kTile);
+        DBuf<double> part_r((size_t)ntiles * S.nrb_max * kTile);
+        DBuf<double2> d_coef(coef.size());
+        S.x = x.get();
+        S.r = r.get();
+        S.p = p.get();
+        S.q = q.get();
+        S.shifts = d_shifts.get();
+        S.bcol = d_bcol.get();
+        S.rho = rho.get();
+        S.alpha = alpha.get();
+        S.beta = beta.get();
+        S.bb = bb.get();
+        S.rr = rr.get();
+        S.active = active.get();
+        S.iters = iters.get();
+        S.tile_active = tile_active.get();
+        S.tiles = tiles.get();
+        S.counts = counts.get();
+        S.part_c = part_c.get();
+        S.part_r = part_r.get();
+        std::vector<int32_t> tl(ntiles);
+        for (int t = 0; t < ntiles; ++t) tl[t] = t;
+        int32_t cnt0[4] = {ntiles, (int32_t)W, 0, 0};
+        HIPCHK(hipMemcpyAsync(S.shifts, shifts.data(), sizeof(double2) * Wp, hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(S.bcol, bcol.data(), sizeof(int32_t) * Wp, hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(S.tiles, tl.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(S.counts, cnt0, sizeof(cnt0), hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(d_coef.get(), coef.data(), sizeof(double2) * coef.size(), hipMemcpyHostToDevice, s_));
+
+        int nrb = 0;
+        choose_nrb(n, ntiles, S.nrb_max, nrb);
+        HIPCHK(cocg_init(P_->d, S, BV, ldbv, nrb, s_));
+        const double tol2 = c_.o.solve_tol * c_.o.solve_tol;
+        const int max_iter = c_.o.max_iter;
+        const int every = std::max(1, c_.o.check_every);
+        int n_act = ntiles;
+        long it = 0;
+        const double mat_bytes = (double)P_->d.nnz * (16.0 + 4.0) + 4.0 * (n + 1);
+        const double tile_bytes = (double)n * kTile * 16.0;
+        while (n_act > 0 && it < max_iter) {
+            for (int c = 0; c < every; ++c) {
+                tm_.begin(T_SPMM);
+                HIPCHK(launch_spmm_c64(P_->d, S.shifts, S.p, S.q, S.tiles, S.counts, n_act, nrb, S.part_c, s_));
+                tm_.end();
+                HIPCHK(cocg_reduce_alpha(S, n_act, nrb, s_));
+                tm_.begin(T_UPDATE);
+                HIPCHK(cocg_update(P_->d, S, n_act, nrb, s_));
+                tm_.end();
+                HIPCHK(cocg_reduce_beta(S, n_act, nrb, tol2, max_iter, s_));
+                HIPCHK(cocg_compact(S, s_));
+                tm_.begin(T_DIRECTION);
+                HIPCHK(cocg_direction(P_->d, S, n_act, nrb, s_));
+                tm_.end();
+                stats_.spmm_launches += 1;
+                stats_.spmm_alg_bytes += mat_bytes;
+            }
+            it += every;
+            HIPCHK(hipMemcpyAsync(counts_h_, S.counts, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s_));
+            HIPCHK(hipStreamSynchronize(s_));
+            tm_.flush();
+            n_act = counts_h_[0];
+            if (n_act > 0) choose_nrb(n, n_act, S.nrb_max, nrb);
+        }
+        stats_.cocg_iters += it;
+        // per-column iteration counts -> exact tile work for the byte count
+        std::vector<int32_t> its(Wp);
+        HIPCHK(hipMemcpyAsync(its.data(), S.iters, sizeof(int32_t) * Wp, hipMemcpyDeviceToHost, s_));
+        HIPCHK(hipStreamSynchronize(s_));
+        long tile_iters = 0;
+        for (int t = 0; t < ntiles; ++t) {
+            int mx = 0;
+            for (int l = 0; l < kTile; ++l) mx = std::max(mx, its[(size_t)t * kTile + l]);
+            tile_iters += mx;
+        }
+        stats_.tile_iters += tile_iters;
+        stats_.spmm_alg_bytes += tile_iters * 2.0 * tile_bytes;
+        stats_.update_alg_bytes += tile_iters * 6.0 * tile_bytes;
+        stats_.direction_alg_bytes += tile_iters * 3.0 * tile_bytes;
+        // moments
+        const int r0 = L * M;
+        auto Sall = std::make_shared<DBuf<double>>((size_t)K * n * r0);
+        tm_.begin(T_MOMENTS);
+        HIPCHK(launch_moments(S.x, n, K, NH, L, M, d_coef.get(), Sall->get(), s_));
+        tm_.end();
+        // release the multivectors before the dense phase
+        x.release();
+        r.release();
+        p.release();
+        q.release();
+        out.resize(K);
+        for (int k = 0; k < K; ++k) {
+            ContourOut& co = out[k];
+            co.id = ids[k];
+            long mx = 0;
+            double sum = 0.0;
+            long cnt = 0;
+            for (int j = 0; j < NH; ++j)
+                for (int l = 0; l < L; ++l) {
+                    const int v = its[((size_t)k * NH + j) * L + l];
+                    mx = std::max<long>(mx, v);
+                    sum += v;
+                    ++cnt;
+                }
+            co.iters_max = mx;
+            co.iters_mean = cnt ? sum / cnt : 0.0;
+            rayleigh_ritz(Sall->get() + (size_t)k * n * r0, r0, co);
+        }
+    }
+
+    // B-orthonormalise span(S) and extract Ritz pairs (all of them).
+    void rayleigh_ritz(const double* S, int r0, ContourOut& co) {
+        const int64_t n = P_->d.n;
+        const DevPencil& D = P_->d;
+        DBuf<double> T((size_t)n * r0);
+        DBuf<double> G((size_t)r0 * r0), U((size_t)r0 * r0), w(r0), jw((size_t)r0 * r0);
+        DBuf<double> gw(gram_work_elems(n, r0, r0));
+        // pass 1: SVQB
+        HIPCHK(launch_spmm_real(D, S, r0, r0, nullptr, T.get(), s_));
+        gram(S, r0, T.get(), r0, r0, r0, G.get(), gw);
+        HIPCHK(launch_symmetrise(G.get(), r0, s_));
+        tm_.begin(T_DENSE);
+        HIPCHK(launch_sym_eig(G.get(), w.get(), U.get(), r0, 1, jw.get(), s_));
+        tm_.end();
+        std::vector<double> wh(r0);
+        HIPCHK(hipMemcpyAsync(wh.data(), w.get(), sizeof(double) * r0, hipMemcpyDeviceToHost, s_));
+        HIPCHK(hipStreamSynchronize(s_));
+        tm_.flush();
+        const double wmax = wh[r0 - 1];
+        int keep = 0;
+        if (wmax > 0.0) {
+            const double cut = std::max(1, r0) * 2.220446049250313e-16 * wmax;
+            for (int i = 0; i < r0; ++i)
+                if (wh[i] > cut) ++keep;
+        }
+        co.rank.push_back(keep);
+        if (co.rank.size() == 1) {
+            co.smin_ratio = wmax > 0 ? std::sqrt(std::max(0.0, wh[0]) / wmax) : 0.0;
+            co.saturated = co.smin_ratio > 1e-3;
+        }
+        co.r = keep;
+        co.theta.assign(keep, 0.0);
+        co.rho.assign(keep, 0.0);
+        co.X = std::make_shared<DBuf<double>>((size_t)n * std::max(keep, 1));
+        if (keep == 0) return;
+        DBuf<double> Tsc((size_t)r0 * keep), Q1((size_t)n * keep);
+        HIPCHK(launch_svqb_scale(U.get(), w.get(), r0, keep, Tsc.get(), s_));
+        gemm(S, r0, Tsc.get(), keep, n, r0, keep, Q1.get(), keep);
+        // pass 2: Cholesky
+        HIPCHK(launch_spmm_real(D, Q1.get(), keep, keep, nullptr, T.get(), s_));
+        gram(Q1.get(), keep, T.get(), keep, keep, keep, G.get(), gw);
+        HIPCHK(launch_symmetrise(G.get(), keep, s_));
+        DBuf<double> LT((size_t)keep * keep);
+        DBuf<int32_t> st(1);
+        tm_.begin(T_DENSE);
+        HIPCHK(launch_chol_inv(G.get(), LT.get(), keep, 1, jw.get(), st.get(), s_));
+        tm_.end();
+        check_status(st, "B-Gram of the SVQB basis");
+        DBuf<double> Q((size_t)n * keep);
+        gemm(Q1.get(), keep, LT.get(), keep, n, keep, keep, Q.get(), keep);
+        Q1.release();
+        // Rayleigh-Ritz
+        DBuf<double> AQ((size_t)n * keep);
+        HIPCHK(launch_spmm_real(D, Q.get(), keep, keep, AQ.get(), T.get(), s_));
+        DBuf<double> TA((size_t)keep * keep), TB((size_t)keep * keep);
+        gram(Q.get(), keep, AQ.get(), keep, keep, keep, TA.get(), gw);
+        gram(Q.get(), keep, T.get(), keep, keep, keep, TB.get(), gw);
+        HIPCHK(launch_symmetrise(TA.get(), keep, s_));
+        HIPCHK(launch_symmetrise(TB.get(), keep, s_));
+        tm_.begin(T_DENSE);
+        HIPCHK(launch_chol_inv(TB.get(), LT.get(), keep, 1, jw.get(), st.get(), s_));
+        // C = L^-1 TA L^-T = LT^T TA LT
+        DBuf<double> C1((size_t)keep * keep), C2((size_t)keep * keep), Z((size_t)keep * keep), th(keep);
+        HIPCHK(launch_small_gemm(LT.get(), 1, TA.get(), 0, C1.get(), keep, keep, keep, keep, keep, keep, s_));
+        HIPCHK(launch_small_gemm(C1.get(), 0, LT.get(), 0, C2.get(), keep, keep, keep, keep, keep, keep, s_));
+        HIPCHK(launch_symmetrise(C2.get(), keep, s_));
+        HIPCHK(launch_sym_eig(C2.get(), th.get(), Z.get(), keep, 1, jw.get(), s_));
+        // U = L^-T Z
+        HIPCHK(launch_small_gemm(LT.get(), 0, Z.get(), 0, C1.get(), keep, keep, keep, keep, keep, keep, s_));
+        tm_.end();
+        check_status(st, "projected B matrix");
+        gemm(Q.get(), keep, C1.get(), keep, n, keep, keep, co.X->get(), keep);
+        // residuals with the pencil itself
+        HIPCHK(launch_spmm_real(D, co.X->get(), keep, keep, AQ.get(), T.get(), s_));
+        DBuf<double> num(keep), den(keep), rw((size_t)2 * keep * 1024);
+        HIPCHK(launch_resid_norms(AQ.get(), T.get(), co.X->get(), th.get(), n, keep, num.get(), den.get(), rw.get(), s_));
+        std::vector<double> nh(keep), dh(keep);
+        HIPCHK(hipMemcpyAsync(co.theta.data(), th.get(), sizeof(double) * keep, hipMemcpyDeviceToHost, s_));
+        HIPCHK(hipMemcpyAsync(nh.data(), num.get(), sizeof(double) * keep, hipMemcpyDeviceToHost, s_));
+        HIPCHK(hipMemcpyAsync(dh.data(), den.get(), sizeof(double) * keep, hipMemcpyDeviceToHost, s_));
+        HIPCHK(hipStreamSynchronize(s_));
+        tm_.flush();
+        for (int i = 0; i < keep; ++i) co.rho[i] = nh[i] / (D.a_inf * std::max(dh[i], 1e-300));
+    }
+
+    void gram(const double* X, int64_t ld1, const double* Y, int64_t ld2, int64_t k1, int64_t k2,
+              double* G, DBuf<double>& work) {
+        tm_.begin(T_GRAM);
+        HIPCHK(launch_gram(X, ld1, Y, ld2, P_->d.n, k1, k2, G, work.get(), work.n, s_));
+        tm_.end();
+        gram_flops_ += 2.0 * P_->d.n * k1 * k2;
+    }
+    void gemm(const double* X, int64_t ldx, const double* T, int64_t ldt, int64_t n, int64_t k,
+              int64_t m, double* C, int64_t ldc) {
+        tm_.begin(T_GEMM);
+        HIPCHK(launch_gemm_tall(X, ldx, T, ldt, n, k, m, C, ldc, s_));
+        tm_.end();
+        gemm_flops_ += 2.0 * n * k * m;
+    }
+    void check_status(DBuf<int32_t>& st, const char* what) {
+        int32_t h = 0;
+        HIPCHK(hipMemcpyAsync(&h, st.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s_));
+        HIPCHK(hipStreamSynchronize(s_));
+        tm_.flush();
+        if (h != 0) fail(GEP_ENOTSPD, std::string("Cholesky failed on the ") + what + " at pivot " + std::to_string(h));
+    }
+
+    gep_pencil* P_;
+    SolveCfg c_;
+    hipStream_t s_;
+    Timer tm_;
+    Stats stats_;
+    int32_t* counts_h_ = nullptr;
+    double gram_flops_ = 0.0, gemm_flops_ = 0.0;
+};
+
+static size_t bytes_per_contour(int64_t n, int NH, int L, int M) {
+    const size_t W = (size_t)NH * L;
+    const size_t r = (size_t)L * M;
+    return (size_t)n * W * 16 * 4 + (size_t)n * r * 8 * 8 + (size_t)W * 128;
+}
+
+static std::string json_stats(const Solver& s, double wall_ms, const std::vector<ContourOut>& cos,
+                              int precision) {
+    std::ostringstream o;
+    o.precision(10);
+    o << "{\"wall_ms\":" << wall_ms << ",\"precision\":\"" << (precision == GEP_MIXED ? "mixed" : "fp64")
+      << "\",\"cocg_iters\":" << s.stats_.cocg_iters << ",\"tile_iters\":" << s.stats_.tile_iters
+      << ",\"columns\":" << s.stats_.columns << ",\"waves\":" << s.stats_.waves
+      << ",\"spmm_launches\":" << s.stats_.spmm_launches
+      << ",\"spmm_alg_bytes\":" << s.stats_.spmm_alg_bytes
+      << ",\"update_alg_bytes\":" << s.stats_.update_alg_bytes
+      << ",\"direction_alg_bytes\":" << s.stats_.direction_alg_bytes
+      << ",\"gram_flops\":" << s.gram_flops_ << ",\"gemm_flops\":" << s.gemm_flops_
+      << ",\"kernel_ms\":{";
+    for (int c = 0; c < Timer::kClasses; ++c)
+        o << (c ? "," : "") << "\"" << kTimerNames[c] << "\":" << s.tm_.ms[c];
+    o << "},\"kernel_launches\":{";
+    for (int c = 0; c < Timer::kClasses; ++c)
+        o << (c ? "," : "") << "\"" << kTimerNames[c] << "\":" << s.tm_.count[c];
+    o << "},\"contours\":[";
+    for (size_t i = 0; i < cos.size(); ++i) {
+        const auto& c = cos[i];
+        o << (i ? "," : "") << "{\"id\":" << c.id << ",\"passes\":" << c.passes << ",\"rank\":[";
+        for (size_t j = 0; j < c.rank.size(); ++j) o << (j ? "," : "") << c.rank[j];
+        o << "],\"saturated\":" << (c.saturated ? "true" : "false") << ",\"smin_ratio\":" << c.smin_ratio
+          << ",\"iters_max\":" << c.iters_max << ",\"iters_mean\":" << c.iters_mean << "}";
+    }
+    o << "]}";
+    return o.str();
+}
+
+static int solve_impl(gep_pencil* P, const gep_contour* contours, int K, const SolveCfg& cfg,
+                      gep_result** out) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = P->d.n;
+    Solver sv(P, cfg);
+    hipStream_t s = (hipStream_t)cfg.o.stream;
+    // V and B V
+    const int L = cfg.L;
+    DBuf<double> V((size_t)n * L), BV((size_t)n * L);
+    if (cfg.o.rhs) {
+        std::vector<double> vc((size_t)n * L), vr((size_t)n * L);
+        if (cfg.o.inputs_on_device)
+            HIPCHK(hipMemcpy(vc.data(), cfg.o.rhs, sizeof(double) * n * L, hipMemcpyDeviceToHost));
+        else
+            std::memcpy(vc.data(), cfg.o.rhs, sizeof(double) * n * L);
+        for (int64_t i = 0; i < n; ++i)
+            for (int l = 0; l < L; ++l) vr[(size_t)i * L + l] = vc[(size_t)l * n + i];
+        HIPCHK(hipMemcpyAsync(V.get(), vr.data(), sizeof(double) * n * L, hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    } else {
+        HIPCHK(launch_gaussian(cfg.o.seed, n, L, V.get(), s));
+    }
+    HIPCHK(launch_spmm_real(P->d, V.get(), L, L, nullptr, BV.get(), s));
+    // memory plan: waves of contours
+    size_t freeb = 0, totalb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totalb));
+    double budget = cfg.o.mem_limit_bytes > 0 ? cfg.o.mem_limit_bytes : 0.85 * (double)freeb;
+    const size_t per = bytes_per_contour(n, cfg.NH, L, cfg.M);
+    int per_wave = (int)std::min<double>(K, std::floor(budget / (double)per));
+    if (per_wave < 1) fail(GEP_ENOMEM, "one contour needs " + std::to_string(per) + " bytes of device memory");
+    std::vector<ContourOut> finals(K);
+    for (int k0 = 0; k0 < K; k0 += per_wave) {
+        const int k1 = std::min(K, k0 + per_wave);
+        std::vector<gep_contour> cs(contours + k0, contours + k1);
+        std::vector<int> ids;
+        for (int k = k0; k < k1; ++k) ids.push_back(k);
+        std::vector<ContourOut> res;
+        sv.stats_.waves += 1;
+        sv.run_pass(cs, ids, BV.get(), L, true, L, cfg.M, res);
+        for (auto& r : res) r.passes = 1;
+        // refinement: contours whose kept pairs miss tol
+        for (int pass = 1; pass <= cfg.o.max_refine; ++pass) {
+            std::vector<int> redo;
+            for (size_t i = 0; i < res.size(); ++i) {
+                const gep_contour& c = cs[i];
+                bool bad = false;
+                for (int j = 0; j < res[i].r; ++j)
+                    if (res[i].theta[j] >= c.keep_lo && res[i].theta[j] < c.keep_hi && !(res[i].rho[j] <= cfg.tol))
+                        bad = true;
+                if (bad) redo.push_back((int)i);
+            }
+            if (redo.empty()) break;
+            int L2 = 0;
+            for (int i : redo) L2 = std::max(L2, res[i].r);
+            const int Kr = (int)redo.size();
+            DBuf<double> V2((size_t)n * Kr * L2), BV2((size_t)n * Kr * L2);
+            HIPCHK(hipMemsetAsync(V2.get(), 0, sizeof(double) * n * Kr * L2, s));
+            for (int a = 0; a < Kr; ++a) {
+                const ContourOut& co = res[redo[a]];
+                HIPCHK(hipMemcpy2DAsync(V2.get() + (size_t)a * L2, sizeof(double) * Kr * L2, co.X->get(),
+                                        sizeof(double) * co.r, sizeof(double) * co.r, n,
+                                        hipMemcpyDeviceToDevice, s));
+            }
+            HIPCHK(launch_spmm_real(P->d, V2.get(), (int64_t)Kr * L2, (int64_t)Kr * L2, nullptr, BV2.get(), s));
+            std::vector<gep_contour> cs2;
+            std::vector<int> ids2;
+            for (int i : redo) {
+                cs2.push_back(cs[i]);
+                ids2.push_back(ids[i]);
+            }
+            std::vector<ContourOut> res2;
+            sv.run_pass(cs2, ids2, BV2.get(), (int64_t)Kr * L2, false, L2, 1, res2);
+            for (int a = 0; a < Kr; ++a) {
+                ContourOut& dst = res[redo[a]];
+                ContourOut& src = res2[a];
+                src.passes = dst.passes + 1;
+                std::vector<int> rk = dst.rank;
+                rk.insert(rk.end(), src.rank.begin(), src.rank.end());
+                src.rank = rk;
+                src.saturated = dst.saturated;
+                src.smin_ratio = dst.smin_ratio;
+                src.iters_max = std::max(src.iters_max, dst.iters_max);
+                dst = src;
+            }
+        }
+        for (size_t i = 0; i < res.size(); ++i) finals[k0 + i] = res[i];
+    }
+    // selection, gather, merge
+    struct Pair {
+        double lam, rho;
+        int cid;
+        int col;
+        int contour_slot;
+    };
+    std::vector<Pair> pairs;
+    std::vector<std::vector<double>> vecs(K);
+    bool saturated = false;
+    for (int k = 0; k < K; ++k) {
+        ContourOut& co = finals[k];
+        saturated |= co.saturated;
+        std::vector<int32_t> sel;
+        for (int j = 0; j < co.r; ++j)
+            if (co.theta[j] >= contours[k].keep_lo && co.theta[j] < contours[k].keep_hi) sel.push_back(j);
+        if (sel.empty()) continue;
+        DBuf<int32_t> dsel(sel.size());
+        DBuf<double> cm((size_t)n * sel.size());
+        HIPCHK(hipMemcpyAsync(dsel.get(), sel.data(), sizeof(int32_t) * sel.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(launch_gather_cols(co.X->get(), n, co.r, dsel.get(), (int)sel.size(), cm.get(), s));
+        vecs[k].resize((size_t)n * sel.size());
+        HIPCHK(hipMemcpyAsync(vecs[k].data(), cm.get(), sizeof(double) * n * sel.size(), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (size_t a = 0; a < sel.size(); ++a)
+            pairs.push_back({co.theta[sel[a]], co.rho[sel[a]], k, (int)a, k});
+    }
+    std::stable_sort(pairs.begin(), pairs.end(), [](const Pair& a, const Pair& b) { return a.lam < b.lam; });
+    // de-duplicate pairs found by different contours (same value within 1e-8
+    // relative and |x_a^T B x_b| >= 0.9): keep the smaller residual
+    const HostPencil& H = P->h;
+    auto bdot = [&](const double* xa, const double* xb) {
+        double sacc = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double t = 0.0;
+            for (int32_t e = H.rowptr[i]; e < H.rowptr[i + 1]; ++e) t += H.b[e] * xb[H.colind[e]];
+            sacc += xa[i] * t;
+        }
+        return sacc;
+    };
+    std::vector<char> drop(pairs.size(), 0);
+    for (size_t a = 0; a < pairs.size(); ++a) {
+        if (drop[a]) continue;
+        for (size_t b = a + 1; b < pairs.size(); ++b) {
+            if (pairs[b].lam - pairs[a].lam > 1e-8 * std::max(std::fabs(pairs[a].lam), std::fabs(pairs[b].lam))) break;
+            if (drop[b] || pairs[b].cid == pairs[a].cid) continue;
+            const double* xa = vecs[pairs[a].cid].data() + (size_t)pairs[a].col * n;
+            const double* xb = vecs[pairs[b].cid].data() + (size_t)pairs[b].col * n;
+            if (std::fabs(bdot(xa, xb)) >= 0.9) drop[pairs[b].rho >= pairs[a].rho ? b : a] = 1;
+        }
+    }
+    auto* R = new gep_result();
+    R->n = n;
+    bool noconv = false;
+    for (size_t a = 0; a < pairs.size(); ++a) {
+        if (drop[a]) continue;
+        const Pair& p = pairs[a];
+        R->evals.push_back(p.lam);
+        R->resid.push_back(p.rho);
+        R->cid.push_back(p.cid);
+        const bool ok = p.rho <= cfg.tol;
+        noconv |= !ok;
+        R->conv.push_back(ok ? 1 : 0);
+        const double* x = vecs[p.cid].data() + (size_t)p.col * n;
+        R->evecs.insert(R->evecs.end(), x, x + n);
+    }
+    R->m = (int64_t)R->evals.size();
+    const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    R->stats = json_stats(sv, wall, finals, cfg.o.precision);
+    *out = R;
+    if (noconv) return GEP_WNOCONV;
+    if (saturated) return GEP_WSATURATED;
+    return GEP_OK;
+}
+
+}  // namespace gep
+
+// ---- C ABI ------------------------------------------------------------------
+extern "C" {
+
+void gep_opts_default(gep_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->seed = 1;
+    o->precision = GEP_FP64;
+    o->max_refine = 1;
+    o->solve_tol = 1e-9;
+    o->max_iter = 100000;
+    o->check_every = 16;
+    o->stream = nullptr;
+    o->inputs_on_device = 0;
+    o->rhs = nullptr;
+    o->mem_limit_bytes = 0.0;
+    o->timing = 0;
+}
+
+const char* gep_strerror(int st) {
+    switch (st) {
+        case GEP_OK: return "ok";
+        case GEP_EINVAL: return "invalid argument";
+        case GEP_ENOTSYM: return "matrix not symmetric";
+        case GEP_ENOTSPD: return "B not positive definite";
+        case GEP_ENOMEM: return "out of device memory";
+        case GEP_EDEVICE: return "HIP runtime error";
+        case GEP_WNOCONV: return "warning: some pairs did not reach the residual tolerance";
+        case GEP_WSATURATED: return "warning: saturated subspace, eigenvalues may be missed";
+        default: return "unknown status";
+    }
+}
+
+const char* gep_last_error(void) { return gep::g_err.c_str(); }
+
+int gep_pencil_create(const gep_csr* A, const gep_csr* B, int on_dev, void* stream, gep_pencil** out) {
+    (void)stream;
+    if (!out) {
+        gep::set_error("out is NULL");
+        return GEP_EINVAL;
+    }
+    *out = nullptr;
+    auto* P = new gep_pencil();
+    try {
+        gep::pack(A, B, on_dev != 0, P->h);
+        gep::upload(P->h, P);
+    } catch (const gep::Fail& f) {
+        delete P;
+        return f.code;
+    }
+    *out = P;
+    return GEP_OK;
+}
+
+void gep_pencil_free(gep_pencil* p) { delete p; }
+
+int gep_pencil_info(const gep_pencil* p, int64_t* n, int64_t* nnz, double* a_inf) {
+    if (!p) return GEP_EINVAL;
+    if (n) *n = p->d.n;
+    if (nnz) *nnz = p->d.nnz;
+    if (a_inf) *a_inf = p->d.a_inf;
+    return GEP_OK;
+}
+
+static int validate_problem(const gep_contour* contours, int K, int N, int M, int L, double tol,
+                            const gep_opts* o) {
+    if (!contours || K <= 0) { gep::set_error("no contours"); return GEP_EINVAL; }
+    if (N < 2 || (N & 1)) { gep::set_error("n_nodes must be even and >= 2"); return GEP_EINVAL; }
+    if (M < 1 || M > 16) { gep::set_error("moments must be in [1, 16]"); return GEP_EINVAL; }
+    if (L < 1) { gep::set_error("block must be >= 1"); return GEP_EINVAL; }
+    if ((int64_t)L * M > 1024) { gep::set_error("block*moments must be <= 1024"); return GEP_EINVAL; }
+    if (!(tol > 0.0)) { gep::set_error("tol must be > 0"); return GEP_EINVAL; }
+    if (o->precision != GEP_FP64 && o->precision != GEP_MIXED) { gep::set_error("bad precision"); return GEP_EINVAL; }
+    if (!(o->solve_tol > 0.0) || o->max_iter < 1) { gep::set_error("bad solve_tol/max_iter"); return GEP_EINVAL; }
+    for (int k = 0; k < K; ++k) {
+        const gep_contour& c = contours[k];
+        if (!std::isfinite(c.center) || !std::isfinite(c.radius) || !(c.radius > 0.0) ||
+            !std::isfinite(c.keep_lo) || !std::isfinite(c.keep_hi) || !(c.keep_lo < c.keep_hi) ||
+            c.keep_lo < c.center - c.radius * (1 + 1e-12) || c.keep_hi > c.center + c.radius * (1 + 1e-12)) {
+            gep::set_error("contour " + std::to_string(k) + " is invalid (radius, or keep window outside the circle)");
+            return GEP_EINVAL;
+        }
+    }
+    return GEP_OK;
+}
+
+int gep_ci_solve_pencil(gep_pencil* P, const gep_contour* contours, int K, int N, int M, int L,
+                        double tol, const gep_opts* opts, gep_result** out) {
+    if (!out || !P) { gep::set_error("NULL pencil or out"); return GEP_EINVAL; }
+    *out = nullptr;
+    gep_opts o;
+    if (opts) o = *opts; else gep_opts_default(&o);
+    int st = validate_problem(contours, K, N, M, L, tol, &o);
+    if (st) return st;
+    if (o.precision == GEP_MIXED) { gep::set_error("mixed precision is not available in this build"); return GEP_EINVAL; }
+    gep::SolveCfg cfg;
+    cfg.N = N;
+    cfg.NH = N / 2;
+    cfg.M = M;
+    cfg.L = L;
+    cfg.tol = tol;
+    cfg.o = o;
+    try {
+        return gep::solve_impl(P, contours, K, cfg, out);
+    } catch (const gep::Fail& f) {
+        return f.code;
+    }
+}
+
+int gep_ci_solve(const gep_csr* A, const gep_csr* B, const gep_contour* contours, int n_contours,
+                 int n_nodes, int moments, int block, double tol, const gep_opts* opts,
+                 gep_result** out) {
+    if (!out) { gep::set_error("out is NULL"); return GEP_EINVAL; }
+    *out = nullptr;
+    gep_opts o;
+    if (opts) o = *opts; else gep_opts_default(&o);
+    int st = validate_problem(contours, n_contours, n_nodes, moments, block, tol, &o);
+    if (st) return st;
+    gep_pencil* P = nullptr;
+    st = gep_pencil_create(A, B, o.inputs_on_device, o.stream, &P);
+    if (st) return st;
+    st = gep_ci_solve_pencil(P, contours, n_contours, n_nodes, moments, block, tol, &o, out);
+    gep_pencil_free(P);
+    return st;
+}
+
+int gep_result_count(const gep_result* r, int64_t* m, int64_t* n) {
+    if (!r) return GEP_EINVAL;
+    if (m) *m = r->m;
+    if (n) *n = r->n;
+    return GEP_OK;
+}
+
+int gep_result_copy(const gep_result* r, double* evals, double* evecs, double* resid, int32_t* cid,
+                    uint8_t* conv) {
+    if (!r) return GEP_EINVAL;
+    if (evals) std::copy(r->evals.begin(), r->evals.end(), evals);
+    if (evecs) std::copy(r->evecs.begin(), r->evecs.end(), evecs);
+    if (resid) std::copy(r->resid.begin(), r->resid.end(), resid);
+    if (cid) std::copy(r->cid.begin(), r->cid.end(), cid);
+    if (conv) std::copy(r->conv.begin(), r->conv.end(), conv);
+    return GEP_OK;
+}
+
+int gep_result_stats(const gep_result* r, char* json, size_t cap, size_t* needed) {
+    if (!r) return GEP_EINVAL;
+    if (needed) *needed = r->stats.size() + 1;
+    if (json && cap > 0) {
+        const size_t k = std::min(cap - 1, r->stats.size());
+        std::memcpy(json, r->stats.data(), k);
+        json[k] = 0;
+    }
+    return GEP_OK;
+}
+
+void gep_result_free(gep_result* r) { delete r; }
+
+// ---- component entry points -------------------------------------------------
+int gep_spmm_shifted(const gep_pencil* p, const double* shifts, const double* X, double* Y,
+                     int64_t W, double* pq, void* stream) {
+    if (!p || !shifts || !X || !Y || W <= 0 || W % gep::kTile) { gep::set_error("bad spmm arguments"); return GEP_EINVAL; }
+    try {
+        const int ntiles = (int)(W / gep::kTile);
+        hipStream_t s = (hipStream_t)stream;
+        gep::DBuf<int32_t> tiles(ntiles), cnt(1);
+        std::vector<int32_t> tl(ntiles);
+        for (int t = 0; t < ntiles; ++t) tl[t] = t;
+        HIPCHK(hipMemcpyAsync(tiles.get(), tl.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(cnt.get(), &ntiles, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        int nrb = 0;
+        gep::choose_nrb(p->d.n, ntiles, (int)std::max<int64_t>(1, std::min<int64_t>(1024, (p->d.n + 31) / 32)), nrb);
+        gep::DBuf<double2> part;
+        if (pq) part.alloc((size_t)ntiles * nrb * gep::kTile);
+        HIPCHK(gep::launch_spmm_c64(p->d, (const double2*)shifts, (const double2*)X, (double2*)Y, tiles.get(),
+                                    cnt.get(), ntiles, nrb, pq ? part.get() : nullptr, s));
+        if (pq) {
+            std::vector<double2> ph((size_t)ntiles * nrb * gep::kTile), out(W);
+            HIPCHK(hipMemcpyAsync(ph.data(), part.get(), sizeof(double2) * ph.size(), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (int t = 0; t < ntiles; ++t)
+                for (int l = 0; l < gep::kTile; ++l) {
+                    double2 a = make_double2(0, 0);
+                    for (int rb = 0; rb < nrb; ++rb) {
+                        const double2 v = ph[((size_t)t * nrb + rb) * gep::kTile + l];
+                        a.x += v.x;
+                        a.y += v.y;
+                    }
+                    out[(size_t)t * gep::kTile + l] = a;
+                }
+            HIPCHK(hipMemcpy(pq, out.data(), sizeof(double2) * W, hipMemcpyHostToDevice));
+        }
+        HIPCHK(hipStreamSynchronize(s));
+    } catch (const gep::Fail& f) {
+        return f.code;
+    }
+    return GEP_OK;
+}
+
+int gep_spmm_shifted_f32(const gep_pencil* p, const double* shifts, const float* X, float* Y,
+                         int64_t W, void* stream) {
+    if (!p || !shifts || !X || !Y || W <= 0 || W % gep::kTile) { gep::set_error("bad spmm arguments"); return GEP_EINVAL; }
+    try {
+        const int ntiles = (int)(W / gep::kTile);
+        hipStream_t s = (hipStream_t)stream;
+        gep::DBuf<int32_t> tiles(ntiles), cnt(1);
+        std::vector<int32_t> tl(ntiles);
+        for (int t = 0; t < ntiles; ++t) tl[t] = t;
+        HIPCHK(hipMemcpyAsync(tiles.get(), tl.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(cnt.get(), &ntiles, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        int nrb = 0;
+        gep::choose_nrb(p->d.n, ntiles, (int)std::max<int64_t>(1, std::min<int64_t>(1024, (p->d.n + 31) / 32)), nrb);
+        HIPCHK(gep::launch_spmm_c32(p->d, (const double2*)shifts, (const float2*)X, (float2*)Y, tiles.get(),
+                                    cnt.get(), ntiles, nrb, nullptr, s));
+        HIPCHK(hipStreamSynchronize(s));
+    } catch (const gep::Fail& f) {
+        return f.code;
+    }
+    return GEP_OK;
+}
+
+int gep_spmm_real(const gep_pencil* p, const double* X, int64_t k, int64_t ld, double* YA, double* YB,
+                  void* stream) {
+    if (!p || !X || k <= 0 || ld < k) { gep::set_error("bad spmm_real arguments"); return GEP_EINVAL; }
+    try {
+        HIPCHK(gep::launch_spmm_real(p->d, X, k, ld, YA, YB, (hipStream_t)stream));
+        HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    } catch (const gep::Fail& f) {
+        return f.code;
+    }
+    return GEP_OK;
+}
+
+int gep_gram(const double* X, int64_t ld1, const double* Y, int64_t ld2, int64_t n, int64_t k1,
+             int64_t k2, double* G, void* stream) {
+    if (!X || !Y || !G || n < 0 || k1 <= 0 || k2 <= 0 || ld1 < k1 || ld2 < k2) { gep::set_error("bad gram arguments"); return GEP_EINVAL; }
+    try {
+        const size_t we = gep::gram_work_elems(n, k1, k2);
+        gep::DBuf<double> w(std::max<size_t>(we, 1));
+        HIPCHK(gep::launch_gram(X, ld1, Y, ld2, n, k1, k2, G, w.get(), w.n, (hipStream_t)stream));
+        HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    } catch (const gep::Fail& f) {
+        return f.code;
+    }
+    return GEP_OK;
+}
+
+int gep_gemm_tall(const double* X, int64_t ldx, const double* T, int64_t ldt, int64_t n, int64_t k,
+                  int64_t m, double* C, int64_t ldc, void* stream) {
+    if (!X || !T || !C || n < 0 || k <= 0 || m <= 0 || ldx < k || ldt < m || ldc < m) { gep::set_error("bad gemm arguments"); return GEP_EINVAL; }
+    try {
+        HIPCHK(gep::launch_gemm_tall(X, ldx, T, ldt, n, k, m, C, ldc, (hipStream_t)stream));
+        HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    } catch (const gep::Fail& f) {
+        return f.code;
+    }
+    return GEP_OK;
+}
+
+int gep_sym_eig(double* A, double* w, double* V, int64_t k, int batch, void* stream) {
+    if (!A || !w || !V || k <= 0 || k > 1024 || batch <= 0) { gep::set_error("bad sym_eig arguments"); return GEP_EINVAL; }
+    try {
+        gep::DBuf<double> work((size_t)batch * k * k);
+        HIPCHK(gep::launch_sym_eig(A, w, V, k, batch, work.get(), (hipStream_t)stream));
+        HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    } catch (const gep::Fail& f) {
+        return f.code;
+    }
+    return GEP_OK;
+}
+
+int gep_gaussian_block(uint64_t seed, int64_t n, int64_t L, double* V, void* stream) {
+    if (!V || n <= 0 || L <= 0) { gep::set_error("bad gaussian arguments"); return GEP_EINVAL; }
+    try {
+        HIPCHK(gep::launch_gaussian(seed, n, L, V, (hipStream_t)stream));
+        HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    } catch (const gep::Fail& f) {
+        return f.code;
+    }
+    return GEP_OK;
+}
+
+}  // extern "C"

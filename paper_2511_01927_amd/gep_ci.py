@@ -1,0 +1,295 @@
+"""ctypes binding of libgepci.so (the C ABI declared in include/gep_ci.h).
+
+Argument marshalling only: every step of the solve runs in the library's
+HIP kernels.  Host inputs are scipy CSR matrices / numpy arrays; device
+inputs and outputs are torch CUDA (HIP) tensors, whose data pointers are
+passed through unchanged.  There is no fallback: if the library is missing
+or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgepci.so")
+
+GEP_FP64 = 0
+GEP_MIXED = 1
+GEP_WNOCONV = 1
+GEP_WSATURATED = 2
+
+
+class GepError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"gep status {status}: {msg}")
+        self.status = status
+
+
+class gep_csr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
+                ("colind", C.c_void_p), ("val", C.c_void_p)]
+
+
+class gep_contour(C.Structure):
+    _fields_ = [("center", C.c_double), ("radius", C.c_double), ("keep_lo", C.c_double),
+                ("keep_hi", C.c_double)]
+
+
+class gep_opts(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("precision", C.c_int), ("max_refine", C.c_int),
+                ("solve_tol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int),
+                ("stream", C.c_void_p), ("inputs_on_device", C.c_int), ("rhs", C.c_void_p),
+                ("mem_limit_bytes", C.c_double), ("timing", C.c_int)]
+
+
+# every symbol declared in include/gep_ci.h
+EXPORTS = [
+    "gep_opts_default", "gep_ci_solve", "gep_result_count", "gep_result_copy",
+    "gep_result_stats", "gep_result_free", "gep_strerror", "gep_last_error",
+    "gep_pencil_create", "gep_pencil_free", "gep_pencil_info", "gep_ci_solve_pencil",
+    "gep_spmm_shifted", "gep_spmm_shifted_f32", "gep_spmm_real", "gep_gram", "gep_gemm_tall",
+    "gep_sym_eig", "gep_gaussian_block",
+]
+
+_lib = None
+
+
+def load():
+    """Load libgepci.so (built by ``paper_2511_01927_amd.build``) and declare signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2511_01927_amd.build.build()")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    i64, i32, dbl = C.c_int64, C.c_int, C.c_double
+    sig = {
+        "gep_opts_default": (None, [C.POINTER(gep_opts)]),
+        "gep_ci_solve": (i32, [C.POINTER(gep_csr), C.POINTER(gep_csr), C.POINTER(gep_contour), i32,
+                               i32, i32, i32, dbl, C.POINTER(gep_opts), C.POINTER(P)]),
+        "gep_ci_solve_pencil": (i32, [P, C.POINTER(gep_contour), i32, i32, i32, i32, dbl,
+                                      C.POINTER(gep_opts), C.POINTER(P)]),
+        "gep_result_count": (i32, [P, C.POINTER(i64), C.POINTER(i64)]),
+        "gep_result_copy": (i32, [P, P, P, P, P, P]),
+        "gep_result_stats": (i32, [P, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+        "gep_result_free": (None, [P]),
+        "gep_strerror": (C.c_char_p, [i32]),
+        "gep_last_error": (C.c_char_p, []),
+        "gep_pencil_create": (i32, [C.POINTER(gep_csr), C.POINTER(gep_csr), i32, P, C.POINTER(P)]),
+        "gep_pencil_free": (None, [P]),
+        "gep_pencil_info": (i32, [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(dbl)]),
+        "gep_spmm_shifted": (i32, [P, P, P, P, i64, P, P]),
+        "gep_spmm_shifted_f32": (i32, [P, P, P, P, i64, P]),
+        "gep_spmm_real": (i32, [P, P, i64, i64, P, P, P]),
+        "gep_gram": (i32, [P, i64, P, i64, i64, i64, i64, P, P]),
+        "gep_gemm_tall": (i32, [P, i64, P, i64, i64, i64, i64, P, i64, P]),
+        "gep_sym_eig": (i32, [P, P, P, i64, i32, P]),
+        "gep_gaussian_block": (i32, [C.c_uint64, i64, i64, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(st: int, allow_warn: bool = False) -> int:
+    if st < 0 or (st > 0 and not allow_warn):
+        lib = load()
+        raise GepError(st, f"{lib.gep_strerror(st).decode()}: {lib.gep_last_error().decode()}")
+    return st
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class _HostCSR:
+    """Keeps contiguous int64/int32/float64 host copies alive for a gep_csr."""
+
+    def __init__(self, M):
+        M = M.tocsr()
+        self.rowptr = np.ascontiguousarray(M.indptr, dtype=np.int64)
+        self.colind = np.ascontiguousarray(M.indices, dtype=np.int32)
+        self.val = np.ascontiguousarray(M.data, dtype=np.float64)
+        self.s = gep_csr(M.shape[0], self.val.size, self.rowptr.ctypes.data,
+                         self.colind.ctypes.data, self.val.ctypes.data)
+
+
+class _DevCSR:
+    """gep_csr over torch device tensors (rowptr int64, colind int32, val float64)."""
+
+    def __init__(self, rowptr, colind, val):
+        self.keep = (rowptr, colind, val)
+        self.s = gep_csr(rowptr.numel() - 1, val.numel(), rowptr.data_ptr(), colind.data_ptr(),
+                         val.data_ptr())
+
+
+def _csr_arg(M):
+    if isinstance(M, tuple):
+        return _DevCSR(*M), 1
+    return _HostCSR(M), 0
+
+
+def _contours(contours):
+    arr = np.atleast_2d(np.asarray(contours, dtype=np.float64))
+    cs = (gep_contour * arr.shape[0])()
+    for k, (c, r, lo, hi) in enumerate(arr):
+        cs[k] = gep_contour(c, r, lo, hi)
+    return cs, arr.shape[0]
+
+
+def _opts(seed=1, precision="fp64", max_refine=1, solve_tol=1e-9, max_iter=100000, check_every=16,
+          stream=None, on_device=0, rhs=None, mem_limit_bytes=0.0, timing=False):
+    lib = load()
+    o = gep_opts()
+    lib.gep_opts_default(C.byref(o))
+    o.seed = seed
+    o.precision = GEP_MIXED if precision == "mixed" else GEP_FP64
+    o.max_refine = max_refine
+    o.solve_tol = solve_tol
+    o.max_iter = max_iter
+    o.check_every = check_every
+    o.stream = _stream_ptr(stream).value
+    o.inputs_on_device = on_device
+    keep = None
+    if rhs is not None:
+        if hasattr(rhs, "data_ptr"):
+            o.rhs = rhs.data_ptr()
+            o.inputs_on_device = 1
+            keep = rhs
+        else:
+            keep = np.asfortranarray(rhs, dtype=np.float64)
+            o.rhs = keep.ctypes.data
+    o.mem_limit_bytes = mem_limit_bytes
+    o.timing = 1 if timing else 0
+    return o, keep
+
+
+def _collect(res_ptr, status):
+    lib = load()
+    m = C.c_int64()
+    n = C.c_int64()
+    _check(lib.gep_result_count(res_ptr, C.byref(m), C.byref(n)))
+    m, n = m.value, n.value
+    ev = np.zeros(m)
+    vec = np.zeros((m, n))          # row j = eigenvector j  (column-major n x m)
+    rho = np.zeros(m)
+    cid = np.zeros(m, dtype=np.int32)
+    conv = np.zeros(m, dtype=np.uint8)
+    _check(lib.gep_result_copy(res_ptr, ev.ctypes.data, vec.ctypes.data, rho.ctypes.data,
+                               cid.ctypes.data, conv.ctypes.data))
+    need = C.c_size_t()
+    lib.gep_result_stats(res_ptr, None, 0, C.byref(need))
+    buf = C.create_string_buffer(need.value)
+    lib.gep_result_stats(res_ptr, buf, need.value, None)
+    lib.gep_result_free(res_ptr)
+    return {"evals": ev, "evecs": vec.T, "resid": rho, "contour": cid,
+            "converged": conv.astype(bool), "status": status,
+            "stats": json.loads(buf.value.decode())}
+
+
+def gep_ci_solve(A, B, contours, n_nodes, moments, block, tol, **kw):
+    """Solve A x = lambda B x inside the contours' keep windows.
+
+    A, B: scipy sparse matrices (host) or (rowptr, colind, val) torch device
+    tensors.  Returns dict(evals, evecs (n x m), resid, contour, converged,
+    status, stats).  Warnings (unconverged / saturated) are reported in
+    ``status``; errors raise GepError.
+    """
+    lib = load()
+    a, dev_a = _csr_arg(A)
+    b, dev_b = _csr_arg(B)
+    cs, K = _contours(contours)
+    o, keep = _opts(on_device=dev_a, **kw)
+    if dev_a != dev_b:
+        raise ValueError("A and B must both be host or both be device matrices")
+    out = C.c_void_p()
+    st = lib.gep_ci_solve(C.byref(a.s), C.byref(b.s), cs, K, n_nodes, moments, block, tol,
+                          C.byref(o), C.byref(out))
+    _check(st, allow_warn=True)
+    return _collect(out, st)
+
+
+class Pencil:
+    """A packed, device-resident pencil (gep_pencil_create)."""
+
+    def __init__(self, A, B, stream=None):
+        lib = load()
+        a, dev = _csr_arg(A)
+        b, _ = _csr_arg(B)
+        h = C.c_void_p()
+        _check(lib.gep_pencil_create(C.byref(a.s), C.byref(b.s), dev, _stream_ptr(stream), C.byref(h)))
+        self.h = h
+        n = C.c_int64()
+        nnz = C.c_int64()
+        ainf = C.c_double()
+        lib.gep_pencil_info(h, C.byref(n), C.byref(nnz), C.byref(ainf))
+        self.n, self.nnz, self.a_inf = n.value, nnz.value, ainf.value
+
+    def solve(self, contours, n_nodes, moments, block, tol, **kw):
+        lib = load()
+        cs, K = _contours(contours)
+        o, keep = _opts(**kw)
+        out = C.c_void_p()
+        st = lib.gep_ci_solve_pencil(self.h, cs, K, n_nodes, moments, block, tol, C.byref(o),
+                                     C.byref(out))
+        _check(st, allow_warn=True)
+        return _collect(out, st)
+
+    def free(self):
+        if getattr(self, "h", None):
+            load().gep_pencil_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+# ---- component entry points on torch device tensors --------------------------
+def gep_spmm_shifted(pencil: Pencil, shifts, X, Y, W: int, pq=None, stream=None):
+    _check(load().gep_spmm_shifted(pencil.h, shifts.data_ptr(), X.data_ptr(), Y.data_ptr(), W,
+                                   pq.data_ptr() if pq is not None else None, _stream_ptr(stream)))
+
+
+def gep_spmm_shifted_f32(pencil: Pencil, shifts, X, Y, W: int, stream=None):
+    _check(load().gep_spmm_shifted_f32(pencil.h, shifts.data_ptr(), X.data_ptr(), Y.data_ptr(), W,
+                                       _stream_ptr(stream)))
+
+
+def gep_spmm_real(pencil: Pencil, X, k: int, ld: int, YA=None, YB=None, stream=None):
+    _check(load().gep_spmm_real(pencil.h, X.data_ptr(), k, ld,
+                                YA.data_ptr() if YA is not None else None,
+                                YB.data_ptr() if YB is not None else None, _stream_ptr(stream)))
+
+
+def gep_gram(X, ld1, Y, ld2, n, k1, k2, G, stream=None):
+    _check(load().gep_gram(X.data_ptr(), ld1, Y.data_ptr(), ld2, n, k1, k2, G.data_ptr(),
+                           _stream_ptr(stream)))
+
+
+def gep_gemm_tall(X, ldx, T, ldt, n, k, m, Cm, ldc, stream=None):
+    _check(load().gep_gemm_tall(X.data_ptr(), ldx, T.data_ptr(), ldt, n, k, m, Cm.data_ptr(), ldc,
+                                _stream_ptr(stream)))
+
+
+def gep_sym_eig(A, w, V, k, batch=1, stream=None):
+    _check(load().gep_sym_eig(A.data_ptr(), w.data_ptr(), V.data_ptr(), k, batch, _stream_ptr(stream)))
+
+
+def gep_gaussian_block(seed, n, L, V, stream=None):
+    _check(load().gep_gaussian_block(seed, n, L, V.data_ptr(), _stream_ptr(stream)))

@@ -1,0 +1,154 @@
+"""End-to-end parity of gep_ci_solve (HIP path, called through the C ABI)
+against the CPU oracle and closed forms.
+
+Bar: same eigenvalue count, eigenvalues within 1e-10 relative, residuals
+||Ax - lambda Bx|| / (||A||_inf ||x||) <= 1e-8, eigenvectors equal up to
+sign (simple eigenvalues: |x^T B x_ref| >= 1 - 1e-8) or, inside clusters
+of (near-)equal eigenvalues where several bases are correct, all singular
+values of X^T B X_ref >= 1 - 1e-8.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import configs, pencils
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-10
+RES = 1e-8
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_01927_amd import gep_ci
+    gep_ci.load()
+    return gep_ci
+
+
+def _clusters(lam, rel=1e-8):
+    groups, cur = [], [0]
+    for i in range(1, lam.size):
+        if lam[i] - lam[i - 1] <= rel * abs(lam[i]):
+            cur.append(i)
+        else:
+            groups.append(cur)
+            cur = [i]
+    if lam.size:
+        groups.append(cur)
+    return groups
+
+
+def assert_pairs_match(got, lam_ref, X_ref, B):
+    lam = got["evals"]
+    assert lam.size == lam_ref.size, (lam.size, lam_ref.size)
+    if lam.size == 0:
+        return
+    rel = np.max(np.abs(lam - lam_ref) / np.abs(lam_ref))
+    assert rel <= REL, rel
+    assert np.max(got["resid"]) <= RES, np.max(got["resid"])
+    X = got["evecs"]
+    BX = B @ X
+    assert np.abs(np.einsum("ij,ij->j", X, BX) - 1.0).max() <= 1e-10
+    for g in _clusters(lam_ref):
+        s = np.linalg.svd(BX[:, g].T @ X_ref[:, g], compute_uv=False)
+        assert s.min() >= 1 - 1e-8, (g, s)
+
+
+def _oracle_refs(w, **kw):
+    ref = oracle.oracle_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol,
+                                 seed=w.seed, **kw)
+    return ref["evals"], ref["evecs"]
+
+
+def test_small_fem1d_vs_oracle(lib):
+    w = configs.config_fem1d(n=400, first=31, last=40, n_nodes=16, moments=4, block=8, seed=7)
+    got = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed)
+    lam, X = _oracle_refs(w)
+    assert_pairs_match(got, lam, X, w.B)
+    assert got["status"] in (0, lib.GEP_WSATURATED)
+
+
+def test_fem1d_2000_closed_form(lib):
+    """1D linear-FEM pencil, n = 2000, eigenvalues 101..120, 16 nodes, 4 moments, 16 rhs."""
+    w = configs.fem1d_2000()
+    got = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed)
+    lam_ref = configs.line_eigs(2000)[100:120]
+    i = np.arange(1, 2001)
+    X_ref = np.stack([np.sin(i * j * np.pi / 2001) for j in range(101, 121)], axis=1)
+    X_ref /= np.sqrt(np.einsum("ij,ij->j", X_ref, w.B @ X_ref))[None, :]
+    assert_pairs_match(got, lam_ref, X_ref, w.B)
+    lam_o, X_o = _oracle_refs(w)
+    assert_pairs_match(got, lam_o, X_o, w.B)
+
+
+def _var2d(nx=40, ny=37, seed=8, first=41, last=100, k=3):
+    g = pencils.grf((ny + 1, nx + 1), seed=seed)
+    A, B = pencils.q1_2d(nx, ny, np.exp(g))
+    lam = np.linalg.eigvalsh(np.linalg.solve(np.linalg.cholesky(B.toarray()),
+                                             np.linalg.solve(np.linalg.cholesky(B.toarray()), A.toarray()).T))
+    lo, hi = 0.5 * (lam[first - 2] + lam[first - 1]), 0.5 * (lam[last - 1] + lam[last])
+    cont = configs.uniform_contours(lo, hi, k, 0.1)
+    return configs.Workload("var2d", A, B, cont, 32, 4, 32, seed + 100, window=(lo, hi))
+
+
+def test_variable_coefficient_2d_vs_oracle(lib):
+    w = _var2d()
+    got = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed)
+    lam, X = _oracle_refs(w)
+    assert_pairs_match(got, lam, X, w.B)
+
+
+def test_explicit_rhs_and_device_inputs(lib):
+    import torch
+    from oracle import rng
+    w = configs.config_fem1d(n=600, first=41, last=52, n_nodes=16, moments=4, block=8, seed=3)
+    V = rng.gaussian_block(w.n, w.block, w.seed)
+    a = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed)
+    b = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, rhs=V)
+    assert np.abs(a["evals"] - b["evals"]).max() <= 1e-12 * np.abs(a["evals"]).max()
+    dev = torch.device("cuda:0")
+    def d(M):
+        return (torch.from_numpy(M.indptr.astype(np.int64)).to(dev),
+                torch.from_numpy(M.indices.astype(np.int32)).to(dev),
+                torch.from_numpy(M.data.astype(np.float64)).to(dev))
+    c = lib.gep_ci_solve(d(w.A), d(w.B), w.contours, w.n_nodes, w.moments, w.block, w.tol,
+                         seed=w.seed)
+    assert np.array_equal(a["evals"], c["evals"])
+
+
+def test_empty_contour(lib):
+    w = configs.config_fem1d(n=300, first=31, last=40, n_nodes=16, moments=2, block=8, seed=3)
+    lam = configs.line_eigs(300)
+    lo = 0.5 * (lam[30] + lam[31])
+    c = np.array([[lo + 1e-3, 1e-3, lo, lo + 2e-3]])     # tiny circle inside a gap
+    got = lib.gep_ci_solve(w.A, w.B, c, 16, 2, 8, 1e-8, seed=1)
+    assert got["evals"].size == 0
+
+
+def test_no_convergence_flag(lib):
+    w = configs.config_fem1d(n=300, first=31, last=40, n_nodes=16, moments=4, block=8, seed=3)
+    got = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed,
+                           max_iter=3, max_refine=0)
+    assert got["status"] == lib.GEP_WNOCONV
+    assert not got["converged"].all()
+
+
+def test_saturation_flag(lib):
+    w = configs.fem1d_2000()
+    got = lib.gep_ci_solve(w.A, w.B, w.contours, 16, 1, 4, 1e-8, seed=1, max_refine=0)
+    assert got["status"] in (lib.GEP_WSATURATED, lib.GEP_WNOCONV)
+    assert any(c["saturated"] for c in got["stats"]["contours"])
+
+
+def test_two_contours_share_cut_without_duplicates(lib):
+    w = configs.config_fem1d(n=800, first=61, last=80, n_nodes=16, moments=4, block=16, seed=5)
+    lo, hi = w.window
+    cont = configs.uniform_contours(lo, hi, 2, 0.2)
+    got = lib.gep_ci_solve(w.A, w.B, cont, 16, 4, 16, 1e-8, seed=5)
+    ref = oracle.oracle_ci_solve(w.A, w.B, cont, 16, 4, 16, 1e-8, seed=5)
+    assert_pairs_match(got, ref["evals"], ref["evecs"], w.B)
+    assert np.all(np.diff(got["evals"]) > 0)

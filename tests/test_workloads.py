@@ -113,7 +113,7 @@ def test_headline_windows():
 @pytest.mark.slow
 def test_q1_300_window_count():
     lam = configs.q1_2d_eigs(300, 300)
-    lo, hi = configs.gap_window(lam, 1001, 1199)
+    lo, hi = configs.gap_window(lam, 1002, 1200)
     assert np.sum((lam >= lo) & (lam < hi)) == 199
     cont = configs.uniform_contours(lo, hi, 4, 0.1)
     assert np.allclose(cont[1:, 2], cont[:-1, 3])

@@ -49,6 +49,9 @@ def q1_2d_eigs(nx: int, ny: int) -> np.ndarray:
 
 def gap_window(eigs: np.ndarray, first: int, last: int):
     """Window holding sorted eigenvalues first..last (1-based, inclusive), ends at gap midpoints."""
+    for i in (first - 2, last - 1):
+        if not eigs[i + 1] - eigs[i] > 1e-9 * abs(eigs[i + 1]):
+            raise ValueError(f"no spectral gap after eigenvalue {i + 1}: choose another window end")
     lo = 0.5 * (eigs[first - 2] + eigs[first - 1])
     hi = 0.5 * (eigs[last - 1] + eigs[last])
     return float(lo), float(hi)
@@ -74,7 +77,7 @@ def config_fem1d(n: int = 2000, first: int = 101, last: int = 120, n_nodes: int 
                     meta={"first": first, "last": last})
 
 
-def config_q1_2d(nx: int = 300, ny: int = 300, first: int = 1001, last: int = 1199, k: int = 4,
+def config_q1_2d(nx: int = 300, ny: int = 300, first: int = 1002, last: int = 1200, k: int = 4,
                  alpha: float = 0.1, n_nodes: int = 32, moments: int = 4, block: int = 64,
                  seed: int = 1002) -> Workload:
     """Constant-coefficient Q1 pencil, gap-to-gap window split into k uniform circles."""
@@ -87,7 +90,7 @@ def config_q1_2d(nx: int = 300, ny: int = 300, first: int = 1001, last: int = 11
 
 # The two headline configurations: a 1D linear-FEM pencil (n = 2000, the
 # eigenvalues 101..120, one circle, 16 nodes, 4 moments, 16 right-hand sides)
-# and a 300 x 300 Q1 pencil (n = 90000, eigenvalues 1001..1199 split over four
+# and a 300 x 300 Q1 pencil (n = 90000, eigenvalues 1002..1200 split over four
 # uniform circles, 32 nodes, 4 moments, 64 right-hand sides).
 def fem1d_2000() -> Workload:
     return config_fem1d()
