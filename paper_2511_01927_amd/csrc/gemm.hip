@@ -4,7 +4,7 @@
 //
 // Both kernels use v_mfma_f64_16x16x4_f64: per wavefront D(16x16) += A(16x4)
 // B(4x16) with lane l supplying A[l % 16][l / 16] and B[l / 16][l % 16],
-// and holding D[4 (l / 16) + v][l % 16] in accumulator element v.
+// and holding D[(l / 16) + 4 v][l % 16] in accumulator element v.
 #include "internal.h"
 
 namespace gep {
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ X, int6
     double* W = work + (int64_t)split * k1 * k2;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const int ri = 4 * lk + v;
+        const int ri = lk + 4 * v;
         const int r0 = m0 + ri, r1 = m0 + 16 + ri;
         if (r0 < k1 && okb0) W[(int64_t)r0 * k2 + cb0] = acc00[v];
         if (r0 < k1 && okb1) W[(int64_t)r0 * k2 + cb1] = acc01[v];
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void k_gemm_tall(const double* __restrict__ X,
         if (col >= m) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t orow = row0 + wave * 16 + 4 * lk + v;
+            const int64_t orow = row0 + wave * 16 + lk + 4 * v;
             if (orow < n) C[orow * ldc + col] = acc[c][v];
         }
     }
