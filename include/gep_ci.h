@@ -98,6 +98,8 @@ typedef struct {
     double mem_limit_bytes; /* device-memory budget for one wave of contours;
                                0 = 85% of free memory */
     int timing;             /* 1: time every kernel class with HIP events */
+    int rows_per_block;     /* rows per work-group of the streaming COCG kernels
+                               (0 = automatic: max(64, n / 2048)) */
 } gep_opts;
 
 typedef struct gep_result gep_result;

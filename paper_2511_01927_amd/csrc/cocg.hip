@@ -4,27 +4,46 @@
 // are independent).  Every column of the tiled multivector is its own
 // system (one node z_c, one right-hand side); all columns advance together.
 //
-// Per iteration (conjugate-orthogonal CG, bilinear form x^T y):
-//   q = K p                      (spmm.hip, fused p^T q partials)
-//   alpha = rho / p^T q          (k_reduce_alpha)
-//   x += alpha p, r -= alpha q, u = D^-1 r, rho' = r^T u, ||r||^2
-//                                (k_update, D = z diag(B) - diag(A))
-//   beta = rho'/rho, convergence ||r|| <= tol ||b||   (k_reduce_beta)
-//   active-tile compaction       (k_compact)
-//   p = u + beta p               (k_direction)
-// Dot products: each lane owns one column, so a wave sums its rows in
-// registers, the 4 waves of a work-group combine in LDS, and per-tile
-// partials over row blocks are summed in a fixed order (deterministic).
+// Conjugate-orthogonal CG (bilinear form x^T y) is carried in "u-form": the
+// preconditioned residual u = D^-1 r is stored instead of r
+// (D = z diag(B) - diag(A)), so r^T u = sum D u^2 and ||r|| = ||D u|| need
+// no division.  One iteration is two streaming kernels:
+//
+//   A  p' = u + beta p (formed on the fly for every gathered neighbour),
+//      q = K p' (K = z B - A), store p', partials of p'^T q      [3 passes]
+//   B  recompute K p' (gather p'), x += alpha p', u -= alpha D^-1 K p',
+//      partials of D u^2 and |D u|^2                              [5 passes]
+//
+// plus three tiny kernels: alpha = rho / p'^T q; beta = rho'/rho with the
+// per-column convergence test ||r|| <= tol ||b||; active-tile compaction.
+// p is double-buffered because neighbours gather the old p while p' is
+// written.  Dot products: each lane owns one column, a wave sums its rows in
+// registers, the work-group's 4 waves combine in LDS, and per-tile partials
+// over row blocks are summed in a fixed order (deterministic).
+//
+// The kernels are templated on the storage type: double2 (FP64 path) or
+// float2 (mixed path, FP32 recurrence; FP64 scalars, dots and the residual
+// replacement of cocg32 kernels below).
 #include "internal.h"
 
 namespace gep {
 
+template <typename VT>
+struct Cx;
+template <>
+struct Cx<double2> {
+    using R = double;
+    using M = double2;
+};
+template <>
+struct Cx<float2> {
+    using R = float;
+    using M = float2;
+};
+
 __device__ inline double2 cdiv(double2 a, double2 b) {
     const double den = b.x * b.x + b.y * b.y;
     return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
-}
-__device__ inline double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
 struct BlockMap {
@@ -68,17 +87,28 @@ __device__ inline void block_partials(const BlockMap& m, int nrb, double2 c, dou
     }
 }
 
-// x = 0, r = b, p = u = D^-1 b; partials of rho = b^T u and ||b||^2.
+template <typename R>
+__device__ inline void cfma_acc(R va, R vb, R xr, R xi, R& ar, R& ai, R& br, R& bi) {
+    ar = fma(va, xr, ar);
+    ai = fma(va, xi, ai);
+    br = fma(vb, xr, br);
+    bi = fma(vb, xi, bi);
+}
+
+// x = 0, u = D^-1 b, p = 0 (with beta = 0 the first kernel A forms p' = u);
+// partials of rho = b^T u and ||b||^2.
+template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_init(int n, const double* __restrict__ dA,
                                                  const double* __restrict__ dB,
                                                  const double2* __restrict__ shifts,
                                                  const int32_t* __restrict__ bcol,
                                                  const double* __restrict__ BV, int64_t ldbv,
-                                                 double2* __restrict__ x, double2* __restrict__ r,
-                                                 double2* __restrict__ p,
+                                                 VT* __restrict__ x, VT* __restrict__ u,
+                                                 VT* __restrict__ p,
                                                  const int32_t* __restrict__ tiles,
                                                  const int32_t* __restrict__ n_active, int nrb,
                                                  int rpb, double2* part_c, double* part_r) {
+    using R = typename Cx<VT>::R;
     BlockMap m;
     if (!map_block(tiles, n_active, nrb, rpb, n, m)) return;
     const int col = m.tile * kTile + m.lane;
@@ -90,158 +120,309 @@ __global__ __launch_bounds__(kBlock) void k_init(int n, const double* __restrict
     for (int i = m.r0 + m.wave; i < m.r1; i += kWaves) {
         const double b = bc >= 0 ? BV[(size_t)i * ldbv + bc] : 0.0;
         const double2 D = make_double2(z.x * dB[i] - dA[i], z.y * dB[i]);
-        const double2 u = cdiv(make_double2(b, 0.0), D);
+        const double2 uv = cdiv(make_double2(b, 0.0), D);
         const size_t o = base + (size_t)i * kTile + m.lane;
-        x[o] = make_double2(0.0, 0.0);
-        r[o] = make_double2(b, 0.0);
-        p[o] = u;
-        rho.x += b * u.x;
-        rho.y += b * u.y;
+        VT zero;
+        zero.x = (R)0;
+        zero.y = (R)0;
+        VT us;
+        us.x = (R)uv.x;
+        us.y = (R)uv.y;
+        x[o] = zero;
+        u[o] = us;
+        p[o] = zero;
+        rho.x += b * uv.x;
+        rho.y += b * uv.y;
         bb += b * b;
     }
     block_partials(m, nrb, rho, bb, part_c, part_r);
 }
 
-// After k_init: rho, ||b||^2, activity per column and per tile.
-__global__ void k_reduce_init(int ntiles, int nrb, const double2* __restrict__ part_c,
-                              const double* __restrict__ part_r, double2* __restrict__ rho,
-                              double* __restrict__ bb, double* __restrict__ rr,
-                              int32_t* __restrict__ active, int32_t* __restrict__ iters,
-                              int32_t* __restrict__ tile_active) {
-    const int tile = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int col = tile * kTile + lane;
-    double2 sc = make_double2(0.0, 0.0);
-    double sr = 0.0;
-    for (int rb = 0; rb < nrb; ++rb) {
-        const size_t o = ((size_t)tile * nrb + rb) * kTile + lane;
-        sc.x += part_c[o].x;
-        sc.y += part_c[o].y;
-        sr += part_r[o];
+// Kernel A: p' = u + beta p, q = K p', store p', partials of p'^T q.
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_spmm_dir(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+    const typename Cx<VT>::M* __restrict__ ab, int n, const double2* __restrict__ shifts,
+    const double2* __restrict__ beta, const VT* __restrict__ U, const VT* __restrict__ P,
+    VT* __restrict__ Pn, const int32_t* __restrict__ tiles, const int32_t* __restrict__ n_active,
+    int nrb, int rpb, double2* __restrict__ part_c) {
+    using R = typename Cx<VT>::R;
+    using M = typename Cx<VT>::M;
+    BlockMap m;
+    if (!map_block(tiles, n_active, nrb, rpb, n, m)) return;
+    const int col = m.tile * kTile + m.lane;
+    const size_t base = (size_t)m.tile * (size_t)n * kTile;
+    const VT* __restrict__ Ut = U + base;
+    const VT* __restrict__ Pt = P + base;
+    VT* __restrict__ Pnt = Pn + base;
+    const double2 zd = shifts[col];
+    const double2 bd = beta[col];
+    const R zr = (R)zd.x, zi = (R)zd.y, br_ = (R)bd.x, bi_ = (R)bd.y;
+    double dr = 0.0, di = 0.0;
+    for (int i = m.r0 + m.wave; i < m.r1; i += kWaves) {
+        const int k0 = rowptr[i];
+        const int k1 = rowptr[i + 1];
+        R ar = 0, ai = 0, sbr = 0, sbi = 0;
+        int k = k0;
+        for (; k + 3 <= k1; k += 3) {
+            const int j0 = colind[k], j1 = colind[k + 1], j2 = colind[k + 2];
+            const M v0 = ab[k], v1 = ab[k + 1], v2 = ab[k + 2];
+            const VT u0 = Ut[(size_t)j0 * kTile + m.lane], p0 = Pt[(size_t)j0 * kTile + m.lane];
+            const VT u1 = Ut[(size_t)j1 * kTile + m.lane], p1 = Pt[(size_t)j1 * kTile + m.lane];
+            const VT u2 = Ut[(size_t)j2 * kTile + m.lane], p2 = Pt[(size_t)j2 * kTile + m.lane];
+            R xr = u0.x + br_ * p0.x - bi_ * p0.y, xi = u0.y + br_ * p0.y + bi_ * p0.x;
+            cfma_acc(v0.x, v0.y, xr, xi, ar, ai, sbr, sbi);
+            xr = u1.x + br_ * p1.x - bi_ * p1.y;
+            xi = u1.y + br_ * p1.y + bi_ * p1.x;
+            cfma_acc(v1.x, v1.y, xr, xi, ar, ai, sbr, sbi);
+            xr = u2.x + br_ * p2.x - bi_ * p2.y;
+            xi = u2.y + br_ * p2.y + bi_ * p2.x;
+            cfma_acc(v2.x, v2.y, xr, xi, ar, ai, sbr, sbi);
+        }
+        for (; k < k1; ++k) {
+            const int j = colind[k];
+            const M v = ab[k];
+            const VT uj = Ut[(size_t)j * kTile + m.lane], pj = Pt[(size_t)j * kTile + m.lane];
+            const R xr = uj.x + br_ * pj.x - bi_ * pj.y, xi = uj.y + br_ * pj.y + bi_ * pj.x;
+            cfma_acc(v.x, v.y, xr, xi, ar, ai, sbr, sbi);
+        }
+        const size_t o = (size_t)i * kTile + m.lane;
+        const VT ui = Ut[o], pi = Pt[o];
+        VT pn;
+        pn.x = ui.x + br_ * pi.x - bi_ * pi.y;
+        pn.y = ui.y + br_ * pi.y + bi_ * pi.x;
+        Pnt[o] = pn;
+        const R qr = fma(zr, sbr, fma(-zi, sbi, -ar));
+        const R qi = fma(zr, sbi, fma(zi, sbr, -ai));
+        dr += (double)pn.x * (double)qr - (double)pn.y * (double)qi;
+        di += (double)pn.x * (double)qi + (double)pn.y * (double)qr;
     }
-    rho[col] = sc;
-    bb[col] = sr;
-    rr[col] = sr;
-    iters[col] = 0;
-    const int a = sr > 0.0 ? 1 : 0;
-    active[col] = a;
-    __shared__ int cnt;
-    if (lane == 0) cnt = 0;
-    __syncthreads();
-    if (a) atomicAdd(&cnt, 1);
-    __syncthreads();
-    if (lane == 0) tile_active[tile] = cnt;
+    block_partials(m, nrb, make_double2(dr, di), 0.0, part_c, nullptr);
 }
 
-__global__ void k_reduce_alpha(int nrb, const int32_t* __restrict__ tiles,
-                               const int32_t* __restrict__ n_active,
-                               const double2* __restrict__ part_c, const double2* __restrict__ rho,
-                               double2* __restrict__ alpha, int32_t* __restrict__ active) {
+// Kernel B: q = K p (recomputed), x += alpha p, u -= alpha D^-1 q,
+// partials of rho' = sum D u^2 and ||D u||^2.
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_update(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+    const typename Cx<VT>::M* __restrict__ ab, int n, const double* __restrict__ dA,
+    const double* __restrict__ dB, const double2* __restrict__ shifts,
+    const double2* __restrict__ alpha, VT* __restrict__ X, VT* __restrict__ U,
+    const VT* __restrict__ P, const int32_t* __restrict__ tiles,
+    const int32_t* __restrict__ n_active, int nrb, int rpb, double2* __restrict__ part_c,
+    double* __restrict__ part_r) {
+    using R = typename Cx<VT>::R;
+    using M = typename Cx<VT>::M;
+    BlockMap m;
+    if (!map_block(tiles, n_active, nrb, rpb, n, m)) return;
+    const int col = m.tile * kTile + m.lane;
+    const size_t base = (size_t)m.tile * (size_t)n * kTile;
+    VT* __restrict__ Xt = X + base;
+    VT* __restrict__ Ut = U + base;
+    const VT* __restrict__ Pt = P + base;
+    const double2 zd = shifts[col];
+    const double2 ad = alpha[col];
+    const R zr = (R)zd.x, zi = (R)zd.y, alr = (R)ad.x, ali = (R)ad.y;
+    double2 rho = make_double2(0.0, 0.0);
+    double rr = 0.0;
+    for (int i = m.r0 + m.wave; i < m.r1; i += kWaves) {
+        const int k0 = rowptr[i];
+        const int k1 = rowptr[i + 1];
+        R ar = 0, ai = 0, sbr = 0, sbi = 0;
+        int k = k0;
+        for (; k + 4 <= k1; k += 4) {
+            const int j0 = colind[k], j1 = colind[k + 1], j2 = colind[k + 2], j3 = colind[k + 3];
+            const M v0 = ab[k], v1 = ab[k + 1], v2 = ab[k + 2], v3 = ab[k + 3];
+            const VT p0 = Pt[(size_t)j0 * kTile + m.lane];
+            const VT p1 = Pt[(size_t)j1 * kTile + m.lane];
+            const VT p2 = Pt[(size_t)j2 * kTile + m.lane];
+            const VT p3 = Pt[(size_t)j3 * kTile + m.lane];
+            cfma_acc(v0.x, v0.y, p0.x, p0.y, ar, ai, sbr, sbi);
+            cfma_acc(v1.x, v1.y, p1.x, p1.y, ar, ai, sbr, sbi);
+            cfma_acc(v2.x, v2.y, p2.x, p2.y, ar, ai, sbr, sbi);
+            cfma_acc(v3.x, v3.y, p3.x, p3.y, ar, ai, sbr, sbi);
+        }
+        for (; k < k1; ++k) {
+            const int j = colind[k];
+            const M v = ab[k];
+            const VT pj = Pt[(size_t)j * kTile + m.lane];
+            cfma_acc(v.x, v.y, pj.x, pj.y, ar, ai, sbr, sbi);
+        }
+        const R qr = fma(zr, sbr, fma(-zi, sbi, -ar));
+        const R qi = fma(zr, sbi, fma(zi, sbr, -ai));
+        const size_t o = (size_t)i * kTile + m.lane;
+        const VT pi = Pt[o];
+        VT xv = Xt[o], uv = Ut[o];
+        xv.x = fma(alr, pi.x, fma(-ali, pi.y, xv.x));
+        xv.y = fma(alr, pi.y, fma(ali, pi.x, xv.y));
+        // s = alpha q / D
+        const double2 D = make_double2(zd.x * dB[i] - dA[i], zd.y * dB[i]);
+        const R aqr = alr * qr - ali * qi, aqi = alr * qi + ali * qr;
+        const double2 s = cdiv(make_double2((double)aqr, (double)aqi), D);
+        uv.x = uv.x - (R)s.x;
+        uv.y = uv.y - (R)s.y;
+        Xt[o] = xv;
+        Ut[o] = uv;
+        // r = D u
+        const double ux = (double)uv.x, uy = (double)uv.y;
+        const double rx = D.x * ux - D.y * uy, ry = D.x * uy + D.y * ux;
+        rho.x += rx * ux - ry * uy;
+        rho.y += rx * uy + ry * ux;
+        rr += rx * rx + ry * ry;
+    }
+    block_partials(m, nrb, rho, rr, part_c, part_r);
+}
+
+// After k_init: rho, ||b||^2, activity per column and per tile.
+__global__ __launch_bounds__(kBlock) void k_reduce_init(int nrb, const double2* __restrict__ part_c,
+                                                        const double* __restrict__ part_r,
+                                                        double2* __restrict__ rho,
+                                                        double* __restrict__ bb,
+                                                        double* __restrict__ rr,
+                                                        double* __restrict__ rmax,
+                                                        int32_t* __restrict__ flag,
+                                                        double2* __restrict__ beta,
+                                                        int32_t* __restrict__ active,
+                                                        int32_t* __restrict__ iters,
+                                                        int32_t* __restrict__ tile_active) {
+    __shared__ double2 sc[kWaves][kTile];
+    __shared__ double sr[kWaves][kTile];
+    __shared__ int cnt;
+    const int tile = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double2 a = make_double2(0.0, 0.0);
+    double d = 0.0;
+    for (int rb = wave; rb < nrb; rb += kWaves) {
+        const size_t o = ((size_t)tile * nrb + rb) * kTile + lane;
+        a.x += part_c[o].x;
+        a.y += part_c[o].y;
+        d += part_r[o];
+    }
+    sc[wave][lane] = a;
+    sr[wave][lane] = d;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    if (wave == 0) {
+        for (int w = 1; w < kWaves; ++w) {
+            a.x += sc[w][lane].x;
+            a.y += sc[w][lane].y;
+            d += sr[w][lane];
+        }
+        const int col = tile * kTile + lane;
+        rho[col] = a;
+        bb[col] = d;
+        rr[col] = d;
+        rmax[col] = d;
+        flag[col] = 0;
+        beta[col] = make_double2(0.0, 0.0);
+        iters[col] = 0;
+        const int act = d > 0.0 ? 1 : 0;
+        active[col] = act;
+        if (act) atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) tile_active[tile] = cnt;
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_alpha(int nrb, const int32_t* __restrict__ tiles,
+                                                         const int32_t* __restrict__ n_active,
+                                                         const double2* __restrict__ part_c,
+                                                         const double2* __restrict__ rho,
+                                                         double2* __restrict__ alpha,
+                                                         int32_t* __restrict__ active) {
+    __shared__ double2 sc[kWaves][kTile];
     const int slot = blockIdx.x;
     if (slot >= n_active[0]) return;
     const int tile = tiles[slot];
-    const int lane = threadIdx.x;
-    const int col = tile * kTile + lane;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double2 pq = make_double2(0.0, 0.0);
-    for (int rb = 0; rb < nrb; ++rb) {
+    for (int rb = wave; rb < nrb; rb += kWaves) {
         const double2 v = part_c[((size_t)tile * nrb + rb) * kTile + lane];
         pq.x += v.x;
         pq.y += v.y;
     }
+    sc[wave][lane] = pq;
+    __syncthreads();
+    if (wave) return;
+    for (int w = 1; w < kWaves; ++w) {
+        pq.x += sc[w][lane].x;
+        pq.y += sc[w][lane].y;
+    }
+    const int col = tile * kTile + lane;
     double2 a = make_double2(0.0, 0.0);
     if (active[col]) {
         const double m2 = pq.x * pq.x + pq.y * pq.y;
         if (m2 > 0.0 && isfinite(m2)) {
             a = cdiv(rho[col], pq);
         } else {
-            active[col] = 0;   // breakdown: p^T q = 0
+            active[col] = 0;   // breakdown: p^T K p = 0
         }
     }
     alpha[col] = a;
 }
 
-// x += alpha p, r -= alpha q, u = D^-1 r; partials rho' = r^T u, ||r||^2.
-__global__ __launch_bounds__(kBlock) void k_update(int n, const double* __restrict__ dA,
-                                                   const double* __restrict__ dB,
-                                                   const double2* __restrict__ shifts,
-                                                   const double2* __restrict__ alpha,
-                                                   double2* __restrict__ x,
-                                                   double2* __restrict__ r,
-                                                   const double2* __restrict__ p,
-                                                   const double2* __restrict__ q,
-                                                   const int32_t* __restrict__ tiles,
-                                                   const int32_t* __restrict__ n_active, int nrb,
-                                                   int rpb, double2* part_c, double* part_r) {
-    BlockMap m;
-    if (!map_block(tiles, n_active, nrb, rpb, n, m)) return;
-    const int col = m.tile * kTile + m.lane;
-    const double2 a = alpha[col];
-    const double2 z = shifts[col];
-    const size_t base = (size_t)m.tile * (size_t)n * kTile;
-    double2 rho = make_double2(0.0, 0.0);
-    double rr = 0.0;
-    for (int i = m.r0 + m.wave; i < m.r1; i += kWaves) {
-        const size_t o = base + (size_t)i * kTile + m.lane;
-        const double2 pv = p[o], qv = q[o];
-        double2 xv = x[o], rv = r[o];
-        xv.x = fma(a.x, pv.x, fma(-a.y, pv.y, xv.x));
-        xv.y = fma(a.x, pv.y, fma(a.y, pv.x, xv.y));
-        rv.x = fma(-a.x, qv.x, fma(a.y, qv.y, rv.x));
-        rv.y = fma(-a.x, qv.y, fma(-a.y, qv.x, rv.y));
-        x[o] = xv;
-        r[o] = rv;
-        const double2 D = make_double2(z.x * dB[i] - dA[i], z.y * dB[i]);
-        const double2 u = cdiv(rv, D);
-        rho.x += rv.x * u.x - rv.y * u.y;
-        rho.y += rv.x * u.y + rv.y * u.x;
-        rr += rv.x * rv.x + rv.y * rv.y;
-    }
-    block_partials(m, nrb, rho, rr, part_c, part_r);
-}
-
-__global__ void k_reduce_beta(int nrb, const int32_t* __restrict__ tiles,
-                              const int32_t* __restrict__ n_active,
-                              const double2* __restrict__ part_c, const double* __restrict__ part_r,
-                              double2* __restrict__ rho, double2* __restrict__ beta,
-                              const double* __restrict__ bb, double* __restrict__ rr,
-                              int32_t* __restrict__ active, int32_t* __restrict__ iters,
-                              int32_t* __restrict__ tile_active, double tol2, int max_iter) {
+__global__ __launch_bounds__(kBlock) void k_reduce_beta(
+    int nrb, const int32_t* __restrict__ tiles, const int32_t* __restrict__ n_active,
+    const double2* __restrict__ part_c, const double* __restrict__ part_r,
+    double2* __restrict__ rho, double2* __restrict__ beta, const double* __restrict__ bb,
+    double* __restrict__ rr, double* __restrict__ rmax, int32_t* __restrict__ flag,
+    int32_t* __restrict__ active, int32_t* __restrict__ iters, int32_t* __restrict__ tile_active,
+    double tol2, int max_iter, int hold) {
+    __shared__ double2 sc[kWaves][kTile];
+    __shared__ double sr[kWaves][kTile];
+    __shared__ int cnt;
     const int slot = blockIdx.x;
     if (slot >= n_active[0]) return;
     const int tile = tiles[slot];
-    const int lane = threadIdx.x;
-    const int col = tile * kTile + lane;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double2 rn = make_double2(0.0, 0.0);
     double s = 0.0;
-    for (int rb = 0; rb < nrb; ++rb) {
+    for (int rb = wave; rb < nrb; rb += kWaves) {
         const size_t o = ((size_t)tile * nrb + rb) * kTile + lane;
         rn.x += part_c[o].x;
         rn.y += part_c[o].y;
         s += part_r[o];
     }
-    int a = active[col];
-    double2 b = make_double2(0.0, 0.0);
-    if (a) {
-        const int it = iters[col] + 1;
-        iters[col] = it;
-        rr[col] = s;
-        const double2 ro = rho[col];
-        const double m2 = ro.x * ro.x + ro.y * ro.y;
-        if (s <= tol2 * bb[col] || it >= max_iter || !(m2 > 0.0) || !isfinite(s)) {
-            a = 0;
-            active[col] = 0;
-        } else {
-            b = cdiv(rn, ro);
-            rho[col] = rn;
+    sc[wave][lane] = rn;
+    sr[wave][lane] = s;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    if (wave == 0) {
+        for (int w = 1; w < kWaves; ++w) {
+            rn.x += sc[w][lane].x;
+            rn.y += sc[w][lane].y;
+            s += sr[w][lane];
         }
+        const int col = tile * kTile + lane;
+        int a = active[col];
+        double2 b = make_double2(0.0, 0.0);
+        if (a) {
+            const int it = iters[col] + 1;
+            iters[col] = it;
+            rr[col] = s;
+            const double2 ro = rho[col];
+            const double m2 = ro.x * ro.x + ro.y * ro.y;
+            const bool conv = s <= tol2 * bb[col];
+            if (hold) {
+                // mixed path: ask for a residual replacement once the recursive
+                // residual fell by 10x since the last one, or reached tol
+                const double mx = fmax(rmax[col], s);
+                rmax[col] = mx;
+                if (conv || s <= 1e-2 * mx) flag[col] = 1;
+            }
+            if ((conv && !hold) || it >= max_iter || !(m2 > 0.0) || !isfinite(s)) {
+                a = 0;
+                active[col] = 0;
+            } else {
+                b = cdiv(rn, ro);
+                rho[col] = rn;
+            }
+        }
+        beta[col] = b;
+        if (a) atomicAdd(&cnt, 1);
     }
-    beta[col] = b;
-    __shared__ int cnt;
-    if (lane == 0) cnt = 0;
     __syncthreads();
-    if (a) atomicAdd(&cnt, 1);
-    __syncthreads();
-    if (lane == 0) tile_active[tile] = cnt;
+    if (threadIdx.x == 0) tile_active[tile] = cnt;
 }
 
 // Compacts the list of tiles that still have an active column; counts[0] =
@@ -281,46 +462,236 @@ __global__ __launch_bounds__(1024) void k_compact(int ntiles, const int32_t* __r
     }
 }
 
-// p = D^-1 r + beta p
-__global__ __launch_bounds__(kBlock) void k_direction(int n, const double* __restrict__ dA,
-                                                      const double* __restrict__ dB,
-                                                      const double2* __restrict__ shifts,
-                                                      const double2* __restrict__ beta,
-                                                      const double2* __restrict__ r,
-                                                      double2* __restrict__ p,
-                                                      const int32_t* __restrict__ tiles,
-                                                      const int32_t* __restrict__ n_active,
-                                                      int nrb, int rpb) {
+// ---- mixed precision: FP64 residual replacement ----------------------------
+// (reliable updates: the FP32 recurrence keeps its search direction; every
+// few iterations the FP32 correction is folded into the FP64 solution and
+// the residual is recomputed in FP64 with the FP64 pencil.)
+
+// x64 += x32, x32 = 0 on the active tiles.
+__global__ __launch_bounds__(kBlock) void k_fold(int n, double2* __restrict__ X64,
+                                                 float2* __restrict__ X32,
+                                                 const int32_t* __restrict__ tiles,
+                                                 const int32_t* __restrict__ n_active, int nrb,
+                                                 int rpb) {
     BlockMap m;
     if (!map_block(tiles, n_active, nrb, rpb, n, m)) return;
-    const int col = m.tile * kTile + m.lane;
-    const double2 b = beta[col];
-    const double2 z = shifts[col];
     const size_t base = (size_t)m.tile * (size_t)n * kTile;
     for (int i = m.r0 + m.wave; i < m.r1; i += kWaves) {
         const size_t o = base + (size_t)i * kTile + m.lane;
-        const double2 D = make_double2(z.x * dB[i] - dA[i], z.y * dB[i]);
-        const double2 u = cdiv(r[o], D);
-        const double2 pv = p[o];
-        p[o] = make_double2(u.x + b.x * pv.x - b.y * pv.y, u.y + b.x * pv.y + b.y * pv.x);
+        const float2 c = X32[o];
+        double2 xv = X64[o];
+        xv.x += (double)c.x;
+        xv.y += (double)c.y;
+        X64[o] = xv;
+        X32[o] = make_float2(0.f, 0.f);
     }
 }
 
-static inline int rows_per_block(int64_t n, int nrb) { return (int)((n + nrb - 1) / nrb); }
+// r = b - K x64 in FP64, u32 = D^-1 r; partials of r^T u and ||r||^2.
+__global__ __launch_bounds__(kBlock) void k_true_residual(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+    const double2* __restrict__ ab, int n, const double* __restrict__ dA,
+    const double* __restrict__ dB, const double2* __restrict__ shifts,
+    const int32_t* __restrict__ bcol, const double* __restrict__ BV, int64_t ldbv,
+    const double2* __restrict__ X64, float2* __restrict__ U32, const int32_t* __restrict__ flag,
+    const int32_t* __restrict__ tiles, const int32_t* __restrict__ n_active, int nrb, int rpb,
+    double2* part_c, double* part_r) {
+    BlockMap m;
+    if (!map_block(tiles, n_active, nrb, rpb, n, m)) return;
+    const int col = m.tile * kTile + m.lane;
+    const bool fl = flag[col] != 0;
+    // the decision is uniform over the work-group (all waves see the same 64 columns)
+    if (!__any(fl)) {
+        block_partials(m, nrb, make_double2(0.0, 0.0), 0.0, part_c, part_r);
+        return;
+    }
+    const size_t base = (size_t)m.tile * (size_t)n * kTile;
+    const double2* __restrict__ Xt = X64 + base;
+    const double2 z = shifts[col];
+    const int bc = bcol[col];
+    double2 rho = make_double2(0.0, 0.0);
+    double rr = 0.0;
+    for (int i = m.r0 + m.wave; i < m.r1; i += kWaves) {
+        const int k0 = rowptr[i];
+        const int k1 = rowptr[i + 1];
+        double ar = 0, ai = 0, sbr = 0, sbi = 0;
+        for (int k = k0; k < k1; ++k) {
+            const int j = colind[k];
+            const double2 v = ab[k];
+            const double2 xj = Xt[(size_t)j * kTile + m.lane];
+            cfma_acc(v.x, v.y, xj.x, xj.y, ar, ai, sbr, sbi);
+        }
+        const double b = bc >= 0 ? BV[(size_t)i * ldbv + bc] : 0.0;
+        const double rx = b - (z.x * sbr - z.y * sbi - ar);
+        const double ry = -(z.x * sbi + z.y * sbr - ai);
+        const double2 D = make_double2(z.x * dB[i] - dA[i], z.y * dB[i]);
+        const double2 uv = cdiv(make_double2(rx, ry), D);
+        if (fl) {
+            const float2 us = make_float2((float)uv.x, (float)uv.y);
+            U32[base + (size_t)i * kTile + m.lane] = us;
+            const double ux = (double)us.x, uy = (double)us.y;
+            rho.x += rx * ux - ry * uy;
+            rho.y += rx * uy + ry * ux;
+            rr += rx * rx + ry * ry;
+        }
+    }
+    block_partials(m, nrb, rho, rr, part_c, part_r);
+}
 
-// k_init runs over all tiles: the caller fills `tiles` with 0..ntiles-1 and
-// counts[0] = ntiles first.
-hipError_t cocg_init(const DevPencil& P, CocgState& S, const double* BV, int64_t ldbv, int nrb,
-                     hipStream_t s) {
-    const int rpb = rows_per_block(P.n, nrb);
+// rho <- true r^T u, beta rescaled to rho_true / rho_old, convergence on the
+// true residual.
+__global__ __launch_bounds__(kBlock) void k_reduce_replace(
+    int nrb, const int32_t* __restrict__ tiles, const int32_t* __restrict__ n_active,
+    const double2* __restrict__ part_c, const double* __restrict__ part_r,
+    double2* __restrict__ rho, double2* __restrict__ beta, const double* __restrict__ bb,
+    double* __restrict__ rr, double* __restrict__ rmax, int32_t* __restrict__ flag,
+    int32_t* __restrict__ active, int32_t* __restrict__ tile_active, double tol2) {
+    __shared__ double2 sc[kWaves][kTile];
+    __shared__ double sr[kWaves][kTile];
+    __shared__ int cnt;
+    const int slot = blockIdx.x;
+    if (slot >= n_active[0]) return;
+    const int tile = tiles[slot];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double2 rn = make_double2(0.0, 0.0);
+    double s = 0.0;
+    for (int rb = wave; rb < nrb; rb += kWaves) {
+        const size_t o = ((size_t)tile * nrb + rb) * kTile + lane;
+        rn.x += part_c[o].x;
+        rn.y += part_c[o].y;
+        s += part_r[o];
+    }
+    sc[wave][lane] = rn;
+    sr[wave][lane] = s;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    if (wave == 0) {
+        for (int w = 1; w < kWaves; ++w) {
+            rn.x += sc[w][lane].x;
+            rn.y += sc[w][lane].y;
+            s += sr[w][lane];
+        }
+        const int col = tile * kTile + lane;
+        int a = active[col];
+        if (a && flag[col]) {
+            flag[col] = 0;
+            rr[col] = s;
+            rmax[col] = s;
+            const double2 rec = rho[col];
+            const double m2 = rec.x * rec.x + rec.y * rec.y;
+            if (s <= tol2 * bb[col] || !isfinite(s) || !(m2 > 0.0)) {
+                a = 0;
+                active[col] = 0;
+                beta[col] = make_double2(0.0, 0.0);
+            } else {
+                // beta = rho_rec / rho_old was set by k_reduce_beta; rescale
+                const double2 f = cdiv(rn, rec);
+                const double2 b = beta[col];
+                beta[col] = make_double2(b.x * f.x - b.y * f.y, b.x * f.y + b.y * f.x);
+                rho[col] = rn;
+            }
+        }
+        if (a) atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) tile_active[tile] = cnt;
+}
+
+template <typename VT>
+hipError_t launch_init_t(const DevPencil& P, CocgState& S, VT* x, VT* u, VT* p, const double* BV,
+                         int64_t ldbv, int nrb, hipStream_t s) {
+    const int rpb = (int)((P.n + nrb - 1) / nrb);
     const int grid = pad8(S.ntiles * nrb);
-    hipLaunchKernelGGL(k_init, dim3(grid), dim3(kBlock), 0, s, (int)P.n, P.dA, P.dB, S.shifts,
-                       S.bcol, BV, ldbv, S.x, S.r, S.p, S.tiles, S.counts, nrb, rpb, S.part_c,
-                       S.part_r);
+    hipLaunchKernelGGL((k_init<VT>), dim3(grid), dim3(kBlock), 0, s, (int)P.n, P.dA, P.dB, S.shifts,
+                       S.bcol, BV, ldbv, x, u, p, S.tiles, S.counts, nrb, rpb, S.part_c, S.part_r);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_init, dim3(S.ntiles), dim3(kTile), 0, s, S.ntiles, nrb, S.part_c,
-                       S.part_r, S.rho, S.bb, S.rr, S.active, S.iters, S.tile_active);
+    hipLaunchKernelGGL(k_reduce_init, dim3(S.ntiles), dim3(kBlock), 0, s, nrb, S.part_c, S.part_r,
+                       S.rho, S.bb, S.rr, S.rmax, S.flag, S.beta, S.active, S.iters, S.tile_active);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return cocg_compact(S, s);
+}
+
+hipError_t cocg_init(const DevPencil& P, CocgState& S, const double* BV, int64_t ldbv, int nrb,
+                     hipStream_t s) {
+    return launch_init_t<double2>(P, S, S.x, S.u, S.p, BV, ldbv, nrb, s);
+}
+
+template <typename VT>
+hipError_t launch_spmm_dir_t(const DevPencil& P, const void* ab, CocgState& S, const VT* u,
+                             const VT* p, VT* pn, int n_active_host, int nrb, hipStream_t s) {
+    if (n_active_host <= 0) return hipSuccess;
+    const int rpb = (int)((P.n + nrb - 1) / nrb);
+    const int grid = pad8(n_active_host * nrb);
+    hipLaunchKernelGGL((k_spmm_dir<VT>), dim3(grid), dim3(kBlock), 0, s, P.rowptr, P.colind,
+                       (const typename Cx<VT>::M*)ab, (int)P.n, S.shifts, S.beta, u, p, pn,
+                       S.tiles, S.counts, nrb, rpb, S.part_c);
+    return hipGetLastError();
+}
+
+template <typename VT>
+hipError_t launch_update_t(const DevPencil& P, const void* ab, CocgState& S, VT* x, VT* u,
+                           const VT* p, int n_active_host, int nrb, hipStream_t s) {
+    if (n_active_host <= 0) return hipSuccess;
+    const int rpb = (int)((P.n + nrb - 1) / nrb);
+    const int grid = pad8(n_active_host * nrb);
+    hipLaunchKernelGGL((k_update<VT>), dim3(grid), dim3(kBlock), 0, s, P.rowptr, P.colind,
+                       (const typename Cx<VT>::M*)ab, (int)P.n, P.dA, P.dB, S.shifts, S.alpha, x,
+                       u, p, S.tiles, S.counts, nrb, rpb, S.part_c, S.part_r);
+    return hipGetLastError();
+}
+
+hipError_t cocg_spmm_dir(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
+                         hipStream_t s) {
+    return launch_spmm_dir_t<double2>(P, P.ab, S, S.u, S.p, S.pn, n_active_host, nrb, s);
+}
+
+hipError_t cocg_update(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
+                       hipStream_t s) {
+    return launch_update_t<double2>(P, P.ab, S, S.x, S.u, S.pn, n_active_host, nrb, s);
+}
+
+hipError_t cocg32_init(const DevPencil& P, CocgState& S, const double* BV, int64_t ldbv, int nrb,
+                       hipStream_t s) {
+    return launch_init_t<float2>(P, S, S.x32, S.u32, S.p32, BV, ldbv, nrb, s);
+}
+
+hipError_t cocg32_spmm_dir(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
+                           hipStream_t s) {
+    return launch_spmm_dir_t<float2>(P, P.ab32, S, S.u32, S.p32, S.pn32, n_active_host, nrb, s);
+}
+
+hipError_t cocg32_update(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
+                         hipStream_t s) {
+    return launch_update_t<float2>(P, P.ab32, S, S.x32, S.u32, S.pn32, n_active_host, nrb, s);
+}
+
+hipError_t cocg32_fold(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
+                       hipStream_t s) {
+    if (n_active_host <= 0) return hipSuccess;
+    const int rpb = (int)((P.n + nrb - 1) / nrb);
+    const int grid = pad8(n_active_host * nrb);
+    hipLaunchKernelGGL(k_fold, dim3(grid), dim3(kBlock), 0, s, (int)P.n, S.x, S.x32, S.tiles,
+                       S.counts, nrb, rpb);
+    return hipGetLastError();
+}
+
+hipError_t cocg32_replace(const DevPencil& P, CocgState& S, const double* BV, int64_t ldbv,
+                          int n_active_host, int nrb, double tol2, hipStream_t s) {
+    if (n_active_host <= 0) return hipSuccess;
+    hipError_t e = cocg32_fold(P, S, n_active_host, nrb, s);
+    if (e != hipSuccess) return e;
+    const int rpb = (int)((P.n + nrb - 1) / nrb);
+    const int grid = pad8(n_active_host * nrb);
+    hipLaunchKernelGGL(k_true_residual, dim3(grid), dim3(kBlock), 0, s, P.rowptr, P.colind, P.ab,
+                       (int)P.n, P.dA, P.dB, S.shifts, S.bcol, BV, ldbv, S.x, S.u32, S.flag,
+                       S.tiles, S.counts, nrb, rpb, S.part_c, S.part_r);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_replace, dim3(n_active_host), dim3(kBlock), 0, s, nrb, S.tiles,
+                       S.counts, S.part_c, S.part_r, S.rho, S.beta, S.bb, S.rr, S.rmax, S.flag,
+                       S.active, S.tile_active, tol2);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return cocg_compact(S, s);
@@ -328,44 +699,23 @@ hipError_t cocg_init(const DevPencil& P, CocgState& S, const double* BV, int64_t
 
 hipError_t cocg_reduce_alpha(CocgState& S, int n_active_host, int nrb, hipStream_t s) {
     if (n_active_host <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_alpha, dim3(n_active_host), dim3(kTile), 0, s, nrb, S.tiles,
+    hipLaunchKernelGGL(k_reduce_alpha, dim3(n_active_host), dim3(kBlock), 0, s, nrb, S.tiles,
                        S.counts, S.part_c, S.rho, S.alpha, S.active);
     return hipGetLastError();
 }
 
-hipError_t cocg_update(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
-                       hipStream_t s) {
-    if (n_active_host <= 0) return hipSuccess;
-    const int rpb = rows_per_block(P.n, nrb);
-    const int grid = pad8(n_active_host * nrb);
-    hipLaunchKernelGGL(k_update, dim3(grid), dim3(kBlock), 0, s, (int)P.n, P.dA, P.dB, S.shifts,
-                       S.alpha, S.x, S.r, S.p, S.q, S.tiles, S.counts, nrb, rpb, S.part_c,
-                       S.part_r);
-    return hipGetLastError();
-}
-
 hipError_t cocg_reduce_beta(CocgState& S, int n_active_host, int nrb, double tol2, int max_iter,
-                            hipStream_t s) {
+                            int hold, hipStream_t s) {
     if (n_active_host <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_beta, dim3(n_active_host), dim3(kTile), 0, s, nrb, S.tiles,
-                       S.counts, S.part_c, S.part_r, S.rho, S.beta, S.bb, S.rr, S.active, S.iters,
-                       S.tile_active, tol2, max_iter);
+    hipLaunchKernelGGL(k_reduce_beta, dim3(n_active_host), dim3(kBlock), 0, s, nrb, S.tiles,
+                       S.counts, S.part_c, S.part_r, S.rho, S.beta, S.bb, S.rr, S.rmax, S.flag,
+                       S.active, S.iters, S.tile_active, tol2, max_iter, hold);
     return hipGetLastError();
 }
 
 hipError_t cocg_compact(CocgState& S, hipStream_t s) {
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, S.ntiles, S.tile_active, S.tiles,
                        S.counts);
-    return hipGetLastError();
-}
-
-hipError_t cocg_direction(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
-                          hipStream_t s) {
-    if (n_active_host <= 0) return hipSuccess;
-    const int rpb = rows_per_block(P.n, nrb);
-    const int grid = pad8(n_active_host * nrb);
-    hipLaunchKernelGGL(k_direction, dim3(grid), dim3(kBlock), 0, s, (int)P.n, P.dA, P.dB,
-                       S.shifts, S.beta, S.r, S.p, S.tiles, S.counts, nrb, rpb);
     return hipGetLastError();
 }
 

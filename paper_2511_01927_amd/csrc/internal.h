@@ -51,14 +51,19 @@ hipError_t launch_spmm_c32(const DevPencil& P, const double2* shifts, const floa
 hipError_t launch_spmm_real(const DevPencil& P, const double* X, int64_t k, int64_t ld,
                             double* YA, double* YB, hipStream_t s);
 
-// COCG pieces, FP64 (cocg.hip)
+// COCG state (cocg.hip).  FP64 path: x, u, p, pn.  Mixed path: x (FP64
+// solution), x32, u32, p32, pn32 (FP32 recurrence).
 struct CocgState {
     int64_t n = 0;
-    int ntiles = 0;          // W / 64
-    double2* x = nullptr;    // tiled n x W
-    double2* r = nullptr;
-    double2* p = nullptr;
-    double2* q = nullptr;
+    int ntiles = 0;              // W / 64
+    double2* x = nullptr;        // tiled n x W
+    double2* u = nullptr;        // preconditioned residual D^-1 r
+    double2* p = nullptr;        // search direction (read)
+    double2* pn = nullptr;       // search direction (written)
+    float2* x32 = nullptr;
+    float2* u32 = nullptr;
+    float2* p32 = nullptr;
+    float2* pn32 = nullptr;
     double2* shifts = nullptr;   // [W]
     int32_t* bcol = nullptr;     // [W] column of the B V block feeding column c (-1: none)
     double2* rho = nullptr;      // [W]
@@ -66,46 +71,42 @@ struct CocgState {
     double2* beta = nullptr;     // [W]
     double* bb = nullptr;        // [W] ||b||^2
     double* rr = nullptr;        // [W] ||r||^2
+    double* rmax = nullptr;      // [W] mixed: max recursive ||r||^2 since the last replacement
+    int32_t* flag = nullptr;     // [W] mixed: replace this column's residual at the next check
     int32_t* active = nullptr;   // [W]
     int32_t* iters = nullptr;    // [W]
-    int32_t* tile_active = nullptr;  // [ntiles]
+    int32_t* tile_active = nullptr;  // [ntiles] active columns per tile
     int32_t* tiles = nullptr;        // [ntiles] compacted active list
     int32_t* counts = nullptr;       // [2]: active tiles, active columns
-    double2* part_c = nullptr;       // [ntiles][nrb_max][64]
-    double* part_r = nullptr;        // [ntiles][nrb_max][64]
-    int nrb_max = 0;
-    // mixed precision (FP32 recurrence, FP64 true residual / solution)
-    float2* x32 = nullptr;
-    float2* r32 = nullptr;
-    float2* p32 = nullptr;
-    float2* q32 = nullptr;
+    double2* part_c = nullptr;       // [ntiles][nrb][64]
+    double* part_r = nullptr;        // [ntiles][nrb][64]
+    int nrb = 0;
 };
 
 hipError_t cocg_init(const DevPencil& P, CocgState& S, const double* BV, int64_t ldbv, int nrb,
                      hipStream_t s);
-hipError_t cocg_reduce_alpha(CocgState& S, int n_active_host, int nrb, hipStream_t s);
+hipError_t cocg_spmm_dir(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
+                         hipStream_t s);
 hipError_t cocg_update(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
                        hipStream_t s);
+hipError_t cocg_reduce_alpha(CocgState& S, int n_active_host, int nrb, hipStream_t s);
 hipError_t cocg_reduce_beta(CocgState& S, int n_active_host, int nrb, double tol2, int max_iter,
-                            hipStream_t s);
+                            int hold, hipStream_t s);
 hipError_t cocg_compact(CocgState& S, hipStream_t s);
-hipError_t cocg_direction(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
-                          hipStream_t s);
-// mixed precision
 hipError_t cocg32_init(const DevPencil& P, CocgState& S, const double* BV, int64_t ldbv, int nrb,
                        hipStream_t s);
+hipError_t cocg32_spmm_dir(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
+                           hipStream_t s);
 hipError_t cocg32_update(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
                          hipStream_t s);
-hipError_t cocg32_direction(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
-                            hipStream_t s);
-hipError_t cocg32_replace(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
-                          hipStream_t s);
+hipError_t cocg32_fold(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
+                       hipStream_t s);
+hipError_t cocg32_replace(const DevPencil& P, CocgState& S, const double* BV, int64_t ldbv,
+                          int n_active_host, int nrb, double tol2, hipStream_t s);
 
 // moments: S_k[i][m*L + l] = sum_j Re(coef[k][j][m] * x[col(k,j,l)][i])
 hipError_t launch_moments(const double2* X, int64_t n, int K, int NH, int L, int M,
                           const double2* coef, double* S, hipStream_t s);
-hipError_t launch_moments_f32(const float2* X, int64_t n, int K, int NH, int L, int M,
-                              const double2* coef, double* S, hipStream_t s);
 
 // RNG
 hipError_t launch_gaussian(uint64_t seed, int64_t n, int64_t L, double* V, hipStream_t s);

@@ -85,13 +85,4 @@ hipError_t launch_moments(const double2* X, int64_t n, int K, int NH, int L, int
     return hipGetLastError();
 }
 
-hipError_t launch_moments_f32(const float2* X, int64_t n, int K, int NH, int L, int M,
-                              const double2* coef, double* S, hipStream_t s) {
-    if (M > kMaxMoments) return hipErrorInvalidValue;
-    const int64_t blocks = (n * L + 255) / 256;
-    hipLaunchKernelGGL(k_moments<float2>, dim3((unsigned)blocks, K), dim3(256), 0, s, X, n, NH, L,
-                       M, coef, S);
-    return hipGetLastError();
-}
-
 }  // namespace gep

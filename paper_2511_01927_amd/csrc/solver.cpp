@@ -146,8 +146,8 @@ struct Timer {
         for (auto e : pool) (void)hipEventDestroy(e);
     }
 };
-enum { T_SPMM = 0, T_UPDATE, T_DIRECTION, T_REDUCE, T_MOMENTS, T_GRAM, T_GEMM, T_DENSE };
-static const char* kTimerNames[Timer::kClasses] = {"spmm_shifted", "cocg_update", "cocg_direction",
+enum { T_SPMM = 0, T_UPDATE, T_REPLACE, T_REDUCE, T_MOMENTS, T_GRAM, T_GEMM, T_DENSE };
+static const char* kTimerNames[Timer::kClasses] = {"cocg_spmm_dir", "cocg_update", "cocg_replace",
                                                    "cocg_reduce", "moments", "gram",
                                                    "gemm_tall", "dense_small"};
 
@@ -337,9 +337,10 @@ struct Stats {
     long cocg_iters = 0;          // iterations of the COCG loop (all passes)
     long tile_iters = 0;          // sum over tiles of iterations run
     long spmm_launches = 0;
+    long replacements = 0;
     double spmm_alg_bytes = 0.0;  // algorithmic bytes of all shifted SpMM launches
     double update_alg_bytes = 0.0;
-    double direction_alg_bytes = 0.0;
+    double replace_alg_bytes = 0.0;
     long columns = 0;
     int waves = 0;
     std::vector<double> phase_ms;
@@ -403,19 +404,41 @@ class Solver {
         CocgState S;
         S.n = n;
         S.ntiles = ntiles;
-        S.nrb_max = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 31) / 32));
+        const bool mixed = c_.o.precision == GEP_MIXED;
+        // small row blocks keep the +-stencil-offset gathers of concurrently
+        // running work-groups inside the caches
+        const int rpb = c_.o.rows_per_block > 0 ? c_.o.rows_per_block
+                                                : (int)std::max<int64_t>(64, (n + 2047) / 2048);
+        S.nrb = (int)((n + rpb - 1) / rpb);
+        const int nrb = S.nrb;
         const size_t mv = (size_t)n * Wp;
-        DBuf<double2> x(mv), r(mv), p(mv), q(mv);
+        DBuf<double2> x(mv), u, p, pn;
+        DBuf<float2> x32, u32, p32, pn32;
+        if (mixed) {
+            x32.alloc(mv);
+            u32.alloc(mv);
+            p32.alloc(mv);
+            pn32.alloc(mv);
+        } else {
+            u.alloc(mv);
+            p.alloc(mv);
+            pn.alloc(mv);
+        }
         DBuf<double2> d_shifts(Wp), rho(Wp), alpha(Wp), beta(Wp);
         DBuf<int32_t> d_bcol(Wp), active(Wp), iters(Wp), tile_active(ntiles), tiles(ntiles), counts(4);
-        DBuf<double> bb(Wp), rr(Wp);
-        DBuf<double2> part_c((size_t)ntiles * S.nrb_max * kTile);
-        DBuf<double> part_r((size_t)ntiles * S.nrb_max * kTile);
+        DBuf<double> bb(Wp), rr(Wp), rmax(Wp);
+        DBuf<int32_t> flag(Wp);
+        DBuf<double2> part_c((size_t)ntiles * nrb * kTile);
+        DBuf<double> part_r((size_t)ntiles * nrb * kTile);
         DBuf<double2> d_coef(coef.size());
         S.x = x.get();
-        S.r = r.get();
+        S.u = u.get();
         S.p = p.get();
-        S.q = q.get();
+        S.pn = pn.get();
+        S.x32 = x32.get();
+        S.u32 = u32.get();
+        S.p32 = p32.get();
+        S.pn32 = pn32.get();
         S.shifts = d_shifts.get();
         S.bcol = d_bcol.get();
         S.rho = rho.get();
@@ -423,6 +446,8 @@ class Solver {
         S.beta = beta.get();
         S.bb = bb.get();
         S.rr = rr.get();
+        S.rmax = rmax.get();
+        S.flag = flag.get();
         S.active = active.get();
         S.iters = iters.get();
         S.tile_active = tile_active.get();
@@ -438,40 +463,66 @@ class Solver {
         HIPCHK(hipMemcpyAsync(S.tiles, tl.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s_));
         HIPCHK(hipMemcpyAsync(S.counts, cnt0, sizeof(cnt0), hipMemcpyHostToDevice, s_));
         HIPCHK(hipMemcpyAsync(d_coef.get(), coef.data(), sizeof(double2) * coef.size(), hipMemcpyHostToDevice, s_));
-
-        int nrb = 0;
-        choose_nrb(n, ntiles, S.nrb_max, nrb);
-        HIPCHK(cocg_init(P_->d, S, BV, ldbv, nrb, s_));
+        if (mixed) {
+            HIPCHK(hipMemsetAsync(S.x, 0, sizeof(double2) * mv, s_));
+            HIPCHK(cocg32_init(P_->d, S, BV, ldbv, nrb, s_));
+        } else {
+            HIPCHK(cocg_init(P_->d, S, BV, ldbv, nrb, s_));
+        }
         const double tol2 = c_.o.solve_tol * c_.o.solve_tol;
         const int max_iter = c_.o.max_iter;
         const int every = std::max(1, c_.o.check_every);
+        const double cb = mixed ? 8.0 : 16.0;   // bytes per complex element of the recurrence
         int n_act = ntiles;
         long it = 0;
-        const double mat_bytes = (double)P_->d.nnz * (16.0 + 4.0) + 4.0 * (n + 1);
-        const double tile_bytes = (double)n * kTile * 16.0;
+        const double mat_bytes = (double)P_->d.nnz * ((mixed ? 8.0 : 16.0) + 4.0) + 4.0 * (n + 1);
+        const double tile_bytes = (double)n * kTile * cb;
         while (n_act > 0 && it < max_iter) {
             for (int c = 0; c < every; ++c) {
                 tm_.begin(T_SPMM);
-                HIPCHK(launch_spmm_c64(P_->d, S.shifts, S.p, S.q, S.tiles, S.counts, n_act, nrb, S.part_c, s_));
+                if (mixed)
+                    HIPCHK(cocg32_spmm_dir(P_->d, S, n_act, nrb, s_));
+                else
+                    HIPCHK(cocg_spmm_dir(P_->d, S, n_act, nrb, s_));
                 tm_.end();
                 HIPCHK(cocg_reduce_alpha(S, n_act, nrb, s_));
                 tm_.begin(T_UPDATE);
-                HIPCHK(cocg_update(P_->d, S, n_act, nrb, s_));
+                if (mixed)
+                    HIPCHK(cocg32_update(P_->d, S, n_act, nrb, s_));
+                else
+                    HIPCHK(cocg_update(P_->d, S, n_act, nrb, s_));
                 tm_.end();
-                HIPCHK(cocg_reduce_beta(S, n_act, nrb, tol2, max_iter, s_));
+                HIPCHK(cocg_reduce_beta(S, n_act, nrb, tol2, max_iter, mixed ? 1 : 0, s_));
                 HIPCHK(cocg_compact(S, s_));
-                tm_.begin(T_DIRECTION);
-                HIPCHK(cocg_direction(P_->d, S, n_act, nrb, s_));
-                tm_.end();
+                if (mixed)
+                    std::swap(S.p32, S.pn32);
+                else
+                    std::swap(S.p, S.pn);
                 stats_.spmm_launches += 1;
                 stats_.spmm_alg_bytes += mat_bytes;
+                stats_.update_alg_bytes += mat_bytes;
             }
             it += every;
+            if (mixed) {
+                tm_.begin(T_REPLACE);
+                HIPCHK(cocg32_replace(P_->d, S, BV, ldbv, n_act, nrb, tol2, s_));
+                tm_.end();
+                stats_.replacements += 1;
+                // fold: read/write x64 and x32; residual: read x64, write u32
+                stats_.replace_alg_bytes += (double)n_act * n * kTile * (32.0 + 16.0 + 16.0 + 8.0) +
+                                            (double)P_->d.nnz * 20.0;
+            }
             HIPCHK(hipMemcpyAsync(counts_h_, S.counts, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s_));
             HIPCHK(hipStreamSynchronize(s_));
             tm_.flush();
             n_act = counts_h_[0];
-            if (n_act > 0) choose_nrb(n, n_act, S.nrb_max, nrb);
+        }
+        if (mixed) {
+            // fold the remaining FP32 corrections of every tile
+            int32_t cntall[4] = {ntiles, (int32_t)W, 0, 0};
+            HIPCHK(hipMemcpyAsync(S.tiles, tl.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s_));
+            HIPCHK(hipMemcpyAsync(S.counts, cntall, sizeof(cntall), hipMemcpyHostToDevice, s_));
+            HIPCHK(cocg32_fold(P_->d, S, ntiles, nrb, s_));
         }
         stats_.cocg_iters += it;
         // per-column iteration counts -> exact tile work for the byte count
@@ -485,9 +536,9 @@ class Solver {
             tile_iters += mx;
         }
         stats_.tile_iters += tile_iters;
-        stats_.spmm_alg_bytes += tile_iters * 2.0 * tile_bytes;
-        stats_.update_alg_bytes += tile_iters * 6.0 * tile_bytes;
-        stats_.direction_alg_bytes += tile_iters * 3.0 * tile_bytes;
+        // kernel A: read u, p, write p' (3 passes); kernel B: read x, u, p', write x, u (5)
+        stats_.spmm_alg_bytes += tile_iters * 3.0 * tile_bytes;
+        stats_.update_alg_bytes += tile_iters * 5.0 * tile_bytes;
         // moments
         const int r0 = L * M;
         auto Sall = std::make_shared<DBuf<double>>((size_t)K * n * r0);
@@ -496,9 +547,13 @@ class Solver {
         tm_.end();
         // release the multivectors before the dense phase
         x.release();
-        r.release();
+        u.release();
         p.release();
-        q.release();
+        pn.release();
+        x32.release();
+        u32.release();
+        p32.release();
+        pn32.release();
         out.resize(K);
         for (int k = 0; k < K; ++k) {
             ContourOut& co = out[k];
@@ -649,9 +704,10 @@ static std::string json_stats(const Solver& s, double wall_ms, const std::vector
       << "\",\"cocg_iters\":" << s.stats_.cocg_iters << ",\"tile_iters\":" << s.stats_.tile_iters
       << ",\"columns\":" << s.stats_.columns << ",\"waves\":" << s.stats_.waves
       << ",\"spmm_launches\":" << s.stats_.spmm_launches
+      << ",\"replacements\":" << s.stats_.replacements
       << ",\"spmm_alg_bytes\":" << s.stats_.spmm_alg_bytes
       << ",\"update_alg_bytes\":" << s.stats_.update_alg_bytes
-      << ",\"direction_alg_bytes\":" << s.stats_.direction_alg_bytes
+      << ",\"replace_alg_bytes\":" << s.stats_.replace_alg_bytes
       << ",\"gram_flops\":" << s.gram_flops_ << ",\"gemm_flops\":" << s.gemm_flops_
       << ",\"kernel_ms\":{";
     for (int c = 0; c < Timer::kClasses; ++c)
@@ -852,6 +908,7 @@ void gep_opts_default(gep_opts* o) {
     o->rhs = nullptr;
     o->mem_limit_bytes = 0.0;
     o->timing = 0;
+    o->rows_per_block = 0;
 }
 
 const char* gep_strerror(int st) {
@@ -909,6 +966,7 @@ static int validate_problem(const gep_contour* contours, int K, int N, int M, in
     if (!(tol > 0.0)) { gep::set_error("tol must be > 0"); return GEP_EINVAL; }
     if (o->precision != GEP_FP64 && o->precision != GEP_MIXED) { gep::set_error("bad precision"); return GEP_EINVAL; }
     if (!(o->solve_tol > 0.0) || o->max_iter < 1) { gep::set_error("bad solve_tol/max_iter"); return GEP_EINVAL; }
+    if (o->rows_per_block < 0) { gep::set_error("rows_per_block must be >= 0"); return GEP_EINVAL; }
     for (int k = 0; k < K; ++k) {
         const gep_contour& c = contours[k];
         if (!std::isfinite(c.center) || !std::isfinite(c.radius) || !(c.radius > 0.0) ||
@@ -929,7 +987,6 @@ int gep_ci_solve_pencil(gep_pencil* P, const gep_contour* contours, int K, int N
     if (opts) o = *opts; else gep_opts_default(&o);
     int st = validate_problem(contours, K, N, M, L, tol, &o);
     if (st) return st;
-    if (o.precision == GEP_MIXED) { gep::set_error("mixed precision is not available in this build"); return GEP_EINVAL; }
     gep::SolveCfg cfg;
     cfg.N = N;
     cfg.NH = N / 2;

@@ -43,7 +43,7 @@ class gep_opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("precision", C.c_int), ("max_refine", C.c_int),
                 ("solve_tol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int),
                 ("stream", C.c_void_p), ("inputs_on_device", C.c_int), ("rhs", C.c_void_p),
-                ("mem_limit_bytes", C.c_double), ("timing", C.c_int)]
+                ("mem_limit_bytes", C.c_double), ("timing", C.c_int), ("rows_per_block", C.c_int)]
 
 
 # every symbol declared in include/gep_ci.h
@@ -151,7 +151,7 @@ def _contours(contours):
 
 
 def _opts(seed=1, precision="fp64", max_refine=1, solve_tol=1e-9, max_iter=100000, check_every=16,
-          stream=None, on_device=0, rhs=None, mem_limit_bytes=0.0, timing=False):
+          stream=None, on_device=0, rhs=None, mem_limit_bytes=0.0, timing=False, rows_per_block=0):
     lib = load()
     o = gep_opts()
     lib.gep_opts_default(C.byref(o))
@@ -174,6 +174,7 @@ def _opts(seed=1, precision="fp64", max_refine=1, solve_tol=1e-9, max_iter=10000
             o.rhs = keep.ctypes.data
     o.mem_limit_bytes = mem_limit_bytes
     o.timing = 1 if timing else 0
+    o.rows_per_block = rows_per_block
     return o, keep
 
 

@@ -152,3 +152,23 @@ def test_two_contours_share_cut_without_duplicates(lib):
     ref = oracle.oracle_ci_solve(w.A, w.B, cont, 16, 4, 16, 1e-8, seed=5)
     assert_pairs_match(got, ref["evals"], ref["evecs"], w.B)
     assert np.all(np.diff(got["evals"]) > 0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_precisions_fem1d_2000(lib, prec):
+    """FP32 COCG with FP64 residual replacement meets the same bar as FP64."""
+    w = configs.fem1d_2000()
+    got = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed,
+                           precision=prec)
+    lam_o, X_o = _oracle_refs(w)
+    assert_pairs_match(got, lam_o, X_o, w.B)
+    assert got["stats"]["precision"] == prec
+
+
+def test_mixed_variable_coefficient_2d_vs_oracle(lib):
+    w = _var2d(seed=9)
+    got = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed,
+                           precision="mixed")
+    lam, X = _oracle_refs(w)
+    assert_pairs_match(got, lam, X, w.B)
+    assert got["stats"]["replacements"] > 0
