@@ -53,8 +53,14 @@ def cpu_baseline(w, sample_contours: int):
     workers = default_workers()
     cont = w.contours[:sample_contours]
     t0 = time.perf_counter()
+    done = [0]
+
+    def progress(msg):
+        done[0] += 1
+        print(f"# cpu baseline: {msg} ({done[0]})", flush=True)
+
     res = oracle.oracle_ci_solve(w.A, w.B, cont, w.n_nodes, w.moments, w.block, w.tol,
-                                 seed=w.seed, workers=workers)
+                                 seed=w.seed, workers=workers, progress=progress)
     dt = time.perf_counter() - t0
     ok = int(np.sum(res["resid"] <= w.tol))
     return {"value": ok / dt, "unit": "eigenpairs/s", "cores": workers, "kind": "oracle",

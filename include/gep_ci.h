@@ -99,7 +99,7 @@ typedef struct {
                                0 = 85% of free memory */
     int timing;             /* 1: time every kernel class with HIP events */
     int rows_per_block;     /* rows per work-group of the streaming COCG kernels
-                               (0 = automatic: max(64, n / 2048)) */
+                               (0 = automatic: max(32, n / 4096)) */
 } gep_opts;
 
 typedef struct gep_result gep_result;

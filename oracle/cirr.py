@@ -36,6 +36,7 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spl
+from threadpoolctl import threadpool_limits
 
 from .rng import gaussian_block
 
@@ -64,41 +65,56 @@ def residuals(A, B, lam: np.ndarray, X: np.ndarray) -> np.ndarray:
     return np.linalg.norm(R, axis=0) / (inf_norm(A) * np.linalg.norm(X, axis=0))
 
 
+_SHARED = {}
+
+
 def _pair_moments(args):
     """Moments contributed by the conjugate node pair (j, N+1-j) of one circle.
 
     Both nodes are solved with their own LU; the pair's imaginary parts cancel
     for a real pencil and real V, and the real part is returned together with
     the size of the cancelled imaginary part (a check of the quadrature).
+    The pencil and B V are read from the fork-inherited _SHARED table.
     """
-    A, B, BV, c, R, N, M, jpair = args
+    c, R, N, M, jpair = args
+    A, B, BV = _SHARED["A"], _SHARED["B"], _SHARED["BV"]
     z, w, zeta = quadrature(c, R, N)
     n, L = BV.shape
     acc = np.zeros((n, L * M), dtype=np.complex128)
-    for j in jpair:
-        K = (z[j] * B - A).tocsc()
-        lu = spl.splu(K, permc_spec="MMD_AT_PLUS_A")
-        Y = lu.solve(BV.astype(np.complex128))
-        for m in range(M):
-            acc[:, m * L:(m + 1) * L] += (w[j] * zeta[j] ** m) * Y
+    with threadpool_limits(1):
+        for j in jpair:
+            K = (z[j] * B - A).tocsc()
+            lu = spl.splu(K, permc_spec="MMD_AT_PLUS_A")
+            Y = lu.solve(BV.astype(np.complex128))
+            for m in range(M):
+                acc[:, m * L:(m + 1) * L] += (w[j] * zeta[j] ** m) * Y
     return acc.real.copy(), float(np.linalg.norm(acc.imag)), float(np.linalg.norm(acc.real))
 
 
-def contour_moments(A, B, V, center, radius, n_nodes, moments, pool=None):
+def contour_moments(A, B, V, center, radius, n_nodes, moments, workers=1, progress=None):
     """S = [S_0 ... S_{M-1}] (n x L*M, real) for one circle, all N nodes solved."""
     if n_nodes % 2:
         raise ValueError("the oracle pairs conjugate nodes: N must be even")
-    BV = B @ V
-    tasks = [(A, B, BV, center, radius, n_nodes, moments, (j, n_nodes - 1 - j))
+    _SHARED.update(A=A, B=B, BV=B @ V)
+    tasks = [(center, radius, n_nodes, moments, (j, n_nodes - 1 - j))
              for j in range(n_nodes // 2)]
+    pool = None
+    if workers > 1:
+        pool = ProcessPoolExecutor(max_workers=min(workers, len(tasks)),
+                                   mp_context=mp.get_context("fork"))
     it = pool.map(_pair_moments, tasks) if pool is not None else map(_pair_moments, tasks)
     S = None
     im2 = 0.0
     re2 = 0.0
     for part, im, re in it:
+        if progress is not None:
+            progress("node pair solved")
         S = part if S is None else S + part
         im2 += im * im
         re2 += re * re
+    if pool is not None:
+        pool.shutdown()
+    _SHARED.clear()
     if np.sqrt(im2) > 1e-10 * max(np.sqrt(re2), 1e-300):
         raise AssertionError("conjugate node pairs did not cancel the imaginary part")
     return S
@@ -142,11 +158,11 @@ def _normalise(X: np.ndarray, B) -> np.ndarray:
     return X * sgn[None, :]
 
 
-def _solve_contour(A, B, V0, c, R, lo, hi, N, M, tol, max_refine, rank_tol, pool):
+def _solve_contour(A, B, V0, c, R, lo, hi, N, M, tol, max_refine, rank_tol, workers, progress=None):
     V, Mcur = V0, M
     info = {"passes": 0, "rank": [], "saturated": False}
     for p in range(max_refine + 1):
-        S = contour_moments(A, B, V, c, R, N, Mcur, pool)
+        S = contour_moments(A, B, V, c, R, N, Mcur, workers, progress)
         Q, r, smin = orth(S, rank_tol)
         info["rank"].append(r)
         if p == 0 and smin > SATURATION:
@@ -184,7 +200,7 @@ def dedupe(lam, X, rho, cid, B, rel: float = 1e-8, overlap: float = 0.9):
 
 def oracle_ci_solve(A, B, contours, n_nodes: int, moments: int, block: int, tol: float = 1e-8,
                     seed: int | None = 1, V: np.ndarray | None = None, max_refine: int = 1,
-                    rank_tol: float = 1e-12, workers: int = 1):
+                    rank_tol: float = 1e-12, workers: int = 1, progress=None):
     """All eigenpairs of (A, B) inside the contours' keep windows.
 
     contours: array (K, 4) of [centre, radius, keep_lo, keep_hi]; keep windows
@@ -197,22 +213,15 @@ def oracle_ci_solve(A, B, contours, n_nodes: int, moments: int, block: int, tol:
     contours = np.atleast_2d(np.asarray(contours, dtype=np.float64))
     if V is None:
         V = gaussian_block(n, block, seed)
-    pool = None
-    if workers > 1:
-        pool = ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork"))
     lams, Xs, rhos, cids, infos = [], [], [], [], []
-    try:
-        for k, (c, R, lo, hi) in enumerate(contours):
-            lam, X, rho, info = _solve_contour(A, B, V, c, R, lo, hi, n_nodes, moments, tol,
-                                               max_refine, rank_tol, pool)
-            lams.append(lam)
-            Xs.append(X)
-            rhos.append(rho)
-            cids.append(np.full(lam.size, k, dtype=np.int32))
-            infos.append(info)
-    finally:
-        if pool is not None:
-            pool.shutdown()
+    for k, (c, R, lo, hi) in enumerate(contours):
+        lam, X, rho, info = _solve_contour(A, B, V, c, R, lo, hi, n_nodes, moments, tol,
+                                           max_refine, rank_tol, workers, progress)
+        lams.append(lam)
+        Xs.append(X)
+        rhos.append(rho)
+        cids.append(np.full(lam.size, k, dtype=np.int32))
+        infos.append(info)
     lam = np.concatenate(lams)
     X = np.concatenate(Xs, axis=1) if Xs else np.zeros((n, 0))
     rho = np.concatenate(rhos)

@@ -31,7 +31,8 @@ __device__ inline double block_sum(double v, double* red) {
 __global__ __launch_bounds__(kDenseThreads) void k_jacobi(double* __restrict__ Aall,
                                                           double* __restrict__ wout,
                                                           double* __restrict__ Vout,
-                                                          double* __restrict__ Vwork, int k) {
+                                                          double* __restrict__ Vwork, int kmax,
+                                                          const int32_t* __restrict__ ks) {
     __shared__ double red[kDenseThreads];
     __shared__ int pp[kDenseThreads / 2], qq[kDenseThreads / 2];
     __shared__ double cs[kDenseThreads / 2], sn[kDenseThreads / 2];
@@ -39,8 +40,10 @@ __global__ __launch_bounds__(kDenseThreads) void k_jacobi(double* __restrict__ A
     const int b = blockIdx.x;
     const int t = threadIdx.x;
     const int nt = blockDim.x;
-    double* A = Aall + (int64_t)b * k * k;
-    double* V = Vwork + (int64_t)b * k * k;
+    const int k = ks ? ks[b] : kmax;   // matrix b is k x k, stored with stride kmax * kmax
+    double* A = Aall + (int64_t)b * kmax * kmax;
+    double* V = Vwork + (int64_t)b * kmax * kmax;
+    if (k <= 0) return;
     const int kp = k + (k & 1);
     const int np = kp / 2;
     for (int e = t; e < k * k; e += nt) V[e] = (e / k == e % k) ? 1.0 : 0.0;
@@ -125,32 +128,35 @@ __global__ __launch_bounds__(kDenseThreads) void k_jacobi(double* __restrict__ A
         const double wj = wl[j];
         int rank = 0;
         for (int i = 0; i < k; ++i) rank += (wl[i] < wj) || (wl[i] == wj && i < j);
-        wout[(int64_t)b * k + rank] = wj;
-        double* Vo = Vout + (int64_t)b * k * k;
+        wout[(int64_t)b * kmax + rank] = wj;
+        double* Vo = Vout + (int64_t)b * kmax * kmax;
         for (int i = 0; i < k; ++i) Vo[(int64_t)i * k + rank] = V[(int64_t)i * k + j];
     }
 }
 
-hipError_t launch_sym_eig(double* A, double* w, double* V, int64_t k, int batch, double* work,
-                          hipStream_t s) {
-    if (k <= 0 || batch <= 0) return hipSuccess;
-    if (k > kDenseThreads) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_jacobi, dim3(batch), dim3(kDenseThreads), 0, s, A, w, V, work, (int)k);
+hipError_t launch_sym_eig(double* A, double* w, double* V, int64_t kmax, int batch,
+                          const int32_t* ks, double* work, hipStream_t s) {
+    if (kmax <= 0 || batch <= 0) return hipSuccess;
+    if (kmax > kDenseThreads) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_jacobi, dim3(batch), dim3(kDenseThreads), 0, s, A, w, V, work, (int)kmax,
+                       ks);
     return hipGetLastError();
 }
 
 // ---- Cholesky G = L L^T and LinvT = L^-T ---------------------------------
 __global__ __launch_bounds__(kDenseThreads) void k_chol_inv(const double* __restrict__ Gall,
                                                             double* __restrict__ Tall,
-                                                            double* __restrict__ Wall, int k,
+                                                            double* __restrict__ Wall, int kmax,
+                                                            const int32_t* __restrict__ ks,
                                                             int32_t* __restrict__ status) {
     __shared__ int fail;
     const int b = blockIdx.x;
     const int t = threadIdx.x;
     const int nt = blockDim.x;
-    const double* G = Gall + (int64_t)b * k * k;
-    double* W = Wall + (int64_t)b * k * k;   // holds L (lower)
-    double* T = Tall + (int64_t)b * k * k;   // receives L^-T
+    const int k = ks ? ks[b] : kmax;   // matrix b is k x k (leading dimension k), stride kmax^2
+    const double* G = Gall + (int64_t)b * kmax * kmax;
+    double* W = Wall + (int64_t)b * kmax * kmax;   // holds L (lower)
+    double* T = Tall + (int64_t)b * kmax * kmax;   // receives L^-T
     for (int e = t; e < k * k; e += nt) W[e] = G[e];
     if (t == 0) fail = 0;
     __syncthreads();
@@ -190,11 +196,11 @@ __global__ __launch_bounds__(kDenseThreads) void k_chol_inv(const double* __rest
     // T currently holds row c = column c of L^-1, i.e. T = (L^-1)^T = L^-T.
 }
 
-hipError_t launch_chol_inv(const double* G, double* LinvT, int64_t k, int batch, double* work,
-                           int32_t* status, hipStream_t s) {
-    if (k <= 0 || batch <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_chol_inv, dim3(batch), dim3(kDenseThreads), 0, s, G, LinvT, work, (int)k,
-                       status);
+hipError_t launch_chol_inv(const double* G, double* LinvT, int64_t kmax, int batch,
+                           const int32_t* ks, double* work, int32_t* status, hipStream_t s) {
+    if (kmax <= 0 || batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chol_inv, dim3(batch), dim3(kDenseThreads), 0, s, G, LinvT, work,
+                       (int)kmax, ks, status);
     return hipGetLastError();
 }
 

@@ -118,12 +118,14 @@ hipError_t launch_gram(const double* X, int64_t ld1, const double* Y, int64_t ld
 size_t gram_work_elems(int64_t n, int64_t k1, int64_t k2);
 hipError_t launch_gemm_tall(const double* X, int64_t ldx, const double* T, int64_t ldt, int64_t n,
                             int64_t k, int64_t m, double* C, int64_t ldc, hipStream_t s);
-hipError_t launch_sym_eig(double* A, double* w, double* V, int64_t k, int batch, double* work,
-                          hipStream_t s);
-// Cholesky of k x k SPD matrices; writes L^-T (upper) into LinvT; status[b] = 0 ok,
-// j+1 if pivot j failed.
-hipError_t launch_chol_inv(const double* G, double* LinvT, int64_t k, int batch, double* work,
-                           int32_t* status, hipStream_t s);
+// Batched symmetric eigensolver; matrix b is ks[b] x ks[b] (row-major, leading
+// dimension ks[b]) at offset b * kmax^2; ks == NULL means all kmax.
+hipError_t launch_sym_eig(double* A, double* w, double* V, int64_t kmax, int batch,
+                          const int32_t* ks, double* work, hipStream_t s);
+// Cholesky of SPD matrices (same batching); writes L^-T (upper) into LinvT;
+// status[b] = 0 ok, j+1 if pivot j failed.
+hipError_t launch_chol_inv(const double* G, double* LinvT, int64_t kmax, int batch,
+                           const int32_t* ks, double* work, int32_t* status, hipStream_t s);
 // C = op(A) op(B) for k x k row-major small matrices (ta/tb transpose flags).
 hipError_t launch_small_gemm(const double* A, int ta, const double* B, int tb, double* C,
                              int64_t m, int64_t n, int64_t kk, int64_t lda, int64_t ldb,

@@ -327,7 +327,8 @@ struct ContourOut {
     bool saturated = false;
     double smin_ratio = 0.0;
     std::vector<double> theta, rho;   // all Ritz pairs of the last pass
-    std::shared_ptr<DBuf<double>> X;  // n x r row-major Ritz vectors of the last pass
+    std::shared_ptr<DBuf<double>> Xbuf;  // owner of the Ritz vectors of the last pass
+    double* X = nullptr;                 // n x r row-major Ritz vectors (inside Xbuf)
     int r = 0;
     long iters_max = 0;
     double iters_mean = 0.0;
@@ -408,7 +409,7 @@ class Solver {
         // small row blocks keep the +-stencil-offset gathers of concurrently
         // running work-groups inside the caches
         const int rpb = c_.o.rows_per_block > 0 ? c_.o.rows_per_block
-                                                : (int)std::max<int64_t>(64, (n + 2047) / 2048);
+                                                : (int)std::max<int64_t>(32, (n + 4095) / 4096);
         S.nrb = (int)((n + rpb - 1) / rpb);
         const int nrb = S.nrb;
         const size_t mv = (size_t)n * Wp;
@@ -570,93 +571,134 @@ class Solver {
                 }
             co.iters_max = mx;
             co.iters_mean = cnt ? sum / cnt : 0.0;
-            rayleigh_ritz(Sall->get() + (size_t)k * n * r0, r0, co);
         }
+        rayleigh_ritz_batch(Sall->get(), K, r0, out);
     }
 
-    // B-orthonormalise span(S) and extract Ritz pairs (all of them).
-    void rayleigh_ritz(const double* S, int r0, ContourOut& co) {
+    // B-orthonormalise span(S_k) for every contour k of the pass and extract
+    // all Ritz pairs.  S_k is n x r0 row-major at Sall + k n r0.  Per-contour
+    // products are launched one contour at a time; the small dense solves
+    // (eigen-decompositions, Cholesky) run batched, one work-group per contour.
+    void rayleigh_ritz_batch(const double* Sall, int K, int r0, std::vector<ContourOut>& outs) {
         const int64_t n = P_->d.n;
         const DevPencil& D = P_->d;
-        DBuf<double> T((size_t)n * r0);
-        DBuf<double> G((size_t)r0 * r0), U((size_t)r0 * r0), w(r0), jw((size_t)r0 * r0);
+        const size_t nr = (size_t)n * r0, rr2 = (size_t)r0 * r0;
+        DBuf<double> T(nr * K), Q1(nr * K), G(rr2 * K), U(rr2 * K), w((size_t)r0 * K), jw(rr2 * K);
         DBuf<double> gw(gram_work_elems(n, r0, r0));
-        // pass 1: SVQB
-        HIPCHK(launch_spmm_real(D, S, r0, r0, nullptr, T.get(), s_));
-        gram(S, r0, T.get(), r0, r0, r0, G.get(), gw);
-        HIPCHK(launch_symmetrise(G.get(), r0, s_));
+        DBuf<int32_t> ks(K), st(K);
+        // pass 1: SVQB on the B-Gram G = S^T B S
+        for (int k = 0; k < K; ++k) {
+            const double* S = Sall + k * nr;
+            HIPCHK(launch_spmm_real(D, S, r0, r0, nullptr, T.get() + k * nr, s_));
+            gram(S, r0, T.get() + k * nr, r0, r0, r0, G.get() + k * rr2, gw);
+            HIPCHK(launch_symmetrise(G.get() + k * rr2, r0, s_));
+        }
         tm_.begin(T_DENSE);
-        HIPCHK(launch_sym_eig(G.get(), w.get(), U.get(), r0, 1, jw.get(), s_));
+        HIPCHK(launch_sym_eig(G.get(), w.get(), U.get(), r0, K, nullptr, jw.get(), s_));
         tm_.end();
-        std::vector<double> wh(r0);
-        HIPCHK(hipMemcpyAsync(wh.data(), w.get(), sizeof(double) * r0, hipMemcpyDeviceToHost, s_));
+        std::vector<double> wh((size_t)r0 * K);
+        HIPCHK(hipMemcpyAsync(wh.data(), w.get(), sizeof(double) * r0 * K, hipMemcpyDeviceToHost, s_));
         HIPCHK(hipStreamSynchronize(s_));
         tm_.flush();
-        const double wmax = wh[r0 - 1];
-        int keep = 0;
-        if (wmax > 0.0) {
-            const double cut = std::max(1, r0) * 2.220446049250313e-16 * wmax;
-            for (int i = 0; i < r0; ++i)
-                if (wh[i] > cut) ++keep;
+        std::vector<int32_t> keep(K, 0);
+        int kmax = 0;
+        for (int k = 0; k < K; ++k) {
+            ContourOut& co = outs[k];
+            const double* wk = wh.data() + (size_t)k * r0;
+            const double wmax = wk[r0 - 1];
+            if (wmax > 0.0) {
+                const double cut = std::max(1, r0) * 2.220446049250313e-16 * wmax;
+                for (int i = 0; i < r0; ++i)
+                    if (wk[i] > cut) ++keep[k];
+            }
+            co.rank.push_back(keep[k]);
+            if (co.rank.size() == 1) {
+                co.smin_ratio = wmax > 0 ? std::sqrt(std::max(0.0, wk[0]) / wmax) : 0.0;
+                co.saturated = co.smin_ratio > 1e-3;
+            }
+            co.r = keep[k];
+            co.theta.assign(keep[k], 0.0);
+            co.rho.assign(keep[k], 0.0);
+            kmax = std::max(kmax, keep[k]);
         }
-        co.rank.push_back(keep);
-        if (co.rank.size() == 1) {
-            co.smin_ratio = wmax > 0 ? std::sqrt(std::max(0.0, wh[0]) / wmax) : 0.0;
-            co.saturated = co.smin_ratio > 1e-3;
+        auto Xbuf = std::make_shared<DBuf<double>>(std::max<size_t>(nr * K, 1));
+        for (int k = 0; k < K; ++k) {
+            outs[k].Xbuf = Xbuf;
+            outs[k].X = Xbuf->get() + k * nr;
         }
-        co.r = keep;
-        co.theta.assign(keep, 0.0);
-        co.rho.assign(keep, 0.0);
-        co.X = std::make_shared<DBuf<double>>((size_t)n * std::max(keep, 1));
-        if (keep == 0) return;
-        DBuf<double> Tsc((size_t)r0 * keep), Q1((size_t)n * keep);
-        HIPCHK(launch_svqb_scale(U.get(), w.get(), r0, keep, Tsc.get(), s_));
-        gemm(S, r0, Tsc.get(), keep, n, r0, keep, Q1.get(), keep);
-        // pass 2: Cholesky
-        HIPCHK(launch_spmm_real(D, Q1.get(), keep, keep, nullptr, T.get(), s_));
-        gram(Q1.get(), keep, T.get(), keep, keep, keep, G.get(), gw);
-        HIPCHK(launch_symmetrise(G.get(), keep, s_));
-        DBuf<double> LT((size_t)keep * keep);
-        DBuf<int32_t> st(1);
+        if (kmax == 0) return;
+        HIPCHK(hipMemcpyAsync(ks.get(), keep.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice, s_));
+        // Q1_k = S_k U_k,keep Sigma^-1/2; pass 2: Cholesky of Q1^T B Q1
+        DBuf<double> Tsc(rr2 * K), LT(rr2 * K);
+        for (int k = 0; k < K; ++k) {
+            const int kk = keep[k];
+            if (!kk) continue;
+            HIPCHK(launch_svqb_scale(U.get() + k * rr2, w.get() + (size_t)k * r0, r0, kk, Tsc.get() + k * rr2, s_));
+            gemm(Sall + k * nr, r0, Tsc.get() + k * rr2, kk, n, r0, kk, Q1.get() + k * nr, kk);
+            HIPCHK(launch_spmm_real(D, Q1.get() + k * nr, kk, kk, nullptr, T.get() + k * nr, s_));
+            gram(Q1.get() + k * nr, kk, T.get() + k * nr, kk, kk, kk, G.get() + k * rr2, gw);
+            HIPCHK(launch_symmetrise(G.get() + k * rr2, kk, s_));
+        }
         tm_.begin(T_DENSE);
-        HIPCHK(launch_chol_inv(G.get(), LT.get(), keep, 1, jw.get(), st.get(), s_));
+        HIPCHK(launch_chol_inv(G.get(), LT.get(), r0, K, ks.get(), jw.get(), st.get(), s_));
         tm_.end();
-        check_status(st, "B-Gram of the SVQB basis");
-        DBuf<double> Q((size_t)n * keep);
-        gemm(Q1.get(), keep, LT.get(), keep, n, keep, keep, Q.get(), keep);
+        check_status(st, K, "B-Gram of the SVQB basis");
+        // Q = Q1 L^-T (B-orthonormal); Rayleigh-Ritz matrices
+        DBuf<double> Q(nr * K), AQ(nr * K), TA(rr2 * K), TB(rr2 * K);
+        for (int k = 0; k < K; ++k) {
+            const int kk = keep[k];
+            if (!kk) continue;
+            double* Qk = Q.get() + k * nr;
+            gemm(Q1.get() + k * nr, kk, LT.get() + k * rr2, kk, n, kk, kk, Qk, kk);
+            HIPCHK(launch_spmm_real(D, Qk, kk, kk, AQ.get() + k * nr, T.get() + k * nr, s_));
+            gram(Qk, kk, AQ.get() + k * nr, kk, kk, kk, TA.get() + k * rr2, gw);
+            gram(Qk, kk, T.get() + k * nr, kk, kk, kk, TB.get() + k * rr2, gw);
+            HIPCHK(launch_symmetrise(TA.get() + k * rr2, kk, s_));
+            HIPCHK(launch_symmetrise(TB.get() + k * rr2, kk, s_));
+        }
         Q1.release();
-        // Rayleigh-Ritz
-        DBuf<double> AQ((size_t)n * keep);
-        HIPCHK(launch_spmm_real(D, Q.get(), keep, keep, AQ.get(), T.get(), s_));
-        DBuf<double> TA((size_t)keep * keep), TB((size_t)keep * keep);
-        gram(Q.get(), keep, AQ.get(), keep, keep, keep, TA.get(), gw);
-        gram(Q.get(), keep, T.get(), keep, keep, keep, TB.get(), gw);
-        HIPCHK(launch_symmetrise(TA.get(), keep, s_));
-        HIPCHK(launch_symmetrise(TB.get(), keep, s_));
         tm_.begin(T_DENSE);
-        HIPCHK(launch_chol_inv(TB.get(), LT.get(), keep, 1, jw.get(), st.get(), s_));
+        HIPCHK(launch_chol_inv(TB.get(), LT.get(), r0, K, ks.get(), jw.get(), st.get(), s_));
         // C = L^-1 TA L^-T = LT^T TA LT
-        DBuf<double> C1((size_t)keep * keep), C2((size_t)keep * keep), Z((size_t)keep * keep), th(keep);
-        HIPCHK(launch_small_gemm(LT.get(), 1, TA.get(), 0, C1.get(), keep, keep, keep, keep, keep, keep, s_));
-        HIPCHK(launch_small_gemm(C1.get(), 0, LT.get(), 0, C2.get(), keep, keep, keep, keep, keep, keep, s_));
-        HIPCHK(launch_symmetrise(C2.get(), keep, s_));
-        HIPCHK(launch_sym_eig(C2.get(), th.get(), Z.get(), keep, 1, jw.get(), s_));
-        // U = L^-T Z
-        HIPCHK(launch_small_gemm(LT.get(), 0, Z.get(), 0, C1.get(), keep, keep, keep, keep, keep, keep, s_));
+        DBuf<double> C1(rr2 * K), C2(rr2 * K), Z(rr2 * K), th((size_t)r0 * K);
+        for (int k = 0; k < K; ++k) {
+            const int kk = keep[k];
+            if (!kk) continue;
+            HIPCHK(launch_small_gemm(LT.get() + k * rr2, 1, TA.get() + k * rr2, 0, C1.get() + k * rr2, kk, kk, kk, kk, kk, kk, s_));
+            HIPCHK(launch_small_gemm(C1.get() + k * rr2, 0, LT.get() + k * rr2, 0, C2.get() + k * rr2, kk, kk, kk, kk, kk, kk, s_));
+            HIPCHK(launch_symmetrise(C2.get() + k * rr2, kk, s_));
+        }
+        HIPCHK(launch_sym_eig(C2.get(), th.get(), Z.get(), r0, K, ks.get(), jw.get(), s_));
+        for (int k = 0; k < K; ++k) {
+            const int kk = keep[k];
+            if (!kk) continue;
+            // U = L^-T Z
+            HIPCHK(launch_small_gemm(LT.get() + k * rr2, 0, Z.get() + k * rr2, 0, C1.get() + k * rr2, kk, kk, kk, kk, kk, kk, s_));
+        }
         tm_.end();
-        check_status(st, "projected B matrix");
-        gemm(Q.get(), keep, C1.get(), keep, n, keep, keep, co.X->get(), keep);
-        // residuals with the pencil itself
-        HIPCHK(launch_spmm_real(D, co.X->get(), keep, keep, AQ.get(), T.get(), s_));
-        DBuf<double> num(keep), den(keep), rw((size_t)2 * keep * 1024);
-        HIPCHK(launch_resid_norms(AQ.get(), T.get(), co.X->get(), th.get(), n, keep, num.get(), den.get(), rw.get(), s_));
-        std::vector<double> nh(keep), dh(keep);
-        HIPCHK(hipMemcpyAsync(co.theta.data(), th.get(), sizeof(double) * keep, hipMemcpyDeviceToHost, s_));
-        HIPCHK(hipMemcpyAsync(nh.data(), num.get(), sizeof(double) * keep, hipMemcpyDeviceToHost, s_));
-        HIPCHK(hipMemcpyAsync(dh.data(), den.get(), sizeof(double) * keep, hipMemcpyDeviceToHost, s_));
+        check_status(st, K, "projected B matrix");
+        DBuf<double> num((size_t)r0 * K), den((size_t)r0 * K), rw((size_t)2 * r0 * 1024);
+        for (int k = 0; k < K; ++k) {
+            const int kk = keep[k];
+            if (!kk) continue;
+            double* Xk = outs[k].X;
+            gemm(Q.get() + k * nr, kk, C1.get() + k * rr2, kk, n, kk, kk, Xk, kk);
+            // residuals with the pencil itself
+            HIPCHK(launch_spmm_real(D, Xk, kk, kk, AQ.get() + k * nr, T.get() + k * nr, s_));
+            HIPCHK(launch_resid_norms(AQ.get() + k * nr, T.get() + k * nr, Xk, th.get() + (size_t)k * r0, n, kk,
+                                      num.get() + (size_t)k * r0, den.get() + (size_t)k * r0, rw.get(), s_));
+        }
+        std::vector<double> thh((size_t)r0 * K), nh((size_t)r0 * K), dh((size_t)r0 * K);
+        HIPCHK(hipMemcpyAsync(thh.data(), th.get(), sizeof(double) * r0 * K, hipMemcpyDeviceToHost, s_));
+        HIPCHK(hipMemcpyAsync(nh.data(), num.get(), sizeof(double) * r0 * K, hipMemcpyDeviceToHost, s_));
+        HIPCHK(hipMemcpyAsync(dh.data(), den.get(), sizeof(double) * r0 * K, hipMemcpyDeviceToHost, s_));
         HIPCHK(hipStreamSynchronize(s_));
         tm_.flush();
-        for (int i = 0; i < keep; ++i) co.rho[i] = nh[i] / (D.a_inf * std::max(dh[i], 1e-300));
+        for (int k = 0; k < K; ++k)
+            for (int i = 0; i < keep[k]; ++i) {
+                outs[k].theta[i] = thh[(size_t)k * r0 + i];
+                outs[k].rho[i] = nh[(size_t)k * r0 + i] / (D.a_inf * std::max(dh[(size_t)k * r0 + i], 1e-300));
+            }
     }
 
     void gram(const double* X, int64_t ld1, const double* Y, int64_t ld2, int64_t k1, int64_t k2,
@@ -673,12 +715,15 @@ class Solver {
         tm_.end();
         gemm_flops_ += 2.0 * n * k * m;
     }
-    void check_status(DBuf<int32_t>& st, const char* what) {
-        int32_t h = 0;
-        HIPCHK(hipMemcpyAsync(&h, st.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s_));
+    void check_status(DBuf<int32_t>& st, int K, const char* what) {
+        std::vector<int32_t> h(K, 0);
+        HIPCHK(hipMemcpyAsync(h.data(), st.get(), sizeof(int32_t) * K, hipMemcpyDeviceToHost, s_));
         HIPCHK(hipStreamSynchronize(s_));
         tm_.flush();
-        if (h != 0) fail(GEP_ENOTSPD, std::string("Cholesky failed on the ") + what + " at pivot " + std::to_string(h));
+        for (int k = 0; k < K; ++k)
+            if (h[k] != 0)
+                fail(GEP_ENOTSPD, std::string("Cholesky failed on the ") + what + " of contour slot " +
+                                      std::to_string(k) + " at pivot " + std::to_string(h[k]));
     }
 
     gep_pencil* P_;
@@ -786,7 +831,7 @@ static int solve_impl(gep_pencil* P, const gep_contour* contours, int K, const S
             HIPCHK(hipMemsetAsync(V2.get(), 0, sizeof(double) * n * Kr * L2, s));
             for (int a = 0; a < Kr; ++a) {
                 const ContourOut& co = res[redo[a]];
-                HIPCHK(hipMemcpy2DAsync(V2.get() + (size_t)a * L2, sizeof(double) * Kr * L2, co.X->get(),
+                HIPCHK(hipMemcpy2DAsync(V2.get() + (size_t)a * L2, sizeof(double) * Kr * L2, co.X,
                                         sizeof(double) * co.r, sizeof(double) * co.r, n,
                                         hipMemcpyDeviceToDevice, s));
             }
@@ -834,7 +879,7 @@ static int solve_impl(gep_pencil* P, const gep_contour* contours, int K, const S
         DBuf<int32_t> dsel(sel.size());
         DBuf<double> cm((size_t)n * sel.size());
         HIPCHK(hipMemcpyAsync(dsel.get(), sel.data(), sizeof(int32_t) * sel.size(), hipMemcpyHostToDevice, s));
-        HIPCHK(launch_gather_cols(co.X->get(), n, co.r, dsel.get(), (int)sel.size(), cm.get(), s));
+        HIPCHK(launch_gather_cols(co.X, n, co.r, dsel.get(), (int)sel.size(), cm.get(), s));
         vecs[k].resize((size_t)n * sel.size());
         HIPCHK(hipMemcpyAsync(vecs[k].data(), cm.get(), sizeof(double) * n * sel.size(), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -1154,7 +1199,7 @@ int gep_sym_eig(double* A, double* w, double* V, int64_t k, int batch, void* str
     if (!A || !w || !V || k <= 0 || k > 1024 || batch <= 0) { gep::set_error("bad sym_eig arguments"); return GEP_EINVAL; }
     try {
         gep::DBuf<double> work((size_t)batch * k * k);
-        HIPCHK(gep::launch_sym_eig(A, w, V, k, batch, work.get(), (hipStream_t)stream));
+        HIPCHK(gep::launch_sym_eig(A, w, V, k, batch, nullptr, work.get(), (hipStream_t)stream));
         HIPCHK(hipStreamSynchronize((hipStream_t)stream));
     } catch (const gep::Fail& f) {
         return f.code;
