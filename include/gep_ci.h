@@ -100,6 +100,9 @@ typedef struct {
     int timing;             /* 1: time every kernel class with HIP events */
     int rows_per_block;     /* rows per work-group of the streaming COCG kernels
                                (0 = automatic: max(32, n / 4096)) */
+    int verbose;            /* > 0: progress line on stderr every `verbose` COCG iterations */
+    int use_graph;          /* 1 (default): replay each chunk of check_every COCG
+                               iterations from a captured HIP graph (not with timing) */
 } gep_opts;
 
 typedef struct gep_result gep_result;
@@ -116,6 +119,19 @@ void gep_opts_default(gep_opts* opts);
 int gep_ci_solve(const gep_csr* A, const gep_csr* B, const gep_contour* contours,
                  int n_contours, int n_nodes, int moments, int block, double tol,
                  const gep_opts* opts, gep_result** out);
+
+/* Batched solve of n_problems independent pencils (A[p], B[p]) with their
+ * own circles contours[p][0..n_contours[p]) and common n_nodes, moments,
+ * block and tol.  The shifted systems of every contour of every pencil are
+ * iterated together (one set of kernel launches per COCG iteration); pencils
+ * of different sizes share the launches through per-tile row ranges.
+ * Problem p draws V from seed opts->seed + p (opts->rhs must be NULL).
+ * out[p] receives problem p's result (free each with gep_result_free).
+ * Returns the worst status over the problems (errors: no result is kept). */
+int gep_ci_solve_batch(int n_problems, const gep_csr* A, const gep_csr* B,
+                       const gep_contour* const* contours, const int* n_contours, int n_nodes,
+                       int moments, int block, double tol, const gep_opts* opts,
+                       gep_result** out);
 
 /* Number m of returned eigenpairs and the problem size n. */
 int gep_result_count(const gep_result* res, int64_t* m, int64_t* n);

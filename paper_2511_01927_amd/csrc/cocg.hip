@@ -47,11 +47,16 @@ __device__ inline double2 cdiv(double2 a, double2 b) {
 }
 
 struct BlockMap {
-    int slot, rb, tile, lane, wave, r0, r1;
+    int slot, rb, tile, lane, wave, r0, r1, row0;
+    int64_t base;   // element offset of the tile's row 0
+    int64_t goff;   // base - row0 * 64: offset of global row j is goff + j * 64
 };
 
+// Work-group -> (active tile, row block).  Rows are local to the tile's
+// pencil; row blocks past the tile's row count run with an empty range so
+// that every partial slot is written.
 __device__ inline bool map_block(const int32_t* tiles, const int32_t* n_active, int nrb, int rpb,
-                                 int n, BlockMap& m) {
+                                 const TileGeom& g, BlockMap& m) {
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     m.slot = lb / nrb;
     m.rb = lb - m.slot * nrb;
@@ -59,8 +64,12 @@ __device__ inline bool map_block(const int32_t* tiles, const int32_t* n_active, 
     m.tile = tiles[m.slot];
     m.lane = threadIdx.x & 63;
     m.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    m.r0 = m.rb * rpb;
-    m.r1 = min(n, m.r0 + rpb);
+    const int nt = g.n[m.tile];
+    m.row0 = g.row0[m.tile];
+    m.base = g.base[m.tile];
+    m.goff = m.base - (int64_t)m.row0 * kTile;
+    m.r0 = min(nt, m.rb * rpb);
+    m.r1 = min(nt, m.r0 + rpb);
     return true;
 }
 
@@ -98,10 +107,10 @@ __device__ inline void cfma_acc(R va, R vb, R xr, R xi, R& ar, R& ai, R& br, R& 
 // x = 0, u = D^-1 b, p = 0 (with beta = 0 the first kernel A forms p' = u);
 // partials of rho = b^T u and ||b||^2.
 template <typename VT>
-__global__ __launch_bounds__(kBlock) void k_init(int n, const double* __restrict__ dA,
+__global__ __launch_bounds__(kBlock) void k_init(TileGeom geom, const double* __restrict__ dA,
                                                  const double* __restrict__ dB,
                                                  const double2* __restrict__ shifts,
-                                                 const int32_t* __restrict__ bcol,
+                                                 const int64_t* __restrict__ bsrc,
                                                  const double* __restrict__ BV, int64_t ldbv,
                                                  VT* __restrict__ x, VT* __restrict__ u,
                                                  VT* __restrict__ p,
@@ -110,16 +119,17 @@ __global__ __launch_bounds__(kBlock) void k_init(int n, const double* __restrict
                                                  int rpb, double2* part_c, double* part_r) {
     using R = typename Cx<VT>::R;
     BlockMap m;
-    if (!map_block(tiles, n_active, nrb, rpb, n, m)) return;
+    if (!map_block(tiles, n_active, nrb, rpb, geom, m)) return;
     const int col = m.tile * kTile + m.lane;
-    const int bc = bcol[col];
+    const int64_t bs = bsrc[col];
     const double2 z = shifts[col];
-    const size_t base = (size_t)m.tile * (size_t)n * kTile;
+    const int64_t base = m.base;
     double2 rho = make_double2(0.0, 0.0);
     double bb = 0.0;
     for (int i = m.r0 + m.wave; i < m.r1; i += kWaves) {
-        const double b = bc >= 0 ? BV[(size_t)i * ldbv + bc] : 0.0;
-        const double2 D = make_double2(z.x * dB[i] - dA[i], z.y * dB[i]);
+        const int g = m.row0 + i;
+        const double b = bs >= 0 ? BV[bs + (int64_t)i * ldbv] : 0.0;
+        const double2 D = make_double2(z.x * dB[g] - dA[g], z.y * dB[g]);
         const double2 uv = cdiv(make_double2(b, 0.0), D);
         const size_t o = base + (size_t)i * kTile + m.lane;
         VT zero;
@@ -142,26 +152,27 @@ __global__ __launch_bounds__(kBlock) void k_init(int n, const double* __restrict
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_spmm_dir(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-    const typename Cx<VT>::M* __restrict__ ab, int n, const double2* __restrict__ shifts,
+    const typename Cx<VT>::M* __restrict__ ab, TileGeom geom, const double2* __restrict__ shifts,
     const double2* __restrict__ beta, const VT* __restrict__ U, const VT* __restrict__ P,
     VT* __restrict__ Pn, const int32_t* __restrict__ tiles, const int32_t* __restrict__ n_active,
     int nrb, int rpb, double2* __restrict__ part_c) {
     using R = typename Cx<VT>::R;
     using M = typename Cx<VT>::M;
     BlockMap m;
-    if (!map_block(tiles, n_active, nrb, rpb, n, m)) return;
+    if (!map_block(tiles, n_active, nrb, rpb, geom, m)) return;
     const int col = m.tile * kTile + m.lane;
-    const size_t base = (size_t)m.tile * (size_t)n * kTile;
-    const VT* __restrict__ Ut = U + base;
-    const VT* __restrict__ Pt = P + base;
-    VT* __restrict__ Pnt = Pn + base;
+    // offsets below are global row indices of the concatenated pencil
+    const VT* __restrict__ Ut = U + m.goff;
+    const VT* __restrict__ Pt = P + m.goff;
+    VT* __restrict__ Pnt = Pn + m.goff;
     const double2 zd = shifts[col];
     const double2 bd = beta[col];
     const R zr = (R)zd.x, zi = (R)zd.y, br_ = (R)bd.x, bi_ = (R)bd.y;
     double dr = 0.0, di = 0.0;
     for (int i = m.r0 + m.wave; i < m.r1; i += kWaves) {
-        const int k0 = rowptr[i];
-        const int k1 = rowptr[i + 1];
+        const int g = m.row0 + i;
+        const int k0 = rowptr[g];
+        const int k1 = rowptr[g + 1];
         R ar = 0, ai = 0, sbr = 0, sbi = 0;
         int k = k0;
         for (; k + 3 <= k1; k += 3) {
@@ -186,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_dir(
             const R xr = uj.x + br_ * pj.x - bi_ * pj.y, xi = uj.y + br_ * pj.y + bi_ * pj.x;
             cfma_acc(v.x, v.y, xr, xi, ar, ai, sbr, sbi);
         }
-        const size_t o = (size_t)i * kTile + m.lane;
+        const size_t o = (size_t)g * kTile + m.lane;
         const VT ui = Ut[o], pi = Pt[o];
         VT pn;
         pn.x = ui.x + br_ * pi.x - bi_ * pi.y;
@@ -205,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_dir(
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_update(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-    const typename Cx<VT>::M* __restrict__ ab, int n, const double* __restrict__ dA,
+    const typename Cx<VT>::M* __restrict__ ab, TileGeom geom, const double* __restrict__ dA,
     const double* __restrict__ dB, const double2* __restrict__ shifts,
     const double2* __restrict__ alpha, VT* __restrict__ X, VT* __restrict__ U,
     const VT* __restrict__ P, const int32_t* __restrict__ tiles,
@@ -214,20 +225,20 @@ __global__ __launch_bounds__(kBlock) void k_update(
     using R = typename Cx<VT>::R;
     using M = typename Cx<VT>::M;
     BlockMap m;
-    if (!map_block(tiles, n_active, nrb, rpb, n, m)) return;
+    if (!map_block(tiles, n_active, nrb, rpb, geom, m)) return;
     const int col = m.tile * kTile + m.lane;
-    const size_t base = (size_t)m.tile * (size_t)n * kTile;
-    VT* __restrict__ Xt = X + base;
-    VT* __restrict__ Ut = U + base;
-    const VT* __restrict__ Pt = P + base;
+    VT* __restrict__ Xt = X + m.goff;
+    VT* __restrict__ Ut = U + m.goff;
+    const VT* __restrict__ Pt = P + m.goff;
     const double2 zd = shifts[col];
     const double2 ad = alpha[col];
     const R zr = (R)zd.x, zi = (R)zd.y, alr = (R)ad.x, ali = (R)ad.y;
     double2 rho = make_double2(0.0, 0.0);
     double rr = 0.0;
     for (int i = m.r0 + m.wave; i < m.r1; i += kWaves) {
-        const int k0 = rowptr[i];
-        const int k1 = rowptr[i + 1];
+        const int g = m.row0 + i;
+        const int k0 = rowptr[g];
+        const int k1 = rowptr[g + 1];
         R ar = 0, ai = 0, sbr = 0, sbi = 0;
         int k = k0;
         for (; k + 4 <= k1; k += 4) {
@@ -250,13 +261,13 @@ __global__ __launch_bounds__(kBlock) void k_update(
         }
         const R qr = fma(zr, sbr, fma(-zi, sbi, -ar));
         const R qi = fma(zr, sbi, fma(zi, sbr, -ai));
-        const size_t o = (size_t)i * kTile + m.lane;
+        const size_t o = (size_t)g * kTile + m.lane;
         const VT pi = Pt[o];
         VT xv = Xt[o], uv = Ut[o];
         xv.x = fma(alr, pi.x, fma(-ali, pi.y, xv.x));
         xv.y = fma(alr, pi.y, fma(ali, pi.x, xv.y));
         // s = alpha q / D
-        const double2 D = make_double2(zd.x * dB[i] - dA[i], zd.y * dB[i]);
+        const double2 D = make_double2(zd.x * dB[g] - dA[g], zd.y * dB[g]);
         const R aqr = alr * qr - ali * qi, aqi = alr * qi + ali * qr;
         const double2 s = cdiv(make_double2((double)aqr, (double)aqi), D);
         uv.x = uv.x - (R)s.x;
@@ -468,14 +479,14 @@ __global__ __launch_bounds__(1024) void k_compact(int ntiles, const int32_t* __r
 // the residual is recomputed in FP64 with the FP64 pencil.)
 
 // x64 += x32, x32 = 0 on the active tiles.
-__global__ __launch_bounds__(kBlock) void k_fold(int n, double2* __restrict__ X64,
+__global__ __launch_bounds__(kBlock) void k_fold(TileGeom geom, double2* __restrict__ X64,
                                                  float2* __restrict__ X32,
                                                  const int32_t* __restrict__ tiles,
                                                  const int32_t* __restrict__ n_active, int nrb,
                                                  int rpb) {
     BlockMap m;
-    if (!map_block(tiles, n_active, nrb, rpb, n, m)) return;
-    const size_t base = (size_t)m.tile * (size_t)n * kTile;
+    if (!map_block(tiles, n_active, nrb, rpb, geom, m)) return;
+    const int64_t base = m.base;
     for (int i = m.r0 + m.wave; i < m.r1; i += kWaves) {
         const size_t o = base + (size_t)i * kTile + m.lane;
         const float2 c = X32[o];
@@ -490,14 +501,14 @@ __global__ __launch_bounds__(kBlock) void k_fold(int n, double2* __restrict__ X6
 // r = b - K x64 in FP64, u32 = D^-1 r; partials of r^T u and ||r||^2.
 __global__ __launch_bounds__(kBlock) void k_true_residual(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-    const double2* __restrict__ ab, int n, const double* __restrict__ dA,
+    const double2* __restrict__ ab, TileGeom geom, const double* __restrict__ dA,
     const double* __restrict__ dB, const double2* __restrict__ shifts,
-    const int32_t* __restrict__ bcol, const double* __restrict__ BV, int64_t ldbv,
+    const int64_t* __restrict__ bsrc, const double* __restrict__ BV, int64_t ldbv,
     const double2* __restrict__ X64, float2* __restrict__ U32, const int32_t* __restrict__ flag,
     const int32_t* __restrict__ tiles, const int32_t* __restrict__ n_active, int nrb, int rpb,
     double2* part_c, double* part_r) {
     BlockMap m;
-    if (!map_block(tiles, n_active, nrb, rpb, n, m)) return;
+    if (!map_block(tiles, n_active, nrb, rpb, geom, m)) return;
     const int col = m.tile * kTile + m.lane;
     const bool fl = flag[col] != 0;
     // the decision is uniform over the work-group (all waves see the same 64 columns)
@@ -505,15 +516,16 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(
         block_partials(m, nrb, make_double2(0.0, 0.0), 0.0, part_c, part_r);
         return;
     }
-    const size_t base = (size_t)m.tile * (size_t)n * kTile;
-    const double2* __restrict__ Xt = X64 + base;
+    const int64_t base = m.base;
+    const double2* __restrict__ Xt = X64 + m.goff;
     const double2 z = shifts[col];
-    const int bc = bcol[col];
+    const int64_t bs = bsrc[col];
     double2 rho = make_double2(0.0, 0.0);
     double rr = 0.0;
     for (int i = m.r0 + m.wave; i < m.r1; i += kWaves) {
-        const int k0 = rowptr[i];
-        const int k1 = rowptr[i + 1];
+        const int g = m.row0 + i;
+        const int k0 = rowptr[g];
+        const int k1 = rowptr[g + 1];
         double ar = 0, ai = 0, sbr = 0, sbi = 0;
         for (int k = k0; k < k1; ++k) {
             const int j = colind[k];
@@ -521,10 +533,10 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(
             const double2 xj = Xt[(size_t)j * kTile + m.lane];
             cfma_acc(v.x, v.y, xj.x, xj.y, ar, ai, sbr, sbi);
         }
-        const double b = bc >= 0 ? BV[(size_t)i * ldbv + bc] : 0.0;
+        const double b = bs >= 0 ? BV[bs + (int64_t)i * ldbv] : 0.0;
         const double rx = b - (z.x * sbr - z.y * sbi - ar);
         const double ry = -(z.x * sbi + z.y * sbr - ai);
-        const double2 D = make_double2(z.x * dB[i] - dA[i], z.y * dB[i]);
+        const double2 D = make_double2(z.x * dB[g] - dA[g], z.y * dB[g]);
         const double2 uv = cdiv(make_double2(rx, ry), D);
         if (fl) {
             const float2 us = make_float2((float)uv.x, (float)uv.y);
@@ -600,10 +612,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce_replace(
 template <typename VT>
 hipError_t launch_init_t(const DevPencil& P, CocgState& S, VT* x, VT* u, VT* p, const double* BV,
                          int64_t ldbv, int nrb, hipStream_t s) {
-    const int rpb = (int)((P.n + nrb - 1) / nrb);
+    const int rpb = S.rpb;
     const int grid = pad8(S.ntiles * nrb);
-    hipLaunchKernelGGL((k_init<VT>), dim3(grid), dim3(kBlock), 0, s, (int)P.n, P.dA, P.dB, S.shifts,
-                       S.bcol, BV, ldbv, x, u, p, S.tiles, S.counts, nrb, rpb, S.part_c, S.part_r);
+    hipLaunchKernelGGL((k_init<VT>), dim3(grid), dim3(kBlock), 0, s, S.geom, P.dA, P.dB, S.shifts,
+                       S.bsrc, BV, ldbv, x, u, p, S.tiles, S.counts, nrb, rpb, S.part_c, S.part_r);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_init, dim3(S.ntiles), dim3(kBlock), 0, s, nrb, S.part_c, S.part_r,
@@ -622,10 +634,10 @@ template <typename VT>
 hipError_t launch_spmm_dir_t(const DevPencil& P, const void* ab, CocgState& S, const VT* u,
                              const VT* p, VT* pn, int n_active_host, int nrb, hipStream_t s) {
     if (n_active_host <= 0) return hipSuccess;
-    const int rpb = (int)((P.n + nrb - 1) / nrb);
+    const int rpb = S.rpb;
     const int grid = pad8(n_active_host * nrb);
     hipLaunchKernelGGL((k_spmm_dir<VT>), dim3(grid), dim3(kBlock), 0, s, P.rowptr, P.colind,
-                       (const typename Cx<VT>::M*)ab, (int)P.n, S.shifts, S.beta, u, p, pn,
+                       (const typename Cx<VT>::M*)ab, S.geom, S.shifts, S.beta, u, p, pn,
                        S.tiles, S.counts, nrb, rpb, S.part_c);
     return hipGetLastError();
 }
@@ -634,10 +646,10 @@ template <typename VT>
 hipError_t launch_update_t(const DevPencil& P, const void* ab, CocgState& S, VT* x, VT* u,
                            const VT* p, int n_active_host, int nrb, hipStream_t s) {
     if (n_active_host <= 0) return hipSuccess;
-    const int rpb = (int)((P.n + nrb - 1) / nrb);
+    const int rpb = S.rpb;
     const int grid = pad8(n_active_host * nrb);
     hipLaunchKernelGGL((k_update<VT>), dim3(grid), dim3(kBlock), 0, s, P.rowptr, P.colind,
-                       (const typename Cx<VT>::M*)ab, (int)P.n, P.dA, P.dB, S.shifts, S.alpha, x,
+                       (const typename Cx<VT>::M*)ab, S.geom, P.dA, P.dB, S.shifts, S.alpha, x,
                        u, p, S.tiles, S.counts, nrb, rpb, S.part_c, S.part_r);
     return hipGetLastError();
 }
@@ -670,9 +682,9 @@ hipError_t cocg32_update(const DevPencil& P, CocgState& S, int n_active_host, in
 hipError_t cocg32_fold(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
                        hipStream_t s) {
     if (n_active_host <= 0) return hipSuccess;
-    const int rpb = (int)((P.n + nrb - 1) / nrb);
+    const int rpb = S.rpb;
     const int grid = pad8(n_active_host * nrb);
-    hipLaunchKernelGGL(k_fold, dim3(grid), dim3(kBlock), 0, s, (int)P.n, S.x, S.x32, S.tiles,
+    hipLaunchKernelGGL(k_fold, dim3(grid), dim3(kBlock), 0, s, S.geom, S.x, S.x32, S.tiles,
                        S.counts, nrb, rpb);
     return hipGetLastError();
 }
@@ -682,10 +694,10 @@ hipError_t cocg32_replace(const DevPencil& P, CocgState& S, const double* BV, in
     if (n_active_host <= 0) return hipSuccess;
     hipError_t e = cocg32_fold(P, S, n_active_host, nrb, s);
     if (e != hipSuccess) return e;
-    const int rpb = (int)((P.n + nrb - 1) / nrb);
+    const int rpb = S.rpb;
     const int grid = pad8(n_active_host * nrb);
     hipLaunchKernelGGL(k_true_residual, dim3(grid), dim3(kBlock), 0, s, P.rowptr, P.colind, P.ab,
-                       (int)P.n, P.dA, P.dB, S.shifts, S.bcol, BV, ldbv, S.x, S.u32, S.flag,
+                       S.geom, P.dA, P.dB, S.shifts, S.bsrc, BV, ldbv, S.x, S.u32, S.flag,
                        S.tiles, S.counts, nrb, rpb, S.part_c, S.part_r);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -48,8 +48,19 @@ hipError_t launch_spmm_c64(const DevPencil& P, const double2* shifts, const doub
 hipError_t launch_spmm_c32(const DevPencil& P, const double2* shifts, const float2* X, float2* Y,
                            const int32_t* tiles, const int32_t* n_active, int n_active_host,
                            int nrb, double2* partial, hipStream_t s);
+// rows [row0, row0 + nloc) of the (concatenated) pencil; nloc < 0 means all n.
 hipError_t launch_spmm_real(const DevPencil& P, const double* X, int64_t k, int64_t ld,
-                            double* YA, double* YB, hipStream_t s);
+                            double* YA, double* YB, hipStream_t s, int64_t row0 = 0,
+                            int64_t nloc = -1);
+
+// Geometry of the tiles of a multivector that may span several pencils of a
+// batch: tile t holds rows [row0[t], row0[t] + n[t]) of the concatenated
+// pencil, element (i, lane) at base[t] + i * 64 + lane.
+struct TileGeom {
+    const int64_t* base = nullptr;
+    const int32_t* n = nullptr;
+    const int32_t* row0 = nullptr;
+};
 
 // COCG state (cocg.hip).  FP64 path: x, u, p, pn.  Mixed path: x (FP64
 // solution), x32, u32, p32, pn32 (FP32 recurrence).
@@ -65,7 +76,8 @@ struct CocgState {
     float2* p32 = nullptr;
     float2* pn32 = nullptr;
     double2* shifts = nullptr;   // [W]
-    int32_t* bcol = nullptr;     // [W] column of the B V block feeding column c (-1: none)
+    int64_t* bsrc = nullptr;     // [W] offset in B V of column c's right-hand side at its
+                                 // pencil's row 0 (rows stride ldbv); -1: none
     double2* rho = nullptr;      // [W]
     double2* alpha = nullptr;    // [W]
     double2* beta = nullptr;     // [W]
@@ -81,6 +93,8 @@ struct CocgState {
     double2* part_c = nullptr;       // [ntiles][nrb][64]
     double* part_r = nullptr;        // [ntiles][nrb][64]
     int nrb = 0;
+    int rpb = 0;                     // rows per work-group
+    TileGeom geom;
 };
 
 hipError_t cocg_init(const DevPencil& P, CocgState& S, const double* BV, int64_t ldbv, int nrb,
@@ -104,8 +118,10 @@ hipError_t cocg32_fold(const DevPencil& P, CocgState& S, int n_active_host, int 
 hipError_t cocg32_replace(const DevPencil& P, CocgState& S, const double* BV, int64_t ldbv,
                           int n_active_host, int nrb, double tol2, hipStream_t s);
 
-// moments: S_k[i][m*L + l] = sum_j Re(coef[k][j][m] * x[col(k,j,l)][i])
-hipError_t launch_moments(const double2* X, int64_t n, int K, int NH, int L, int M,
+// moments: S_k[i][m*L + l] = sum_j Re(coef[k][j][m] * x[coff[k] + j*L + l][i]) for
+// i < cn[k]; S_k starts at S + soff[k]; nmax = max cn.
+hipError_t launch_moments(const double2* X, const TileGeom& g, int64_t nmax, int K, int NH, int L,
+                          int M, const int64_t* coff, const int32_t* cn, const int64_t* soff,
                           const double2* coef, double* S, hipStream_t s);
 
 // RNG

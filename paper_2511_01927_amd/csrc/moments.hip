@@ -48,11 +48,14 @@ hipError_t launch_gaussian(uint64_t seed, int64_t n, int64_t L, double* V, hipSt
 
 constexpr int kMaxMoments = 16;
 
-template <typename VT>
-__global__ __launch_bounds__(256) void k_moments(const VT* __restrict__ X, int64_t n, int NH,
-                                                 int L, int M, const double2* __restrict__ coef,
+__global__ __launch_bounds__(256) void k_moments(const double2* __restrict__ X, TileGeom g, int NH,
+                                                 int L, int M, const int64_t* __restrict__ coff,
+                                                 const int32_t* __restrict__ cn,
+                                                 const int64_t* __restrict__ soff,
+                                                 const double2* __restrict__ coef,
                                                  double* __restrict__ S) {
     const int k = blockIdx.y;
+    const int64_t n = cn[k];
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * L) return;
     const int64_t i = e / L;
@@ -60,28 +63,29 @@ __global__ __launch_bounds__(256) void k_moments(const VT* __restrict__ X, int64
     double acc[kMaxMoments];
 #pragma unroll
     for (int m = 0; m < kMaxMoments; ++m) acc[m] = 0.0;
-    const int64_t off = (int64_t)k * NH * L;
     for (int j = 0; j < NH; ++j) {
-        const int64_t col = off + (int64_t)j * L + l;
-        const VT xv = X[((col / kTile) * n + i) * kTile + (col % kTile)];
-        const double xr = (double)xv.x, xi = (double)xv.y;
+        const int64_t col = coff[k] + (int64_t)j * L + l;
+        const int64_t t = col / kTile;
+        const double2 xv = X[g.base[t] + i * kTile + (col % kTile)];
         const double2* cj = coef + ((int64_t)k * NH + j) * M;
 #pragma unroll
         for (int m = 0; m < kMaxMoments; ++m)
-            if (m < M) acc[m] += cj[m].x * xr - cj[m].y * xi;
+            if (m < M) acc[m] += cj[m].x * xv.x - cj[m].y * xv.y;
     }
-    double* Sk = S + ((int64_t)k * n + i) * ((int64_t)L * M);
+    double* Sk = S + soff[k] + i * ((int64_t)L * M);
 #pragma unroll
     for (int m = 0; m < kMaxMoments; ++m)
         if (m < M) Sk[(int64_t)m * L + l] = acc[m];
 }
 
-hipError_t launch_moments(const double2* X, int64_t n, int K, int NH, int L, int M,
+hipError_t launch_moments(const double2* X, const TileGeom& g, int64_t nmax, int K, int NH, int L,
+                          int M, const int64_t* coff, const int32_t* cn, const int64_t* soff,
                           const double2* coef, double* S, hipStream_t s) {
     if (M > kMaxMoments) return hipErrorInvalidValue;
-    const int64_t blocks = (n * L + 255) / 256;
-    hipLaunchKernelGGL(k_moments<double2>, dim3((unsigned)blocks, K), dim3(256), 0, s, X, n, NH,
-                       L, M, coef, S);
+    if (K <= 0 || nmax <= 0) return hipSuccess;
+    const int64_t blocks = (nmax * L + 255) / 256;
+    hipLaunchKernelGGL(k_moments, dim3((unsigned)blocks, K), dim3(256), 0, s, X, g, NH, L, M, coff,
+                       cn, soff, coef, S);
     return hipGetLastError();
 }
 

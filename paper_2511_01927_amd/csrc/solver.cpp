@@ -80,6 +80,9 @@ struct DBuf {
 };
 
 // Host copy of the packed pencil (needed for validation and the merge).
+// A batch of pencils is stored as one block-diagonal pencil: problem p owns
+// rows [prob_row0[p], prob_row0[p] + prob_n[p]) and its column indices are
+// global.
 struct HostPencil {
     int64_t n = 0, nnz = 0;
     std::vector<int32_t> rowptr, colind;
@@ -87,7 +90,28 @@ struct HostPencil {
     std::vector<double> dA, dB;
     double a_inf = 0.0;
     int max_row = 0;
+    std::vector<int64_t> prob_row0, prob_n;
+    std::vector<double> prob_ainf;
 };
+
+static void append_pencil(HostPencil& dst, const HostPencil& src) {
+    const int64_t r0 = dst.n;
+    const int32_t e0 = dst.rowptr.empty() ? 0 : dst.rowptr.back();
+    if (dst.rowptr.empty()) dst.rowptr.push_back(0);
+    for (int64_t i = 0; i < src.n; ++i) dst.rowptr.push_back(e0 + src.rowptr[i + 1]);
+    for (int32_t c : src.colind) dst.colind.push_back((int32_t)(c + r0));
+    dst.a.insert(dst.a.end(), src.a.begin(), src.a.end());
+    dst.b.insert(dst.b.end(), src.b.begin(), src.b.end());
+    dst.dA.insert(dst.dA.end(), src.dA.begin(), src.dA.end());
+    dst.dB.insert(dst.dB.end(), src.dB.begin(), src.dB.end());
+    dst.n += src.n;
+    dst.nnz += src.nnz;
+    dst.a_inf = std::max(dst.a_inf, src.a_inf);
+    dst.max_row = std::max(dst.max_row, src.max_row);
+    dst.prob_row0.push_back(r0);
+    dst.prob_n.push_back(src.n);
+    dst.prob_ainf.push_back(src.a_inf);
+}
 
 // ---- per-kernel-class timing with HIP events -----------------------------
 struct Timer {
@@ -274,6 +298,9 @@ static void pack(const gep_csr* A, const gep_csr* B, bool on_dev, HostPencil& H)
     }
     H.nnz = (int64_t)H.colind.size();
     if (H.nnz >= (1ll << 31) - 1) fail(GEP_EINVAL, "union pattern nnz >= 2^31");
+    H.prob_row0 = {0};
+    H.prob_n = {n};
+    H.prob_ainf = {H.a_inf};
 }
 
 static void upload(const HostPencil& H, gep_pencil* P) {
@@ -320,13 +347,24 @@ struct SolveCfg {
     gep_opts o;
 };
 
+// One contour of one pencil of the batch.
+struct Job {
+    gep_contour c{};
+    int prob = 0;        // problem index in the batch
+    int id = 0;          // contour index within its problem
+    int64_t row0 = 0;    // first row of the problem in the concatenated pencil
+    int64_t n = 0;       // rows of the problem
+    int64_t bsrc0 = 0;   // offset in B V of this job's right-hand side 0 at row 0
+};
+
 struct ContourOut {
     int id = 0;
+    int prob = 0;
     int passes = 0;
     std::vector<int> rank;
     bool saturated = false;
     double smin_ratio = 0.0;
-    std::vector<double> theta, rho;   // all Ritz pairs of the last pass
+    std::vector<double> theta, rho;      // all Ritz pairs of the last pass
     std::shared_ptr<DBuf<double>> Xbuf;  // owner of the Ritz vectors of the last pass
     double* X = nullptr;                 // n x r row-major Ritz vectors (inside Xbuf)
     int r = 0;
@@ -339,15 +377,16 @@ struct Stats {
     long tile_iters = 0;          // sum over tiles of iterations run
     long spmm_launches = 0;
     long replacements = 0;
+    long graph_captures = 0;
     double spmm_alg_bytes = 0.0;  // algorithmic bytes of all shifted SpMM launches
     double update_alg_bytes = 0.0;
     double replace_alg_bytes = 0.0;
     long columns = 0;
     int waves = 0;
-    std::vector<double> phase_ms;
 };
 
 static void choose_nrb(int64_t n, int n_active, int nrb_max, int& nrb) {
+    (void)n;
     int v = (4096 + n_active - 1) / std::max(1, n_active);
     v = std::max(1, std::min(v, nrb_max));
     nrb = v;
@@ -357,33 +396,61 @@ class Solver {
    public:
     Solver(gep_pencil* P, const SolveCfg& c) : P_(P), c_(c) {
         s_ = (hipStream_t)c.o.stream;
+        if (!s_) {
+            // the legacy default stream cannot be captured into a graph: work on
+            // a private blocking stream, which orders itself with the default one
+            HIPCHK(hipStreamCreate(&own_));
+            s_ = own_;
+        }
         tm_.on = c.o.timing != 0;
         tm_.s = s_;
         HIPCHK(hipHostMalloc((void**)&counts_h_, sizeof(int32_t) * 4, 0));
     }
     ~Solver() {
         if (counts_h_) (void)hipHostFree(counts_h_);
+        if (own_) {
+            (void)hipStreamSynchronize(own_);
+            (void)hipStreamDestroy(own_);
+        }
     }
 
-    // One pass of the pipeline for a set of contours sharing (L, M).
-    // BV: row-major n x ldbv; column feeding (contour slot k, rhs l) is
-    // bv_col(k, l) = shared ? l : k*L + l.
-    void run_pass(const std::vector<gep_contour>& cs, const std::vector<int>& ids,
-                  const double* BV, int64_t ldbv, bool shared, int L, int M,
+    // One pass of the pipeline for a set of jobs sharing (L, M).  Job k's
+    // right-hand side l is the column of B V starting at offset
+    // jobs[k].bsrc0 + l, rows of its pencil at stride ldbv.
+    void run_pass(const std::vector<Job>& jobs, const double* BV, int64_t ldbv, int L, int M,
                   std::vector<ContourOut>& out) {
-        const int K = (int)cs.size();
+        const int K = (int)jobs.size();
         const int NH = c_.NH;
-        const int64_t n = P_->d.n;
-        const int64_t W = (int64_t)K * NH * L;
-        const int ntiles = (int)((W + kTile - 1) / kTile);
+        const int64_t per = (int64_t)NH * L;                     // columns per job
+        const int tper = (int)((per + kTile - 1) / kTile);       // tiles per job
+        const int ntiles = K * tper;
         const int64_t Wp = (int64_t)ntiles * kTile;
-        stats_.columns += W;
-        // per-column metadata
-        std::vector<double2> shifts(Wp, make_double2(0.0, 1.0));
-        std::vector<int32_t> bcol(Wp, -1);
-        std::vector<double2> coef((size_t)K * NH * M);
+        stats_.columns += per * K;
+        // tile geometry and per-column metadata
+        std::vector<int64_t> tbase(ntiles);
+        std::vector<int32_t> tn(ntiles), trow0(ntiles);
+        int64_t elems = 0, nmax = 0;
         for (int k = 0; k < K; ++k) {
-            const double c = cs[k].center, R = cs[k].radius;
+            nmax = std::max(nmax, jobs[k].n);
+            for (int t = 0; t < tper; ++t) {
+                const int tt = k * tper + t;
+                tbase[tt] = elems;
+                tn[tt] = (int32_t)jobs[k].n;
+                trow0[tt] = (int32_t)jobs[k].row0;
+                elems += jobs[k].n * kTile;
+            }
+        }
+        std::vector<double2> shifts(Wp, make_double2(0.0, 1.0));
+        std::vector<int64_t> bsrc(Wp, -1);
+        std::vector<double2> coef((size_t)K * NH * M);
+        std::vector<int64_t> coff(K), soff(K + 1, 0);
+        std::vector<int32_t> cn(K);
+        const int r0 = L * M;
+        for (int k = 0; k < K; ++k) {
+            const double c = jobs[k].c.center, R = jobs[k].c.radius;
+            coff[k] = (int64_t)k * tper * kTile;
+            cn[k] = (int32_t)jobs[k].n;
+            soff[k + 1] = soff[k] + jobs[k].n * r0;
             for (int j = 0; j < NH; ++j) {
                 const double th = M_PI * (2.0 * (j + 1) - 1.0) / c_.N;
                 const std::complex<double> zeta(std::cos(th), std::sin(th));
@@ -396,23 +463,23 @@ class Solver {
                     zm *= zeta;
                 }
                 for (int l = 0; l < L; ++l) {
-                    const int64_t col = ((int64_t)k * NH + j) * L + l;
+                    const int64_t col = coff[k] + (int64_t)j * L + l;
                     shifts[col] = make_double2(z.real(), z.imag());
-                    bcol[col] = shared ? l : k * L + l;
+                    bsrc[col] = jobs[k].bsrc0 + l;
                 }
             }
         }
         CocgState S;
-        S.n = n;
         S.ntiles = ntiles;
         const bool mixed = c_.o.precision == GEP_MIXED;
         // small row blocks keep the +-stencil-offset gathers of concurrently
         // running work-groups inside the caches
-        const int rpb = c_.o.rows_per_block > 0 ? c_.o.rows_per_block
-                                                : (int)std::max<int64_t>(32, (n + 4095) / 4096);
-        S.nrb = (int)((n + rpb - 1) / rpb);
+        S.rpb = c_.o.rows_per_block > 0 ? c_.o.rows_per_block
+                                        : (int)std::max<int64_t>(32, (nmax + 4095) / 4096);
+        S.nrb = (int)((nmax + S.rpb - 1) / S.rpb);
+        S.n = nmax;
         const int nrb = S.nrb;
-        const size_t mv = (size_t)n * Wp;
+        const size_t mv = (size_t)elems;
         DBuf<double2> x(mv), u, p, pn;
         DBuf<float2> x32, u32, p32, pn32;
         if (mixed) {
@@ -426,7 +493,9 @@ class Solver {
             pn.alloc(mv);
         }
         DBuf<double2> d_shifts(Wp), rho(Wp), alpha(Wp), beta(Wp);
-        DBuf<int32_t> d_bcol(Wp), active(Wp), iters(Wp), tile_active(ntiles), tiles(ntiles), counts(4);
+        DBuf<int64_t> d_bsrc(Wp), d_tbase(ntiles), d_coff(K), d_soff(K);
+        DBuf<int32_t> active(Wp), iters(Wp), tile_active(ntiles), tiles(ntiles), counts(4);
+        DBuf<int32_t> d_tn(ntiles), d_trow0(ntiles), d_cn(K);
         DBuf<double> bb(Wp), rr(Wp), rmax(Wp);
         DBuf<int32_t> flag(Wp);
         DBuf<double2> part_c((size_t)ntiles * nrb * kTile);
@@ -441,7 +510,7 @@ class Solver {
         S.p32 = p32.get();
         S.pn32 = pn32.get();
         S.shifts = d_shifts.get();
-        S.bcol = d_bcol.get();
+        S.bsrc = d_bsrc.get();
         S.rho = rho.get();
         S.alpha = alpha.get();
         S.beta = beta.get();
@@ -456,11 +525,20 @@ class Solver {
         S.counts = counts.get();
         S.part_c = part_c.get();
         S.part_r = part_r.get();
+        S.geom.base = d_tbase.get();
+        S.geom.n = d_tn.get();
+        S.geom.row0 = d_trow0.get();
         std::vector<int32_t> tl(ntiles);
         for (int t = 0; t < ntiles; ++t) tl[t] = t;
-        int32_t cnt0[4] = {ntiles, (int32_t)W, 0, 0};
+        int32_t cnt0[4] = {ntiles, (int32_t)(per * K), 0, 0};
         HIPCHK(hipMemcpyAsync(S.shifts, shifts.data(), sizeof(double2) * Wp, hipMemcpyHostToDevice, s_));
-        HIPCHK(hipMemcpyAsync(S.bcol, bcol.data(), sizeof(int32_t) * Wp, hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(S.bsrc, bsrc.data(), sizeof(int64_t) * Wp, hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(d_tbase.get(), tbase.data(), sizeof(int64_t) * ntiles, hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(d_tn.get(), tn.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(d_trow0.get(), trow0.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(d_coff.get(), coff.data(), sizeof(int64_t) * K, hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(d_soff.get(), soff.data(), sizeof(int64_t) * K, hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(d_cn.get(), cn.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice, s_));
         HIPCHK(hipMemcpyAsync(S.tiles, tl.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s_));
         HIPCHK(hipMemcpyAsync(S.counts, cnt0, sizeof(cnt0), hipMemcpyHostToDevice, s_));
         HIPCHK(hipMemcpyAsync(d_coef.get(), coef.data(), sizeof(double2) * coef.size(), hipMemcpyHostToDevice, s_));
@@ -472,55 +550,97 @@ class Solver {
         }
         const double tol2 = c_.o.solve_tol * c_.o.solve_tol;
         const int max_iter = c_.o.max_iter;
-        const int every = std::max(1, c_.o.check_every);
+        int every = std::max(2, c_.o.check_every);
+        every += every & 1;   // even: the p / p' buffers are back in place after a chunk
         const double cb = mixed ? 8.0 : 16.0;   // bytes per complex element of the recurrence
         int n_act = ntiles;
         long it = 0;
-        const double mat_bytes = (double)P_->d.nnz * ((mixed ? 8.0 : 16.0) + 4.0) + 4.0 * (n + 1);
-        const double tile_bytes = (double)n * kTile * cb;
-        while (n_act > 0 && it < max_iter) {
+        const double mat_bytes = (double)P_->d.nnz * ((mixed ? 8.0 : 16.0) + 4.0) + 4.0 * (P_->d.n + 1);
+        // One chunk = `every` COCG iterations (+ the mixed path's residual
+        // replacement), enqueued eagerly or replayed from a captured HIP graph.
+        // The chunk's launch grids depend on the active-tile count known to the
+        // host, so a graph is captured again whenever that count changes.
+        auto enqueue_chunk = [&](bool timed) {
             for (int c = 0; c < every; ++c) {
-                tm_.begin(T_SPMM);
+                if (timed) tm_.begin(T_SPMM);
                 if (mixed)
                     HIPCHK(cocg32_spmm_dir(P_->d, S, n_act, nrb, s_));
                 else
                     HIPCHK(cocg_spmm_dir(P_->d, S, n_act, nrb, s_));
-                tm_.end();
+                if (timed) tm_.end();
                 HIPCHK(cocg_reduce_alpha(S, n_act, nrb, s_));
-                tm_.begin(T_UPDATE);
+                if (timed) tm_.begin(T_UPDATE);
                 if (mixed)
                     HIPCHK(cocg32_update(P_->d, S, n_act, nrb, s_));
                 else
                     HIPCHK(cocg_update(P_->d, S, n_act, nrb, s_));
-                tm_.end();
+                if (timed) tm_.end();
                 HIPCHK(cocg_reduce_beta(S, n_act, nrb, tol2, max_iter, mixed ? 1 : 0, s_));
                 HIPCHK(cocg_compact(S, s_));
                 if (mixed)
                     std::swap(S.p32, S.pn32);
                 else
                     std::swap(S.p, S.pn);
-                stats_.spmm_launches += 1;
-                stats_.spmm_alg_bytes += mat_bytes;
-                stats_.update_alg_bytes += mat_bytes;
             }
+            if (mixed) {
+                if (timed) tm_.begin(T_REPLACE);
+                HIPCHK(cocg32_replace(P_->d, S, BV, ldbv, n_act, nrb, tol2, s_));
+                if (timed) tm_.end();
+            }
+        };
+        const bool use_graph = c_.o.use_graph != 0 && !tm_.on;
+        hipGraphExec_t gexec = nullptr;
+        int graph_nact = -1;
+        struct GraphGuard {
+            hipGraphExec_t* e;
+            ~GraphGuard() {
+                if (*e) (void)hipGraphExecDestroy(*e);
+            }
+        } gguard{&gexec};
+        while (n_act > 0 && it < max_iter) {
+            if (use_graph) {
+                if (graph_nact != n_act) {
+                    if (gexec) {
+                        HIPCHK(hipGraphExecDestroy(gexec));
+                        gexec = nullptr;
+                    }
+                    hipGraph_t graph = nullptr;
+                    HIPCHK(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+                    enqueue_chunk(false);
+                    HIPCHK(hipStreamEndCapture(s_, &graph));
+                    hipError_t e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(graph);
+                    HIPCHK(e);
+                    graph_nact = n_act;
+                    stats_.graph_captures += 1;
+                }
+                HIPCHK(hipGraphLaunch(gexec, s_));
+            } else {
+                enqueue_chunk(true);
+            }
+            stats_.spmm_launches += every;
+            stats_.spmm_alg_bytes += every * mat_bytes;
+            stats_.update_alg_bytes += every * mat_bytes;
             it += every;
             if (mixed) {
-                tm_.begin(T_REPLACE);
-                HIPCHK(cocg32_replace(P_->d, S, BV, ldbv, n_act, nrb, tol2, s_));
-                tm_.end();
                 stats_.replacements += 1;
                 // fold: read/write x64 and x32; residual: read x64, write u32
-                stats_.replace_alg_bytes += (double)n_act * n * kTile * (32.0 + 16.0 + 16.0 + 8.0) +
+                stats_.replace_alg_bytes += (double)n_act * nmax * kTile * (32.0 + 16.0 + 16.0 + 8.0) +
                                             (double)P_->d.nnz * 20.0;
             }
             HIPCHK(hipMemcpyAsync(counts_h_, S.counts, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s_));
             HIPCHK(hipStreamSynchronize(s_));
             tm_.flush();
             n_act = counts_h_[0];
+            if (c_.o.verbose > 0 && (it % c_.o.verbose) < every) {
+                std::fprintf(stderr, "gep: pass columns %lld, iteration %ld, active tiles %d/%d, active columns %d\n",
+                             (long long)(per * K), it, n_act, ntiles, counts_h_[1]);
+                std::fflush(stderr);
+            }
         }
         if (mixed) {
             // fold the remaining FP32 corrections of every tile
-            int32_t cntall[4] = {ntiles, (int32_t)W, 0, 0};
+            int32_t cntall[4] = {ntiles, (int32_t)(per * K), 0, 0};
             HIPCHK(hipMemcpyAsync(S.tiles, tl.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s_));
             HIPCHK(hipMemcpyAsync(S.counts, cntall, sizeof(cntall), hipMemcpyHostToDevice, s_));
             HIPCHK(cocg32_fold(P_->d, S, ntiles, nrb, s_));
@@ -530,22 +650,22 @@ class Solver {
         std::vector<int32_t> its(Wp);
         HIPCHK(hipMemcpyAsync(its.data(), S.iters, sizeof(int32_t) * Wp, hipMemcpyDeviceToHost, s_));
         HIPCHK(hipStreamSynchronize(s_));
-        long tile_iters = 0;
         for (int t = 0; t < ntiles; ++t) {
             int mx = 0;
             for (int l = 0; l < kTile; ++l) mx = std::max(mx, its[(size_t)t * kTile + l]);
-            tile_iters += mx;
+            stats_.tile_iters += mx;
+            const double tile_bytes = (double)tn[t] * kTile * cb;
+            // kernel A: read u, p, write p' (3 passes); kernel B: read x, u, p', write x, u (5)
+            stats_.spmm_alg_bytes += mx * 3.0 * tile_bytes;
+            stats_.update_alg_bytes += mx * 5.0 * tile_bytes;
         }
-        stats_.tile_iters += tile_iters;
-        // kernel A: read u, p, write p' (3 passes); kernel B: read x, u, p', write x, u (5)
-        stats_.spmm_alg_bytes += tile_iters * 3.0 * tile_bytes;
-        stats_.update_alg_bytes += tile_iters * 5.0 * tile_bytes;
         // moments
-        const int r0 = L * M;
-        auto Sall = std::make_shared<DBuf<double>>((size_t)K * n * r0);
+        auto Sall = std::make_shared<DBuf<double>>(std::max<int64_t>(soff[K], 1));
         tm_.begin(T_MOMENTS);
-        HIPCHK(launch_moments(S.x, n, K, NH, L, M, d_coef.get(), Sall->get(), s_));
+        HIPCHK(launch_moments(S.x, S.geom, nmax, K, NH, L, M, d_coff.get(), d_cn.get(), d_soff.get(),
+                              d_coef.get(), Sall->get(), s_));
         tm_.end();
+        HIPCHK(hipStreamSynchronize(s_));
         // release the multivectors before the dense phase
         x.release();
         u.release();
@@ -558,13 +678,14 @@ class Solver {
         out.resize(K);
         for (int k = 0; k < K; ++k) {
             ContourOut& co = out[k];
-            co.id = ids[k];
+            co.id = jobs[k].id;
+            co.prob = jobs[k].prob;
             long mx = 0;
             double sum = 0.0;
             long cnt = 0;
             for (int j = 0; j < NH; ++j)
                 for (int l = 0; l < L; ++l) {
-                    const int v = its[((size_t)k * NH + j) * L + l];
+                    const int v = its[coff[k] + (size_t)j * L + l];
                     mx = std::max<long>(mx, v);
                     sum += v;
                     ++cnt;
@@ -572,25 +693,30 @@ class Solver {
             co.iters_max = mx;
             co.iters_mean = cnt ? sum / cnt : 0.0;
         }
-        rayleigh_ritz_batch(Sall->get(), K, r0, out);
+        rayleigh_ritz_batch(Sall->get(), soff, jobs, r0, out);
     }
 
-    // B-orthonormalise span(S_k) for every contour k of the pass and extract
-    // all Ritz pairs.  S_k is n x r0 row-major at Sall + k n r0.  Per-contour
-    // products are launched one contour at a time; the small dense solves
-    // (eigen-decompositions, Cholesky) run batched, one work-group per contour.
-    void rayleigh_ritz_batch(const double* Sall, int K, int r0, std::vector<ContourOut>& outs) {
-        const int64_t n = P_->d.n;
+    // B-orthonormalise span(S_k) for every job k of the pass and extract all
+    // Ritz pairs.  S_k is n_k x r0 row-major at Sall + soff[k].  Products run
+    // one job at a time on the job's rows of the pencil; the small dense
+    // solves (eigen-decompositions, Cholesky) run batched, one work-group per
+    // job.
+    void rayleigh_ritz_batch(const double* Sall, const std::vector<int64_t>& soff,
+                             const std::vector<Job>& jobs, int r0, std::vector<ContourOut>& outs) {
         const DevPencil& D = P_->d;
-        const size_t nr = (size_t)n * r0, rr2 = (size_t)r0 * r0;
-        DBuf<double> T(nr * K), Q1(nr * K), G(rr2 * K), U(rr2 * K), w((size_t)r0 * K), jw(rr2 * K);
-        DBuf<double> gw(gram_work_elems(n, r0, r0));
+        const int K = (int)jobs.size();
+        const size_t tot = (size_t)soff[K], rr2 = (size_t)r0 * r0;
+        int64_t nmax = 0;
+        for (const Job& j : jobs) nmax = std::max(nmax, j.n);
+        DBuf<double> T(tot), Q1(tot), G(rr2 * K), U(rr2 * K), w((size_t)r0 * K), jw(rr2 * K);
+        DBuf<double> gw(gram_work_elems(nmax, r0, r0));
         DBuf<int32_t> ks(K), st(K);
         // pass 1: SVQB on the B-Gram G = S^T B S
         for (int k = 0; k < K; ++k) {
-            const double* S = Sall + k * nr;
-            HIPCHK(launch_spmm_real(D, S, r0, r0, nullptr, T.get() + k * nr, s_));
-            gram(S, r0, T.get() + k * nr, r0, r0, r0, G.get() + k * rr2, gw);
+            const double* Sk = Sall + soff[k];
+            const int64_t nk = jobs[k].n;
+            HIPCHK(launch_spmm_real(D, Sk, r0, r0, nullptr, T.get() + soff[k], s_, jobs[k].row0, nk));
+            gram(Sk, r0, T.get() + soff[k], r0, nk, r0, r0, G.get() + k * rr2, gw);
             HIPCHK(launch_symmetrise(G.get() + k * rr2, r0, s_));
         }
         tm_.begin(T_DENSE);
@@ -621,10 +747,10 @@ class Solver {
             co.rho.assign(keep[k], 0.0);
             kmax = std::max(kmax, keep[k]);
         }
-        auto Xbuf = std::make_shared<DBuf<double>>(std::max<size_t>(nr * K, 1));
+        auto Xbuf = std::make_shared<DBuf<double>>(std::max<size_t>(tot, 1));
         for (int k = 0; k < K; ++k) {
             outs[k].Xbuf = Xbuf;
-            outs[k].X = Xbuf->get() + k * nr;
+            outs[k].X = Xbuf->get() + soff[k];
         }
         if (kmax == 0) return;
         HIPCHK(hipMemcpyAsync(ks.get(), keep.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice, s_));
@@ -633,10 +759,11 @@ class Solver {
         for (int k = 0; k < K; ++k) {
             const int kk = keep[k];
             if (!kk) continue;
+            const int64_t nk = jobs[k].n;
             HIPCHK(launch_svqb_scale(U.get() + k * rr2, w.get() + (size_t)k * r0, r0, kk, Tsc.get() + k * rr2, s_));
-            gemm(Sall + k * nr, r0, Tsc.get() + k * rr2, kk, n, r0, kk, Q1.get() + k * nr, kk);
-            HIPCHK(launch_spmm_real(D, Q1.get() + k * nr, kk, kk, nullptr, T.get() + k * nr, s_));
-            gram(Q1.get() + k * nr, kk, T.get() + k * nr, kk, kk, kk, G.get() + k * rr2, gw);
+            gemm(Sall + soff[k], r0, Tsc.get() + k * rr2, kk, nk, r0, kk, Q1.get() + soff[k], kk);
+            HIPCHK(launch_spmm_real(D, Q1.get() + soff[k], kk, kk, nullptr, T.get() + soff[k], s_, jobs[k].row0, nk));
+            gram(Q1.get() + soff[k], kk, T.get() + soff[k], kk, nk, kk, kk, G.get() + k * rr2, gw);
             HIPCHK(launch_symmetrise(G.get() + k * rr2, kk, s_));
         }
         tm_.begin(T_DENSE);
@@ -644,15 +771,16 @@ class Solver {
         tm_.end();
         check_status(st, K, "B-Gram of the SVQB basis");
         // Q = Q1 L^-T (B-orthonormal); Rayleigh-Ritz matrices
-        DBuf<double> Q(nr * K), AQ(nr * K), TA(rr2 * K), TB(rr2 * K);
+        DBuf<double> Q(tot), AQ(tot), TA(rr2 * K), TB(rr2 * K);
         for (int k = 0; k < K; ++k) {
             const int kk = keep[k];
             if (!kk) continue;
-            double* Qk = Q.get() + k * nr;
-            gemm(Q1.get() + k * nr, kk, LT.get() + k * rr2, kk, n, kk, kk, Qk, kk);
-            HIPCHK(launch_spmm_real(D, Qk, kk, kk, AQ.get() + k * nr, T.get() + k * nr, s_));
-            gram(Qk, kk, AQ.get() + k * nr, kk, kk, kk, TA.get() + k * rr2, gw);
-            gram(Qk, kk, T.get() + k * nr, kk, kk, kk, TB.get() + k * rr2, gw);
+            const int64_t nk = jobs[k].n;
+            double* Qk = Q.get() + soff[k];
+            gemm(Q1.get() + soff[k], kk, LT.get() + k * rr2, kk, nk, kk, kk, Qk, kk);
+            HIPCHK(launch_spmm_real(D, Qk, kk, kk, AQ.get() + soff[k], T.get() + soff[k], s_, jobs[k].row0, nk));
+            gram(Qk, kk, AQ.get() + soff[k], kk, nk, kk, kk, TA.get() + k * rr2, gw);
+            gram(Qk, kk, T.get() + soff[k], kk, nk, kk, kk, TB.get() + k * rr2, gw);
             HIPCHK(launch_symmetrise(TA.get() + k * rr2, kk, s_));
             HIPCHK(launch_symmetrise(TB.get() + k * rr2, kk, s_));
         }
@@ -681,11 +809,12 @@ class Solver {
         for (int k = 0; k < K; ++k) {
             const int kk = keep[k];
             if (!kk) continue;
+            const int64_t nk = jobs[k].n;
             double* Xk = outs[k].X;
-            gemm(Q.get() + k * nr, kk, C1.get() + k * rr2, kk, n, kk, kk, Xk, kk);
+            gemm(Q.get() + soff[k], kk, C1.get() + k * rr2, kk, nk, kk, kk, Xk, kk);
             // residuals with the pencil itself
-            HIPCHK(launch_spmm_real(D, Xk, kk, kk, AQ.get() + k * nr, T.get() + k * nr, s_));
-            HIPCHK(launch_resid_norms(AQ.get() + k * nr, T.get() + k * nr, Xk, th.get() + (size_t)k * r0, n, kk,
+            HIPCHK(launch_spmm_real(D, Xk, kk, kk, AQ.get() + soff[k], T.get() + soff[k], s_, jobs[k].row0, nk));
+            HIPCHK(launch_resid_norms(AQ.get() + soff[k], T.get() + soff[k], Xk, th.get() + (size_t)k * r0, nk, kk,
                                       num.get() + (size_t)k * r0, den.get() + (size_t)k * r0, rw.get(), s_));
         }
         std::vector<double> thh((size_t)r0 * K), nh((size_t)r0 * K), dh((size_t)r0 * K);
@@ -694,19 +823,21 @@ class Solver {
         HIPCHK(hipMemcpyAsync(dh.data(), den.get(), sizeof(double) * r0 * K, hipMemcpyDeviceToHost, s_));
         HIPCHK(hipStreamSynchronize(s_));
         tm_.flush();
-        for (int k = 0; k < K; ++k)
+        for (int k = 0; k < K; ++k) {
+            const double ainf = P_->h.prob_ainf[jobs[k].prob];
             for (int i = 0; i < keep[k]; ++i) {
                 outs[k].theta[i] = thh[(size_t)k * r0 + i];
-                outs[k].rho[i] = nh[(size_t)k * r0 + i] / (D.a_inf * std::max(dh[(size_t)k * r0 + i], 1e-300));
+                outs[k].rho[i] = nh[(size_t)k * r0 + i] / (ainf * std::max(dh[(size_t)k * r0 + i], 1e-300));
             }
+        }
     }
 
-    void gram(const double* X, int64_t ld1, const double* Y, int64_t ld2, int64_t k1, int64_t k2,
-              double* G, DBuf<double>& work) {
+    void gram(const double* X, int64_t ld1, const double* Y, int64_t ld2, int64_t n, int64_t k1,
+              int64_t k2, double* G, DBuf<double>& work) {
         tm_.begin(T_GRAM);
-        HIPCHK(launch_gram(X, ld1, Y, ld2, P_->d.n, k1, k2, G, work.get(), work.n, s_));
+        HIPCHK(launch_gram(X, ld1, Y, ld2, n, k1, k2, G, work.get(), work.n, s_));
         tm_.end();
-        gram_flops_ += 2.0 * P_->d.n * k1 * k2;
+        gram_flops_ += 2.0 * n * k1 * k2;
     }
     void gemm(const double* X, int64_t ldx, const double* T, int64_t ldt, int64_t n, int64_t k,
               int64_t m, double* C, int64_t ldc) {
@@ -728,17 +859,19 @@ class Solver {
 
     gep_pencil* P_;
     SolveCfg c_;
-    hipStream_t s_;
+    hipStream_t s_ = nullptr;
+    hipStream_t own_ = nullptr;
     Timer tm_;
     Stats stats_;
     int32_t* counts_h_ = nullptr;
     double gram_flops_ = 0.0, gemm_flops_ = 0.0;
 };
 
-static size_t bytes_per_contour(int64_t n, int NH, int L, int M) {
-    const size_t W = (size_t)NH * L;
+static size_t bytes_per_job(int64_t n, int NH, int L, int M, bool mixed) {
+    const size_t W = (size_t)((NH * L + kTile - 1) / kTile) * kTile;
     const size_t r = (size_t)L * M;
-    return (size_t)n * W * 16 * 4 + (size_t)n * r * 8 * 8 + (size_t)W * 128;
+    const size_t mv = mixed ? (size_t)n * W * (16 + 8 * 4) : (size_t)n * W * 16 * 4;
+    return mv + (size_t)n * r * 8 * 9 + (size_t)W * 160 + (size_t)W / kTile * 2048 * kTile * 24;
 }
 
 static std::string json_stats(const Solver& s, double wall_ms, const std::vector<ContourOut>& cos,
@@ -750,6 +883,7 @@ static std::string json_stats(const Solver& s, double wall_ms, const std::vector
       << ",\"columns\":" << s.stats_.columns << ",\"waves\":" << s.stats_.waves
       << ",\"spmm_launches\":" << s.stats_.spmm_launches
       << ",\"replacements\":" << s.stats_.replacements
+      << ",\"graph_captures\":" << s.stats_.graph_captures
       << ",\"spmm_alg_bytes\":" << s.stats_.spmm_alg_bytes
       << ",\"update_alg_bytes\":" << s.stats_.update_alg_bytes
       << ",\"replace_alg_bytes\":" << s.stats_.replace_alg_bytes
@@ -763,7 +897,8 @@ static std::string json_stats(const Solver& s, double wall_ms, const std::vector
     o << "},\"contours\":[";
     for (size_t i = 0; i < cos.size(); ++i) {
         const auto& c = cos[i];
-        o << (i ? "," : "") << "{\"id\":" << c.id << ",\"passes\":" << c.passes << ",\"rank\":[";
+        o << (i ? "," : "") << "{\"id\":" << c.id << ",\"problem\":" << c.prob << ",\"passes\":" << c.passes
+          << ",\"rank\":[";
         for (size_t j = 0; j < c.rank.size(); ++j) o << (j ? "," : "") << c.rank[j];
         o << "],\"saturated\":" << (c.saturated ? "true" : "false") << ",\"smin_ratio\":" << c.smin_ratio
           << ",\"iters_max\":" << c.iters_max << ",\"iters_mean\":" << c.iters_mean << "}";
@@ -772,16 +907,21 @@ static std::string json_stats(const Solver& s, double wall_ms, const std::vector
     return o.str();
 }
 
-static int solve_impl(gep_pencil* P, const gep_contour* contours, int K, const SolveCfg& cfg,
-                      gep_result** out) {
+// Solve every problem of a (possibly single-element) batch.  contours[p] and
+// n_contours[p] describe problem p's circles.  out[p] receives its result.
+static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* const* contours,
+                            const int* n_contours, const SolveCfg& cfg, gep_result** out) {
     auto t0 = std::chrono::steady_clock::now();
-    const int64_t n = P->d.n;
+    const HostPencil& H = P->h;
+    const int64_t ntot = P->d.n;
     Solver sv(P, cfg);
-    hipStream_t s = (hipStream_t)cfg.o.stream;
-    // V and B V
+    hipStream_t s = sv.s_;
     const int L = cfg.L;
-    DBuf<double> V((size_t)n * L), BV((size_t)n * L);
+    // V (problem p: counter-based stream of seed + p on its own rows) and B V
+    DBuf<double> V((size_t)ntot * L), BV((size_t)ntot * L);
     if (cfg.o.rhs) {
+        if (n_problems != 1) fail(GEP_EINVAL, "an explicit right-hand-side block needs a single problem");
+        const int64_t n = ntot;
         std::vector<double> vc((size_t)n * L), vr((size_t)n * L);
         if (cfg.o.inputs_on_device)
             HIPCHK(hipMemcpy(vc.data(), cfg.o.rhs, sizeof(double) * n * L, hipMemcpyDeviceToHost));
@@ -792,31 +932,51 @@ static int solve_impl(gep_pencil* P, const gep_contour* contours, int K, const S
         HIPCHK(hipMemcpyAsync(V.get(), vr.data(), sizeof(double) * n * L, hipMemcpyHostToDevice, s));
         HIPCHK(hipStreamSynchronize(s));
     } else {
-        HIPCHK(launch_gaussian(cfg.o.seed, n, L, V.get(), s));
+        for (int p = 0; p < n_problems; ++p)
+            HIPCHK(launch_gaussian(cfg.o.seed + (uint64_t)p, H.prob_n[p], L, V.get() + H.prob_row0[p] * L, s));
     }
     HIPCHK(launch_spmm_real(P->d, V.get(), L, L, nullptr, BV.get(), s));
-    // memory plan: waves of contours
+    V.release();
+    // jobs and memory plan: waves of jobs in order
+    std::vector<Job> all;
+    for (int p = 0; p < n_problems; ++p)
+        for (int k = 0; k < n_contours[p]; ++k) {
+            Job j;
+            j.c = contours[p][k];
+            j.prob = p;
+            j.id = k;
+            j.row0 = H.prob_row0[p];
+            j.n = H.prob_n[p];
+            j.bsrc0 = H.prob_row0[p] * L;
+            all.push_back(j);
+        }
     size_t freeb = 0, totalb = 0;
     HIPCHK(hipMemGetInfo(&freeb, &totalb));
-    double budget = cfg.o.mem_limit_bytes > 0 ? cfg.o.mem_limit_bytes : 0.85 * (double)freeb;
-    const size_t per = bytes_per_contour(n, cfg.NH, L, cfg.M);
-    int per_wave = (int)std::min<double>(K, std::floor(budget / (double)per));
-    if (per_wave < 1) fail(GEP_ENOMEM, "one contour needs " + std::to_string(per) + " bytes of device memory");
-    std::vector<ContourOut> finals(K);
-    for (int k0 = 0; k0 < K; k0 += per_wave) {
-        const int k1 = std::min(K, k0 + per_wave);
-        std::vector<gep_contour> cs(contours + k0, contours + k1);
-        std::vector<int> ids;
-        for (int k = k0; k < k1; ++k) ids.push_back(k);
+    const double budget = cfg.o.mem_limit_bytes > 0 ? cfg.o.mem_limit_bytes : 0.85 * (double)freeb;
+    const bool mixed = cfg.o.precision == GEP_MIXED;
+    std::vector<ContourOut> finals(all.size());
+    size_t k0 = 0;
+    while (k0 < all.size()) {
+        size_t k1 = k0;
+        double used = 0.0;
+        while (k1 < all.size()) {
+            const double need = (double)bytes_per_job(all[k1].n, cfg.NH, L, cfg.M, mixed);
+            if (k1 > k0 && used + need > budget) break;
+            used += need;
+            ++k1;
+        }
+        if (used > budget)
+            fail(GEP_ENOMEM, "one contour needs " + std::to_string((long long)used) + " bytes of device memory");
+        std::vector<Job> jobs(all.begin() + k0, all.begin() + k1);
         std::vector<ContourOut> res;
         sv.stats_.waves += 1;
-        sv.run_pass(cs, ids, BV.get(), L, true, L, cfg.M, res);
+        sv.run_pass(jobs, BV.get(), L, L, cfg.M, res);
         for (auto& r : res) r.passes = 1;
-        // refinement: contours whose kept pairs miss tol
+        // refinement: jobs whose kept pairs miss tol (FEAST-type pass, V <- all Ritz vectors)
         for (int pass = 1; pass <= cfg.o.max_refine; ++pass) {
             std::vector<int> redo;
             for (size_t i = 0; i < res.size(); ++i) {
-                const gep_contour& c = cs[i];
+                const gep_contour& c = jobs[i].c;
                 bool bad = false;
                 for (int j = 0; j < res[i].r; ++j)
                     if (res[i].theta[j] >= c.keep_lo && res[i].theta[j] < c.keep_hi && !(res[i].rho[j] <= cfg.tol))
@@ -826,25 +986,28 @@ static int solve_impl(gep_pencil* P, const gep_contour* contours, int K, const S
             if (redo.empty()) break;
             int L2 = 0;
             for (int i : redo) L2 = std::max(L2, res[i].r);
-            const int Kr = (int)redo.size();
-            DBuf<double> V2((size_t)n * Kr * L2), BV2((size_t)n * Kr * L2);
-            HIPCHK(hipMemsetAsync(V2.get(), 0, sizeof(double) * n * Kr * L2, s));
-            for (int a = 0; a < Kr; ++a) {
-                const ContourOut& co = res[redo[a]];
-                HIPCHK(hipMemcpy2DAsync(V2.get() + (size_t)a * L2, sizeof(double) * Kr * L2, co.X,
-                                        sizeof(double) * co.r, sizeof(double) * co.r, n,
-                                        hipMemcpyDeviceToDevice, s));
-            }
-            HIPCHK(launch_spmm_real(P->d, V2.get(), (int64_t)Kr * L2, (int64_t)Kr * L2, nullptr, BV2.get(), s));
-            std::vector<gep_contour> cs2;
-            std::vector<int> ids2;
+            // per-job row-major blocks n_k x L2 (columns beyond the job's rank stay zero)
+            std::vector<Job> jobs2;
+            int64_t off = 0;
             for (int i : redo) {
-                cs2.push_back(cs[i]);
-                ids2.push_back(ids[i]);
+                Job j = jobs[i];
+                j.bsrc0 = off;
+                off += j.n * L2;
+                jobs2.push_back(j);
+            }
+            DBuf<double> V2((size_t)off), BV2((size_t)off);
+            HIPCHK(hipMemsetAsync(V2.get(), 0, sizeof(double) * off, s));
+            for (size_t a = 0; a < redo.size(); ++a) {
+                const ContourOut& co = res[redo[a]];
+                const Job& j = jobs2[a];
+                if (co.r > 0)
+                    HIPCHK(hipMemcpy2DAsync(V2.get() + j.bsrc0, sizeof(double) * L2, co.X, sizeof(double) * co.r,
+                                            sizeof(double) * co.r, j.n, hipMemcpyDeviceToDevice, s));
+                HIPCHK(launch_spmm_real(P->d, V2.get() + j.bsrc0, L2, L2, nullptr, BV2.get() + j.bsrc0, s, j.row0, j.n));
             }
             std::vector<ContourOut> res2;
-            sv.run_pass(cs2, ids2, BV2.get(), (int64_t)Kr * L2, false, L2, 1, res2);
-            for (int a = 0; a < Kr; ++a) {
+            sv.run_pass(jobs2, BV2.get(), L2, L2, 1, res2);
+            for (size_t a = 0; a < redo.size(); ++a) {
                 ContourOut& dst = res[redo[a]];
                 ContourOut& src = res2[a];
                 src.passes = dst.passes + 1;
@@ -858,80 +1021,96 @@ static int solve_impl(gep_pencil* P, const gep_contour* contours, int K, const S
             }
         }
         for (size_t i = 0; i < res.size(); ++i) finals[k0 + i] = res[i];
+        k0 = k1;
     }
-    // selection, gather, merge
-    struct Pair {
-        double lam, rho;
-        int cid;
-        int col;
-        int contour_slot;
-    };
-    std::vector<Pair> pairs;
-    std::vector<std::vector<double>> vecs(K);
-    bool saturated = false;
-    for (int k = 0; k < K; ++k) {
-        ContourOut& co = finals[k];
-        saturated |= co.saturated;
-        std::vector<int32_t> sel;
-        for (int j = 0; j < co.r; ++j)
-            if (co.theta[j] >= contours[k].keep_lo && co.theta[j] < contours[k].keep_hi) sel.push_back(j);
-        if (sel.empty()) continue;
-        DBuf<int32_t> dsel(sel.size());
-        DBuf<double> cm((size_t)n * sel.size());
-        HIPCHK(hipMemcpyAsync(dsel.get(), sel.data(), sizeof(int32_t) * sel.size(), hipMemcpyHostToDevice, s));
-        HIPCHK(launch_gather_cols(co.X, n, co.r, dsel.get(), (int)sel.size(), cm.get(), s));
-        vecs[k].resize((size_t)n * sel.size());
-        HIPCHK(hipMemcpyAsync(vecs[k].data(), cm.get(), sizeof(double) * n * sel.size(), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        for (size_t a = 0; a < sel.size(); ++a)
-            pairs.push_back({co.theta[sel[a]], co.rho[sel[a]], k, (int)a, k});
-    }
-    std::stable_sort(pairs.begin(), pairs.end(), [](const Pair& a, const Pair& b) { return a.lam < b.lam; });
-    // de-duplicate pairs found by different contours (same value within 1e-8
-    // relative and |x_a^T B x_b| >= 0.9): keep the smaller residual
-    const HostPencil& H = P->h;
-    auto bdot = [&](const double* xa, const double* xb) {
-        double sacc = 0.0;
-        for (int64_t i = 0; i < n; ++i) {
-            double t = 0.0;
-            for (int32_t e = H.rowptr[i]; e < H.rowptr[i + 1]; ++e) t += H.b[e] * xb[H.colind[e]];
-            sacc += xa[i] * t;
+    // per problem: selection, gather, merge
+    const double wall_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    int worst = GEP_OK;
+    size_t base = 0;
+    for (int p = 0; p < n_problems; ++p) {
+        const int K = n_contours[p];
+        const int64_t n = H.prob_n[p];
+        const int64_t row0 = H.prob_row0[p];
+        struct Pair {
+            double lam, rho;
+            int cid;
+            int col;
+        };
+        std::vector<Pair> pairs;
+        std::vector<std::vector<double>> vecs(K);
+        bool saturated = false;
+        std::vector<ContourOut> mine(finals.begin() + base, finals.begin() + base + K);
+        for (int k = 0; k < K; ++k) {
+            ContourOut& co = mine[k];
+            const gep_contour& cc = contours[p][k];
+            saturated |= co.saturated;
+            std::vector<int32_t> sel;
+            for (int j = 0; j < co.r; ++j)
+                if (co.theta[j] >= cc.keep_lo && co.theta[j] < cc.keep_hi) sel.push_back(j);
+            if (sel.empty()) continue;
+            DBuf<int32_t> dsel(sel.size());
+            DBuf<double> cm((size_t)n * sel.size());
+            HIPCHK(hipMemcpyAsync(dsel.get(), sel.data(), sizeof(int32_t) * sel.size(), hipMemcpyHostToDevice, s));
+            HIPCHK(launch_gather_cols(co.X, n, co.r, dsel.get(), (int)sel.size(), cm.get(), s));
+            vecs[k].resize((size_t)n * sel.size());
+            HIPCHK(hipMemcpyAsync(vecs[k].data(), cm.get(), sizeof(double) * n * sel.size(), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (size_t a = 0; a < sel.size(); ++a) pairs.push_back({co.theta[sel[a]], co.rho[sel[a]], k, (int)a});
         }
-        return sacc;
-    };
-    std::vector<char> drop(pairs.size(), 0);
-    for (size_t a = 0; a < pairs.size(); ++a) {
-        if (drop[a]) continue;
-        for (size_t b = a + 1; b < pairs.size(); ++b) {
-            if (pairs[b].lam - pairs[a].lam > 1e-8 * std::max(std::fabs(pairs[a].lam), std::fabs(pairs[b].lam))) break;
-            if (drop[b] || pairs[b].cid == pairs[a].cid) continue;
-            const double* xa = vecs[pairs[a].cid].data() + (size_t)pairs[a].col * n;
-            const double* xb = vecs[pairs[b].cid].data() + (size_t)pairs[b].col * n;
-            if (std::fabs(bdot(xa, xb)) >= 0.9) drop[pairs[b].rho >= pairs[a].rho ? b : a] = 1;
+        std::stable_sort(pairs.begin(), pairs.end(), [](const Pair& a, const Pair& b) { return a.lam < b.lam; });
+        // de-duplicate pairs found by different contours (same value within 1e-8
+        // relative and |x_a^T B x_b| >= 0.9): keep the smaller residual
+        auto bdot = [&](const double* xa, const double* xb) {
+            double sacc = 0.0;
+            for (int64_t i = 0; i < n; ++i) {
+                double t = 0.0;
+                for (int32_t e = H.rowptr[row0 + i]; e < H.rowptr[row0 + i + 1]; ++e)
+                    t += H.b[e] * xb[H.colind[e] - row0];
+                sacc += xa[i] * t;
+            }
+            return sacc;
+        };
+        std::vector<char> drop(pairs.size(), 0);
+        for (size_t a = 0; a < pairs.size(); ++a) {
+            if (drop[a]) continue;
+            for (size_t b = a + 1; b < pairs.size(); ++b) {
+                if (pairs[b].lam - pairs[a].lam > 1e-8 * std::max(std::fabs(pairs[a].lam), std::fabs(pairs[b].lam))) break;
+                if (drop[b] || pairs[b].cid == pairs[a].cid) continue;
+                const double* xa = vecs[pairs[a].cid].data() + (size_t)pairs[a].col * n;
+                const double* xb = vecs[pairs[b].cid].data() + (size_t)pairs[b].col * n;
+                if (std::fabs(bdot(xa, xb)) >= 0.9) drop[pairs[b].rho >= pairs[a].rho ? b : a] = 1;
+            }
         }
+        auto* R = new gep_result();
+        R->n = n;
+        bool noconv = false;
+        for (size_t a = 0; a < pairs.size(); ++a) {
+            if (drop[a]) continue;
+            const Pair& pr = pairs[a];
+            R->evals.push_back(pr.lam);
+            R->resid.push_back(pr.rho);
+            R->cid.push_back(pr.cid);
+            const bool ok = pr.rho <= cfg.tol;
+            noconv |= !ok;
+            R->conv.push_back(ok ? 1 : 0);
+            const double* x = vecs[pr.cid].data() + (size_t)pr.col * n;
+            R->evecs.insert(R->evecs.end(), x, x + n);
+        }
+        R->m = (int64_t)R->evals.size();
+        R->stats = json_stats(sv, wall_solve, mine, cfg.o.precision);
+        out[p] = R;
+        const int st = noconv ? GEP_WNOCONV : (saturated ? GEP_WSATURATED : GEP_OK);
+        if (st == GEP_WNOCONV || (st == GEP_WSATURATED && worst == GEP_OK)) worst = st;
+        base += K;
     }
-    auto* R = new gep_result();
-    R->n = n;
-    bool noconv = false;
-    for (size_t a = 0; a < pairs.size(); ++a) {
-        if (drop[a]) continue;
-        const Pair& p = pairs[a];
-        R->evals.push_back(p.lam);
-        R->resid.push_back(p.rho);
-        R->cid.push_back(p.cid);
-        const bool ok = p.rho <= cfg.tol;
-        noconv |= !ok;
-        R->conv.push_back(ok ? 1 : 0);
-        const double* x = vecs[p.cid].data() + (size_t)p.col * n;
-        R->evecs.insert(R->evecs.end(), x, x + n);
-    }
-    R->m = (int64_t)R->evals.size();
-    const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    R->stats = json_stats(sv, wall, finals, cfg.o.precision);
-    *out = R;
-    if (noconv) return GEP_WNOCONV;
-    if (saturated) return GEP_WSATURATED;
-    return GEP_OK;
+    return worst;
+}
+
+static int solve_impl(gep_pencil* P, const gep_contour* contours, int K, const SolveCfg& cfg,
+                      gep_result** out) {
+    const gep_contour* cs[1] = {contours};
+    int nk[1] = {K};
+    return solve_batch_impl(P, 1, cs, nk, cfg, out);
 }
 
 }  // namespace gep
@@ -954,6 +1133,8 @@ void gep_opts_default(gep_opts* o) {
     o->mem_limit_bytes = 0.0;
     o->timing = 0;
     o->rows_per_block = 0;
+    o->verbose = 0;
+    o->use_graph = 1;
 }
 
 const char* gep_strerror(int st) {
@@ -1060,6 +1241,52 @@ int gep_ci_solve(const gep_csr* A, const gep_csr* B, const gep_contour* contours
     if (st) return st;
     st = gep_ci_solve_pencil(P, contours, n_contours, n_nodes, moments, block, tol, &o, out);
     gep_pencil_free(P);
+    return st;
+}
+
+int gep_ci_solve_batch(int n_problems, const gep_csr* A, const gep_csr* B,
+                       const gep_contour* const* contours, const int* n_contours, int n_nodes,
+                       int moments, int block, double tol, const gep_opts* opts, gep_result** out) {
+    if (!out || n_problems <= 0 || !A || !B || !contours || !n_contours) {
+        gep::set_error("bad batch arguments");
+        return GEP_EINVAL;
+    }
+    for (int p = 0; p < n_problems; ++p) out[p] = nullptr;
+    gep_opts o;
+    if (opts) o = *opts; else gep_opts_default(&o);
+    for (int p = 0; p < n_problems; ++p) {
+        int st = validate_problem(contours[p], n_contours[p], n_nodes, moments, block, tol, &o);
+        if (st) {
+            gep::set_error("problem " + std::to_string(p) + ": " + gep::g_err);
+            return st;
+        }
+    }
+    auto* P = new gep_pencil();
+    gep::SolveCfg cfg;
+    cfg.N = n_nodes;
+    cfg.NH = n_nodes / 2;
+    cfg.M = moments;
+    cfg.L = block;
+    cfg.tol = tol;
+    cfg.o = o;
+    int st = GEP_OK;
+    try {
+        for (int p = 0; p < n_problems; ++p) {
+            gep::HostPencil h;
+            gep::pack(&A[p], &B[p], o.inputs_on_device != 0, h);
+            gep::append_pencil(P->h, h);
+        }
+        if (P->h.nnz >= (1ll << 31) - 1) gep::fail(GEP_EINVAL, "batch nnz >= 2^31");
+        gep::upload(P->h, P);
+        st = gep::solve_batch_impl(P, n_problems, contours, n_contours, cfg, out);
+    } catch (const gep::Fail& f) {
+        for (int p = 0; p < n_problems; ++p) {
+            delete out[p];
+            out[p] = nullptr;
+        }
+        st = f.code;
+    }
+    delete P;
     return st;
 }
 

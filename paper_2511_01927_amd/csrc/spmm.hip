@@ -142,8 +142,8 @@ hipError_t launch_spmm_c32(const DevPencil& P, const double2* shifts, const floa
 // 64-column chunk.
 __global__ __launch_bounds__(kBlock) void k_spmm_real(const int32_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ colind,
-                                                      const double2* __restrict__ ab, int n,
-                                                      const double* __restrict__ X, int k,
+                                                      const double2* __restrict__ ab, int row0,
+                                                      int n, const double* __restrict__ X, int k,
                                                       int64_t ld, double* __restrict__ YA,
                                                       double* __restrict__ YB, int nrb, int rpb) {
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
@@ -158,11 +158,11 @@ __global__ __launch_bounds__(kBlock) void k_spmm_real(const int32_t* __restrict_
     const int r0 = rb * rpb;
     const int r1 = min(n, r0 + rpb);
     for (int i = r0 + wave; i < r1; i += kWaves) {
-        const int k0 = rowptr[i];
-        const int k1 = rowptr[i + 1];
+        const int k0 = rowptr[row0 + i];
+        const int k1 = rowptr[row0 + i + 1];
         double sa = 0.0, sb = 0.0;
         for (int e = k0; e < k1; ++e) {
-            const int j = colind[e];
+            const int j = colind[e] - row0;
             const double2 v = ab[e];
             const double x = ok ? X[(size_t)j * ld + col] : 0.0;
             sa = fma(v.x, x, sa);
@@ -176,16 +176,16 @@ __global__ __launch_bounds__(kBlock) void k_spmm_real(const int32_t* __restrict_
 }
 
 hipError_t launch_spmm_real(const DevPencil& P, const double* X, int64_t k, int64_t ld,
-                            double* YA, double* YB, hipStream_t s) {
-    if (k <= 0 || P.n <= 0) return hipSuccess;
-    const int n = (int)P.n;
+                            double* YA, double* YB, hipStream_t s, int64_t row0, int64_t nloc) {
+    const int n = (int)(nloc < 0 ? P.n : nloc);
+    if (k <= 0 || n <= 0) return hipSuccess;
     const int nchunks = (int)((k + kTile - 1) / kTile);
     int nrb = (2048 + nchunks - 1) / nchunks;
     nrb = max(1, min(nrb, (n + 15) / 16));
     const int rpb = (n + nrb - 1) / nrb;
     const int grid = pad8(nchunks * nrb);
-    hipLaunchKernelGGL(k_spmm_real, dim3(grid), dim3(kBlock), 0, s, P.rowptr, P.colind, P.ab, n,
-                       X, (int)k, ld, YA, YB, nrb, rpb);
+    hipLaunchKernelGGL(k_spmm_real, dim3(grid), dim3(kBlock), 0, s, P.rowptr, P.colind, P.ab,
+                       (int)row0, n, X, (int)k, ld, YA, YB, nrb, rpb);
     return hipGetLastError();
 }
 

@@ -43,7 +43,8 @@ class gep_opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("precision", C.c_int), ("max_refine", C.c_int),
                 ("solve_tol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int),
                 ("stream", C.c_void_p), ("inputs_on_device", C.c_int), ("rhs", C.c_void_p),
-                ("mem_limit_bytes", C.c_double), ("timing", C.c_int), ("rows_per_block", C.c_int)]
+                ("mem_limit_bytes", C.c_double), ("timing", C.c_int), ("rows_per_block", C.c_int),
+                ("verbose", C.c_int), ("use_graph", C.c_int)]
 
 
 # every symbol declared in include/gep_ci.h
@@ -52,7 +53,7 @@ EXPORTS = [
     "gep_result_stats", "gep_result_free", "gep_strerror", "gep_last_error",
     "gep_pencil_create", "gep_pencil_free", "gep_pencil_info", "gep_ci_solve_pencil",
     "gep_spmm_shifted", "gep_spmm_shifted_f32", "gep_spmm_real", "gep_gram", "gep_gemm_tall",
-    "gep_sym_eig", "gep_gaussian_block",
+    "gep_sym_eig", "gep_gaussian_block", "gep_ci_solve_batch",
 ]
 
 _lib = None
@@ -90,6 +91,9 @@ def load():
         "gep_gemm_tall": (i32, [P, i64, P, i64, i64, i64, i64, P, i64, P]),
         "gep_sym_eig": (i32, [P, P, P, i64, i32, P]),
         "gep_gaussian_block": (i32, [C.c_uint64, i64, i64, P, P]),
+        "gep_ci_solve_batch": (i32, [i32, C.POINTER(gep_csr), C.POINTER(gep_csr),
+                                     C.POINTER(C.POINTER(gep_contour)), C.POINTER(C.c_int), i32, i32,
+                                     i32, dbl, C.POINTER(gep_opts), C.POINTER(P)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -151,7 +155,7 @@ def _contours(contours):
 
 
 def _opts(seed=1, precision="fp64", max_refine=1, solve_tol=1e-9, max_iter=100000, check_every=16,
-          stream=None, on_device=0, rhs=None, mem_limit_bytes=0.0, timing=False, rows_per_block=0):
+          stream=None, on_device=0, rhs=None, mem_limit_bytes=0.0, timing=False, rows_per_block=0, verbose=0, use_graph=True):
     lib = load()
     o = gep_opts()
     lib.gep_opts_default(C.byref(o))
@@ -175,6 +179,8 @@ def _opts(seed=1, precision="fp64", max_refine=1, solve_tol=1e-9, max_iter=10000
     o.mem_limit_bytes = mem_limit_bytes
     o.timing = 1 if timing else 0
     o.rows_per_block = rows_per_block
+    o.verbose = verbose
+    o.use_graph = 1 if use_graph else 0
     return o, keep
 
 
@@ -221,6 +227,27 @@ def gep_ci_solve(A, B, contours, n_nodes, moments, block, tol, **kw):
                           C.byref(o), C.byref(out))
     _check(st, allow_warn=True)
     return _collect(out, st)
+
+
+def gep_ci_solve_batch(problems, n_nodes, moments, block, tol, **kw):
+    """Solve a batch of independent pencils in one set of launches.
+
+    problems: list of (A, B, contours) with host scipy matrices.  Returns a
+    list of result dicts (as gep_ci_solve), problem p using seed + p.
+    """
+    lib = load()
+    P = len(problems)
+    hosts = [(_HostCSR(a), _HostCSR(b)) for a, b, _ in problems]
+    As = (gep_csr * P)(*[h[0].s for h in hosts])
+    Bs = (gep_csr * P)(*[h[1].s for h in hosts])
+    conts = [_contours(c) for _, _, c in problems]
+    cptr = (C.POINTER(gep_contour) * P)(*[C.cast(c[0], C.POINTER(gep_contour)) for c in conts])
+    nks = (C.c_int * P)(*[c[1] for c in conts])
+    o, keep = _opts(**kw)
+    outs = (C.c_void_p * P)()
+    st = lib.gep_ci_solve_batch(P, As, Bs, cptr, nks, n_nodes, moments, block, tol, C.byref(o), outs)
+    _check(st, allow_warn=True)
+    return [_collect(C.c_void_p(outs[p]), st) for p in range(P)]
 
 
 class Pencil:

@@ -172,3 +172,35 @@ def test_mixed_variable_coefficient_2d_vs_oracle(lib):
     lam, X = _oracle_refs(w)
     assert_pairs_match(got, lam, X, w.B)
     assert got["stats"]["replacements"] > 0
+
+
+def test_batch_of_uneven_pencils_vs_oracle(lib):
+    """gep_ci_solve_batch: pencils of different sizes share the COCG launches;
+    problem p draws V from seed + p and must match its own oracle solve."""
+    w1 = configs.config_fem1d(n=400, first=31, last=40, n_nodes=16, moments=4, block=16, seed=11)
+    w2 = _var2d(nx=30, ny=27, seed=4, first=21, last=40, k=2)
+    w3 = configs.config_fem1d(n=900, first=51, last=62, n_nodes=16, moments=4, block=16, seed=11)
+    probs = [(w.A, w.B, w.contours) for w in (w1, w2, w3)]
+    got = lib.gep_ci_solve_batch(probs, 16, 4, 16, 1e-8, seed=11)
+    for p, w in enumerate((w1, w2, w3)):
+        ref = oracle.oracle_ci_solve(w.A, w.B, w.contours, 16, 4, 16, 1e-8, seed=11 + p)
+        assert_pairs_match(got[p], ref["evals"], ref["evecs"], w.B)
+        assert all(c["problem"] == p for c in got[p]["stats"]["contours"])
+
+
+def test_graph_replay_equals_eager(lib):
+    """Chunks of COCG iterations replayed from captured HIP graphs give the
+    same result as eager launches (same kernels, grids and reductions)."""
+    import torch
+    w = _var2d(nx=32, ny=30, seed=6, first=31, last=60, k=2)
+    s = torch.cuda.Stream()
+    eager = lib.gep_ci_solve(w.A, w.B, w.contours, 32, 4, 16, 1e-8, seed=5, use_graph=False, stream=s)
+    torch.cuda.synchronize()
+    graph = lib.gep_ci_solve(w.A, w.B, w.contours, 32, 4, 16, 1e-8, seed=5, use_graph=True, stream=s)
+    torch.cuda.synchronize()
+    again = lib.gep_ci_solve(w.A, w.B, w.contours, 32, 4, 16, 1e-8, seed=5, use_graph=True)
+    assert graph["stats"]["graph_captures"] > 0
+    assert np.array_equal(eager["evals"], graph["evals"])
+    assert np.array_equal(eager["resid"], graph["resid"])
+    assert np.array_equal(eager["evals"], again["evals"])
+    assert eager["stats"]["cocg_iters"] == graph["stats"]["cocg_iters"]

@@ -98,3 +98,44 @@ def fem1d_2000() -> Workload:
 
 def q1_2d_300() -> Workload:
     return config_q1_2d()
+
+
+def weyl_index_to_lambda(kappa_nodes: np.ndarray, index: float, dim: int = 3) -> float:
+    """Invert Weyl's law for -div(kappa grad u) = lambda u on the unit box.
+
+    N(lambda) ~ c_d lambda^{d/2} * mean(kappa^{-d/2}) with c_3 = 1/(6 pi^2),
+    c_2 = 1/(4 pi).  Used only to place target windows on variable-coefficient
+    pencils whose spectrum has no closed form.
+    """
+    if dim == 3:
+        c = 1.0 / (6.0 * np.pi ** 2)
+    else:
+        c = 1.0 / (4.0 * np.pi)
+    m = float(np.mean(kappa_nodes ** (-dim / 2.0)))
+    return float((index / (c * m)) ** (2.0 / dim))
+
+
+def config_fd7_3d(m: int = 64, first: int = 2000, last: int = 2500, k: int = 10,
+                  alpha: float = 0.1, n_nodes: int = 32, moments: int = 4, block: int = 32,
+                  sigma: float = 1.0, field_seed: int = 2003, seed: int = 1003) -> Workload:
+    """7-point FD diffusion pencil on m^3 nodes, log-normal kappa, lumped mass B = h^3 I.
+
+    The window covers roughly the eigenvalue indices first..last by Weyl's law
+    (the actual count is whatever the pencil has there) and is split into k
+    uniform circles.
+    """
+    g = pencils.grf((m + 2,) * 3, seed=field_seed, sigma=sigma)
+    kap = np.exp(g)
+    A, B = pencils.fd7_3d(m, kap)
+    lo = weyl_index_to_lambda(kap, first)
+    hi = weyl_index_to_lambda(kap, last)
+    cont = uniform_contours(lo, hi, k, alpha)
+    return Workload(f"fd7_3d_{m}", A, B, cont, n_nodes, moments, block, seed, window=(lo, hi),
+                    meta={"first": first, "last": last, "sigma": sigma, "field_seed": field_seed})
+
+
+# 3D configuration: 7-point variable-coefficient diffusion on 64^3 (n = 262144),
+# log-normal coefficient (sigma = 1), lumped mass, ~500 interior eigenvalues over
+# 10 uniform circles, 32 nodes, 4 moments, 32 right-hand sides.
+def fd7_3d_64() -> Workload:
+    return config_fd7_3d()
