@@ -103,6 +103,11 @@ typedef struct {
     int verbose;            /* > 0: progress line on stderr every `verbose` COCG iterations */
     int use_graph;          /* 1 (default): replay each chunk of check_every COCG
                                iterations from a captured HIP graph (not with timing) */
+    const int* blocks;      /* optional per-contour block sizes (host, n_contours
+                               entries, each 1..block) for gep_ci_solve and
+                               gep_ci_solve_pencil: contour k uses the first
+                               blocks[k] columns of V.  NULL: every contour uses
+                               `block`.  Ignored by gep_ci_solve_batch. */
 } gep_opts;
 
 typedef struct gep_result gep_result;
@@ -211,6 +216,50 @@ int gep_sym_eig(double* A, double* w, double* V, int64_t k, int batch, void* str
  * V[i*L + l] = entry at counter l*n + i of the SplitMix64 + Box-Muller
  * stream of `seed`. */
 int gep_gaussian_block(uint64_t seed, int64_t n, int64_t L, double* V, void* stream);
+
+/* ---- learned contours (spectral prior + KDE) ----------------------------
+ * KDE contour construction (paper Sec. 4.2, interval sparsity function and
+ * Alg. "Adaptive Contour Construction via KDE"): recursively split the
+ * initial interval at the minimiser of G_k(t) = sum_j exp(-w (t - lam_j)^2 /
+ * (e - s)^2) over midpoints between consecutive predicted eigenvalues until
+ * every interval holds <= nmax of them, merge intervals holding < nmin with
+ * the smaller neighbour (splitting again above nmax), and map [s, e) to the
+ * circle centre (s+e)/2, radius (1+alpha)(e-s)/2.  The initial interval is
+ * [window_lo, window_hi] when both are finite, else [min - eps, max + eps],
+ * eps = beta (max - min).  lam_hat: host array of m predictions.  *count
+ * receives the number of contours; out (host, cap entries) may be NULL to
+ * query it.  Host computation; no GPU work. */
+int gep_kde_contours(const double* lam_hat, int64_t m, int nmin, int nmax, double w, double alpha,
+                     double beta, double window_lo, double window_hi, gep_contour* out, int cap,
+                     int* count);
+
+/* Spectral-density network: 3-layer MLP din -> dhidden -> dhidden -> dout,
+ * GELU, BF16 matrix-core GEMMs with FP32 accumulation, FP32 master weights
+ * and Adam state (paper Sec. 4.1: the learned spectral predictor, trained
+ * with a mean squared error).  Device pointers; rows of X are samples
+ * (row-major B x din, FP32); max_batch bounds B.  Weights: Glorot-uniform
+ * from SplitMix64(seed). */
+typedef struct gep_density gep_density;
+int gep_density_create(int din, int dhidden, int dout, int max_batch, uint64_t seed,
+                       gep_density** out);
+void gep_density_free(gep_density* net);
+/* Y (device, B x dout FP32) = net(X). */
+int gep_density_forward(gep_density* net, const float* X, int B, float* Y, void* stream);
+/* Forward, loss = mean((Y - T)^2) over B x dout (T device FP32), and the
+ * gradients of all parameters (kept in the net).  *loss (host) if non-NULL. */
+int gep_density_grads(gep_density* net, const float* X, const float* T, int B, double* loss,
+                      void* stream);
+/* One Adam step (Kingma and Ba) with the stored gradients. */
+int gep_density_adam(gep_density* net, float lr, float beta1, float beta2, float eps, void* stream);
+/* Copy parameter tensor `which` (0: W1 din x dh, 1: b1, 2: W2, 3: b2, 4: W3 dh x dout,
+ * 5: b3; row-major) or its gradient (grad = 1) to (set = 0) or from (set = 1)
+ * a HOST buffer. */
+int gep_density_param(gep_density* net, int which, int grad, float* host, int set);
+/* C = op(A) op(B) on BF16 matrix cores, FP32 accumulation (the network's
+ * GEMM): A(m, k) = A[m*sam + k*sak], B(k, n) = B[k*sbk + n*sbn] as raw BF16
+ * bit patterns, C row-major M x N FP32 with ldc.  Device pointers. */
+int gep_gemm_bf16(const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B, int64_t sbk,
+                  int64_t sbn, float* C, int64_t ldc, int M, int N, int K, void* stream);
 
 #ifdef __cplusplus
 }

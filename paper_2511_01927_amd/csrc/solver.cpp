@@ -355,6 +355,7 @@ struct Job {
     int64_t row0 = 0;    // first row of the problem in the concatenated pencil
     int64_t n = 0;       // rows of the problem
     int64_t bsrc0 = 0;   // offset in B V of this job's right-hand side 0 at row 0
+    int L = 0;           // right-hand sides (block size) of this job
 };
 
 struct ContourOut {
@@ -948,6 +949,7 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
             j.row0 = H.prob_row0[p];
             j.n = H.prob_n[p];
             j.bsrc0 = H.prob_row0[p] * L;
+            j.L = (n_problems == 1 && cfg.o.blocks) ? cfg.o.blocks[k] : L;
             all.push_back(j);
         }
     size_t freeb = 0, totalb = 0;
@@ -955,22 +957,30 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
     const double budget = cfg.o.mem_limit_bytes > 0 ? cfg.o.mem_limit_bytes : 0.85 * (double)freeb;
     const bool mixed = cfg.o.precision == GEP_MIXED;
     std::vector<ContourOut> finals(all.size());
+    // jobs ordered by block size so that equal sizes share waves
+    std::vector<size_t> ord(all.size());
+    for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return all[a].L < all[b].L; });
+    std::vector<Job> sorted_jobs;
+    for (size_t i : ord) sorted_jobs.push_back(all[i]);
     size_t k0 = 0;
-    while (k0 < all.size()) {
+    while (k0 < sorted_jobs.size()) {
+        // a wave holds consecutive jobs with the same block size
         size_t k1 = k0;
         double used = 0.0;
-        while (k1 < all.size()) {
-            const double need = (double)bytes_per_job(all[k1].n, cfg.NH, L, cfg.M, mixed);
+        const int Lw = sorted_jobs[k0].L;
+        while (k1 < sorted_jobs.size() && sorted_jobs[k1].L == Lw) {
+            const double need = (double)bytes_per_job(sorted_jobs[k1].n, cfg.NH, Lw, cfg.M, mixed);
             if (k1 > k0 && used + need > budget) break;
             used += need;
             ++k1;
         }
         if (used > budget)
             fail(GEP_ENOMEM, "one contour needs " + std::to_string((long long)used) + " bytes of device memory");
-        std::vector<Job> jobs(all.begin() + k0, all.begin() + k1);
+        std::vector<Job> jobs(sorted_jobs.begin() + k0, sorted_jobs.begin() + k1);
         std::vector<ContourOut> res;
         sv.stats_.waves += 1;
-        sv.run_pass(jobs, BV.get(), L, L, cfg.M, res);
+        sv.run_pass(jobs, BV.get(), L, Lw, cfg.M, res);
         for (auto& r : res) r.passes = 1;
         // refinement: jobs whose kept pairs miss tol (FEAST-type pass, V <- all Ritz vectors)
         for (int pass = 1; pass <= cfg.o.max_refine; ++pass) {
@@ -992,6 +1002,7 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
             for (int i : redo) {
                 Job j = jobs[i];
                 j.bsrc0 = off;
+                j.L = L2;
                 off += j.n * L2;
                 jobs2.push_back(j);
             }
@@ -1020,7 +1031,7 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
                 dst = src;
             }
         }
-        for (size_t i = 0; i < res.size(); ++i) finals[k0 + i] = res[i];
+        for (size_t i = 0; i < res.size(); ++i) finals[ord[k0 + i]] = res[i];
         k0 = k1;
     }
     // per problem: selection, gather, merge
@@ -1135,6 +1146,7 @@ void gep_opts_default(gep_opts* o) {
     o->rows_per_block = 0;
     o->verbose = 0;
     o->use_graph = 1;
+    o->blocks = nullptr;
 }
 
 const char* gep_strerror(int st) {
@@ -1213,6 +1225,12 @@ int gep_ci_solve_pencil(gep_pencil* P, const gep_contour* contours, int K, int N
     if (opts) o = *opts; else gep_opts_default(&o);
     int st = validate_problem(contours, K, N, M, L, tol, &o);
     if (st) return st;
+    if (o.blocks)
+        for (int k = 0; k < K; ++k)
+            if (o.blocks[k] < 1 || o.blocks[k] > L) {
+                gep::set_error("blocks[" + std::to_string(k) + "] must be in [1, block]");
+                return GEP_EINVAL;
+            }
     gep::SolveCfg cfg;
     cfg.N = N;
     cfg.NH = N / 2;
@@ -1254,6 +1272,7 @@ int gep_ci_solve_batch(int n_problems, const gep_csr* A, const gep_csr* B,
     for (int p = 0; p < n_problems; ++p) out[p] = nullptr;
     gep_opts o;
     if (opts) o = *opts; else gep_opts_default(&o);
+    o.blocks = nullptr;
     for (int p = 0; p < n_problems; ++p) {
         int st = validate_problem(contours[p], n_contours[p], n_nodes, moments, block, tol, &o);
         if (st) {

@@ -44,7 +44,7 @@ class gep_opts(C.Structure):
                 ("solve_tol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int),
                 ("stream", C.c_void_p), ("inputs_on_device", C.c_int), ("rhs", C.c_void_p),
                 ("mem_limit_bytes", C.c_double), ("timing", C.c_int), ("rows_per_block", C.c_int),
-                ("verbose", C.c_int), ("use_graph", C.c_int)]
+                ("verbose", C.c_int), ("use_graph", C.c_int), ("blocks", C.c_void_p)]
 
 
 # every symbol declared in include/gep_ci.h
@@ -53,7 +53,9 @@ EXPORTS = [
     "gep_result_stats", "gep_result_free", "gep_strerror", "gep_last_error",
     "gep_pencil_create", "gep_pencil_free", "gep_pencil_info", "gep_ci_solve_pencil",
     "gep_spmm_shifted", "gep_spmm_shifted_f32", "gep_spmm_real", "gep_gram", "gep_gemm_tall",
-    "gep_sym_eig", "gep_gaussian_block", "gep_ci_solve_batch",
+    "gep_sym_eig", "gep_gaussian_block", "gep_ci_solve_batch", "gep_kde_contours",
+    "gep_density_create", "gep_density_free", "gep_density_forward", "gep_density_grads",
+    "gep_density_adam", "gep_density_param", "gep_gemm_bf16",
 ]
 
 _lib = None
@@ -91,6 +93,15 @@ def load():
         "gep_gemm_tall": (i32, [P, i64, P, i64, i64, i64, i64, P, i64, P]),
         "gep_sym_eig": (i32, [P, P, P, i64, i32, P]),
         "gep_gaussian_block": (i32, [C.c_uint64, i64, i64, P, P]),
+        "gep_kde_contours": (i32, [P, i64, i32, i32, dbl, dbl, dbl, dbl, dbl, P, i32,
+                                   C.POINTER(C.c_int)]),
+        "gep_density_create": (i32, [i32, i32, i32, i32, C.c_uint64, C.POINTER(P)]),
+        "gep_density_free": (None, [P]),
+        "gep_density_forward": (i32, [P, P, i32, P, P]),
+        "gep_density_grads": (i32, [P, P, P, i32, C.POINTER(dbl), P]),
+        "gep_density_adam": (i32, [P, C.c_float, C.c_float, C.c_float, C.c_float, P]),
+        "gep_density_param": (i32, [P, i32, i32, P, i32]),
+        "gep_gemm_bf16": (i32, [P, i64, i64, P, i64, i64, P, i64, i32, i32, i32, P]),
         "gep_ci_solve_batch": (i32, [i32, C.POINTER(gep_csr), C.POINTER(gep_csr),
                                      C.POINTER(C.POINTER(gep_contour)), C.POINTER(C.c_int), i32, i32,
                                      i32, dbl, C.POINTER(gep_opts), C.POINTER(P)]),
@@ -155,7 +166,7 @@ def _contours(contours):
 
 
 def _opts(seed=1, precision="fp64", max_refine=1, solve_tol=1e-9, max_iter=100000, check_every=16,
-          stream=None, on_device=0, rhs=None, mem_limit_bytes=0.0, timing=False, rows_per_block=0, verbose=0, use_graph=True):
+          stream=None, on_device=0, rhs=None, mem_limit_bytes=0.0, timing=False, rows_per_block=0, verbose=0, use_graph=True, blocks=None):
     lib = load()
     o = gep_opts()
     lib.gep_opts_default(C.byref(o))
@@ -181,6 +192,10 @@ def _opts(seed=1, precision="fp64", max_refine=1, solve_tol=1e-9, max_iter=10000
     o.rows_per_block = rows_per_block
     o.verbose = verbose
     o.use_graph = 1 if use_graph else 0
+    if blocks is not None:
+        bl = np.ascontiguousarray(blocks, dtype=np.int32)
+        o.blocks = bl.ctypes.data
+        keep = (keep, bl)
     return o, keep
 
 
@@ -321,3 +336,66 @@ def gep_sym_eig(A, w, V, k, batch=1, stream=None):
 
 def gep_gaussian_block(seed, n, L, V, stream=None):
     _check(load().gep_gaussian_block(seed, n, L, V.data_ptr(), _stream_ptr(stream)))
+
+
+# ---- learned contours -----------------------------------------------------------
+def gep_kde_contours(lam_hat, nmin=10, nmax=50, w=10.0, alpha=0.1, beta=0.0, window=None):
+    """KDE contour construction; returns an array (K, 4) of centre, radius, keep_lo, keep_hi."""
+    lib = load()
+    lam = np.ascontiguousarray(lam_hat, dtype=np.float64)
+    lo, hi = (window if window is not None else (float("nan"), float("nan")))
+    cnt = C.c_int()
+    _check(lib.gep_kde_contours(lam.ctypes.data, lam.size, nmin, nmax, w, alpha, beta, lo, hi, None,
+                                0, C.byref(cnt)))
+    buf = (gep_contour * max(cnt.value, 1))()
+    _check(lib.gep_kde_contours(lam.ctypes.data, lam.size, nmin, nmax, w, alpha, beta, lo, hi, buf,
+                                cnt.value, C.byref(cnt)))
+    return np.array([[c.center, c.radius, c.keep_lo, c.keep_hi] for c in buf[:cnt.value]]).reshape(-1, 4)
+
+
+class DensityNet:
+    """Handle on gep_density (device-resident MLP with BF16 matrix-core GEMMs)."""
+
+    def __init__(self, din, dhidden, dout, max_batch, seed=1):
+        lib = load()
+        h = C.c_void_p()
+        _check(lib.gep_density_create(din, dhidden, dout, max_batch, seed, C.byref(h)))
+        self.h, self.din, self.dh, self.dout = h, din, dhidden, dout
+        self.shapes = [(din, dhidden), (dhidden,), (dhidden, dhidden), (dhidden,), (dhidden, dout), (dout,)]
+
+    def forward(self, X, Y, stream=None):
+        _check(load().gep_density_forward(self.h, X.data_ptr(), X.shape[0], Y.data_ptr(), _stream_ptr(stream)))
+
+    def grads(self, X, T, stream=None):
+        loss = C.c_double()
+        _check(load().gep_density_grads(self.h, X.data_ptr(), T.data_ptr(), X.shape[0], C.byref(loss),
+                                        _stream_ptr(stream)))
+        return loss.value
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(load().gep_density_adam(self.h, lr, beta1, beta2, eps, _stream_ptr(stream)))
+
+    def param(self, which, grad=False):
+        a = np.zeros(self.shapes[which], dtype=np.float32)
+        _check(load().gep_density_param(self.h, which, 1 if grad else 0, a.ctypes.data, 0))
+        return a
+
+    def set_param(self, which, value):
+        a = np.ascontiguousarray(value, dtype=np.float32).reshape(self.shapes[which])
+        _check(load().gep_density_param(self.h, which, 0, a.ctypes.data, 1))
+
+    def free(self):
+        if getattr(self, "h", None):
+            load().gep_density_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def gep_gemm_bf16(A, sam, sak, B, sbk, sbn, Cm, ldc, M, N, K, stream=None):
+    _check(load().gep_gemm_bf16(A.data_ptr(), sam, sak, B.data_ptr(), sbk, sbn, Cm.data_ptr(), ldc, M, N, K,
+                                _stream_ptr(stream)))

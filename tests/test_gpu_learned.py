@@ -1,0 +1,180 @@
+"""Learned-contour components through the C ABI: KDE contours vs the oracle,
+BF16 matrix-core GEMM and density-net gradients vs float64 references,
+training, and what the trained prior gains over uniform contours."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import density, kde
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_01927_amd import gep_ci
+    gep_ci.load()
+    return gep_ci
+
+
+def _bf16(a):
+    """Round float32 to bfloat16 (round to nearest even) and return (bits, values)."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    back = (r.astype(np.uint32) << 16).view(np.float32)
+    return r, back
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_kde_library_matches_oracle(lib, seed):
+    r = np.random.default_rng(seed)
+    lam = np.concatenate([r.normal(c, 0.3, r.integers(5, 60)) for c in np.cumsum(r.uniform(1, 3, 8))])
+    win = (float(lam.min()) - 0.5, float(lam.max()) + 0.5)
+    for w in (10.0, 100.0):
+        got = lib.gep_kde_contours(lam, nmin=10, nmax=50, w=w, alpha=0.1, window=win)
+        ref = np.array(kde.kde_contours(lam, nmin=10, nmax=50, w=w, alpha=0.1, window=win))
+        assert got.shape == ref.shape and np.array_equal(got, ref)
+    got = lib.gep_kde_contours(lam, nmin=10, nmax=50, w=10.0, alpha=0.2, beta=0.05)
+    ref = np.array(kde.kde_contours(lam, nmin=10, nmax=50, w=10.0, alpha=0.2, beta=0.05))
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("M,N,K,ta,tb", [(64, 64, 64, 0, 0), (37, 50, 91, 1, 0), (33, 17, 40, 0, 1), (5, 3, 2, 1, 1)])
+def test_gemm_bf16_layout(lib, M, N, K, ta, tb):
+    import torch
+    r = np.random.default_rng(M * N + K)
+    A = r.standard_normal((K, M) if ta else (M, K)).astype(np.float32)
+    B = r.standard_normal((N, K) if tb else (K, N)).astype(np.float32)
+    ab, av = _bf16(A)
+    bb, bv = _bf16(B)
+    ref = (av.T if ta else av).astype(np.float64) @ (bv.T if tb else bv).astype(np.float64)
+    dev = torch.device("cuda:0")
+    Ad = torch.from_numpy(ab.view(np.int16)).to(dev)
+    Bd = torch.from_numpy(bb.view(np.int16)).to(dev)
+    Cd = torch.zeros((M, N), dtype=torch.float32, device=dev)
+    sam, sak = (1, M) if ta else (K, 1)
+    sbk, sbn = (1, K) if tb else (N, 1)
+    lib.gep_gemm_bf16(Ad, sam, sak, Bd, sbk, sbn, Cd, N, M, N, K)
+    assert np.abs(Cd.cpu().numpy() - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max())
+
+
+def test_density_forward_and_gradients_vs_float64(lib):
+    import torch
+    din, dh, dout, B = 64, 32, 16, 24
+    net = lib.DensityNet(din, dh, dout, 64, seed=3)
+    r = np.random.default_rng(5)
+    params = [net.param(i).astype(np.float64) for i in range(6)]
+    params[1] = r.standard_normal(dh) * 0.1
+    params[3] = r.standard_normal(dh) * 0.1
+    params[5] = r.standard_normal(dout) * 0.1
+    for i in (1, 3, 5):
+        net.set_param(i, params[i])
+    # the network multiplies bf16 copies of the weights and activations
+    pb = [(_bf16(p.astype(np.float32))[1].astype(np.float64) if i % 2 == 0 else p) for i, p in enumerate(params)]
+    X = r.standard_normal((B, din)).astype(np.float32)
+    T = r.standard_normal((B, dout)).astype(np.float32)
+    dev = torch.device("cuda:0")
+    Xd, Td = torch.from_numpy(X).to(dev), torch.from_numpy(T).to(dev)
+    Y = torch.zeros((B, dout), dtype=torch.float32, device=dev)
+    net.forward(Xd, Y)
+    Yref, _ = density.forward(pb, _bf16(X)[1].astype(np.float64))
+    assert np.abs(Y.cpu().numpy() - Yref).max() <= 3e-2 * np.abs(Yref).max()
+    loss = net.grads(Xd, Td)
+    lref, gref = density.loss_and_grads(pb, _bf16(X)[1].astype(np.float64), T.astype(np.float64))
+    assert abs(loss - lref) <= 2e-2 * lref
+    for i in range(6):
+        g = net.param(i, grad=True).astype(np.float64)
+        rel = np.linalg.norm(g - gref[i]) / np.linalg.norm(gref[i])
+        assert rel <= 5e-2, (i, rel)
+
+
+def test_density_training_reduces_loss(lib):
+    from paper_2511_01927_amd import learned
+    r = np.random.default_rng(0)
+    X = r.standard_normal((128, 256)).astype(np.float32)
+    Wt = r.standard_normal((256, 32)) / 16
+    T = np.tanh(X @ Wt).astype(np.float32) + 1.0
+    prior = learned.SpectralPrior(n_bins=32, hidden=128, max_batch=64, seed=2)
+    l0 = prior.loss(X, T)
+    hist = prior.train(X, T, epochs=60, batch=32, lr=2e-3)
+    assert hist[-1] < 0.2 * l0, (l0, hist[-1])
+
+
+def _instance(nx, seed, first, last):
+    from workloads import pencils
+    from paper_2511_01927_amd import learned
+    g = pencils.grf((nx + 1, nx + 1), seed=seed)
+    kap = np.exp(g)
+    A, B = pencils.q1_2d(nx, nx, kap)
+    win = learned.weyl_window_2d(kap, first, last)
+    return A, B, g, win
+
+
+def test_learned_contours_gain_over_uniform(lib):
+    """Train the prior on labels from this library's own solves (40 x 40
+    grids, 96 random fields), apply it to held-out fields on 40 x 40 grids and
+    compare with uniform contours sized without spectral knowledge."""
+    from paper_2511_01927_amd import learned
+    first, last = 30, 110
+    nbins = 32
+    expected = last - first
+    feats, targs = [], []
+    train_seeds = list(range(100, 196))
+    probs = []
+    for s in train_seeds:
+        A, B, g, win = _instance(40, s, first, last)
+        probs.append((A, B, learned.uniform_contours(win, 4)))
+        feats.append(learned.field_features(g))
+    # labels: eigenvalues found by the CI solver itself (batched, generous subspace)
+    res = lib.gep_ci_solve_batch(probs, 32, 4, 32, 1e-8, seed=1, max_refine=1)
+    for (A, B, c), r_ in zip(probs, res):
+        win = (c[0][2], c[-1][3])
+        ok = r_["evals"][r_["resid"] <= 1e-8]
+        targs.append(learned.histogram_target(ok, win, nbins, expected))
+    X, T = np.array(feats), np.array(targs)
+    prior = learned.SpectralPrior(n_bins=nbins, hidden=256, max_batch=64, seed=7)
+    hist = prior.train(X, T, epochs=150, batch=32, lr=1e-3)
+    assert hist[-1] < hist[0]
+    # held-out fields.  Both strategies size the block
+    # for 2.5x their per-contour count estimate (moments = 4) and fall back to
+    # split contours when the solver flags a contour; the uniform one only
+    # knows the Weyl estimate of the total.
+    import time
+    tot = {"learned": [0, 0.0, 0, 0, 0], "uniform": [0, 0.0, 0, 0, 0]}   # pairs, s, columns, missed, fallbacks
+    f = 2.5
+    for s in (900, 901, 902):
+        A, B, g, win = _instance(40, s, first, last)
+        lam = np.linalg.eigvalsh(np.linalg.solve(np.linalg.cholesky(B.toarray()),
+                                                 np.linalg.solve(np.linalg.cholesky(B.toarray()), A.toarray()).T))
+        ref = lam[(lam >= win[0]) & (lam < win[1])]
+        h = prior.predict(learned.field_features(g)[None, :])[0]
+        cont, pred = learned.learned_contours(h, win, expected, nmin=10, nmax=50, w=10.0, alpha=0.1)
+        bl = learned.blocks_for(pred, 4, factor=f)
+        t0 = time.perf_counter()
+        got, nfb = learned.solve_with_fallback(A, B, cont, pred, 32, 4, max(bl), 1e-8, seed=3, blocks=bl)
+        dt = time.perf_counter() - t0
+        ku = max(1, math.ceil(expected / 40))
+        pu = np.full(ku, expected / ku)
+        Lu = learned.blocks_for(pu, 4, factor=f)[0]
+        t1 = time.perf_counter()
+        uni, nfu = learned.solve_with_fallback(A, B, learned.uniform_contours(win, ku), pu, 32, 4, Lu, 1e-8, seed=3)
+        du = time.perf_counter() - t1
+        for name, r_, d, nf in (("learned", got, dt, nfb), ("uniform", uni, du, nfu)):
+            good = r_["evals"][r_["resid"] <= 1e-8]
+            hit = sum(np.any(np.abs(good - x) <= 1e-10 * abs(x)) for x in ref)
+            tot[name][0] += int(hit)
+            tot[name][1] += d
+            tot[name][2] += int(r_["stats"]["columns"])
+            tot[name][3] += int(ref.size - hit)
+            tot[name][4] += nf
+    print("learned vs uniform:", tot)
+    for name, v in tot.items():
+        print(f"{name}: {v[0]} pairs, {v[0] / v[1]:.1f} eigenpairs/s, {v[2]} columns, {v[3]} missed, {v[4]} fallbacks")
+    # the prior must not lose eigenpairs, and must need fewer shifted-system columns
+    assert tot["learned"][3] == 0
+    assert tot["learned"][2] < tot["uniform"][2]

@@ -204,3 +204,19 @@ def test_graph_replay_equals_eager(lib):
     assert np.array_equal(eager["resid"], graph["resid"])
     assert np.array_equal(eager["evals"], again["evals"])
     assert eager["stats"]["cocg_iters"] == graph["stats"]["cocg_iters"]
+
+
+def test_per_contour_block_sizes_vs_oracle(lib):
+    """opts.blocks: contour k solves with the first blocks[k] columns of V."""
+    from oracle import rng
+    w = configs.config_fem1d(n=800, first=61, last=80, n_nodes=16, moments=4, block=16, seed=5)
+    cont = configs.uniform_contours(*w.window, 2, 0.2)
+    blocks = [8, 16]
+    got = lib.gep_ci_solve(w.A, w.B, cont, 16, 4, 16, 1e-8, seed=5, blocks=blocks)
+    V = rng.gaussian_block(w.n, 16, 5)
+    lams, Xs = [], []
+    for k in range(2):
+        ref = oracle.oracle_ci_solve(w.A, w.B, cont[k:k + 1], 16, 4, blocks[k], 1e-8, V=V[:, :blocks[k]])
+        lams.append(ref["evals"])
+        Xs.append(ref["evecs"])
+    assert_pairs_match(got, np.concatenate(lams), np.concatenate(Xs, axis=1), w.B)
