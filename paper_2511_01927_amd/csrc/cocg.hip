@@ -284,6 +284,48 @@ __global__ __launch_bounds__(kBlock) void k_update(
     block_partials(m, nrb, rho, rr, part_c, part_r);
 }
 
+// First level of the per-tile sums: work-group (slot, g) adds row blocks
+// [g * chunk, (g + 1) * chunk) of the active tile's partials into part2
+// [tile][g][64], so the per-column kernels below only sum G entries.
+__global__ __launch_bounds__(kBlock) void k_fold_partials(int nrb, int G,
+                                                          const int32_t* __restrict__ tiles,
+                                                          const int32_t* __restrict__ n_active,
+                                                          const double2* __restrict__ part_c,
+                                                          const double* __restrict__ part_r,
+                                                          double2* __restrict__ part2_c,
+                                                          double* __restrict__ part2_r) {
+    __shared__ double2 sc[kWaves][kTile];
+    __shared__ double sr[kWaves][kTile];
+    const int slot = blockIdx.x / G;
+    const int g = blockIdx.x - slot * G;
+    if (slot >= n_active[0]) return;
+    const int tile = tiles[slot];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int chunk = (nrb + G - 1) / G;
+    const int r0 = g * chunk, r1 = min(nrb, r0 + chunk);
+    double2 a = make_double2(0.0, 0.0);
+    double d = 0.0;
+    for (int rb = r0 + wave; rb < r1; rb += kWaves) {
+        const size_t o = ((size_t)tile * nrb + rb) * kTile + lane;
+        const double2 v = part_c[o];
+        a.x += v.x;
+        a.y += v.y;
+        if (part_r) d += part_r[o];
+    }
+    sc[wave][lane] = a;
+    sr[wave][lane] = d;
+    __syncthreads();
+    if (wave) return;
+    for (int w = 1; w < kWaves; ++w) {
+        a.x += sc[w][lane].x;
+        a.y += sc[w][lane].y;
+        d += sr[w][lane];
+    }
+    const size_t o = ((size_t)tile * G + g) * kTile + lane;
+    part2_c[o] = a;
+    if (part_r) part2_r[o] = d;
+}
+
 // After k_init: rho, ||b||^2, activity per column and per tile.
 __global__ __launch_bounds__(kBlock) void k_reduce_init(int nrb, const double2* __restrict__ part_c,
                                                         const double* __restrict__ part_r,
@@ -689,6 +731,9 @@ hipError_t cocg32_fold(const DevPencil& P, CocgState& S, int n_active_host, int 
     return hipGetLastError();
 }
 
+static hipError_t fold_partials(CocgState& S, int n_active_host, int nrb, bool with_r,
+                                const double2*& pc, const double*& pr, int& cnt, hipStream_t s);
+
 hipError_t cocg32_replace(const DevPencil& P, CocgState& S, const double* BV, int64_t ldbv,
                           int n_active_host, int nrb, double tol2, hipStream_t s) {
     if (n_active_host <= 0) return hipSuccess;
@@ -701,26 +746,58 @@ hipError_t cocg32_replace(const DevPencil& P, CocgState& S, const double* BV, in
                        S.tiles, S.counts, nrb, rpb, S.part_c, S.part_r);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_replace, dim3(n_active_host), dim3(kBlock), 0, s, nrb, S.tiles,
-                       S.counts, S.part_c, S.part_r, S.rho, S.beta, S.bb, S.rr, S.rmax, S.flag,
+    const double2* pc;
+    const double* pr;
+    int cnt;
+    e = fold_partials(S, n_active_host, nrb, true, pc, pr, cnt, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_replace, dim3(n_active_host), dim3(kBlock), 0, s, cnt, S.tiles,
+                       S.counts, pc, pr, S.rho, S.beta, S.bb, S.rr, S.rmax, S.flag,
                        S.active, S.tile_active, tol2);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return cocg_compact(S, s);
 }
 
+// Folds the partials of the active tiles to G entries when that pays;
+// returns the partial arrays and their row-block count to sum.
+static hipError_t fold_partials(CocgState& S, int n_active_host, int nrb, bool with_r,
+                                const double2*& pc, const double*& pr, int& cnt, hipStream_t s) {
+    pc = S.part_c;
+    pr = S.part_r;
+    cnt = nrb;
+    if (S.G <= 0 || nrb <= 2 * S.G) return hipSuccess;
+    hipLaunchKernelGGL(k_fold_partials, dim3(n_active_host * S.G), dim3(kBlock), 0, s, nrb, S.G,
+                       S.tiles, S.counts, S.part_c, with_r ? S.part_r : nullptr, S.part2_c,
+                       S.part2_r);
+    pc = S.part2_c;
+    pr = S.part2_r;
+    cnt = S.G;
+    return hipGetLastError();
+}
+
 hipError_t cocg_reduce_alpha(CocgState& S, int n_active_host, int nrb, hipStream_t s) {
     if (n_active_host <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_alpha, dim3(n_active_host), dim3(kBlock), 0, s, nrb, S.tiles,
-                       S.counts, S.part_c, S.rho, S.alpha, S.active);
+    const double2* pc;
+    const double* pr;
+    int cnt;
+    hipError_t e = fold_partials(S, n_active_host, nrb, false, pc, pr, cnt, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_alpha, dim3(n_active_host), dim3(kBlock), 0, s, cnt, S.tiles,
+                       S.counts, pc, S.rho, S.alpha, S.active);
     return hipGetLastError();
 }
 
 hipError_t cocg_reduce_beta(CocgState& S, int n_active_host, int nrb, double tol2, int max_iter,
                             int hold, hipStream_t s) {
     if (n_active_host <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_beta, dim3(n_active_host), dim3(kBlock), 0, s, nrb, S.tiles,
-                       S.counts, S.part_c, S.part_r, S.rho, S.beta, S.bb, S.rr, S.rmax, S.flag,
+    const double2* pc;
+    const double* pr;
+    int cnt;
+    hipError_t e = fold_partials(S, n_active_host, nrb, true, pc, pr, cnt, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_beta, dim3(n_active_host), dim3(kBlock), 0, s, cnt, S.tiles,
+                       S.counts, pc, pr, S.rho, S.beta, S.bb, S.rr, S.rmax, S.flag,
                        S.active, S.iters, S.tile_active, tol2, max_iter, hold);
     return hipGetLastError();
 }

@@ -94,6 +94,9 @@ struct CocgState {
     double* part_r = nullptr;        // [ntiles][nrb][64]
     int nrb = 0;
     int rpb = 0;                     // rows per work-group
+    int G = 0;                       // first-level groups of the partial sums (0: none)
+    double2* part2_c = nullptr;      // [ntiles][G][64]
+    double* part2_r = nullptr;
     TileGeom geom;
 };
 

@@ -501,6 +501,11 @@ class Solver {
         DBuf<int32_t> flag(Wp);
         DBuf<double2> part_c((size_t)ntiles * nrb * kTile);
         DBuf<double> part_r((size_t)ntiles * nrb * kTile);
+        S.G = nrb > 64 ? 32 : 0;
+        DBuf<double2> part2_c((size_t)ntiles * std::max(S.G, 1) * kTile);
+        DBuf<double> part2_r((size_t)ntiles * std::max(S.G, 1) * kTile);
+        S.part2_c = part2_c.get();
+        S.part2_r = part2_r.get();
         DBuf<double2> d_coef(coef.size());
         S.x = x.get();
         S.u = u.get();
