@@ -98,8 +98,9 @@ typedef struct {
     double mem_limit_bytes; /* device-memory budget for one wave of contours;
                                0 = 85% of free memory */
     int timing;             /* 1: time every kernel class with HIP events */
-    int rows_per_block;     /* rows per work-group of the streaming COCG kernels
-                               (0 = automatic: max(32, n / 4096)) */
+    int rows_per_block;     /* rows per work-group of the streaming COCG kernels,
+                               rounded up to a whole number of row groups
+                               (0 = automatic: 16 with 4-row groups, 8 without) */
     int verbose;            /* > 0: progress line on stderr every `verbose` COCG iterations */
     int use_graph;          /* 1 (default): replay each chunk of check_every COCG
                                iterations from a captured HIP graph (not with timing) */
@@ -108,6 +109,11 @@ typedef struct {
                                gep_ci_solve_pencil: contour k uses the first
                                blocks[k] columns of V.  NULL: every contour uses
                                `block`.  Ignored by gep_ci_solve_batch. */
+    int row_group;          /* rows whose neighbour gathers the COCG kernels share:
+                               4 (groups of 4 consecutive rows of one pencil, union
+                               of their columns), 1 (plain CSR), 0 (default:
+                               4 when that saves at least 20% of the gathers).
+                               Results do not depend on it. */
 } gep_opts;
 
 typedef struct gep_result gep_result;

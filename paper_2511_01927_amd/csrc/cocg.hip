@@ -14,6 +14,9 @@
 //   B  recompute K p' (gather p'), x += alpha p', u -= alpha D^-1 K p',
 //      partials of D u^2 and |D u|^2                              [5 passes]
 //
+// Both walk the pencil in row groups (see group_walk below) so that
+// neighbours shared by consecutive rows are gathered once.
+//
 // plus three tiny kernels: alpha = rho / p'^T q; beta = rho'/rho with the
 // per-column convergence test ||r|| <= tol ||b||; active-tile compaction.
 // p is double-buffered because neighbours gather the old p while p' is
@@ -148,16 +151,78 @@ __global__ __launch_bounds__(kBlock) void k_init(TileGeom geom, const double* __
     block_partials(m, nrb, rho, bb, part_c, part_r);
 }
 
+// Row groups.  The pencil is also stored as a sequence of groups of R
+// consecutive rows (never crossing a pencil of a batch): group k holds the
+// sorted union of its rows' column indices, gcol[gptr[k] .. gptr[k+1]), and
+// an R-wide coefficient block gab[c * R + r] = (a, b) of row r at column
+// gcol[c], zero where row r has no entry.  A wave walks the union once and
+// applies every gathered neighbour to all R rows, so a neighbour shared by
+// consecutive rows is loaded once instead of once per row (R = 4 halves the
+// gathers of a 2D nine-point pattern).  Per row the nonzero terms are added
+// in ascending column order, as a CSR walk would, and the zero padding adds
+// exact zeros, so every row's K p' is the same for any R (the dot-product
+// partials follow the rows each wave owns, so their rounding does not).
+// R = 1 is plain CSR.
+// Every row holds its diagonal (B has a positive diagonal), so the union of a
+// group contains the group's own rows and their values are picked up on the
+// way instead of being loaded again.
+template <typename VT, int R>
+struct GroupAcc {
+    using Rt = typename Cx<VT>::R;
+    Rt ar[R], ai[R], br[R], bi[R];
+    VT own[R];
+    __device__ void clear() {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            ar[r] = ai[r] = br[r] = bi[r] = 0;
+            own[r].x = 0;
+            own[r].y = 0;
+        }
+    }
+};
+
+// Chunk of union columns loaded together (more loads in flight per wave).
+constexpr int kChunk = 3;
+
+// Walk group k's union: for each column j, v = fetch(j) (the gathered value),
+// accumulate A v and B v into every row of the group, and keep v for the
+// group's own rows.  grow is the group's first global row.
+template <typename VT, int R, typename F>
+__device__ inline void group_walk(const int32_t* __restrict__ gcol,
+                                  const typename Cx<VT>::M* __restrict__ gab, int c0, int c1,
+                                  int grow, GroupAcc<VT, R>& acc, F fetch) {
+    using M = typename Cx<VT>::M;
+    for (int c = c0; c < c1; c += kChunk) {
+        int j[kChunk];
+#pragma unroll
+        for (int t = 0; t < kChunk; ++t) j[t] = gcol[min(c + t, c1 - 1)];
+        VT v[kChunk];
+#pragma unroll
+        for (int t = 0; t < kChunk; ++t) v[t] = fetch(j[t]);
+#pragma unroll
+        for (int t = 0; t < kChunk; ++t) {
+            const bool ok = c + t < c1;
+            const int cc = ok ? c + t : c1 - 1;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                M w = gab[(size_t)cc * R + r];
+                if (!ok) w.x = w.y = 0;
+                cfma_acc(w.x, w.y, v[t].x, v[t].y, acc.ar[r], acc.ai[r], acc.br[r], acc.bi[r]);
+                if (j[t] == grow + r) acc.own[r] = v[t];
+            }
+        }
+    }
+}
+
 // Kernel A: p' = u + beta p, q = K p', store p', partials of p'^T q.
-template <typename VT>
+template <typename VT, int R>
 __global__ __launch_bounds__(kBlock) void k_spmm_dir(
-    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-    const typename Cx<VT>::M* __restrict__ ab, TileGeom geom, const double2* __restrict__ shifts,
+    const int32_t* __restrict__ gptr, const int32_t* __restrict__ gcol,
+    const typename Cx<VT>::M* __restrict__ gab, TileGeom geom, const double2* __restrict__ shifts,
     const double2* __restrict__ beta, const VT* __restrict__ U, const VT* __restrict__ P,
     VT* __restrict__ Pn, const int32_t* __restrict__ tiles, const int32_t* __restrict__ n_active,
     int nrb, int rpb, double2* __restrict__ part_c) {
-    using R = typename Cx<VT>::R;
-    using M = typename Cx<VT>::M;
+    using Rt = typename Cx<VT>::R;
     BlockMap m;
     if (!map_block(tiles, n_active, nrb, rpb, geom, m)) return;
     const int col = m.tile * kTile + m.lane;
@@ -167,63 +232,50 @@ __global__ __launch_bounds__(kBlock) void k_spmm_dir(
     VT* __restrict__ Pnt = Pn + m.goff;
     const double2 zd = shifts[col];
     const double2 bd = beta[col];
-    const R zr = (R)zd.x, zi = (R)zd.y, br_ = (R)bd.x, bi_ = (R)bd.y;
+    const Rt zr = (Rt)zd.x, zi = (Rt)zd.y, br_ = (Rt)bd.x, bi_ = (Rt)bd.y;
+    const int gbase = geom.g0[m.tile];
     double dr = 0.0, di = 0.0;
-    for (int i = m.r0 + m.wave; i < m.r1; i += kWaves) {
-        const int g = m.row0 + i;
-        const int k0 = rowptr[g];
-        const int k1 = rowptr[g + 1];
-        R ar = 0, ai = 0, sbr = 0, sbi = 0;
-        int k = k0;
-        for (; k + 3 <= k1; k += 3) {
-            const int j0 = colind[k], j1 = colind[k + 1], j2 = colind[k + 2];
-            const M v0 = ab[k], v1 = ab[k + 1], v2 = ab[k + 2];
-            const VT u0 = Ut[(size_t)j0 * kTile + m.lane], p0 = Pt[(size_t)j0 * kTile + m.lane];
-            const VT u1 = Ut[(size_t)j1 * kTile + m.lane], p1 = Pt[(size_t)j1 * kTile + m.lane];
-            const VT u2 = Ut[(size_t)j2 * kTile + m.lane], p2 = Pt[(size_t)j2 * kTile + m.lane];
-            R xr = u0.x + br_ * p0.x - bi_ * p0.y, xi = u0.y + br_ * p0.y + bi_ * p0.x;
-            cfma_acc(v0.x, v0.y, xr, xi, ar, ai, sbr, sbi);
-            xr = u1.x + br_ * p1.x - bi_ * p1.y;
-            xi = u1.y + br_ * p1.y + bi_ * p1.x;
-            cfma_acc(v1.x, v1.y, xr, xi, ar, ai, sbr, sbi);
-            xr = u2.x + br_ * p2.x - bi_ * p2.y;
-            xi = u2.y + br_ * p2.y + bi_ * p2.x;
-            cfma_acc(v2.x, v2.y, xr, xi, ar, ai, sbr, sbi);
-        }
-        for (; k < k1; ++k) {
-            const int j = colind[k];
-            const M v = ab[k];
+    // r0 is a multiple of R except for row blocks past the pencil's end,
+    // where r0 = r1 = n and the range below is empty
+    const int k_end = (m.r1 + R - 1) / R;
+    for (int k = (m.r0 + R - 1) / R + m.wave; k < k_end; k += kWaves) {
+        const int gk = gbase + k;
+        const int grow = m.row0 + k * R;
+        GroupAcc<VT, R> acc;
+        acc.clear();
+        group_walk<VT, R>(gcol, gab, gptr[gk], gptr[gk + 1], grow, acc, [&](int j) {
             const VT uj = Ut[(size_t)j * kTile + m.lane], pj = Pt[(size_t)j * kTile + m.lane];
-            const R xr = uj.x + br_ * pj.x - bi_ * pj.y, xi = uj.y + br_ * pj.y + bi_ * pj.x;
-            cfma_acc(v.x, v.y, xr, xi, ar, ai, sbr, sbi);
+            VT x;
+            x.x = uj.x + br_ * pj.x - bi_ * pj.y;
+            x.y = uj.y + br_ * pj.y + bi_ * pj.x;
+            return x;
+        });
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (k * R + r >= m.r1) break;
+            const VT pn = acc.own[r];
+            Pnt[(size_t)(grow + r) * kTile + m.lane] = pn;
+            const Rt qr = fma(zr, acc.br[r], fma(-zi, acc.bi[r], -acc.ar[r]));
+            const Rt qi = fma(zr, acc.bi[r], fma(zi, acc.br[r], -acc.ai[r]));
+            dr += (double)pn.x * (double)qr - (double)pn.y * (double)qi;
+            di += (double)pn.x * (double)qi + (double)pn.y * (double)qr;
         }
-        const size_t o = (size_t)g * kTile + m.lane;
-        const VT ui = Ut[o], pi = Pt[o];
-        VT pn;
-        pn.x = ui.x + br_ * pi.x - bi_ * pi.y;
-        pn.y = ui.y + br_ * pi.y + bi_ * pi.x;
-        Pnt[o] = pn;
-        const R qr = fma(zr, sbr, fma(-zi, sbi, -ar));
-        const R qi = fma(zr, sbi, fma(zi, sbr, -ai));
-        dr += (double)pn.x * (double)qr - (double)pn.y * (double)qi;
-        di += (double)pn.x * (double)qi + (double)pn.y * (double)qr;
     }
     block_partials(m, nrb, make_double2(dr, di), 0.0, part_c, nullptr);
 }
 
 // Kernel B: q = K p (recomputed), x += alpha p, u -= alpha D^-1 q,
 // partials of rho' = sum D u^2 and ||D u||^2.
-template <typename VT>
+template <typename VT, int R>
 __global__ __launch_bounds__(kBlock) void k_update(
-    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-    const typename Cx<VT>::M* __restrict__ ab, TileGeom geom, const double* __restrict__ dA,
+    const int32_t* __restrict__ gptr, const int32_t* __restrict__ gcol,
+    const typename Cx<VT>::M* __restrict__ gab, TileGeom geom, const double* __restrict__ dA,
     const double* __restrict__ dB, const double2* __restrict__ shifts,
     const double2* __restrict__ alpha, VT* __restrict__ X, VT* __restrict__ U,
     const VT* __restrict__ P, const int32_t* __restrict__ tiles,
     const int32_t* __restrict__ n_active, int nrb, int rpb, double2* __restrict__ part_c,
     double* __restrict__ part_r) {
-    using R = typename Cx<VT>::R;
-    using M = typename Cx<VT>::M;
+    using Rt = typename Cx<VT>::R;
     BlockMap m;
     if (!map_block(tiles, n_active, nrb, rpb, geom, m)) return;
     const int col = m.tile * kTile + m.lane;
@@ -232,54 +284,46 @@ __global__ __launch_bounds__(kBlock) void k_update(
     const VT* __restrict__ Pt = P + m.goff;
     const double2 zd = shifts[col];
     const double2 ad = alpha[col];
-    const R zr = (R)zd.x, zi = (R)zd.y, alr = (R)ad.x, ali = (R)ad.y;
+    const Rt zr = (Rt)zd.x, zi = (Rt)zd.y, alr = (Rt)ad.x, ali = (Rt)ad.y;
+    const int gbase = geom.g0[m.tile];
     double2 rho = make_double2(0.0, 0.0);
     double rr = 0.0;
-    for (int i = m.r0 + m.wave; i < m.r1; i += kWaves) {
-        const int g = m.row0 + i;
-        const int k0 = rowptr[g];
-        const int k1 = rowptr[g + 1];
-        R ar = 0, ai = 0, sbr = 0, sbi = 0;
-        int k = k0;
-        for (; k + 4 <= k1; k += 4) {
-            const int j0 = colind[k], j1 = colind[k + 1], j2 = colind[k + 2], j3 = colind[k + 3];
-            const M v0 = ab[k], v1 = ab[k + 1], v2 = ab[k + 2], v3 = ab[k + 3];
-            const VT p0 = Pt[(size_t)j0 * kTile + m.lane];
-            const VT p1 = Pt[(size_t)j1 * kTile + m.lane];
-            const VT p2 = Pt[(size_t)j2 * kTile + m.lane];
-            const VT p3 = Pt[(size_t)j3 * kTile + m.lane];
-            cfma_acc(v0.x, v0.y, p0.x, p0.y, ar, ai, sbr, sbi);
-            cfma_acc(v1.x, v1.y, p1.x, p1.y, ar, ai, sbr, sbi);
-            cfma_acc(v2.x, v2.y, p2.x, p2.y, ar, ai, sbr, sbi);
-            cfma_acc(v3.x, v3.y, p3.x, p3.y, ar, ai, sbr, sbi);
+    // r0 is a multiple of R except for row blocks past the pencil's end,
+    // where r0 = r1 = n and the range below is empty
+    const int k_end = (m.r1 + R - 1) / R;
+    for (int k = (m.r0 + R - 1) / R + m.wave; k < k_end; k += kWaves) {
+        const int gk = gbase + k;
+        const int grow = m.row0 + k * R;
+        GroupAcc<VT, R> acc;
+        acc.clear();
+        group_walk<VT, R>(gcol, gab, gptr[gk], gptr[gk + 1], grow, acc,
+                          [&](int j) { return Pt[(size_t)j * kTile + m.lane]; });
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (k * R + r >= m.r1) break;
+            const int g = grow + r;
+            const Rt qr = fma(zr, acc.br[r], fma(-zi, acc.bi[r], -acc.ar[r]));
+            const Rt qi = fma(zr, acc.bi[r], fma(zi, acc.br[r], -acc.ai[r]));
+            const size_t o = (size_t)g * kTile + m.lane;
+            const VT pi = acc.own[r];
+            VT xv = Xt[o], uv = Ut[o];
+            xv.x = fma(alr, pi.x, fma(-ali, pi.y, xv.x));
+            xv.y = fma(alr, pi.y, fma(ali, pi.x, xv.y));
+            // s = alpha q / D
+            const double2 D = make_double2(zd.x * dB[g] - dA[g], zd.y * dB[g]);
+            const Rt aqr = alr * qr - ali * qi, aqi = alr * qi + ali * qr;
+            const double2 s = cdiv(make_double2((double)aqr, (double)aqi), D);
+            uv.x = uv.x - (Rt)s.x;
+            uv.y = uv.y - (Rt)s.y;
+            Xt[o] = xv;
+            Ut[o] = uv;
+            // r = D u
+            const double ux = (double)uv.x, uy = (double)uv.y;
+            const double rx = D.x * ux - D.y * uy, ry = D.x * uy + D.y * ux;
+            rho.x += rx * ux - ry * uy;
+            rho.y += rx * uy + ry * ux;
+            rr += rx * rx + ry * ry;
         }
-        for (; k < k1; ++k) {
-            const int j = colind[k];
-            const M v = ab[k];
-            const VT pj = Pt[(size_t)j * kTile + m.lane];
-            cfma_acc(v.x, v.y, pj.x, pj.y, ar, ai, sbr, sbi);
-        }
-        const R qr = fma(zr, sbr, fma(-zi, sbi, -ar));
-        const R qi = fma(zr, sbi, fma(zi, sbr, -ai));
-        const size_t o = (size_t)g * kTile + m.lane;
-        const VT pi = Pt[o];
-        VT xv = Xt[o], uv = Ut[o];
-        xv.x = fma(alr, pi.x, fma(-ali, pi.y, xv.x));
-        xv.y = fma(alr, pi.y, fma(ali, pi.x, xv.y));
-        // s = alpha q / D
-        const double2 D = make_double2(zd.x * dB[g] - dA[g], zd.y * dB[g]);
-        const R aqr = alr * qr - ali * qi, aqi = alr * qi + ali * qr;
-        const double2 s = cdiv(make_double2((double)aqr, (double)aqi), D);
-        uv.x = uv.x - (R)s.x;
-        uv.y = uv.y - (R)s.y;
-        Xt[o] = xv;
-        Ut[o] = uv;
-        // r = D u
-        const double ux = (double)uv.x, uy = (double)uv.y;
-        const double rx = D.x * ux - D.y * uy, ry = D.x * uy + D.y * ux;
-        rho.x += rx * ux - ry * uy;
-        rho.y += rx * uy + ry * ux;
-        rr += rx * rx + ry * ry;
     }
     block_partials(m, nrb, rho, rr, part_c, part_r);
 }
@@ -673,37 +717,49 @@ hipError_t cocg_init(const DevPencil& P, CocgState& S, const double* BV, int64_t
 }
 
 template <typename VT>
-hipError_t launch_spmm_dir_t(const DevPencil& P, const void* ab, CocgState& S, const VT* u,
+hipError_t launch_spmm_dir_t(const DevPencil& P, const void* gab, CocgState& S, const VT* u,
                              const VT* p, VT* pn, int n_active_host, int nrb, hipStream_t s) {
     if (n_active_host <= 0) return hipSuccess;
     const int rpb = S.rpb;
     const int grid = pad8(n_active_host * nrb);
-    hipLaunchKernelGGL((k_spmm_dir<VT>), dim3(grid), dim3(kBlock), 0, s, P.rowptr, P.colind,
-                       (const typename Cx<VT>::M*)ab, S.geom, S.shifts, S.beta, u, p, pn,
-                       S.tiles, S.counts, nrb, rpb, S.part_c);
+    using M = typename Cx<VT>::M;
+    if (P.grp == 4)
+        hipLaunchKernelGGL((k_spmm_dir<VT, 4>), dim3(grid), dim3(kBlock), 0, s, P.gptr, P.gcol,
+                           (const M*)gab, S.geom, S.shifts, S.beta, u, p, pn, S.tiles, S.counts,
+                           nrb, rpb, S.part_c);
+    else
+        hipLaunchKernelGGL((k_spmm_dir<VT, 1>), dim3(grid), dim3(kBlock), 0, s, P.gptr, P.gcol,
+                           (const M*)gab, S.geom, S.shifts, S.beta, u, p, pn, S.tiles, S.counts,
+                           nrb, rpb, S.part_c);
     return hipGetLastError();
 }
 
 template <typename VT>
-hipError_t launch_update_t(const DevPencil& P, const void* ab, CocgState& S, VT* x, VT* u,
+hipError_t launch_update_t(const DevPencil& P, const void* gab, CocgState& S, VT* x, VT* u,
                            const VT* p, int n_active_host, int nrb, hipStream_t s) {
     if (n_active_host <= 0) return hipSuccess;
     const int rpb = S.rpb;
     const int grid = pad8(n_active_host * nrb);
-    hipLaunchKernelGGL((k_update<VT>), dim3(grid), dim3(kBlock), 0, s, P.rowptr, P.colind,
-                       (const typename Cx<VT>::M*)ab, S.geom, P.dA, P.dB, S.shifts, S.alpha, x,
-                       u, p, S.tiles, S.counts, nrb, rpb, S.part_c, S.part_r);
+    using M = typename Cx<VT>::M;
+    if (P.grp == 4)
+        hipLaunchKernelGGL((k_update<VT, 4>), dim3(grid), dim3(kBlock), 0, s, P.gptr, P.gcol,
+                           (const M*)gab, S.geom, P.dA, P.dB, S.shifts, S.alpha, x, u, p,
+                           S.tiles, S.counts, nrb, rpb, S.part_c, S.part_r);
+    else
+        hipLaunchKernelGGL((k_update<VT, 1>), dim3(grid), dim3(kBlock), 0, s, P.gptr, P.gcol,
+                           (const M*)gab, S.geom, P.dA, P.dB, S.shifts, S.alpha, x, u, p,
+                           S.tiles, S.counts, nrb, rpb, S.part_c, S.part_r);
     return hipGetLastError();
 }
 
 hipError_t cocg_spmm_dir(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
                          hipStream_t s) {
-    return launch_spmm_dir_t<double2>(P, P.ab, S, S.u, S.p, S.pn, n_active_host, nrb, s);
+    return launch_spmm_dir_t<double2>(P, P.gab, S, S.u, S.p, S.pn, n_active_host, nrb, s);
 }
 
 hipError_t cocg_update(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
                        hipStream_t s) {
-    return launch_update_t<double2>(P, P.ab, S, S.x, S.u, S.pn, n_active_host, nrb, s);
+    return launch_update_t<double2>(P, P.gab, S, S.x, S.u, S.pn, n_active_host, nrb, s);
 }
 
 hipError_t cocg32_init(const DevPencil& P, CocgState& S, const double* BV, int64_t ldbv, int nrb,
@@ -713,12 +769,12 @@ hipError_t cocg32_init(const DevPencil& P, CocgState& S, const double* BV, int64
 
 hipError_t cocg32_spmm_dir(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
                            hipStream_t s) {
-    return launch_spmm_dir_t<float2>(P, P.ab32, S, S.u32, S.p32, S.pn32, n_active_host, nrb, s);
+    return launch_spmm_dir_t<float2>(P, P.gab32, S, S.u32, S.p32, S.pn32, n_active_host, nrb, s);
 }
 
 hipError_t cocg32_update(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
                          hipStream_t s) {
-    return launch_update_t<float2>(P, P.ab32, S, S.x32, S.u32, S.pn32, n_active_host, nrb, s);
+    return launch_update_t<float2>(P, P.gab32, S, S.x32, S.u32, S.pn32, n_active_host, nrb, s);
 }
 
 hipError_t cocg32_fold(const DevPencil& P, CocgState& S, int n_active_host, int nrb,

@@ -27,6 +27,23 @@ struct DevPencil {
     double* dB = nullptr;       // diag(B)
     double a_inf = 0.0;         // max absolute row sum of A
     int max_row_nnz = 0;
+    // Row-group form used by the COCG kernels (cocg.hip, group_walk): groups of
+    // `grp` consecutive rows of one pencil of a batch, the sorted union of
+    // their columns and an grp-wide coefficient block per union column.
+    // grp == 1 aliases the CSR arrays.
+    // The packed pencil holds the 4-row form; `grp`, gptr, gcol, gab and
+    // gab32 are the view a solve uses (set per solve; grp == 1 is the CSR).
+    int grp = 1;
+    int32_t* gptr = nullptr;    // groups + 1
+    int32_t* gcol = nullptr;    // union columns
+    double2* gab = nullptr;     // union columns * grp (a, b); zero where a row has no entry
+    float2* gab32 = nullptr;    // FP32 copy
+    int32_t* g4ptr = nullptr;
+    int32_t* g4col = nullptr;
+    double2* g4ab = nullptr;
+    float2* g4ab32 = nullptr;
+    int64_t g4nnz = 0;          // union columns of the 4-row form
+    int auto_grp = 1;           // 4 when the 4-row form saves at least 20% of the gathers
 };
 
 // XCD-aware remap of a flat work-group id: the hardware deals work-groups
@@ -60,6 +77,7 @@ struct TileGeom {
     const int64_t* base = nullptr;
     const int32_t* n = nullptr;
     const int32_t* row0 = nullptr;
+    const int32_t* g0 = nullptr;   // row-group index of the tile's row 0
 };
 
 // COCG state (cocg.hip).  FP64 path: x, u, p, pn.  Mixed path: x (FP64

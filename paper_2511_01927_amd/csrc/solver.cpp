@@ -92,6 +92,7 @@ struct HostPencil {
     int max_row = 0;
     std::vector<int64_t> prob_row0, prob_n;
     std::vector<double> prob_ainf;
+    std::vector<int32_t> prob_g4;   // first 4-row group of each problem (set by upload)
 };
 
 static void append_pencil(HostPencil& dst, const HostPencil& src) {
@@ -338,6 +339,71 @@ static void upload(const HostPencil& H, gep_pencil* P) {
     HIPCHK(hipMemcpy(D.ab32, ab32.data(), sizeof(float2) * H.nnz, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(D.dA, H.dA.data(), sizeof(double) * H.n, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(D.dB, H.dB.data(), sizeof(double) * H.n, hipMemcpyHostToDevice));
+    // 4-row groups of each problem: sorted union of the rows' columns and a
+    // 4-wide coefficient block per union column (zero where a row has no entry)
+    constexpr int G = 4;
+    std::vector<int32_t> gptr(1, 0), gcol, cols;
+    std::vector<double2> gab;
+    std::vector<int32_t> g0;
+    for (size_t pi = 0; pi < H.prob_row0.size(); ++pi) {
+        g0.push_back((int32_t)(gptr.size() - 1));
+        const int64_t r0 = H.prob_row0[pi], r1 = r0 + H.prob_n[pi];
+        for (int64_t gr = r0; gr < r1; gr += G) {
+            const int64_t ge = std::min(r1, gr + G);
+            cols.clear();
+            for (int64_t i = gr; i < ge; ++i)
+                cols.insert(cols.end(), H.colind.begin() + H.rowptr[i], H.colind.begin() + H.rowptr[i + 1]);
+            std::sort(cols.begin(), cols.end());
+            cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+            int32_t cur[G];
+            for (int r = 0; r < G; ++r) cur[r] = gr + r < ge ? H.rowptr[gr + r] : 0;
+            for (int32_t c : cols) {
+                gcol.push_back(c);
+                for (int r = 0; r < G; ++r) {
+                    double2 v = make_double2(0.0, 0.0);
+                    if (gr + r < ge && cur[r] < H.rowptr[gr + r + 1] && H.colind[cur[r]] == c) {
+                        v = make_double2(H.a[cur[r]], H.b[cur[r]]);
+                        ++cur[r];
+                    }
+                    gab.push_back(v);
+                }
+            }
+            if ((int64_t)gcol.size() >= (1ll << 31) - 1) fail(GEP_EINVAL, "row-group pattern >= 2^31");
+            gptr.push_back((int32_t)gcol.size());
+        }
+    }
+    P->h.prob_g4 = g0;
+    D.g4nnz = (int64_t)gcol.size();
+    D.auto_grp = (double)D.g4nnz <= 0.8 * (double)H.nnz ? G : 1;
+    D.g4ptr = (int32_t*)dalloc(sizeof(int32_t) * gptr.size());
+    D.g4col = (int32_t*)dalloc(sizeof(int32_t) * gcol.size());
+    D.g4ab = (double2*)dalloc(sizeof(double2) * gab.size());
+    D.g4ab32 = (float2*)dalloc(sizeof(float2) * gab.size());
+    std::vector<float2> gab32(gab.size());
+    for (size_t e = 0; e < gab.size(); ++e) gab32[e] = make_float2((float)gab[e].x, (float)gab[e].y);
+    HIPCHK(hipMemcpy(D.g4ptr, gptr.data(), sizeof(int32_t) * gptr.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(D.g4col, gcol.data(), sizeof(int32_t) * gcol.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(D.g4ab, gab.data(), sizeof(double2) * gab.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(D.g4ab32, gab32.data(), sizeof(float2) * gab.size(), hipMemcpyHostToDevice));
+}
+
+// The row-group view a solve uses: rg = 0 picks the pencil's automatic choice.
+static DevPencil group_view(const DevPencil& D, int rg) {
+    DevPencil v = D;
+    v.grp = rg == 0 ? D.auto_grp : rg;
+    if (v.grp == 4) {
+        v.gptr = D.g4ptr;
+        v.gcol = D.g4col;
+        v.gab = D.g4ab;
+        v.gab32 = D.g4ab32;
+    } else {
+        v.grp = 1;
+        v.gptr = D.rowptr;
+        v.gcol = D.colind;
+        v.gab = D.ab;
+        v.gab32 = D.ab32;
+    }
+    return v;
 }
 
 // ---- solve ----------------------------------------------------------------
@@ -395,7 +461,7 @@ static void choose_nrb(int64_t n, int n_active, int nrb_max, int& nrb) {
 
 class Solver {
    public:
-    Solver(gep_pencil* P, const SolveCfg& c) : P_(P), c_(c) {
+    Solver(gep_pencil* P, const SolveCfg& c) : P_(P), c_(c), dv_(group_view(P->d, c.o.row_group)) {
         s_ = (hipStream_t)c.o.stream;
         if (!s_) {
             // the legacy default stream cannot be captured into a graph: work on
@@ -429,7 +495,7 @@ class Solver {
         stats_.columns += per * K;
         // tile geometry and per-column metadata
         std::vector<int64_t> tbase(ntiles);
-        std::vector<int32_t> tn(ntiles), trow0(ntiles);
+        std::vector<int32_t> tn(ntiles), trow0(ntiles), tg0(ntiles);
         int64_t elems = 0, nmax = 0;
         for (int k = 0; k < K; ++k) {
             nmax = std::max(nmax, jobs[k].n);
@@ -438,6 +504,7 @@ class Solver {
                 tbase[tt] = elems;
                 tn[tt] = (int32_t)jobs[k].n;
                 trow0[tt] = (int32_t)jobs[k].row0;
+                tg0[tt] = dv_.grp == 4 ? P_->h.prob_g4[jobs[k].prob] : (int32_t)jobs[k].row0;
                 elems += jobs[k].n * kTile;
             }
         }
@@ -473,10 +540,12 @@ class Solver {
         CocgState S;
         S.ntiles = ntiles;
         const bool mixed = c_.o.precision == GEP_MIXED;
-        // small row blocks keep the +-stencil-offset gathers of concurrently
-        // running work-groups inside the caches
-        S.rpb = c_.o.rows_per_block > 0 ? c_.o.rows_per_block
-                                        : (int)std::max<int64_t>(32, (nmax + 4095) / 4096);
+        // small row blocks keep the gathers of concurrently running
+        // work-groups inside the caches; one row group per wave by default,
+        // and a whole number of groups per work-group
+        const int grp = dv_.grp;
+        S.rpb = c_.o.rows_per_block > 0 ? c_.o.rows_per_block : (grp == 4 ? 4 * kWaves : 2 * kWaves);
+        S.rpb = (S.rpb + grp - 1) / grp * grp;
         S.nrb = (int)((nmax + S.rpb - 1) / S.rpb);
         S.n = nmax;
         const int nrb = S.nrb;
@@ -496,7 +565,7 @@ class Solver {
         DBuf<double2> d_shifts(Wp), rho(Wp), alpha(Wp), beta(Wp);
         DBuf<int64_t> d_bsrc(Wp), d_tbase(ntiles), d_coff(K), d_soff(K);
         DBuf<int32_t> active(Wp), iters(Wp), tile_active(ntiles), tiles(ntiles), counts(4);
-        DBuf<int32_t> d_tn(ntiles), d_trow0(ntiles), d_cn(K);
+        DBuf<int32_t> d_tn(ntiles), d_trow0(ntiles), d_tg0(ntiles), d_cn(K);
         DBuf<double> bb(Wp), rr(Wp), rmax(Wp);
         DBuf<int32_t> flag(Wp);
         DBuf<double2> part_c((size_t)ntiles * nrb * kTile);
@@ -534,6 +603,7 @@ class Solver {
         S.geom.base = d_tbase.get();
         S.geom.n = d_tn.get();
         S.geom.row0 = d_trow0.get();
+        S.geom.g0 = d_tg0.get();
         std::vector<int32_t> tl(ntiles);
         for (int t = 0; t < ntiles; ++t) tl[t] = t;
         int32_t cnt0[4] = {ntiles, (int32_t)(per * K), 0, 0};
@@ -542,6 +612,7 @@ class Solver {
         HIPCHK(hipMemcpyAsync(d_tbase.get(), tbase.data(), sizeof(int64_t) * ntiles, hipMemcpyHostToDevice, s_));
         HIPCHK(hipMemcpyAsync(d_tn.get(), tn.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s_));
         HIPCHK(hipMemcpyAsync(d_trow0.get(), trow0.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(d_tg0.get(), tg0.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s_));
         HIPCHK(hipMemcpyAsync(d_coff.get(), coff.data(), sizeof(int64_t) * K, hipMemcpyHostToDevice, s_));
         HIPCHK(hipMemcpyAsync(d_soff.get(), soff.data(), sizeof(int64_t) * K, hipMemcpyHostToDevice, s_));
         HIPCHK(hipMemcpyAsync(d_cn.get(), cn.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice, s_));
@@ -550,9 +621,9 @@ class Solver {
         HIPCHK(hipMemcpyAsync(d_coef.get(), coef.data(), sizeof(double2) * coef.size(), hipMemcpyHostToDevice, s_));
         if (mixed) {
             HIPCHK(hipMemsetAsync(S.x, 0, sizeof(double2) * mv, s_));
-            HIPCHK(cocg32_init(P_->d, S, BV, ldbv, nrb, s_));
+            HIPCHK(cocg32_init(dv_, S, BV, ldbv, nrb, s_));
         } else {
-            HIPCHK(cocg_init(P_->d, S, BV, ldbv, nrb, s_));
+            HIPCHK(cocg_init(dv_, S, BV, ldbv, nrb, s_));
         }
         const double tol2 = c_.o.solve_tol * c_.o.solve_tol;
         const int max_iter = c_.o.max_iter;
@@ -561,7 +632,7 @@ class Solver {
         const double cb = mixed ? 8.0 : 16.0;   // bytes per complex element of the recurrence
         int n_act = ntiles;
         long it = 0;
-        const double mat_bytes = (double)P_->d.nnz * ((mixed ? 8.0 : 16.0) + 4.0) + 4.0 * (P_->d.n + 1);
+        const double mat_bytes = (double)dv_.nnz * ((mixed ? 8.0 : 16.0) + 4.0) + 4.0 * (dv_.n + 1);
         // One chunk = `every` COCG iterations (+ the mixed path's residual
         // replacement), enqueued eagerly or replayed from a captured HIP graph.
         // The chunk's launch grids depend on the active-tile count known to the
@@ -570,16 +641,16 @@ class Solver {
             for (int c = 0; c < every; ++c) {
                 if (timed) tm_.begin(T_SPMM);
                 if (mixed)
-                    HIPCHK(cocg32_spmm_dir(P_->d, S, n_act, nrb, s_));
+                    HIPCHK(cocg32_spmm_dir(dv_, S, n_act, nrb, s_));
                 else
-                    HIPCHK(cocg_spmm_dir(P_->d, S, n_act, nrb, s_));
+                    HIPCHK(cocg_spmm_dir(dv_, S, n_act, nrb, s_));
                 if (timed) tm_.end();
                 HIPCHK(cocg_reduce_alpha(S, n_act, nrb, s_));
                 if (timed) tm_.begin(T_UPDATE);
                 if (mixed)
-                    HIPCHK(cocg32_update(P_->d, S, n_act, nrb, s_));
+                    HIPCHK(cocg32_update(dv_, S, n_act, nrb, s_));
                 else
-                    HIPCHK(cocg_update(P_->d, S, n_act, nrb, s_));
+                    HIPCHK(cocg_update(dv_, S, n_act, nrb, s_));
                 if (timed) tm_.end();
                 HIPCHK(cocg_reduce_beta(S, n_act, nrb, tol2, max_iter, mixed ? 1 : 0, s_));
                 HIPCHK(cocg_compact(S, s_));
@@ -590,7 +661,7 @@ class Solver {
             }
             if (mixed) {
                 if (timed) tm_.begin(T_REPLACE);
-                HIPCHK(cocg32_replace(P_->d, S, BV, ldbv, n_act, nrb, tol2, s_));
+                HIPCHK(cocg32_replace(dv_, S, BV, ldbv, n_act, nrb, tol2, s_));
                 if (timed) tm_.end();
             }
         };
@@ -632,7 +703,7 @@ class Solver {
                 stats_.replacements += 1;
                 // fold: read/write x64 and x32; residual: read x64, write u32
                 stats_.replace_alg_bytes += (double)n_act * nmax * kTile * (32.0 + 16.0 + 16.0 + 8.0) +
-                                            (double)P_->d.nnz * 20.0;
+                                            (double)dv_.nnz * 20.0;
             }
             HIPCHK(hipMemcpyAsync(counts_h_, S.counts, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s_));
             HIPCHK(hipStreamSynchronize(s_));
@@ -649,7 +720,7 @@ class Solver {
             int32_t cntall[4] = {ntiles, (int32_t)(per * K), 0, 0};
             HIPCHK(hipMemcpyAsync(S.tiles, tl.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s_));
             HIPCHK(hipMemcpyAsync(S.counts, cntall, sizeof(cntall), hipMemcpyHostToDevice, s_));
-            HIPCHK(cocg32_fold(P_->d, S, ntiles, nrb, s_));
+            HIPCHK(cocg32_fold(dv_, S, ntiles, nrb, s_));
         }
         stats_.cocg_iters += it;
         // per-column iteration counts -> exact tile work for the byte count
@@ -709,7 +780,7 @@ class Solver {
     // job.
     void rayleigh_ritz_batch(const double* Sall, const std::vector<int64_t>& soff,
                              const std::vector<Job>& jobs, int r0, std::vector<ContourOut>& outs) {
-        const DevPencil& D = P_->d;
+        const DevPencil& D = dv_;
         const int K = (int)jobs.size();
         const size_t tot = (size_t)soff[K], rr2 = (size_t)r0 * r0;
         int64_t nmax = 0;
@@ -865,6 +936,7 @@ class Solver {
 
     gep_pencil* P_;
     SolveCfg c_;
+    DevPencil dv_;   // the pencil with the row-group view of this solve
     hipStream_t s_ = nullptr;
     hipStream_t own_ = nullptr;
     Timer tm_;
@@ -1152,6 +1224,7 @@ void gep_opts_default(gep_opts* o) {
     o->verbose = 0;
     o->use_graph = 1;
     o->blocks = nullptr;
+    o->row_group = 0;
 }
 
 const char* gep_strerror(int st) {
@@ -1210,6 +1283,10 @@ static int validate_problem(const gep_contour* contours, int K, int N, int M, in
     if (o->precision != GEP_FP64 && o->precision != GEP_MIXED) { gep::set_error("bad precision"); return GEP_EINVAL; }
     if (!(o->solve_tol > 0.0) || o->max_iter < 1) { gep::set_error("bad solve_tol/max_iter"); return GEP_EINVAL; }
     if (o->rows_per_block < 0) { gep::set_error("rows_per_block must be >= 0"); return GEP_EINVAL; }
+    if (o->row_group != 0 && o->row_group != 1 && o->row_group != 4) {
+        gep::set_error("row_group must be 0, 1 or 4");
+        return GEP_EINVAL;
+    }
     for (int k = 0; k < K; ++k) {
         const gep_contour& c = contours[k];
         if (!std::isfinite(c.center) || !std::isfinite(c.radius) || !(c.radius > 0.0) ||

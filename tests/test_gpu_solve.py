@@ -58,10 +58,18 @@ def assert_pairs_match(got, lam_ref, X_ref, B):
         assert s.min() >= 1 - 1e-8, (g, s)
 
 
+def _converged(ref, tol=RES):
+    """The oracle's converged pairs.  It also returns, flagged, Ritz pairs in
+    a keep window that still miss tol after refinement (spurious values of
+    the filter); those are not eigenpairs and are not compared."""
+    ok = ref["resid"] <= tol
+    return ref["evals"][ok], ref["evecs"][:, ok]
+
+
 def _oracle_refs(w, **kw):
     ref = oracle.oracle_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol,
                                  seed=w.seed, **kw)
-    return ref["evals"], ref["evecs"]
+    return _converged(ref)
 
 
 def test_small_fem1d_vs_oracle(lib):
@@ -150,7 +158,7 @@ def test_two_contours_share_cut_without_duplicates(lib):
     cont = configs.uniform_contours(lo, hi, 2, 0.2)
     got = lib.gep_ci_solve(w.A, w.B, cont, 16, 4, 16, 1e-8, seed=5)
     ref = oracle.oracle_ci_solve(w.A, w.B, cont, 16, 4, 16, 1e-8, seed=5)
-    assert_pairs_match(got, ref["evals"], ref["evecs"], w.B)
+    assert_pairs_match(got, *_converged(ref), w.B)
     assert np.all(np.diff(got["evals"]) > 0)
 
 
@@ -184,7 +192,7 @@ def test_batch_of_uneven_pencils_vs_oracle(lib):
     got = lib.gep_ci_solve_batch(probs, 16, 4, 16, 1e-8, seed=11)
     for p, w in enumerate((w1, w2, w3)):
         ref = oracle.oracle_ci_solve(w.A, w.B, w.contours, 16, 4, 16, 1e-8, seed=11 + p)
-        assert_pairs_match(got[p], ref["evals"], ref["evecs"], w.B)
+        assert_pairs_match(got[p], *_converged(ref), w.B)
         assert all(c["problem"] == p for c in got[p]["stats"]["contours"])
 
 
@@ -217,6 +225,55 @@ def test_per_contour_block_sizes_vs_oracle(lib):
     lams, Xs = [], []
     for k in range(2):
         ref = oracle.oracle_ci_solve(w.A, w.B, cont[k:k + 1], 16, 4, blocks[k], 1e-8, V=V[:, :blocks[k]])
-        lams.append(ref["evals"])
-        Xs.append(ref["evecs"])
+        lam_k, X_k = _converged(ref)
+        lams.append(lam_k)
+        Xs.append(X_k)
     assert_pairs_match(got, np.concatenate(lams), np.concatenate(Xs, axis=1), w.B)
+
+
+@pytest.mark.parametrize("prec", ["fp64"])
+def test_row_groups_match_csr_and_oracle(lib, prec):
+    """The COCG kernels walk 4-row groups (union of the rows' columns, zero
+    padded coefficients) or plain CSR rows.  Each row's K p' is the same
+    either way; the dot products are summed over different row sets per
+    wave, so the two solves agree to the parity bar, not bit for bit.  The
+    31 x 29 grid has n = 899 rows, so the last group is short."""
+    w = _var2d(nx=31, ny=29, seed=9, first=31, last=60, k=2)
+    assert w.n % 4 != 0
+    r = {g: lib.gep_ci_solve(w.A, w.B, w.contours, 32, 4, 16, 1e-8, seed=5, precision=prec, row_group=g,
+                             rows_per_block=16)
+         for g in (1, 4)}
+    assert r[1]["evals"].size > 0
+    assert_pairs_match(r[4], r[1]["evals"], r[1]["evecs"], w.B)
+    ref = oracle.oracle_ci_solve(w.A, w.B, w.contours, 32, 4, 16, 1e-8, seed=5)
+    assert_pairs_match(r[4], *_converged(ref), w.B)
+
+
+def test_row_groups_in_a_batch_of_uneven_pencils(lib):
+    """Groups never cross the pencils of a batch (sizes 899, 401, 703), and
+    row blocks past a shorter pencil's end stay empty."""
+    w1 = _var2d(nx=31, ny=29, seed=9, first=31, last=60, k=2)
+    w2 = configs.config_fem1d(n=401, first=31, last=40, n_nodes=16, moments=4, block=16, seed=11)
+    w3 = configs.config_fem1d(n=703, first=51, last=62, n_nodes=16, moments=4, block=16, seed=11)
+    probs = [(w.A, w.B, w.contours) for w in (w1, w2, w3)]
+    assert all(w.n % 4 for w in (w1, w2, w3))
+    a = lib.gep_ci_solve_batch(probs, 16, 4, 16, 1e-8, seed=3, row_group=1)
+    b = lib.gep_ci_solve_batch(probs, 16, 4, 16, 1e-8, seed=3, row_group=4)
+    for p, w in enumerate((w1, w2, w3)):
+        assert a[p]["evals"].size > 0
+        assert_pairs_match(b[p], a[p]["evals"], a[p]["evecs"], w.B)
+        ref = oracle.oracle_ci_solve(w.A, w.B, w.contours, 16, 4, 16, 1e-8, seed=3 + p)
+        assert_pairs_match(b[p], *_converged(ref), w.B)
+
+
+@pytest.mark.xfail(reason="FP32 COCG stalls on the shifted systems nearest the real axis; "
+                          "FP64 completion of stalled columns not built yet", strict=False)
+def test_row_groups_mixed_precision(lib):
+    """FP32 recurrence on the 4-row group kernels vs plain CSR rows."""
+    w = _var2d()
+    r = {g: lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed,
+                             precision="mixed", row_group=g)
+         for g in (1, 4)}
+    lam, X = _oracle_refs(w)
+    for g in (1, 4):
+        assert_pairs_match(r[g], lam, X, w.B)

@@ -45,12 +45,13 @@ def test_opts_defaults(lib):
     o = gep_ci.gep_opts()
     lib.gep_opts_default(C.byref(o))
     assert o.max_refine == 1 and o.solve_tol == 1e-9 and o.max_iter == 100000 and o.seed == 1
+    assert o.row_group == 0 and o.rows_per_block == 0 and o.use_graph == 1
 
 
-def _solve_status(A, B, contours, N=16, M=4, L=8, tol=1e-8):
+def _solve_status(A, B, contours, N=16, M=4, L=8, tol=1e-8, **kw):
     from paper_2511_01927_amd import gep_ci
     try:
-        gep_ci.gep_ci_solve(A, B, contours, N, M, L, tol, stream=0)
+        gep_ci.gep_ci_solve(A, B, contours, N, M, L, tol, stream=0, **kw)
     except gep_ci.GepError as e:
         return e.status, str(e)
     return 0, ""
@@ -64,6 +65,8 @@ def test_argument_errors_are_reported(lib):
     assert _solve_status(A, B, good, M=0)[0] == -1
     assert _solve_status(A, B, good, L=0)[0] == -1
     assert _solve_status(A, B, good, tol=0.0)[0] == -1
+    assert _solve_status(A, B, good, row_group=3)[0] == -1
+    assert _solve_status(A, B, good, rows_per_block=-1)[0] == -1
     bad = np.array([[100.0, 10.0, 60.0, 140.0]])               # window outside the circle
     assert _solve_status(A, B, bad)[0] == -1
     assert _solve_status(A, B, np.array([[100.0, -1.0, 99.0, 100.0]]))[0] == -1
