@@ -84,6 +84,16 @@ def main():
     ap.add_argument("--stats-out", default=None)
     ap.add_argument("--verbose", type=int, default=0,
                     help="progress line from the solver every this many COCG iterations")
+    ap.add_argument("--max-iter", type=int, default=None,
+                    help="cap the COCG iterations (profiling runs only: the solve is then "
+                         "incomplete and the acceptance count is not meaningful)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the steps, copy a 1 GiB device buffer three times; hardware "
+                         "counters of that copy calibrate the HBM byte counters")
+    ap.add_argument("--counters", action="store_true",
+                    help="run for hardware-counter collection: no HIP-event timing around the "
+                         "kernels (graph replay as in production), copy probe on; use with "
+                         "--max-iter")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -104,6 +114,11 @@ def main():
     pencil = gep_ci.Pencil(w.A, w.B, stream=stream)
     kw = dict(seed=w.seed, precision=args.precision, solve_tol=args.solve_tol, stream=stream,
               verbose=args.verbose)
+    if args.max_iter:
+        kw["max_iter"] = args.max_iter
+    timed = not args.counters
+    if args.counters:
+        args.copy_probe = True
     for i in range(args.warmup):
         r = pencil.solve(w.contours, w.n_nodes, w.moments, w.block, w.tol, **kw)
         print(f"# warmup {i}: {r['evals'].size} pairs, {r['stats']['wall_ms']:.0f} ms", flush=True)
@@ -111,11 +126,19 @@ def main():
     t0 = time.perf_counter()
     results = []
     for i in range(args.steps):
-        r = pencil.solve(w.contours, w.n_nodes, w.moments, w.block, w.tol, timing=True, **kw)
+        r = pencil.solve(w.contours, w.n_nodes, w.moments, w.block, w.tol, timing=timed, **kw)
         results.append(r)
         print(f"# step {i}: {r['evals'].size} pairs, {r['stats']['wall_ms']:.0f} ms", flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    if args.copy_probe:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy probe: 3 copies of {src.numel() * 8} bytes", flush=True)
 
     good = 0
     for r in results:

@@ -381,6 +381,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce_init(int nrb, const double2* 
                                                         double2* __restrict__ beta,
                                                         int32_t* __restrict__ active,
                                                         int32_t* __restrict__ iters,
+                                                        double* __restrict__ rbest,
+                                                        int32_t* __restrict__ stall,
+                                                        int32_t* __restrict__ stalled,
                                                         int32_t* __restrict__ tile_active) {
     __shared__ double2 sc[kWaves][kTile];
     __shared__ double sr[kWaves][kTile];
@@ -411,6 +414,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce_init(int nrb, const double2* 
         rr[col] = d;
         rmax[col] = d;
         flag[col] = 0;
+        rbest[col] = d;
+        stall[col] = 0;
+        stalled[col] = 0;
         beta[col] = make_double2(0.0, 0.0);
         iters[col] = 0;
         const int act = d > 0.0 ? 1 : 0;
@@ -464,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_beta(
     double2* __restrict__ rho, double2* __restrict__ beta, const double* __restrict__ bb,
     double* __restrict__ rr, double* __restrict__ rmax, int32_t* __restrict__ flag,
     int32_t* __restrict__ active, int32_t* __restrict__ iters, int32_t* __restrict__ tile_active,
-    double tol2, int max_iter, int hold) {
+    int32_t* __restrict__ stalled, double tol2, int max_iter, int hold) {
     __shared__ double2 sc[kWaves][kTile];
     __shared__ double sr[kWaves][kTile];
     __shared__ int cnt;
@@ -510,6 +516,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce_beta(
             if ((conv && !hold) || it >= max_iter || !(m2 > 0.0) || !isfinite(s)) {
                 a = 0;
                 active[col] = 0;
+                // the FP32 recurrence ran out of iterations or broke down:
+                // the FP64 completion takes the column over
+                if (hold && !conv) stalled[col] = 1;
             } else {
                 b = cdiv(rn, ro);
                 rho[col] = rn;
@@ -584,13 +593,16 @@ __global__ __launch_bounds__(kBlock) void k_fold(TileGeom geom, double2* __restr
     }
 }
 
-// r = b - K x64 in FP64, u32 = D^-1 r; partials of r^T u and ||r||^2.
+// r = b - K x64 in FP64, u = D^-1 r stored as UT (float2 for the mixed
+// replacement, double2 for the FP64 completion) for the flagged columns;
+// partials of r^T u and ||r||^2.
+template <typename UT>
 __global__ __launch_bounds__(kBlock) void k_true_residual(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
     const double2* __restrict__ ab, TileGeom geom, const double* __restrict__ dA,
     const double* __restrict__ dB, const double2* __restrict__ shifts,
     const int64_t* __restrict__ bsrc, const double* __restrict__ BV, int64_t ldbv,
-    const double2* __restrict__ X64, float2* __restrict__ U32, const int32_t* __restrict__ flag,
+    const double2* __restrict__ X64, UT* __restrict__ Uo, const int32_t* __restrict__ flag,
     const int32_t* __restrict__ tiles, const int32_t* __restrict__ n_active, int nrb, int rpb,
     double2* part_c, double* part_r) {
     BlockMap m;
@@ -625,8 +637,10 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(
         const double2 D = make_double2(z.x * dB[g] - dA[g], z.y * dB[g]);
         const double2 uv = cdiv(make_double2(rx, ry), D);
         if (fl) {
-            const float2 us = make_float2((float)uv.x, (float)uv.y);
-            U32[base + (size_t)i * kTile + m.lane] = us;
+            UT us;
+            us.x = (decltype(us.x))uv.x;
+            us.y = (decltype(us.y))uv.y;
+            Uo[base + (size_t)i * kTile + m.lane] = us;
             const double ux = (double)us.x, uy = (double)us.y;
             rho.x += rx * ux - ry * uy;
             rho.y += rx * uy + ry * ux;
@@ -636,6 +650,10 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(
     block_partials(m, nrb, rho, rr, part_c, part_r);
 }
 
+// Replacements in a row without progress of the true residual after which a
+// column leaves the FP32 recurrence for the FP64 completion.
+constexpr int kStallLimit = 3;
+
 // rho <- true r^T u, beta rescaled to rho_true / rho_old, convergence on the
 // true residual.
 __global__ __launch_bounds__(kBlock) void k_reduce_replace(
@@ -643,7 +661,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce_replace(
     const double2* __restrict__ part_c, const double* __restrict__ part_r,
     double2* __restrict__ rho, double2* __restrict__ beta, const double* __restrict__ bb,
     double* __restrict__ rr, double* __restrict__ rmax, int32_t* __restrict__ flag,
-    int32_t* __restrict__ active, int32_t* __restrict__ tile_active, double tol2) {
+    int32_t* __restrict__ active, int32_t* __restrict__ tile_active, double* __restrict__ rbest,
+    int32_t* __restrict__ stall, int32_t* __restrict__ stalled, double tol2) {
     __shared__ double2 sc[kWaves][kTile];
     __shared__ double sr[kWaves][kTile];
     __shared__ int cnt;
@@ -677,10 +696,23 @@ __global__ __launch_bounds__(kBlock) void k_reduce_replace(
             rmax[col] = s;
             const double2 rec = rho[col];
             const double m2 = rec.x * rec.x + rec.y * rec.y;
-            if (s <= tol2 * bb[col] || !isfinite(s) || !(m2 > 0.0)) {
+            // progress of the true residual between replacements: the FP32
+            // recurrence is given up after kStallLimit replacements in a row
+            // that did not reduce ||r||^2 by 4x below its best
+            int st = stall[col];
+            if (s < 0.25 * rbest[col]) {
+                rbest[col] = s;
+                st = 0;
+            } else {
+                ++st;
+            }
+            stall[col] = st;
+            const bool done = s <= tol2 * bb[col];
+            if (done || !isfinite(s) || !(m2 > 0.0) || st >= kStallLimit) {
                 a = 0;
                 active[col] = 0;
                 beta[col] = make_double2(0.0, 0.0);
+                if (!done) stalled[col] = 1;
             } else {
                 // beta = rho_rec / rho_old was set by k_reduce_beta; rescale
                 const double2 f = cdiv(rn, rec);
@@ -689,6 +721,60 @@ __global__ __launch_bounds__(kBlock) void k_reduce_replace(
                 rho[col] = rn;
             }
         }
+        if (a) atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) tile_active[tile] = cnt;
+}
+
+
+// FP64 completion: the stalled columns restart from their true residual
+// (rho = r^T u, beta = 0) and become active again; everything else stays
+// inactive.
+__global__ __launch_bounds__(kBlock) void k_reduce_restart(
+    int nrb, const int32_t* __restrict__ tiles, const int32_t* __restrict__ n_active,
+    const double2* __restrict__ part_c, const double* __restrict__ part_r,
+    double2* __restrict__ rho, double2* __restrict__ beta, const double* __restrict__ bb,
+    double* __restrict__ rr, int32_t* __restrict__ stalled, int32_t* __restrict__ active,
+    int32_t* __restrict__ tile_active, double tol2) {
+    __shared__ double2 sc[kWaves][kTile];
+    __shared__ double sr[kWaves][kTile];
+    __shared__ int cnt;
+    const int slot = blockIdx.x;
+    if (slot >= n_active[0]) return;
+    const int tile = tiles[slot];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double2 rn = make_double2(0.0, 0.0);
+    double s = 0.0;
+    for (int rb = wave; rb < nrb; rb += kWaves) {
+        const size_t o = ((size_t)tile * nrb + rb) * kTile + lane;
+        rn.x += part_c[o].x;
+        rn.y += part_c[o].y;
+        s += part_r[o];
+    }
+    sc[wave][lane] = rn;
+    sr[wave][lane] = s;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    if (wave == 0) {
+        for (int w = 1; w < kWaves; ++w) {
+            rn.x += sc[w][lane].x;
+            rn.y += sc[w][lane].y;
+            s += sr[w][lane];
+        }
+        const int col = tile * kTile + lane;
+        int a = 0;
+        if (stalled[col]) {
+            stalled[col] = 0;
+            rr[col] = s;
+            beta[col] = make_double2(0.0, 0.0);
+            const double m2 = rn.x * rn.x + rn.y * rn.y;
+            if (s > tol2 * bb[col] && isfinite(s) && m2 > 0.0) {
+                a = 1;
+                rho[col] = rn;
+            }
+        }
+        active[col] = a;
         if (a) atomicAdd(&cnt, 1);
     }
     __syncthreads();
@@ -705,7 +791,8 @@ hipError_t launch_init_t(const DevPencil& P, CocgState& S, VT* x, VT* u, VT* p, 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_init, dim3(S.ntiles), dim3(kBlock), 0, s, nrb, S.part_c, S.part_r,
-                       S.rho, S.bb, S.rr, S.rmax, S.flag, S.beta, S.active, S.iters, S.tile_active);
+                       S.rho, S.bb, S.rr, S.rmax, S.flag, S.beta, S.active, S.iters, S.rbest,
+                       S.stall, S.stalled, S.tile_active);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return cocg_compact(S, s);
@@ -797,7 +884,7 @@ hipError_t cocg32_replace(const DevPencil& P, CocgState& S, const double* BV, in
     if (e != hipSuccess) return e;
     const int rpb = S.rpb;
     const int grid = pad8(n_active_host * nrb);
-    hipLaunchKernelGGL(k_true_residual, dim3(grid), dim3(kBlock), 0, s, P.rowptr, P.colind, P.ab,
+    hipLaunchKernelGGL((k_true_residual<float2>), dim3(grid), dim3(kBlock), 0, s, P.rowptr, P.colind, P.ab,
                        S.geom, P.dA, P.dB, S.shifts, S.bsrc, BV, ldbv, S.x, S.u32, S.flag,
                        S.tiles, S.counts, nrb, rpb, S.part_c, S.part_r);
     e = hipGetLastError();
@@ -809,7 +896,30 @@ hipError_t cocg32_replace(const DevPencil& P, CocgState& S, const double* BV, in
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_replace, dim3(n_active_host), dim3(kBlock), 0, s, cnt, S.tiles,
                        S.counts, pc, pr, S.rho, S.beta, S.bb, S.rr, S.rmax, S.flag,
-                       S.active, S.tile_active, tol2);
+                       S.active, S.tile_active, S.rbest, S.stall, S.stalled, tol2);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return cocg_compact(S, s);
+}
+
+hipError_t cocg64_restart(const DevPencil& P, CocgState& S, const double* BV, int64_t ldbv,
+                          int nrb, double tol2, hipStream_t s) {
+    const int n_all = S.ntiles;
+    const int rpb = S.rpb;
+    const int grid = pad8(n_all * nrb);
+    hipLaunchKernelGGL((k_true_residual<double2>), dim3(grid), dim3(kBlock), 0, s, P.rowptr,
+                       P.colind, P.ab, S.geom, P.dA, P.dB, S.shifts, S.bsrc, BV, ldbv, S.x, S.u,
+                       S.stalled, S.tiles, S.counts, nrb, rpb, S.part_c, S.part_r);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const double2* pc;
+    const double* pr;
+    int cnt;
+    e = fold_partials(S, n_all, nrb, true, pc, pr, cnt, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_restart, dim3(n_all), dim3(kBlock), 0, s, cnt, S.tiles, S.counts,
+                       pc, pr, S.rho, S.beta, S.bb, S.rr, S.stalled, S.active, S.tile_active,
+                       tol2);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return cocg_compact(S, s);
@@ -854,7 +964,7 @@ hipError_t cocg_reduce_beta(CocgState& S, int n_active_host, int nrb, double tol
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_beta, dim3(n_active_host), dim3(kBlock), 0, s, cnt, S.tiles,
                        S.counts, pc, pr, S.rho, S.beta, S.bb, S.rr, S.rmax, S.flag,
-                       S.active, S.iters, S.tile_active, tol2, max_iter, hold);
+                       S.active, S.iters, S.tile_active, S.stalled, tol2, max_iter, hold);
     return hipGetLastError();
 }
 

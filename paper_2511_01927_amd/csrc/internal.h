@@ -103,6 +103,9 @@ struct CocgState {
     double* rr = nullptr;        // [W] ||r||^2
     double* rmax = nullptr;      // [W] mixed: max recursive ||r||^2 since the last replacement
     int32_t* flag = nullptr;     // [W] mixed: replace this column's residual at the next check
+    double* rbest = nullptr;     // [W] mixed: smallest true ||r||^2 seen at a replacement
+    int32_t* stall = nullptr;    // [W] mixed: replacements since rbest last fell 4x
+    int32_t* stalled = nullptr;  // [W] mixed: FP32 recurrence gave up; finish in FP64
     int32_t* active = nullptr;   // [W]
     int32_t* iters = nullptr;    // [W]
     int32_t* tile_active = nullptr;  // [ntiles] active columns per tile
@@ -134,6 +137,11 @@ hipError_t cocg32_spmm_dir(const DevPencil& P, CocgState& S, int n_active_host, 
                            hipStream_t s);
 hipError_t cocg32_update(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
                          hipStream_t s);
+// FP64 completion of the columns the FP32 recurrence gave up on: r = b - K x
+// in FP64, u = D^-1 r, p = 0, beta = 0; those columns become the active set
+// of an FP64 COCG run that continues from x.  u, p and pn must be zero.
+hipError_t cocg64_restart(const DevPencil& P, CocgState& S, const double* BV, int64_t ldbv,
+                          int nrb, double tol2, hipStream_t s);
 hipError_t cocg32_fold(const DevPencil& P, CocgState& S, int n_active_host, int nrb,
                        hipStream_t s);
 hipError_t cocg32_replace(const DevPencil& P, CocgState& S, const double* BV, int64_t ldbv,

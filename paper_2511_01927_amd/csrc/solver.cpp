@@ -450,6 +450,8 @@ struct Stats {
     double replace_alg_bytes = 0.0;
     long columns = 0;
     int waves = 0;
+    long fp64_columns = 0;        // mixed: columns finished by the FP64 recurrence
+    long fp64_iters = 0;          // mixed: iterations of that FP64 completion
 };
 
 static void choose_nrb(int64_t n, int n_active, int nrb_max, int& nrb) {
@@ -567,7 +569,8 @@ class Solver {
         DBuf<int32_t> active(Wp), iters(Wp), tile_active(ntiles), tiles(ntiles), counts(4);
         DBuf<int32_t> d_tn(ntiles), d_trow0(ntiles), d_tg0(ntiles), d_cn(K);
         DBuf<double> bb(Wp), rr(Wp), rmax(Wp);
-        DBuf<int32_t> flag(Wp);
+        DBuf<int32_t> flag(Wp), stall(Wp), stalled(Wp);
+        DBuf<double> rbest(Wp);
         DBuf<double2> part_c((size_t)ntiles * nrb * kTile);
         DBuf<double> part_r((size_t)ntiles * nrb * kTile);
         S.G = nrb > 64 ? 32 : 0;
@@ -593,6 +596,9 @@ class Solver {
         S.rr = rr.get();
         S.rmax = rmax.get();
         S.flag = flag.get();
+        S.rbest = rbest.get();
+        S.stall = stall.get();
+        S.stalled = stalled.get();
         S.active = active.get();
         S.iters = iters.get();
         S.tile_active = tile_active.get();
@@ -632,7 +638,10 @@ class Solver {
         const double cb = mixed ? 8.0 : 16.0;   // bytes per complex element of the recurrence
         int n_act = ntiles;
         long it = 0;
-        const double mat_bytes = (double)dv_.nnz * ((mixed ? 8.0 : 16.0) + 4.0) + 4.0 * (dv_.n + 1);
+        // the mixed path runs the FP32 recurrence first, then finishes the
+        // columns it gave up on with the FP64 recurrence
+        bool fp32 = mixed;
+        auto mat_bytes = [&]() { return (double)dv_.nnz * ((fp32 ? 8.0 : 16.0) + 4.0) + 4.0 * (dv_.n + 1); };
         // One chunk = `every` COCG iterations (+ the mixed path's residual
         // replacement), enqueued eagerly or replayed from a captured HIP graph.
         // The chunk's launch grids depend on the active-tile count known to the
@@ -640,26 +649,29 @@ class Solver {
         auto enqueue_chunk = [&](bool timed) {
             for (int c = 0; c < every; ++c) {
                 if (timed) tm_.begin(T_SPMM);
-                if (mixed)
+                if (fp32)
                     HIPCHK(cocg32_spmm_dir(dv_, S, n_act, nrb, s_));
                 else
                     HIPCHK(cocg_spmm_dir(dv_, S, n_act, nrb, s_));
                 if (timed) tm_.end();
                 HIPCHK(cocg_reduce_alpha(S, n_act, nrb, s_));
                 if (timed) tm_.begin(T_UPDATE);
-                if (mixed)
+                if (fp32)
                     HIPCHK(cocg32_update(dv_, S, n_act, nrb, s_));
                 else
                     HIPCHK(cocg_update(dv_, S, n_act, nrb, s_));
                 if (timed) tm_.end();
-                HIPCHK(cocg_reduce_beta(S, n_act, nrb, tol2, max_iter, mixed ? 1 : 0, s_));
+                // the FP64 completion continues the columns' iteration counts:
+                // its cap is the sum of both phases' budgets
+                const int cap = (mixed && !fp32) ? (int)std::min<long>(2L * max_iter, INT32_MAX) : max_iter;
+                HIPCHK(cocg_reduce_beta(S, n_act, nrb, tol2, cap, fp32 ? 1 : 0, s_));
                 HIPCHK(cocg_compact(S, s_));
-                if (mixed)
+                if (fp32)
                     std::swap(S.p32, S.pn32);
                 else
                     std::swap(S.p, S.pn);
             }
-            if (mixed) {
+            if (fp32) {
                 if (timed) tm_.begin(T_REPLACE);
                 HIPCHK(cocg32_replace(dv_, S, BV, ldbv, n_act, nrb, tol2, s_));
                 if (timed) tm_.end();
@@ -674,7 +686,9 @@ class Solver {
                 if (*e) (void)hipGraphExecDestroy(*e);
             }
         } gguard{&gexec};
-        while (n_act > 0 && it < max_iter) {
+        auto run_phase = [&]() {
+        long it_phase = 0;
+        while (n_act > 0 && it_phase < max_iter) {
             if (use_graph) {
                 if (graph_nact != n_act) {
                     if (gexec) {
@@ -696,10 +710,11 @@ class Solver {
                 enqueue_chunk(true);
             }
             stats_.spmm_launches += every;
-            stats_.spmm_alg_bytes += every * mat_bytes;
-            stats_.update_alg_bytes += every * mat_bytes;
+            stats_.spmm_alg_bytes += every * mat_bytes();
+            stats_.update_alg_bytes += every * mat_bytes();
             it += every;
-            if (mixed) {
+            it_phase += every;
+            if (fp32) {
                 stats_.replacements += 1;
                 // fold: read/write x64 and x32; residual: read x64, write u32
                 stats_.replace_alg_bytes += (double)n_act * nmax * kTile * (32.0 + 16.0 + 16.0 + 8.0) +
@@ -715,27 +730,76 @@ class Solver {
                 std::fflush(stderr);
             }
         }
+        };
+        // per-column iteration counts -> exact tile work for the byte count
+        std::vector<int32_t> its(Wp), its0(Wp, 0);
+        auto account = [&](double bytes_per_elem) {
+            HIPCHK(hipMemcpyAsync(its.data(), S.iters, sizeof(int32_t) * Wp, hipMemcpyDeviceToHost, s_));
+            HIPCHK(hipStreamSynchronize(s_));
+            for (int t = 0; t < ntiles; ++t) {
+                int mx = 0;
+                for (int l = 0; l < kTile; ++l) {
+                    const size_t c = (size_t)t * kTile + l;
+                    mx = std::max(mx, its[c] - its0[c]);
+                }
+                stats_.tile_iters += mx;
+                const double tile_bytes = (double)tn[t] * kTile * bytes_per_elem;
+                // kernel A: read u, p, write p' (3 passes); kernel B: read x, u, p', write x, u (5)
+                stats_.spmm_alg_bytes += mx * 3.0 * tile_bytes;
+                stats_.update_alg_bytes += mx * 5.0 * tile_bytes;
+            }
+            its0 = its;
+        };
+        run_phase();
+        account(cb);
         if (mixed) {
             // fold the remaining FP32 corrections of every tile
             int32_t cntall[4] = {ntiles, (int32_t)(per * K), 0, 0};
             HIPCHK(hipMemcpyAsync(S.tiles, tl.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s_));
             HIPCHK(hipMemcpyAsync(S.counts, cntall, sizeof(cntall), hipMemcpyHostToDevice, s_));
             HIPCHK(cocg32_fold(dv_, S, ntiles, nrb, s_));
+            // FP64 completion of the columns the FP32 recurrence gave up on
+            std::vector<int32_t> st(Wp);
+            HIPCHK(hipMemcpyAsync(st.data(), S.stalled, sizeof(int32_t) * Wp, hipMemcpyDeviceToHost, s_));
+            HIPCHK(hipStreamSynchronize(s_));
+            long n_stalled = 0;
+            for (int32_t v : st) n_stalled += v != 0;
+            if (n_stalled > 0) {
+                stats_.fp64_columns += n_stalled;
+                HIPCHK(hipStreamSynchronize(s_));
+                x32.release();
+                u32.release();
+                p32.release();
+                pn32.release();
+                S.x32 = S.u32 = S.p32 = S.pn32 = nullptr;
+                u.alloc(mv);
+                p.alloc(mv);
+                pn.alloc(mv);
+                S.u = u.get();
+                S.p = p.get();
+                S.pn = pn.get();
+                HIPCHK(hipMemsetAsync(S.u, 0, sizeof(double2) * mv, s_));
+                HIPCHK(hipMemsetAsync(S.p, 0, sizeof(double2) * mv, s_));
+                HIPCHK(hipMemsetAsync(S.pn, 0, sizeof(double2) * mv, s_));
+                HIPCHK(hipMemcpyAsync(S.tiles, tl.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s_));
+                HIPCHK(hipMemcpyAsync(S.counts, cntall, sizeof(cntall), hipMemcpyHostToDevice, s_));
+                HIPCHK(cocg64_restart(dv_, S, BV, ldbv, nrb, tol2, s_));
+                HIPCHK(hipMemcpyAsync(counts_h_, S.counts, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s_));
+                HIPCHK(hipStreamSynchronize(s_));
+                n_act = counts_h_[0];
+                fp32 = false;
+                if (gexec) {
+                    HIPCHK(hipGraphExecDestroy(gexec));
+                    gexec = nullptr;
+                }
+                graph_nact = -1;
+                const long it0 = it;
+                run_phase();
+                stats_.fp64_iters += it - it0;
+                account(16.0);
+            }
         }
         stats_.cocg_iters += it;
-        // per-column iteration counts -> exact tile work for the byte count
-        std::vector<int32_t> its(Wp);
-        HIPCHK(hipMemcpyAsync(its.data(), S.iters, sizeof(int32_t) * Wp, hipMemcpyDeviceToHost, s_));
-        HIPCHK(hipStreamSynchronize(s_));
-        for (int t = 0; t < ntiles; ++t) {
-            int mx = 0;
-            for (int l = 0; l < kTile; ++l) mx = std::max(mx, its[(size_t)t * kTile + l]);
-            stats_.tile_iters += mx;
-            const double tile_bytes = (double)tn[t] * kTile * cb;
-            // kernel A: read u, p, write p' (3 passes); kernel B: read x, u, p', write x, u (5)
-            stats_.spmm_alg_bytes += mx * 3.0 * tile_bytes;
-            stats_.update_alg_bytes += mx * 5.0 * tile_bytes;
-        }
         // moments
         auto Sall = std::make_shared<DBuf<double>>(std::max<int64_t>(soff[K], 1));
         tm_.begin(T_MOMENTS);
@@ -948,8 +1012,13 @@ class Solver {
 static size_t bytes_per_job(int64_t n, int NH, int L, int M, bool mixed) {
     const size_t W = (size_t)((NH * L + kTile - 1) / kTile) * kTile;
     const size_t r = (size_t)L * M;
-    const size_t mv = mixed ? (size_t)n * W * (16 + 8 * 4) : (size_t)n * W * 16 * 4;
-    return mv + (size_t)n * r * 8 * 9 + (size_t)W * 160 + (size_t)W / kTile * 2048 * kTile * 24;
+    // FP64: x, u, p, pn.  Mixed: x and four FP32 vectors, then (FP64
+    // completion) x, u, p, pn again, so both are planned for the FP64 size.
+    (void)mixed;
+    const size_t mv = (size_t)n * W * 16 * 4;
+    // per-row-block partials: row blocks of at least 8 rows
+    const size_t parts = W * (size_t)((n + 7) / 8) * 24;
+    return mv + parts + (size_t)n * r * 8 * 9 + (size_t)W * 160;
 }
 
 static std::string json_stats(const Solver& s, double wall_ms, const std::vector<ContourOut>& cos,
@@ -961,6 +1030,7 @@ static std::string json_stats(const Solver& s, double wall_ms, const std::vector
       << ",\"columns\":" << s.stats_.columns << ",\"waves\":" << s.stats_.waves
       << ",\"spmm_launches\":" << s.stats_.spmm_launches
       << ",\"replacements\":" << s.stats_.replacements
+      << ",\"fp64_columns\":" << s.stats_.fp64_columns << ",\"fp64_iters\":" << s.stats_.fp64_iters
       << ",\"graph_captures\":" << s.stats_.graph_captures
       << ",\"spmm_alg_bytes\":" << s.stats_.spmm_alg_bytes
       << ",\"update_alg_bytes\":" << s.stats_.update_alg_bytes

@@ -266,8 +266,6 @@ def test_row_groups_in_a_batch_of_uneven_pencils(lib):
         assert_pairs_match(b[p], *_converged(ref), w.B)
 
 
-@pytest.mark.xfail(reason="FP32 COCG stalls on the shifted systems nearest the real axis; "
-                          "FP64 completion of stalled columns not built yet", strict=False)
 def test_row_groups_mixed_precision(lib):
     """FP32 recurrence on the 4-row group kernels vs plain CSR rows."""
     w = _var2d()
@@ -277,3 +275,15 @@ def test_row_groups_mixed_precision(lib):
     lam, X = _oracle_refs(w)
     for g in (1, 4):
         assert_pairs_match(r[g], lam, X, w.B)
+
+
+def test_mixed_fp64_completion_of_stalled_columns(lib):
+    """On this 31 x 29 problem the FP32 recurrence stalls on the shifted
+    systems nearest the real axis; those columns are finished by the FP64
+    recurrence from the folded solution, and every pair meets the bar."""
+    w = _var2d(nx=31, ny=29, seed=9, first=31, last=60, k=2)
+    got = lib.gep_ci_solve(w.A, w.B, w.contours, 32, 4, 16, 1e-8, seed=5, precision="mixed")
+    ref = oracle.oracle_ci_solve(w.A, w.B, w.contours, 32, 4, 16, 1e-8, seed=5)
+    assert_pairs_match(got, *_converged(ref), w.B)
+    assert got["stats"]["fp64_columns"] > 0
+    assert got["stats"]["cocg_iters"] < 2 * 100000
