@@ -31,6 +31,36 @@ import numpy as np  # noqa: E402
 METRIC = "eigenpairs/s at residual ≤1e-8 (learned+mixed vs plain FP64); SpMM HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 
+# Measured HBM traffic of the two COCG kernels on the default workload (FP64),
+# per 64-column tile per launch: two rocprofv3 --pmc runs (FETCH_SIZE, then
+# WRITE_SIZE) of `bench.py --no-cpu-baseline --warmup 0 --steps 1 --counters
+# --max-iter 64`, averaged over the 64 full-width launches of the first pass
+# and scaled by what the same counters read for a 1 GiB device copy in the
+# same process (FETCH_SIZE x2.0, WRITE_SIZE x1.0).  They hold only for the
+# kernel sources they were taken on; with any other source the traffic is
+# reported as null.
+TRAFFIC = {
+    "workload": "q1_2d_300",
+    "precision": "fp64",
+    "sources_sha256": {
+        "paper_2511_01927_amd/csrc/cocg.hip": "d77cbde59f14638d2c50f773f839a7be198170836066b48c624d8ac22f973ea1",
+        "paper_2511_01927_amd/csrc/internal.h": "36a2880ef095f14e3a5520d05cadf39eef28aa42705b1d4c2846e980470b638c",
+    },
+    "per_tile_bytes": {"cocg_spmm_dir": 3.389801e+08, "cocg_update": 5.272175e+08},
+    "profile": "profiles/cocg_q1_300x300_fp64_hbm_traffic.md",
+}
+
+
+def traffic_per_tile(workload: str, precision: str, kernel: str):
+    import hashlib
+    if workload != TRAFFIC["workload"] or precision != TRAFFIC["precision"]:
+        return None
+    for rel, want in TRAFFIC["sources_sha256"].items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != want:
+                return None
+    return TRAFFIC["per_tile_bytes"].get(kernel)
+
 
 def workload(name: str):
     from workloads import configs
@@ -171,8 +201,16 @@ def main():
         avg_s = km[name] / launches / 1e3
         per_launch = cand[name] / launches
         gbs = per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+        # HBM bytes per launch: measured bytes per tile-launch x the tiles an
+        # average launch of this run processed (tile_iters / launches)
+        per_tile = traffic_per_tile(args.workload, args.precision, name)
+        traffic = None
+        if per_tile is not None and not args.max_iter and name != "cocg_replace":
+            traffic = per_tile * st["tile_iters"] / launches
         return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                "frac": round(gbs / HBM_PEAK_GBS, 4),
+                "traffic": round(traffic) if traffic is not None else None,
+                "traffic_unit": "bytes per launch", "kernel": name,
                 "avg_launch_us": round(avg_s * 1e6, 2), "alg_bytes_per_launch": per_launch,
                 "launches": kl[name]}
     out = {

@@ -21,7 +21,7 @@
 // per-column convergence test ||r|| <= tol ||b||; active-tile compaction.
 // p is double-buffered because neighbours gather the old p while p' is
 // written.  Dot products: each lane owns one column, a wave sums its rows in
-// registers, the work-group's 4 waves combine in LDS, and per-tile partials
+// registers, the work-group's waves combine in LDS, and per-tile partials
 // over row blocks are summed in a fixed order (deterministic).
 //
 // The kernels are templated on the storage type: double2 (FP64 path) or
@@ -76,7 +76,7 @@ __device__ inline bool map_block(const int32_t* tiles, const int32_t* n_active, 
     return true;
 }
 
-// Sum a per-lane double2 and double over the 4 waves and store the partials.
+// Sum a per-lane double2 and double over the work-group's waves and store the partials.
 __device__ inline void block_partials(const BlockMap& m, int nrb, double2 c, double d,
                                       double2* part_c, double* part_r) {
     __shared__ double2 rc[kWaves][kTile];
@@ -184,6 +184,21 @@ struct GroupAcc {
 // Chunk of union columns loaded together (more loads in flight per wave).
 constexpr int kChunk = 3;
 
+// Streaming (non-temporal) access for vectors that are touched once per
+// kernel, so that they do not push the gathered neighbour rows out of L2.
+template <typename VT>
+__device__ inline VT nt_load(const VT* p) {
+    VT v;
+    v.x = __builtin_nontemporal_load(&p->x);
+    v.y = __builtin_nontemporal_load(&p->y);
+    return v;
+}
+template <typename VT>
+__device__ inline void nt_store(VT* p, VT v) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+}
+
 // Walk group k's union: for each column j, v = fetch(j) (the gathered value),
 // accumulate A v and B v into every row of the group, and keep v for the
 // group's own rows.  grow is the group's first global row.
@@ -254,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_dir(
         for (int r = 0; r < R; ++r) {
             if (k * R + r >= m.r1) break;
             const VT pn = acc.own[r];
-            Pnt[(size_t)(grow + r) * kTile + m.lane] = pn;
+            nt_store(&Pnt[(size_t)(grow + r) * kTile + m.lane], pn);
             const Rt qr = fma(zr, acc.br[r], fma(-zi, acc.bi[r], -acc.ar[r]));
             const Rt qi = fma(zr, acc.bi[r], fma(zi, acc.br[r], -acc.ai[r]));
             dr += (double)pn.x * (double)qr - (double)pn.y * (double)qi;
@@ -306,17 +321,19 @@ __global__ __launch_bounds__(kBlock) void k_update(
             const Rt qi = fma(zr, acc.bi[r], fma(zi, acc.br[r], -acc.ai[r]));
             const size_t o = (size_t)g * kTile + m.lane;
             const VT pi = acc.own[r];
-            VT xv = Xt[o], uv = Ut[o];
+            VT xv = nt_load(&Xt[o]), uv = nt_load(&Ut[o]);
             xv.x = fma(alr, pi.x, fma(-ali, pi.y, xv.x));
             xv.y = fma(alr, pi.y, fma(ali, pi.x, xv.y));
-            // s = alpha q / D
+            // s = alpha q / D, one reciprocal of |D|^2 per row and column
             const double2 D = make_double2(zd.x * dB[g] - dA[g], zd.y * dB[g]);
             const Rt aqr = alr * qr - ali * qi, aqi = alr * qi + ali * qr;
-            const double2 s = cdiv(make_double2((double)aqr, (double)aqi), D);
-            uv.x = uv.x - (Rt)s.x;
-            uv.y = uv.y - (Rt)s.y;
-            Xt[o] = xv;
-            Ut[o] = uv;
+            const double inv = 1.0 / (D.x * D.x + D.y * D.y);
+            const double sx = ((double)aqr * D.x + (double)aqi * D.y) * inv;
+            const double sy = ((double)aqi * D.x - (double)aqr * D.y) * inv;
+            uv.x = uv.x - (Rt)sx;
+            uv.y = uv.y - (Rt)sy;
+            nt_store(&Xt[o], xv);
+            nt_store(&Ut[o], uv);
             // r = D u
             const double ux = (double)uv.x, uy = (double)uv.y;
             const double rx = D.x * ux - D.y * uy, ry = D.x * uy + D.y * ux;

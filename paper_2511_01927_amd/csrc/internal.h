@@ -10,7 +10,8 @@ namespace gep {
 
 // One wavefront covers 64 columns of a multivector tile.
 constexpr int kTile = 64;
-// Work-group size of the streaming kernels: 4 wavefronts.
+// Work-group size of the streaming kernels: 4 wavefronts (one row group per
+// wave in the COCG kernels; 8-wave work-groups measured slower).
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kTile;
 

@@ -138,7 +138,7 @@ hipError_t launch_spmm_c32(const DevPencil& P, const double2* shifts, const floa
 }
 
 // Real multivector product on row-major n x k blocks (leading dimension ld):
-// YA = A X, YB = B X.  Work-group = 4 waves over consecutive rows of one
+// YA = A X, YB = B X.  The work-group's waves take consecutive rows of one
 // 64-column chunk.
 __global__ __launch_bounds__(kBlock) void k_spmm_real(const int32_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ colind,
