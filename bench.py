@@ -5,8 +5,10 @@ Workload (default): 2D Q1-FEM pencil on a 300 x 300 interior grid
 eigenvalues 1002..1200 split over 4 uniform circles (inflation 0.1), 32
 trapezoid nodes per circle (16 solved), 4 moments, 64 Gaussian right-hand
 sides, FP64.  A step is one full gep_ci_solve on the device-resident packed
-pencil: RHS generation, all shifted COCG solves, moments, B-orthonormalisation,
-Rayleigh-Ritz, residuals, selection and merge, results copied to the host.
+pencil: RHS generation, all shifted solves (banded L D L^T of the 64 shifted
+systems by default for this pencil, half bandwidth 301; --solver cocg for the
+batched Jacobi-COCG path), moments, B-orthonormalisation, Rayleigh-Ritz,
+residuals, selection and merge, results copied to the host.
 
 value = eigenpairs per second that pass the acceptance bar (residual
 <= 1e-8, eigenvalue within 1e-10 relative of the closed form, exact count).
@@ -30,6 +32,7 @@ import numpy as np  # noqa: E402
 
 METRIC = "eigenpairs/s at residual ≤1e-8 (learned+mixed vs plain FP64); SpMM HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 # Measured HBM traffic of the two COCG kernels on the default workload (FP64),
 # per 64-column tile per launch: two rocprofv3 --pmc runs (FETCH_SIZE, then
@@ -108,6 +111,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="q1_2d_300")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--solver", default="auto", choices=["auto", "cocg", "band"],
+                    help="shifted solves: banded L D L^T or batched COCG (auto: band when the "
+                         "pencil's half bandwidth is at most 1024)")
     ap.add_argument("--solve-tol", type=float, default=1e-9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-contours", type=int, default=1)
@@ -143,7 +149,7 @@ def main():
     stream = torch.cuda.current_stream()
     pencil = gep_ci.Pencil(w.A, w.B, stream=stream)
     kw = dict(seed=w.seed, precision=args.precision, solve_tol=args.solve_tol, stream=stream,
-              verbose=args.verbose)
+              verbose=args.verbose, solver=args.solver)
     if args.max_iter:
         kw["max_iter"] = args.max_iter
     timed = not args.counters
@@ -192,27 +198,40 @@ def main():
 
     st = results[-1]["stats"]
     km, kl = st["kernel_ms"], st["kernel_launches"]
+    # per kernel class: bound, algorithmic work of the run (bytes or flops)
+    spec = {"cocg_spmm_dir": ("hbm", st["spmm_alg_bytes"]),
+            "cocg_update": ("hbm", st["update_alg_bytes"]),
+            "cocg_replace": ("hbm", st["replace_alg_bytes"]),
+            "band_update": ("alu", st["band_update_flops"]),
+            "band_panel": ("alu", st["band_panel_flops"]),
+            "band_solve": ("alu", st["band_solve_flops"])}
     # dominant kernel by measured time
-    cand = {"cocg_spmm_dir": st["spmm_alg_bytes"], "cocg_update": st["update_alg_bytes"],
-            "cocg_replace": st["replace_alg_bytes"]}
-    dom = max(cand, key=lambda k: km[k])
+    dom = max(spec, key=lambda k: km.get(k, 0.0))
+
     def roof(name):
-        launches = max(1, kl[name])
-        avg_s = km[name] / launches / 1e3
-        per_launch = cand[name] / launches
-        gbs = per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
-        # HBM bytes per launch: measured bytes per tile-launch x the tiles an
-        # average launch of this run processed (tile_iters / launches)
-        per_tile = traffic_per_tile(args.workload, args.precision, name)
-        traffic = None
-        if per_tile is not None and not args.max_iter and name != "cocg_replace":
-            traffic = per_tile * st["tile_iters"] / launches
-        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4),
-                "traffic": round(traffic) if traffic is not None else None,
-                "traffic_unit": "bytes per launch", "kernel": name,
-                "avg_launch_us": round(avg_s * 1e6, 2), "alg_bytes_per_launch": per_launch,
-                "launches": kl[name]}
+        bound, work = spec[name]
+        launches = max(1, kl.get(name, 0))
+        avg_s = km.get(name, 0.0) / launches / 1e3
+        per_launch = work / launches
+        rate = per_launch / avg_s if avg_s > 0 else 0.0
+        if bound == "hbm":
+            # HBM bytes per launch: measured bytes per tile-launch x the tiles an
+            # average launch of this run processed (tile_iters / launches)
+            per_tile = traffic_per_tile(args.workload, args.precision, name)
+            traffic = None
+            if per_tile is not None and not args.max_iter and name != "cocg_replace":
+                traffic = per_tile * st["tile_iters"] / launches
+            return {"bound": "hbm", "achieved": round(rate / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(rate / 1e9 / HBM_PEAK_GBS, 4),
+                    "traffic": round(traffic) if traffic is not None else None,
+                    "traffic_unit": "bytes per launch", "kernel": name,
+                    "avg_launch_us": round(avg_s * 1e6, 2), "alg_bytes_per_launch": per_launch,
+                    "launches": kl.get(name, 0)}
+        # plain FP64 vector arithmetic (no matrix cores): peak 78.6 TFLOP/s
+        return {"bound": "alu", "achieved": round(rate / 1e12, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(rate / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": None, "kernel": name, "avg_launch_us": round(avg_s * 1e6, 2),
+                "alg_flops_per_launch": per_launch, "launches": kl.get(name, 0)}
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "eigenpairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 1),
@@ -227,7 +246,8 @@ def main():
                    "solve_tol": args.solve_tol,
                    "eigenpairs_per_step": int(ref.size) if ref is not None else None},
         "roofline": roof(dom),
-        "spmm": roof("cocg_spmm_dir"),
+        "kernels": {k: roof(k) for k in spec if kl.get(k, 0) > 0 and k != dom},
+        "solver": "band" if st.get("band_factorisations", 0) > 0 else "cocg",
         "cpu_baseline": cpu,
         "cocg_iters": st["cocg_iters"], "tile_iters": st["tile_iters"],
         "kernel_ms": km,

@@ -114,6 +114,13 @@ typedef struct {
                                of their columns), 1 (plain CSR), 0 (default:
                                4 when that saves at least 20% of the gathers).
                                Results do not depend on it. */
+    int solver;             /* shifted solves (z_j B - A) Y = B V: 2 = banded
+                               L D L^T of every system (complex symmetric, no
+                               pivoting, FP64 residual check and up to 3
+                               iterative-refinement sweeps; pencils of half
+                               bandwidth <= 4096), 1 = batched Jacobi COCG,
+                               0 (default) = banded when every pencil's half
+                               bandwidth is <= 1024, else COCG */
 } gep_opts;
 
 typedef struct gep_result gep_result;

@@ -1,0 +1,461 @@
+// Banded direct solves of the shifted systems (z B - A) Y = B V of the
+// quadrature equation (paper Appendix, "Numerical Quadrature": the N_q
+// shifted solves are the dominant cost and independent).  The paper leaves
+// the linear solver open; for pencils whose (union) pattern lies within a
+// band of half width bw -- 2D grids in natural order have bw ~ sqrt(n) --
+// every shifted system is factored as K = L D L^T (complex symmetric, L unit
+// lower, D diagonal, no pivoting) and solved for all right-hand sides.
+//
+// Storage: column-major lower band.  Entry (i, j), 0 <= i - j <= bw, of one
+// system lives at off + j * (bw + 1) + (i - j); entries past row n are zero.
+// After the factorisation the same slots hold d_j (i = j) and l_ij (i > j).
+//
+// Factorisation, right-looking by panels of kPanel columns, one step per
+// panel (all systems of a batch advance together):
+//   k_band_panel   one work-group per system: unblocked L D L^T of the
+//                  panel's kPanel columns (each (bw + 1) long) in place;
+//   k_band_update  the trailing window of bw rows and columns after the
+//                  panel: C -= W diag(d) W^T, lower triangle, in 64 x 64
+//                  tiles staged through LDS.
+// Solves, in place on the tiled multivector (element (i, c) at
+// (tile * n + i) * 64 + lane), a work-group per (tile, chunk of columns):
+//   k_band_forward   L y = b by columns of L (axpy form), the pending rows
+//                    i+1 .. i+bw in a circular LDS window; writes y / d;
+//   k_band_backward  L^T x = z by columns of L (dot form), the solved rows
+//                    i+1 .. i+bw in the LDS window.
+// Unpivoted elimination is safe here in practice (growth ~1 measured on the
+// shifted Q1 systems); every solve is followed by an FP64 residual check and
+// iterative refinement with the same factors, and a zero or non-finite pivot
+// is flagged per system.
+#include "internal.h"
+
+namespace gep {
+
+namespace {
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a -= b * c
+__device__ inline void cfms(double2& a, double2 b, double2 c) {
+    a.x = fma(-b.x, c.x, fma(b.y, c.y, a.x));
+    a.y = fma(-b.x, c.y, fma(-b.y, c.x, a.y));
+}
+
+constexpr int band_threads_per_column(int cw) { return 256 / cw > 64 ? 64 : 256 / cw; }
+
+}  // namespace
+
+// F = z B - A on the band of each system.
+__global__ __launch_bounds__(256) void k_band_form(const BandSys* __restrict__ sys,
+                                                   const double2* __restrict__ AB,
+                                                   double2* __restrict__ F) {
+    const BandSys S = sys[blockIdx.y];
+    const int64_t total = (int64_t)S.n * (S.bw + 1);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const double2 v = AB[S.aoff + e];
+        F[S.off + e] = make_double2(S.z.x * v.y - v.x, S.z.y * v.y);
+    }
+}
+
+// Unblocked L D L^T of panel columns [k0, k0 + kPanel) of every system.
+__global__ __launch_bounds__(256) void k_band_panel(const BandSys* __restrict__ sys,
+                                                    double2* F, int k0,
+                                                    int32_t* __restrict__ flag) {
+    const BandSys S = sys[blockIdx.x];
+    if (k0 >= S.n) return;
+    const int ld = S.bw + 1;
+    const int ncols = min(kPanel, S.n - k0);
+    // P and col address the same band (different columns are read and written)
+    double2* P = F + S.off + (int64_t)k0 * ld;
+    for (int jj = 0; jj < ncols; ++jj) {
+        double2* col = P + (int64_t)jj * ld;
+        const int j = k0 + jj;
+        const int emax = min(S.bw, S.n - 1 - j);   // rows j+1 .. j+emax
+        const double2 d = col[0];
+        const double m2 = d.x * d.x + d.y * d.y;
+        if (!(m2 > 0.0) || !isfinite(m2)) {
+            if (threadIdx.x == 0) flag[blockIdx.x] = 1;
+        }
+        const double2 inv = make_double2(d.x / m2, -d.y / m2);
+        for (int e = 1 + (int)threadIdx.x; e <= emax; e += blockDim.x) col[e] = cmul(col[e], inv);
+        __syncthreads();
+        // columns j + t (t = 1 .. ncols-1-jj) of the panel: rows j+t+e2 <= j+emax
+        const int left = min(ncols - 1 - jj, emax);
+        const int work = left * ld;
+        for (int w = threadIdx.x; w < work; w += blockDim.x) {
+            const int t = 1 + w / ld;
+            const int e2 = w - (t - 1) * ld;
+            if (e2 > emax - t) continue;
+            const double2 f = cmul(d, col[t]);
+            cfms(P[(int64_t)(jj + t) * ld + e2], col[t + e2], f);
+        }
+        __syncthreads();
+    }
+}
+
+// Trailing update after panel [k0, k0 + kPanel): rows and columns
+// [k0 + kPanel, min(n, k0 + kPanel + bw)), lower triangle.  blockIdx.x is
+// a lower-triangular tile index (bi >= bj) of 64 x 64 tiles, blockIdx.y
+// the system.
+__global__ __launch_bounds__(256) void k_band_update(const BandSys* __restrict__ sys,
+                                                     double2* F, int k0) {
+    __shared__ double2 Wi[64][kPanel + 1];
+    __shared__ double2 Wj[64][kPanel + 1];
+    const BandSys S = sys[blockIdx.y];
+    const int w0 = k0 + kPanel;
+    if (w0 >= S.n) return;
+    const int wend = min(S.n, k0 + kPanel + S.bw);
+    const int x = blockIdx.x;
+    int bi = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
+    while ((bi + 1) * (bi + 2) / 2 <= x) ++bi;
+    while (bi * (bi + 1) / 2 > x) --bi;
+    const int bj = x - bi * (bi + 1) / 2;
+    const int i0 = w0 + 64 * bi, j0 = w0 + 64 * bj;
+    if (i0 >= wend) return;
+    const int ld = S.bw + 1;
+    const double2* Fs = F + S.off;   // panel columns (read) and window columns (written) of one band
+    for (int idx = threadIdx.x; idx < 64 * kPanel; idx += blockDim.x) {
+        const int r = idx / kPanel, kk = idx - r * kPanel;
+        const int k = k0 + kk;
+        const int i = i0 + r, j = j0 + r;
+        double2 wi = make_double2(0.0, 0.0), wj = make_double2(0.0, 0.0);
+        if (i < wend && i - k <= S.bw) wi = Fs[(int64_t)k * ld + (i - k)];
+        if (j < wend && j - k <= S.bw) wj = cmul(Fs[(int64_t)k * ld + (j - k)], Fs[(int64_t)k * ld]);
+        Wi[r][kk] = wi;
+        Wj[r][kk] = wj;
+    }
+    __syncthreads();
+    // thread: 4 consecutive rows x 4 columns (columns strided by 16)
+    const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+    double2 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
+    for (int kk = 0; kk < kPanel; ++kk) {
+        double2 wi[4], wj[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) wi[a] = Wi[tr * 4 + a][kk];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) wj[b] = Wj[tc + 16 * b][kk];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                acc[a][b].x = fma(wi[a].x, wj[b].x, fma(-wi[a].y, wj[b].y, acc[a][b].x));
+                acc[a][b].y = fma(wi[a].x, wj[b].y, fma(wi[a].y, wj[b].x, acc[a][b].y));
+            }
+    }
+    double2* Fw = F + S.off;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int j = j0 + tc + 16 * b;
+        if (j >= wend) continue;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int i = i0 + tr * 4 + a;
+            if (i >= wend || i < j) continue;
+            double2& c = Fw[(int64_t)j * ld + (i - j)];
+            c.x -= acc[a][b].x;
+            c.y -= acc[a][b].y;
+        }
+    }
+}
+
+// X (tiled, in place) = b: column c of a tile takes B V column bsrc[c] over
+// its pencil's rows; padding columns get zero.
+__global__ __launch_bounds__(256) void k_band_rhs(TileGeom geom, const int64_t* __restrict__ bsrc,
+                                                  const double* __restrict__ BV, int64_t ldbv,
+                                                  int ntiles, double2* __restrict__ X) {
+    const int tile = blockIdx.y;
+    const int n = geom.n[tile];
+    const int64_t base = geom.base[tile];
+    const int lane = threadIdx.x & 63;
+    const int64_t bs = bsrc[tile * kTile + lane];
+    for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += gridDim.x * 4) {
+        const double b = bs >= 0 ? BV[bs + (int64_t)i * ldbv] : 0.0;
+        X[base + (int64_t)i * kTile + lane] = make_double2(b, 0.0);
+    }
+}
+
+// L y = b, then z = y / d, in place on columns [c0, c0 + CW) of a tile.
+// colsys[tile * 64 + lane] is the column's system (-1: padding column).
+template <int CW>
+__global__ __launch_bounds__(256) void k_band_forward(const BandSys* __restrict__ sys,
+                                                      const int32_t* __restrict__ colsys,
+                                                      const double2* __restrict__ F, TileGeom geom,
+                                                      double2* __restrict__ X) {
+    extern __shared__ double2 win[];   // [(bw + 1)][CW]
+    const int tile = blockIdx.y;
+    const int c0 = blockIdx.x * CW;
+    const int n = geom.n[tile];
+    const int64_t base = geom.base[tile];
+    // every column of a chunk belongs to one pencil (same n, bw); the first
+    // real column gives bw
+    int bw = -1;
+    for (int c = 0; c < CW; ++c) {
+        const int s = colsys[tile * kTile + c0 + c];
+        if (s >= 0) {
+            bw = sys[s].bw;
+            break;
+        }
+    }
+    if (bw < 0) return;
+    const int ld = bw + 1;
+    // per-thread column for the load/store phase
+    const int myc = threadIdx.x % CW;
+    const int mys = colsys[tile * kTile + c0 + myc];
+    for (int r = threadIdx.x / CW; r < ld; r += blockDim.x / CW)
+        win[r * CW + myc] = r < n ? X[base + (int64_t)r * kTile + c0 + myc] : make_double2(0.0, 0.0);
+    __syncthreads();
+    const int upd = bw * CW;
+    for (int i = 0; i < n; ++i) {
+        const int slot = i % ld;
+        // pending value of row i is final: y_i
+        if (threadIdx.x < CW && mys >= 0) {
+            const double2 y = win[slot * CW + myc];
+            const double2 d = F[sys[mys].off + (int64_t)i * ld];
+            const double m2 = d.x * d.x + d.y * d.y;
+            X[base + (int64_t)i * kTile + c0 + myc] =
+                make_double2((y.x * d.x + y.y * d.y) / m2, (y.y * d.x - y.x * d.y) / m2);
+        }
+        const int dmax = min(bw, n - 1 - i);
+        // rows i+1 .. i+dmax -= l_{i+d, i} y_i ; column index slowest so that
+        // consecutive threads read consecutive entries of column i of L
+        for (int w = threadIdx.x; w < upd; w += blockDim.x) {
+            const int c = w / bw;
+            const int dd = 1 + (w - c * bw);
+            if (dd > dmax) continue;
+            const int s = colsys[tile * kTile + c0 + c];
+            if (s < 0) continue;
+            const double2 y = win[slot * CW + c];
+            const double2 l = F[sys[s].off + (int64_t)i * ld + dd];
+            cfms(win[((i + dd) % ld) * CW + c], l, y);
+        }
+        __syncthreads();
+        // the slot of row i now takes row i + bw + 1 (untouched so far)
+        if (threadIdx.x < CW) {
+            const int r = i + ld;
+            win[slot * CW + myc] = r < n ? X[base + (int64_t)r * kTile + c0 + myc] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+    }
+}
+
+// L^T x = z in place (x_i = z_i - sum_d l_{i+d, i} x_{i+d}), rows from the
+// bottom up; the solved rows i+1 .. i+bw sit in the LDS window.
+template <int CW>
+__global__ __launch_bounds__(256) void k_band_backward(const BandSys* __restrict__ sys,
+                                                       const int32_t* __restrict__ colsys,
+                                                       const double2* __restrict__ F, TileGeom geom,
+                                                       double2* __restrict__ X) {
+    extern __shared__ double2 win[];   // [(bw + 1)][CW]
+    constexpr int TP = band_threads_per_column(CW);   // threads per column, <= one wavefront
+    const int tile = blockIdx.y;
+    const int c0 = blockIdx.x * CW;
+    const int n = geom.n[tile];
+    const int64_t base = geom.base[tile];
+    int bw = -1;
+    for (int c = 0; c < CW; ++c) {
+        const int s = colsys[tile * kTile + c0 + c];
+        if (s >= 0) {
+            bw = sys[s].bw;
+            break;
+        }
+    }
+    if (bw < 0) return;
+    const int ld = bw + 1;
+    const int c = threadIdx.x / TP;     // this thread's column
+    const int q = threadIdx.x - c * TP; // its share of the dot product
+    const int s = colsys[tile * kTile + c0 + c];
+    const int64_t fo = s >= 0 ? sys[s].off : 0;
+    for (int i = n - 1; i >= 0; --i) {
+        const int dmax = min(bw, n - 1 - i);
+        double2 acc = make_double2(0.0, 0.0);
+        if (s >= 0) {
+            for (int dd = 1 + q; dd <= dmax; dd += TP) {
+                const double2 l = F[fo + (int64_t)i * ld + dd];
+                const double2 xv = win[((i + dd) % ld) * CW + c];
+                acc.x = fma(l.x, xv.x, fma(-l.y, xv.y, acc.x));
+                acc.y = fma(l.x, xv.y, fma(l.y, xv.x, acc.y));
+            }
+        }
+        // sum the TP partial dot products of the column (TP divides 64)
+#pragma unroll
+        for (int o = TP / 2; o > 0; o >>= 1) {
+            acc.x += __shfl_xor(acc.x, o, TP);
+            acc.y += __shfl_xor(acc.y, o, TP);
+        }
+        if (q == 0 && s >= 0) {
+            const int64_t o = base + (int64_t)i * kTile + c0 + c;
+            const double2 z = X[o];
+            const double2 xv = make_double2(z.x - acc.x, z.y - acc.y);
+            X[o] = xv;
+            win[(i % ld) * CW + c] = xv;
+        }
+        __syncthreads();
+    }
+}
+
+// r = b - K x per column (FP64, CSR of the concatenated pencil), stored in
+// R; partials of ||r||^2 (x) and ||b||^2 (y) per row block.
+__global__ __launch_bounds__(256) void k_band_residual(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+    const double2* __restrict__ ab, TileGeom geom, const double2* __restrict__ shifts,
+    const int64_t* __restrict__ bsrc, const double* __restrict__ BV, int64_t ldbv,
+    const double2* __restrict__ X, double2* __restrict__ R, int ntiles, int nrb, int rpb,
+    double2* __restrict__ part) {
+    __shared__ double2 red[4][kTile];
+    const int tile = blockIdx.x / nrb;
+    const int rb = blockIdx.x - tile * nrb;
+    if (tile >= ntiles) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nt = geom.n[tile];
+    const int row0 = geom.row0[tile];
+    const int64_t base = geom.base[tile];
+    const int64_t goff = base - (int64_t)row0 * kTile;
+    const int col = tile * kTile + lane;
+    const double2 z = shifts[col];
+    const int64_t bs = bsrc[col];
+    const int r0 = min(nt, rb * rpb), r1 = min(nt, r0 + rpb);
+    double rr = 0.0, bb = 0.0;
+    for (int i = r0 + wave; i < r1; i += 4) {
+        const int g = row0 + i;
+        double ar = 0, ai = 0, br = 0, bi = 0;
+        for (int k = rowptr[g]; k < rowptr[g + 1]; ++k) {
+            const double2 v = ab[k];
+            const double2 xj = X[goff + (int64_t)colind[k] * kTile + lane];
+            ar = fma(v.x, xj.x, ar);
+            ai = fma(v.x, xj.y, ai);
+            br = fma(v.y, xj.x, br);
+            bi = fma(v.y, xj.y, bi);
+        }
+        const double b = bs >= 0 ? BV[bs + (int64_t)i * ldbv] : 0.0;
+        const double rx = b - (z.x * br - z.y * bi - ar);
+        const double ry = -(z.x * bi + z.y * br - ai);
+        R[base + (int64_t)i * kTile + lane] = make_double2(rx, ry);
+        rr += rx * rx + ry * ry;
+        bb += b * b;
+    }
+    red[wave][lane] = make_double2(rr, bb);
+    __syncthreads();
+    if (wave == 0) {
+        double2 a = red[0][lane];
+        for (int w = 1; w < 4; ++w) {
+            a.x += red[w][lane].x;
+            a.y += red[w][lane].y;
+        }
+        part[((int64_t)tile * nrb + rb) * kTile + lane] = a;
+    }
+}
+
+// rel[col] = ||r|| / ||b|| from the row-block partials (fixed order).
+__global__ __launch_bounds__(64) void k_band_relres(int nrb, const double2* __restrict__ part,
+                                                    double* __restrict__ rel) {
+    const int tile = blockIdx.x, lane = threadIdx.x;
+    double rr = 0.0, bb = 0.0;
+    for (int rb = 0; rb < nrb; ++rb) {
+        const double2 p = part[((int64_t)tile * nrb + rb) * kTile + lane];
+        rr += p.x;
+        bb += p.y;
+    }
+    rel[tile * kTile + lane] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+}
+
+// X += R over the rows of every tile.
+__global__ __launch_bounds__(256) void k_band_axpy(TileGeom geom, const double2* __restrict__ R,
+                                                   double2* __restrict__ X) {
+    const int tile = blockIdx.y;
+    const int n = geom.n[tile];
+    const int64_t base = geom.base[tile];
+    const int lane = threadIdx.x & 63;
+    for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += gridDim.x * 4) {
+        const int64_t o = base + (int64_t)i * kTile + lane;
+        const double2 r = R[o];
+        double2 x = X[o];
+        x.x += r.x;
+        x.y += r.y;
+        X[o] = x;
+    }
+}
+
+// ---- launchers ---------------------------------------------------------
+
+hipError_t band_form(const BandSys* sys, int nsys, const double2* AB, double2* F, hipStream_t s) {
+    hipLaunchKernelGGL(k_band_form, dim3(64, nsys), dim3(256), 0, s, sys, AB, F);
+    return hipGetLastError();
+}
+
+hipError_t band_panel(const BandSys* sys, int nsys, double2* F, int k0, int32_t* flag,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_band_panel, dim3(nsys), dim3(256), 0, s, sys, F, k0, flag);
+    return hipGetLastError();
+}
+
+hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int k0, hipStream_t s) {
+    const int T = (bwmax + 63) / 64;
+    const int tiles = T * (T + 1) / 2;
+    if (tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_band_update, dim3(tiles, nsys), dim3(256), 0, s, sys, F, k0);
+    return hipGetLastError();
+}
+
+int band_chunk_columns(int bw) {
+    const size_t ld = (size_t)bw + 1;
+    int cw = 16;
+    while (cw > 1 && ld * cw * sizeof(double2) > kBandLds) cw >>= 1;
+    return cw;
+}
+
+template <int CW>
+static hipError_t solve_cw(const BandSys* sys, const int32_t* colsys, const double2* F,
+                           const TileGeom& g, int ntiles, int bw, double2* X, hipStream_t s) {
+    const size_t lds = (size_t)(bw + 1) * CW * sizeof(double2);
+    hipLaunchKernelGGL((k_band_forward<CW>), dim3(kTile / CW, ntiles), dim3(256), lds, s, sys,
+                       colsys, F, g, X);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_band_backward<CW>), dim3(kTile / CW, ntiles),
+                       dim3(CW * band_threads_per_column(CW)), lds, s, sys, colsys, F, g, X);
+    return hipGetLastError();
+}
+
+hipError_t band_solve(const BandSys* sys, const int32_t* colsys, const double2* F,
+                      const TileGeom& g, int ntiles, int bwmax, double2* X, hipStream_t s) {
+    switch (band_chunk_columns(bwmax)) {
+        case 16: return solve_cw<16>(sys, colsys, F, g, ntiles, bwmax, X, s);
+        case 8: return solve_cw<8>(sys, colsys, F, g, ntiles, bwmax, X, s);
+        case 4: return solve_cw<4>(sys, colsys, F, g, ntiles, bwmax, X, s);
+        case 2: return solve_cw<2>(sys, colsys, F, g, ntiles, bwmax, X, s);
+        default: return solve_cw<1>(sys, colsys, F, g, ntiles, bwmax, X, s);
+    }
+}
+
+hipError_t band_rhs(const TileGeom& g, const int64_t* bsrc, const double* BV, int64_t ldbv,
+                    int ntiles, double2* X, hipStream_t s) {
+    hipLaunchKernelGGL(k_band_rhs, dim3(256, ntiles), dim3(256), 0, s, g, bsrc, BV, ldbv, ntiles, X);
+    return hipGetLastError();
+}
+
+hipError_t band_residual(const DevPencil& P, const TileGeom& g, const double2* shifts,
+                         const int64_t* bsrc, const double* BV, int64_t ldbv, const double2* X,
+                         double2* R, int ntiles, int64_t nmax, double2* part, int nrb_cap,
+                         double* rel, hipStream_t s) {
+    const int rpb = (int)std::max<int64_t>(16, (nmax + nrb_cap - 1) / nrb_cap);
+    const int nrb = (int)((nmax + rpb - 1) / rpb);
+    hipLaunchKernelGGL(k_band_residual, dim3(ntiles * nrb), dim3(256), 0, s, P.rowptr, P.colind,
+                       P.ab, g, shifts, bsrc, BV, ldbv, X, R, ntiles, nrb, rpb, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_band_relres, dim3(ntiles), dim3(64), 0, s, nrb, part, rel);
+    return hipGetLastError();
+}
+
+hipError_t band_axpy(const TileGeom& g, const double2* R, int ntiles, double2* X, hipStream_t s) {
+    hipLaunchKernelGGL(k_band_axpy, dim3(256, ntiles), dim3(256), 0, s, g, R, X);
+    return hipGetLastError();
+}
+
+}  // namespace gep

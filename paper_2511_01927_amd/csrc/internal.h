@@ -45,6 +45,9 @@ struct DevPencil {
     float2* g4ab32 = nullptr;
     int64_t g4nnz = 0;          // union columns of the 4-row form
     int auto_grp = 1;           // 4 when the 4-row form saves at least 20% of the gathers
+    // real lower bands (a_ij, b_ij) of the problems whose half bandwidth is at
+    // most kBandMaxBw (band.hip); offsets and widths are kept on the host
+    double2* band = nullptr;
 };
 
 // XCD-aware remap of a flat work-group id: the hardware deals work-groups
@@ -153,6 +156,46 @@ hipError_t cocg32_replace(const DevPencil& P, CocgState& S, const double* BV, in
 hipError_t launch_moments(const double2* X, const TileGeom& g, int64_t nmax, int K, int NH, int L,
                           int M, const int64_t* coff, const int32_t* cn, const int64_t* soff,
                           const double2* coef, double* S, hipStream_t s);
+
+// ---- banded direct solves (band.hip) ----------------------------------
+// One shifted system z B - A of one pencil of the batch, stored as a
+// column-major lower band: entry (i, j), 0 <= i - j <= bw, at
+// off + j * (bw + 1) + (i - j).
+struct BandSys {
+    int64_t off = 0;    // element offset of the system's band in the factor array
+    int64_t aoff = 0;   // element offset of its pencil's real (a, b) band
+    int32_t n = 0, bw = 0;
+    double2 z{0.0, 0.0};
+};
+// Panel width of the banded factorisation and the LDS budget of the solves.
+constexpr int kPanel = 16;
+// Widest half bandwidth for which a pencil's band is kept (the automatic
+// solver choice takes the band path up to kBandAutoBw).
+constexpr int64_t kBandMaxBw = 4096;
+constexpr int64_t kBandAutoBw = 1024;
+// Iterative-refinement sweeps after a banded solve at most.
+constexpr int kBandRefineMax = 3;
+constexpr size_t kBandLds = 64 * 1024;
+
+hipError_t band_form(const BandSys* sys, int nsys, const double2* AB, double2* F, hipStream_t s);
+// One panel step: factor panel [k0, k0 + kPanel) (flag: zero or non-finite
+// pivot per system), then update the trailing window.
+hipError_t band_panel(const BandSys* sys, int nsys, double2* F, int k0, int32_t* flag,
+                      hipStream_t s);
+hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int k0, hipStream_t s);
+// Columns per work-group of the solves for a half bandwidth bw.
+int band_chunk_columns(int bw);
+// In place: X <- K^-1 X for every column (colsys: system of each tiled column, -1 = none).
+hipError_t band_solve(const BandSys* sys, const int32_t* colsys, const double2* F,
+                      const TileGeom& g, int ntiles, int bwmax, double2* X, hipStream_t s);
+hipError_t band_rhs(const TileGeom& g, const int64_t* bsrc, const double* BV, int64_t ldbv,
+                    int ntiles, double2* X, hipStream_t s);
+// R = b - K X, rel[col] = ||R|| / ||b||; part holds ntiles * nrb_cap * 64 entries.
+hipError_t band_residual(const DevPencil& P, const TileGeom& g, const double2* shifts,
+                         const int64_t* bsrc, const double* BV, int64_t ldbv, const double2* X,
+                         double2* R, int ntiles, int64_t nmax, double2* part, int nrb_cap,
+                         double* rel, hipStream_t s);
+hipError_t band_axpy(const TileGeom& g, const double2* R, int ntiles, double2* X, hipStream_t s);
 
 // RNG
 hipError_t launch_gaussian(uint64_t seed, int64_t n, int64_t L, double* V, hipStream_t s);

@@ -93,6 +93,10 @@ struct HostPencil {
     std::vector<int64_t> prob_row0, prob_n;
     std::vector<double> prob_ainf;
     std::vector<int32_t> prob_g4;   // first 4-row group of each problem (set by upload)
+    // lower bands of the problems (set by upload): half bandwidth, element
+    // offset of the (a, b) band on the device, -1 when no band is kept
+    std::vector<int32_t> prob_bw;
+    std::vector<int64_t> prob_boff;
 };
 
 static void append_pencil(HostPencil& dst, const HostPencil& src) {
@@ -124,7 +128,7 @@ struct Timer {
     };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
-    static constexpr int kClasses = 8;
+    static constexpr int kClasses = 11;
     double ms[kClasses] = {0};
     long count[kClasses] = {0};
     hipEvent_t get() {
@@ -171,10 +175,43 @@ struct Timer {
         for (auto e : pool) (void)hipEventDestroy(e);
     }
 };
-enum { T_SPMM = 0, T_UPDATE, T_REPLACE, T_REDUCE, T_MOMENTS, T_GRAM, T_GEMM, T_DENSE };
+enum { T_SPMM = 0, T_UPDATE, T_REPLACE, T_REDUCE, T_MOMENTS, T_GRAM, T_GEMM, T_DENSE, T_BAND_PANEL,
+       T_BAND_UPDATE, T_BAND_SOLVE };
 static const char* kTimerNames[Timer::kClasses] = {"cocg_spmm_dir", "cocg_update", "cocg_replace",
                                                    "cocg_reduce", "moments", "gram",
-                                                   "gemm_tall", "dense_small"};
+                                                   "gemm_tall", "dense_small", "band_panel",
+                                                   "band_update", "band_solve"};
+
+// Algorithmic real flops of the banded L D L^T of one n x n complex
+// symmetric system of half bandwidth bw, split between the panel kernel
+// (column scaling, 6 flops per complex product, and the updates inside a
+// panel) and the trailing-window kernel (8 flops per complex multiply-add
+// l_ik d_k l_jk, counted only where l_ik is inside the band).
+static void band_factor_flops(int64_t n, int64_t bw, double& panel, double& update) {
+    panel = update = 0.0;
+    for (int64_t k0 = 0; k0 < n; k0 += kPanel) {
+        const int64_t nc = std::min<int64_t>(kPanel, n - k0);
+        for (int64_t jj = 0; jj < nc; ++jj) {
+            const int64_t e = std::min<int64_t>(bw, n - 1 - (k0 + jj));
+            panel += 6.0 * e;
+            const int64_t left = std::min<int64_t>(nc - 1 - jj, e);
+            for (int64_t t = 1; t <= left; ++t) panel += 8.0 * (e - t + 1);
+        }
+        const int64_t w0 = k0 + kPanel, wend = std::min<int64_t>(n, k0 + kPanel + bw);
+        for (int64_t i = w0; i < wend; ++i) {
+            const int64_t kmin = std::max<int64_t>(k0, i - bw);
+            const int64_t c = std::max<int64_t>(0, k0 + kPanel - kmin);
+            update += 8.0 * (double)c * (double)(i - w0 + 1);
+        }
+    }
+}
+
+// Algorithmic real flops of one forward + backward band solve of one column.
+static double band_solve_flops(int64_t n, int64_t bw) {
+    double f = 0.0;
+    for (int64_t i = 0; i < n; ++i) f += 16.0 * (double)std::min<int64_t>(bw, n - 1 - i) + 9.0;
+    return f;
+}
 
 }  // namespace gep
 
@@ -373,6 +410,43 @@ static void upload(const HostPencil& H, gep_pencil* P) {
         }
     }
     P->h.prob_g4 = g0;
+    // column-major lower bands (a_ij, b_ij), 0 <= i - j <= bw, of every problem
+    // whose half bandwidth is at most kBandMaxBw
+    {
+        std::vector<int32_t> pbw(H.prob_row0.size(), 0);
+        std::vector<int64_t> poff(H.prob_row0.size(), -1);
+        int64_t total = 0;
+        for (size_t pi = 0; pi < H.prob_row0.size(); ++pi) {
+            const int64_t r0 = H.prob_row0[pi], r1 = r0 + H.prob_n[pi];
+            int64_t bw = 0;
+            for (int64_t i = r0; i < r1; ++i)
+                for (int32_t e = H.rowptr[i]; e < H.rowptr[i + 1]; ++e)
+                    bw = std::max<int64_t>(bw, std::llabs((int64_t)H.colind[e] - i));
+            pbw[pi] = (int32_t)std::min<int64_t>(bw, INT32_MAX);
+            if (bw <= kBandMaxBw) {
+                poff[pi] = total;
+                total += H.prob_n[pi] * (bw + 1);
+            }
+        }
+        if (total > 0) {
+            std::vector<double2> band((size_t)total, make_double2(0.0, 0.0));
+            for (size_t pi = 0; pi < H.prob_row0.size(); ++pi) {
+                if (poff[pi] < 0) continue;
+                const int64_t r0 = H.prob_row0[pi], r1 = r0 + H.prob_n[pi];
+                const int64_t ld = pbw[pi] + 1;
+                for (int64_t i = r0; i < r1; ++i)
+                    for (int32_t e = H.rowptr[i]; e < H.rowptr[i + 1]; ++e) {
+                        const int64_t j = H.colind[e];
+                        if (j > i) continue;
+                        band[poff[pi] + (j - r0) * ld + (i - j)] = make_double2(H.a[e], H.b[e]);
+                    }
+            }
+            D.band = (double2*)dalloc(sizeof(double2) * band.size());
+            HIPCHK(hipMemcpy(D.band, band.data(), sizeof(double2) * band.size(), hipMemcpyHostToDevice));
+        }
+        P->h.prob_bw = pbw;
+        P->h.prob_boff = poff;
+    }
     D.g4nnz = (int64_t)gcol.size();
     D.auto_grp = (double)D.g4nnz <= 0.8 * (double)H.nnz ? G : 1;
     D.g4ptr = (int32_t*)dalloc(sizeof(int32_t) * gptr.size());
@@ -452,6 +526,14 @@ struct Stats {
     int waves = 0;
     long fp64_columns = 0;        // mixed: columns finished by the FP64 recurrence
     long fp64_iters = 0;          // mixed: iterations of that FP64 completion
+    long band_factorisations = 0; // banded L D L^T of shifted systems
+    long band_panel_steps = 0;
+    long band_solves = 0;         // columns solved with the band factors
+    long band_refinements = 0;    // iterative-refinement sweeps
+    long band_pivot_flags = 0;    // systems with a zero or non-finite pivot
+    long band_unconverged = 0;    // passes whose band residual stayed above solve_tol
+    double band_relres_max = 0.0; // largest ||b - K x|| / ||b|| after refinement
+    double band_panel_flops = 0.0, band_update_flops = 0.0, band_solve_flops = 0.0;
 };
 
 static void choose_nrb(int64_t n, int n_active, int nrb_max, int& nrb) {
@@ -481,6 +563,134 @@ class Solver {
             (void)hipStreamSynchronize(own_);
             (void)hipStreamDestroy(own_);
         }
+    }
+
+    // Shifted solves of a pass by banded L D L^T (band.hip)?  solver: 0 =
+    // automatic (every pencil of the pass has half bandwidth <= kBandAutoBw),
+    // 1 = COCG, 2 = band (error if a pencil's band is wider than kBandMaxBw).
+    bool use_band(const std::vector<Job>& jobs) const {
+        const int mode = c_.o.solver;
+        if (mode == 1) return false;
+        for (const Job& j : jobs) {
+            const int p = j.prob;
+            if (P_->h.prob_boff[p] < 0) {
+                if (mode == 2)
+                    fail(GEP_EINVAL, "band solver: half bandwidth " + std::to_string(P_->h.prob_bw[p]) +
+                                         " of problem " + std::to_string(p) + " exceeds " +
+                                         std::to_string(kBandMaxBw));
+                return false;
+            }
+            if (mode == 0 && P_->h.prob_bw[p] > kBandAutoBw) return false;
+        }
+        return true;
+    }
+
+    // Solutions of every (job, node, rhs) column by banded L D L^T: X (tiled)
+    // = (z B - A)^-1 b.  The factors of a pass are kept for the next pass of
+    // the same solve when its contours and nodes are the same (the
+    // refinement pass).
+    void band_pass(const std::vector<Job>& jobs, CocgState& S, const double* BV, int64_t ldbv,
+                   int L, const std::vector<int64_t>& coff, const std::vector<double2>& shifts,
+                   int64_t nmax, double2* X) {
+        const int K = (int)jobs.size();
+        const int NH = c_.NH;
+        const int nsys = K * NH;
+        const int ntiles = S.ntiles;
+        const int64_t Wp = (int64_t)ntiles * kTile;
+        std::vector<BandSys> sys(nsys);
+        std::vector<double> keys;
+        int64_t total = 0;
+        int bwmax = 0;
+        for (int k = 0; k < K; ++k)
+            for (int j = 0; j < NH; ++j) {
+                BandSys& b = sys[(size_t)k * NH + j];
+                const int p = jobs[k].prob;
+                b.off = total;
+                b.aoff = P_->h.prob_boff[p];
+                b.n = (int32_t)jobs[k].n;
+                b.bw = P_->h.prob_bw[p];
+                b.z = shifts[coff[k] + (int64_t)j * L];
+                total += (int64_t)b.n * (b.bw + 1);
+                bwmax = std::max(bwmax, b.bw);
+                keys.insert(keys.end(), {(double)p, b.z.x, b.z.y});
+            }
+        std::vector<int32_t> colsys(Wp, -1);
+        for (int k = 0; k < K; ++k)
+            for (int j = 0; j < NH; ++j)
+                for (int l = 0; l < L; ++l) colsys[coff[k] + (int64_t)j * L + l] = k * NH + j;
+        DBuf<BandSys> dsys(nsys);
+        DBuf<int32_t> dcol(Wp);
+        HIPCHK(hipMemcpyAsync(dsys.get(), sys.data(), sizeof(BandSys) * nsys, hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(dcol.get(), colsys.data(), sizeof(int32_t) * Wp, hipMemcpyHostToDevice, s_));
+        if (!band_F_ || keys != band_keys_) {
+            band_F_.reset();
+            band_F_ = std::make_unique<DBuf<double2>>(total);
+            DBuf<int32_t> flags(nsys);
+            HIPCHK(hipMemsetAsync(flags.get(), 0, sizeof(int32_t) * nsys, s_));
+            HIPCHK(band_form(dsys.get(), nsys, dv_.band, band_F_->get(), s_));
+            int steps = 0;
+            for (int64_t k0 = 0; k0 < nmax; k0 += kPanel, ++steps) {
+                tm_.begin(T_BAND_PANEL);
+                HIPCHK(band_panel(dsys.get(), nsys, band_F_->get(), (int)k0, flags.get(), s_));
+                tm_.end();
+                if (k0 + kPanel < nmax) {
+                    tm_.begin(T_BAND_UPDATE);
+                    HIPCHK(band_update(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, s_));
+                    tm_.end();
+                }
+            }
+            for (int k = 0; k < K; ++k) {
+                double fp, fu;
+                band_factor_flops(jobs[k].n, P_->h.prob_bw[jobs[k].prob], fp, fu);
+                stats_.band_panel_flops += NH * fp;
+                stats_.band_update_flops += NH * fu;
+            }
+            std::vector<int32_t> fh(nsys);
+            HIPCHK(hipMemcpyAsync(fh.data(), flags.get(), sizeof(int32_t) * nsys, hipMemcpyDeviceToHost, s_));
+            HIPCHK(hipStreamSynchronize(s_));
+            tm_.flush();
+            for (int32_t v : fh) stats_.band_pivot_flags += v != 0;
+            stats_.band_factorisations += nsys;
+            stats_.band_panel_steps += steps;
+            band_keys_ = keys;
+        }
+        for (int k = 0; k < K; ++k)
+            stats_.band_solve_flops +=
+                (double)NH * L * band_solve_flops(jobs[k].n, P_->h.prob_bw[jobs[k].prob]);
+        tm_.begin(T_BAND_SOLVE);
+        HIPCHK(band_rhs(S.geom, S.bsrc, BV, ldbv, ntiles, X, s_));
+        HIPCHK(band_solve(dsys.get(), dcol.get(), band_F_->get(), S.geom, ntiles, bwmax, X, s_));
+        tm_.end();
+        // FP64 residual of every column, iterative refinement with the factors
+        constexpr int kCap = 4096;
+        DBuf<double2> R((size_t)Wp * std::max<int64_t>(nmax, 1));
+        DBuf<double2> part((size_t)ntiles * kCap * kTile);
+        DBuf<double> rel(Wp);
+        std::vector<double> relh(Wp);
+        for (int ref = 0;; ++ref) {
+            HIPCHK(band_residual(dv_, S.geom, S.shifts, S.bsrc, BV, ldbv, X, R.get(), ntiles, nmax,
+                                 part.get(), kCap, rel.get(), s_));
+            HIPCHK(hipMemcpyAsync(relh.data(), rel.get(), sizeof(double) * Wp, hipMemcpyDeviceToHost, s_));
+            HIPCHK(hipStreamSynchronize(s_));
+            tm_.flush();
+            double mx = 0.0;
+            for (int64_t c = 0; c < Wp; ++c)
+                if (colsys[c] >= 0) mx = std::max(mx, std::isfinite(relh[c]) ? relh[c] : INFINITY);
+            stats_.band_relres_max = std::max(stats_.band_relres_max, mx);
+            if (mx <= c_.o.solve_tol || ref == kBandRefineMax) {
+                if (mx > c_.o.solve_tol) stats_.band_unconverged += 1;
+                break;
+            }
+            tm_.begin(T_BAND_SOLVE);
+            HIPCHK(band_solve(dsys.get(), dcol.get(), band_F_->get(), S.geom, ntiles, bwmax, R.get(), s_));
+            HIPCHK(band_axpy(S.geom, R.get(), ntiles, X, s_));
+            for (int k = 0; k < K; ++k)
+                stats_.band_solve_flops +=
+                    (double)NH * L * band_solve_flops(jobs[k].n, P_->h.prob_bw[jobs[k].prob]);
+            tm_.end();
+            stats_.band_refinements += 1;
+        }
+        stats_.band_solves += Wp;
     }
 
     // One pass of the pipeline for a set of jobs sharing (L, M).  Job k's
@@ -539,9 +749,11 @@ class Solver {
                 }
             }
         }
+        // shifted solves: banded L D L^T (band.hip) or batched COCG
+        const bool band = use_band(jobs);
         CocgState S;
         S.ntiles = ntiles;
-        const bool mixed = c_.o.precision == GEP_MIXED;
+        const bool mixed = c_.o.precision == GEP_MIXED && !band;
         // small row blocks keep the gathers of concurrently running
         // work-groups inside the caches; one row group per wave by default,
         // and a whole number of groups per work-group
@@ -554,7 +766,9 @@ class Solver {
         const size_t mv = (size_t)elems;
         DBuf<double2> x(mv), u, p, pn;
         DBuf<float2> x32, u32, p32, pn32;
-        if (mixed) {
+        if (band) {
+            // only x (the solutions); the COCG vectors are not needed
+        } else if (mixed) {
             x32.alloc(mv);
             u32.alloc(mv);
             p32.alloc(mv);
@@ -625,6 +839,10 @@ class Solver {
         HIPCHK(hipMemcpyAsync(S.tiles, tl.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s_));
         HIPCHK(hipMemcpyAsync(S.counts, cnt0, sizeof(cnt0), hipMemcpyHostToDevice, s_));
         HIPCHK(hipMemcpyAsync(d_coef.get(), coef.data(), sizeof(double2) * coef.size(), hipMemcpyHostToDevice, s_));
+        std::vector<int32_t> its(Wp, 0), its0(Wp, 0);
+        if (band) {
+            band_pass(jobs, S, BV, ldbv, L, coff, shifts, nmax, x.get());
+        } else {
         if (mixed) {
             HIPCHK(hipMemsetAsync(S.x, 0, sizeof(double2) * mv, s_));
             HIPCHK(cocg32_init(dv_, S, BV, ldbv, nrb, s_));
@@ -732,7 +950,6 @@ class Solver {
         }
         };
         // per-column iteration counts -> exact tile work for the byte count
-        std::vector<int32_t> its(Wp), its0(Wp, 0);
         auto account = [&](double bytes_per_elem) {
             HIPCHK(hipMemcpyAsync(its.data(), S.iters, sizeof(int32_t) * Wp, hipMemcpyDeviceToHost, s_));
             HIPCHK(hipStreamSynchronize(s_));
@@ -800,6 +1017,7 @@ class Solver {
             }
         }
         stats_.cocg_iters += it;
+        }
         // moments
         auto Sall = std::make_shared<DBuf<double>>(std::max<int64_t>(soff[K], 1));
         tm_.begin(T_MOMENTS);
@@ -1001,6 +1219,9 @@ class Solver {
     gep_pencil* P_;
     SolveCfg c_;
     DevPencil dv_;   // the pencil with the row-group view of this solve
+    // banded factors of the last pass and the (problem, z) list they belong to
+    std::unique_ptr<DBuf<double2>> band_F_;
+    std::vector<double> band_keys_;
     hipStream_t s_ = nullptr;
     hipStream_t own_ = nullptr;
     Timer tm_;
@@ -1009,7 +1230,10 @@ class Solver {
     double gram_flops_ = 0.0, gemm_flops_ = 0.0;
 };
 
-static size_t bytes_per_job(int64_t n, int NH, int L, int M, bool mixed) {
+// Device bytes of one job in a wave.  bw >= 0: the job may take the band
+// path (factors of its NH systems, x and the residual); the larger of the two
+// paths is planned.
+static size_t bytes_per_job(int64_t n, int NH, int L, int M, bool mixed, int64_t bw) {
     const size_t W = (size_t)((NH * L + kTile - 1) / kTile) * kTile;
     const size_t r = (size_t)L * M;
     // FP64: x, u, p, pn.  Mixed: x and four FP32 vectors, then (FP64
@@ -1018,7 +1242,13 @@ static size_t bytes_per_job(int64_t n, int NH, int L, int M, bool mixed) {
     const size_t mv = (size_t)n * W * 16 * 4;
     // per-row-block partials: row blocks of at least 8 rows
     const size_t parts = W * (size_t)((n + 7) / 8) * 24;
-    return mv + parts + (size_t)n * r * 8 * 9 + (size_t)W * 160;
+    size_t solve = mv + parts;
+    if (bw >= 0) {
+        const size_t bandb = (size_t)NH * n * (size_t)(bw + 1) * 16 + (size_t)n * W * 16 * 2 +
+                             W * 4096 * 16;
+        solve = std::max(solve, bandb);
+    }
+    return solve + (size_t)n * r * 8 * 9 + (size_t)W * 160;
 }
 
 static std::string json_stats(const Solver& s, double wall_ms, const std::vector<ContourOut>& cos,
@@ -1031,6 +1261,16 @@ static std::string json_stats(const Solver& s, double wall_ms, const std::vector
       << ",\"spmm_launches\":" << s.stats_.spmm_launches
       << ",\"replacements\":" << s.stats_.replacements
       << ",\"fp64_columns\":" << s.stats_.fp64_columns << ",\"fp64_iters\":" << s.stats_.fp64_iters
+      << ",\"band_factorisations\":" << s.stats_.band_factorisations
+      << ",\"band_panel_steps\":" << s.stats_.band_panel_steps
+      << ",\"band_solves\":" << s.stats_.band_solves
+      << ",\"band_refinements\":" << s.stats_.band_refinements
+      << ",\"band_pivot_flags\":" << s.stats_.band_pivot_flags
+      << ",\"band_unconverged\":" << s.stats_.band_unconverged
+      << ",\"band_relres_max\":" << s.stats_.band_relres_max
+      << ",\"band_panel_flops\":" << s.stats_.band_panel_flops
+      << ",\"band_update_flops\":" << s.stats_.band_update_flops
+      << ",\"band_solve_flops\":" << s.stats_.band_solve_flops
       << ",\"graph_captures\":" << s.stats_.graph_captures
       << ",\"spmm_alg_bytes\":" << s.stats_.spmm_alg_bytes
       << ",\"update_alg_bytes\":" << s.stats_.update_alg_bytes
@@ -1117,7 +1357,9 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
         double used = 0.0;
         const int Lw = sorted_jobs[k0].L;
         while (k1 < sorted_jobs.size() && sorted_jobs[k1].L == Lw) {
-            const double need = (double)bytes_per_job(sorted_jobs[k1].n, cfg.NH, Lw, cfg.M, mixed);
+            const int pj = sorted_jobs[k1].prob;
+            const int64_t bwj = (cfg.o.solver != 1 && P->h.prob_boff[pj] >= 0) ? P->h.prob_bw[pj] : -1;
+            const double need = (double)bytes_per_job(sorted_jobs[k1].n, cfg.NH, Lw, cfg.M, mixed, bwj);
             if (k1 > k0 && used + need > budget) break;
             used += need;
             ++k1;
@@ -1295,6 +1537,7 @@ void gep_opts_default(gep_opts* o) {
     o->use_graph = 1;
     o->blocks = nullptr;
     o->row_group = 0;
+    o->solver = 0;
 }
 
 const char* gep_strerror(int st) {
@@ -1355,6 +1598,10 @@ static int validate_problem(const gep_contour* contours, int K, int N, int M, in
     if (o->rows_per_block < 0) { gep::set_error("rows_per_block must be >= 0"); return GEP_EINVAL; }
     if (o->row_group != 0 && o->row_group != 1 && o->row_group != 4) {
         gep::set_error("row_group must be 0, 1 or 4");
+        return GEP_EINVAL;
+    }
+    if (o->solver < 0 || o->solver > 2) {
+        gep::set_error("solver must be 0 (automatic), 1 (COCG) or 2 (band)");
         return GEP_EINVAL;
     }
     for (int k = 0; k < K; ++k) {

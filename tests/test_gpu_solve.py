@@ -72,18 +72,20 @@ def _oracle_refs(w, **kw):
     return _converged(ref)
 
 
-def test_small_fem1d_vs_oracle(lib):
+@pytest.mark.parametrize("solver", ["cocg", "band"])
+def test_small_fem1d_vs_oracle(lib, solver):
     w = configs.config_fem1d(n=400, first=31, last=40, n_nodes=16, moments=4, block=8, seed=7)
-    got = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed)
+    got = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed, solver=solver)
     lam, X = _oracle_refs(w)
     assert_pairs_match(got, lam, X, w.B)
     assert got["status"] in (0, lib.GEP_WSATURATED)
 
 
-def test_fem1d_2000_closed_form(lib):
+@pytest.mark.parametrize("solver", ["cocg", "band"])
+def test_fem1d_2000_closed_form(lib, solver):
     """1D linear-FEM pencil, n = 2000, eigenvalues 101..120, 16 nodes, 4 moments, 16 rhs."""
     w = configs.fem1d_2000()
-    got = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed)
+    got = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed, solver=solver)
     lam_ref = configs.line_eigs(2000)[100:120]
     i = np.arange(1, 2001)
     X_ref = np.stack([np.sin(i * j * np.pi / 2001) for j in range(101, 121)], axis=1)
@@ -103,20 +105,22 @@ def _var2d(nx=40, ny=37, seed=8, first=41, last=100, k=3):
     return configs.Workload("var2d", A, B, cont, 32, 4, 32, seed + 100, window=(lo, hi))
 
 
-def test_variable_coefficient_2d_vs_oracle(lib):
+@pytest.mark.parametrize("solver", ["cocg", "band"])
+def test_variable_coefficient_2d_vs_oracle(lib, solver):
     w = _var2d()
-    got = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed)
+    got = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed, solver=solver)
     lam, X = _oracle_refs(w)
     assert_pairs_match(got, lam, X, w.B)
 
 
-def test_explicit_rhs_and_device_inputs(lib):
+@pytest.mark.parametrize("solver", ["cocg", "band"])
+def test_explicit_rhs_and_device_inputs(lib, solver):
     import torch
     from oracle import rng
     w = configs.config_fem1d(n=600, first=41, last=52, n_nodes=16, moments=4, block=8, seed=3)
     V = rng.gaussian_block(w.n, w.block, w.seed)
-    a = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed)
-    b = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, rhs=V)
+    a = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed, solver=solver)
+    b = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, rhs=V, solver=solver)
     assert np.abs(a["evals"] - b["evals"]).max() <= 1e-12 * np.abs(a["evals"]).max()
     dev = torch.device("cuda:0")
     def d(M):
@@ -124,39 +128,42 @@ def test_explicit_rhs_and_device_inputs(lib):
                 torch.from_numpy(M.indices.astype(np.int32)).to(dev),
                 torch.from_numpy(M.data.astype(np.float64)).to(dev))
     c = lib.gep_ci_solve(d(w.A), d(w.B), w.contours, w.n_nodes, w.moments, w.block, w.tol,
-                         seed=w.seed)
+                         seed=w.seed, solver=solver)
     assert np.array_equal(a["evals"], c["evals"])
 
 
-def test_empty_contour(lib):
+@pytest.mark.parametrize("solver", ["cocg", "band"])
+def test_empty_contour(lib, solver):
     w = configs.config_fem1d(n=300, first=31, last=40, n_nodes=16, moments=2, block=8, seed=3)
     lam = configs.line_eigs(300)
     lo = 0.5 * (lam[30] + lam[31])
     c = np.array([[lo + 1e-3, 1e-3, lo, lo + 2e-3]])     # tiny circle inside a gap
-    got = lib.gep_ci_solve(w.A, w.B, c, 16, 2, 8, 1e-8, seed=1)
+    got = lib.gep_ci_solve(w.A, w.B, c, 16, 2, 8, 1e-8, seed=1, solver=solver)
     assert got["evals"].size == 0
 
 
 def test_no_convergence_flag(lib):
     w = configs.config_fem1d(n=300, first=31, last=40, n_nodes=16, moments=4, block=8, seed=3)
     got = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed,
-                           max_iter=3, max_refine=0)
+                           max_iter=3, max_refine=0, solver="cocg")
     assert got["status"] == lib.GEP_WNOCONV
     assert not got["converged"].all()
 
 
-def test_saturation_flag(lib):
+@pytest.mark.parametrize("solver", ["cocg", "band"])
+def test_saturation_flag(lib, solver):
     w = configs.fem1d_2000()
-    got = lib.gep_ci_solve(w.A, w.B, w.contours, 16, 1, 4, 1e-8, seed=1, max_refine=0)
+    got = lib.gep_ci_solve(w.A, w.B, w.contours, 16, 1, 4, 1e-8, seed=1, max_refine=0, solver=solver)
     assert got["status"] in (lib.GEP_WSATURATED, lib.GEP_WNOCONV)
     assert any(c["saturated"] for c in got["stats"]["contours"])
 
 
-def test_two_contours_share_cut_without_duplicates(lib):
+@pytest.mark.parametrize("solver", ["cocg", "band"])
+def test_two_contours_share_cut_without_duplicates(lib, solver):
     w = configs.config_fem1d(n=800, first=61, last=80, n_nodes=16, moments=4, block=16, seed=5)
     lo, hi = w.window
     cont = configs.uniform_contours(lo, hi, 2, 0.2)
-    got = lib.gep_ci_solve(w.A, w.B, cont, 16, 4, 16, 1e-8, seed=5)
+    got = lib.gep_ci_solve(w.A, w.B, cont, 16, 4, 16, 1e-8, seed=5, solver=solver)
     ref = oracle.oracle_ci_solve(w.A, w.B, cont, 16, 4, 16, 1e-8, seed=5)
     assert_pairs_match(got, *_converged(ref), w.B)
     assert np.all(np.diff(got["evals"]) > 0)
@@ -167,7 +174,7 @@ def test_precisions_fem1d_2000(lib, prec):
     """FP32 COCG with FP64 residual replacement meets the same bar as FP64."""
     w = configs.fem1d_2000()
     got = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed,
-                           precision=prec)
+                           precision=prec, solver="cocg")
     lam_o, X_o = _oracle_refs(w)
     assert_pairs_match(got, lam_o, X_o, w.B)
     assert got["stats"]["precision"] == prec
@@ -176,20 +183,21 @@ def test_precisions_fem1d_2000(lib, prec):
 def test_mixed_variable_coefficient_2d_vs_oracle(lib):
     w = _var2d(seed=9)
     got = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed,
-                           precision="mixed")
+                           precision="mixed", solver="cocg")
     lam, X = _oracle_refs(w)
     assert_pairs_match(got, lam, X, w.B)
     assert got["stats"]["replacements"] > 0
 
 
-def test_batch_of_uneven_pencils_vs_oracle(lib):
+@pytest.mark.parametrize("solver", ["cocg", "band"])
+def test_batch_of_uneven_pencils_vs_oracle(lib, solver):
     """gep_ci_solve_batch: pencils of different sizes share the COCG launches;
     problem p draws V from seed + p and must match its own oracle solve."""
     w1 = configs.config_fem1d(n=400, first=31, last=40, n_nodes=16, moments=4, block=16, seed=11)
     w2 = _var2d(nx=30, ny=27, seed=4, first=21, last=40, k=2)
     w3 = configs.config_fem1d(n=900, first=51, last=62, n_nodes=16, moments=4, block=16, seed=11)
     probs = [(w.A, w.B, w.contours) for w in (w1, w2, w3)]
-    got = lib.gep_ci_solve_batch(probs, 16, 4, 16, 1e-8, seed=11)
+    got = lib.gep_ci_solve_batch(probs, 16, 4, 16, 1e-8, seed=11, solver=solver)
     for p, w in enumerate((w1, w2, w3)):
         ref = oracle.oracle_ci_solve(w.A, w.B, w.contours, 16, 4, 16, 1e-8, seed=11 + p)
         assert_pairs_match(got[p], *_converged(ref), w.B)
@@ -202,11 +210,11 @@ def test_graph_replay_equals_eager(lib):
     import torch
     w = _var2d(nx=32, ny=30, seed=6, first=31, last=60, k=2)
     s = torch.cuda.Stream()
-    eager = lib.gep_ci_solve(w.A, w.B, w.contours, 32, 4, 16, 1e-8, seed=5, use_graph=False, stream=s)
+    eager = lib.gep_ci_solve(w.A, w.B, w.contours, 32, 4, 16, 1e-8, seed=5, use_graph=False, stream=s, solver="cocg")
     torch.cuda.synchronize()
-    graph = lib.gep_ci_solve(w.A, w.B, w.contours, 32, 4, 16, 1e-8, seed=5, use_graph=True, stream=s)
+    graph = lib.gep_ci_solve(w.A, w.B, w.contours, 32, 4, 16, 1e-8, seed=5, use_graph=True, stream=s, solver="cocg")
     torch.cuda.synchronize()
-    again = lib.gep_ci_solve(w.A, w.B, w.contours, 32, 4, 16, 1e-8, seed=5, use_graph=True)
+    again = lib.gep_ci_solve(w.A, w.B, w.contours, 32, 4, 16, 1e-8, seed=5, use_graph=True, solver="cocg")
     assert graph["stats"]["graph_captures"] > 0
     assert np.array_equal(eager["evals"], graph["evals"])
     assert np.array_equal(eager["resid"], graph["resid"])
@@ -214,13 +222,14 @@ def test_graph_replay_equals_eager(lib):
     assert eager["stats"]["cocg_iters"] == graph["stats"]["cocg_iters"]
 
 
-def test_per_contour_block_sizes_vs_oracle(lib):
+@pytest.mark.parametrize("solver", ["cocg", "band"])
+def test_per_contour_block_sizes_vs_oracle(lib, solver):
     """opts.blocks: contour k solves with the first blocks[k] columns of V."""
     from oracle import rng
     w = configs.config_fem1d(n=800, first=61, last=80, n_nodes=16, moments=4, block=16, seed=5)
     cont = configs.uniform_contours(*w.window, 2, 0.2)
     blocks = [8, 16]
-    got = lib.gep_ci_solve(w.A, w.B, cont, 16, 4, 16, 1e-8, seed=5, blocks=blocks)
+    got = lib.gep_ci_solve(w.A, w.B, cont, 16, 4, 16, 1e-8, seed=5, blocks=blocks, solver=solver)
     V = rng.gaussian_block(w.n, 16, 5)
     lams, Xs = [], []
     for k in range(2):
@@ -241,7 +250,7 @@ def test_row_groups_match_csr_and_oracle(lib, prec):
     w = _var2d(nx=31, ny=29, seed=9, first=31, last=60, k=2)
     assert w.n % 4 != 0
     r = {g: lib.gep_ci_solve(w.A, w.B, w.contours, 32, 4, 16, 1e-8, seed=5, precision=prec, row_group=g,
-                             rows_per_block=16)
+                             rows_per_block=16, solver="cocg")
          for g in (1, 4)}
     assert r[1]["evals"].size > 0
     assert_pairs_match(r[4], r[1]["evals"], r[1]["evecs"], w.B)
@@ -257,8 +266,8 @@ def test_row_groups_in_a_batch_of_uneven_pencils(lib):
     w3 = configs.config_fem1d(n=703, first=51, last=62, n_nodes=16, moments=4, block=16, seed=11)
     probs = [(w.A, w.B, w.contours) for w in (w1, w2, w3)]
     assert all(w.n % 4 for w in (w1, w2, w3))
-    a = lib.gep_ci_solve_batch(probs, 16, 4, 16, 1e-8, seed=3, row_group=1)
-    b = lib.gep_ci_solve_batch(probs, 16, 4, 16, 1e-8, seed=3, row_group=4)
+    a = lib.gep_ci_solve_batch(probs, 16, 4, 16, 1e-8, seed=3, row_group=1, solver="cocg")
+    b = lib.gep_ci_solve_batch(probs, 16, 4, 16, 1e-8, seed=3, row_group=4, solver="cocg")
     for p, w in enumerate((w1, w2, w3)):
         assert a[p]["evals"].size > 0
         assert_pairs_match(b[p], a[p]["evals"], a[p]["evecs"], w.B)
@@ -270,7 +279,7 @@ def test_row_groups_mixed_precision(lib):
     """FP32 recurrence on the 4-row group kernels vs plain CSR rows."""
     w = _var2d()
     r = {g: lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed,
-                             precision="mixed", row_group=g)
+                             precision="mixed", row_group=g, solver="cocg")
          for g in (1, 4)}
     lam, X = _oracle_refs(w)
     for g in (1, 4):
@@ -282,7 +291,7 @@ def test_mixed_fp64_completion_of_stalled_columns(lib):
     systems nearest the real axis; those columns are finished by the FP64
     recurrence from the folded solution, and every pair meets the bar."""
     w = _var2d(nx=31, ny=29, seed=9, first=31, last=60, k=2)
-    got = lib.gep_ci_solve(w.A, w.B, w.contours, 32, 4, 16, 1e-8, seed=5, precision="mixed")
+    got = lib.gep_ci_solve(w.A, w.B, w.contours, 32, 4, 16, 1e-8, seed=5, precision="mixed", solver="cocg")
     ref = oracle.oracle_ci_solve(w.A, w.B, w.contours, 32, 4, 16, 1e-8, seed=5)
     assert_pairs_match(got, *_converged(ref), w.B)
     assert got["stats"]["fp64_columns"] > 0
