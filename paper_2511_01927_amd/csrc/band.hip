@@ -13,7 +13,8 @@
 // Factorisation, right-looking by panels of kPanel columns, one step per
 // panel (all systems of a batch advance together):
 //   k_band_panel   one work-group per system: unblocked L D L^T of the
-//                  panel's kPanel columns (each (bw + 1) long) in place;
+//                  panel's kPanel columns (each (bw + 1) long) in place
+//                  (k_band_panel_reg: the same with the panel in registers);
 //   k_band_update  the trailing window of bw rows and columns after the
 //                  panel: C -= W diag(d) W^T, lower triangle, in 64 x 64
 //                  tiles staged through LDS.
@@ -22,7 +23,10 @@
 //   k_band_forward   L y = b by columns of L (axpy form), the pending rows
 //                    i+1 .. i+bw in a circular LDS window; writes y / d;
 //   k_band_backward  L^T x = z by columns of L (dot form), the solved rows
-//                    i+1 .. i+bw in the LDS window.
+//                    i+1 .. i+bw in the LDS window;
+//   k_band_sweep     the same two sweeps with the window in registers (one
+//                    half wavefront per column, see below), used when every
+//                    chunk of 8 or 16 columns belongs to one system.
 // Unpivoted elimination is safe here in practice (growth ~1 measured on the
 // shifted Q1 systems); every solve is followed by an FP64 residual check and
 // iterative refinement with the same factors, and a zero or non-finite pivot
@@ -92,6 +96,70 @@ __global__ __launch_bounds__(256) void k_band_panel(const BandSys* __restrict__ 
             cfms(P[(int64_t)(jj + t) * ld + e2], col[t + e2], f);
         }
         __syncthreads();
+    }
+}
+
+// Register-resident panel: the kPanel x (bw + 1) panel entries are spread
+// over the 1024 threads (entry f = jj * (bw + 1) + e held by thread f mod
+// 1024, register f / 1024); each column step publishes the pivot and the
+// scaled column through LDS (two barriers) and every thread updates its own
+// entries.  Used for kPanel * (bw + 1) <= 1024 * Q.
+constexpr int kPanelThreads = 1024;
+
+template <int Q>
+__global__ __launch_bounds__(kPanelThreads) void k_band_panel_reg(const BandSys* __restrict__ sys,
+                                                                  double2* F, int k0,
+                                                                  int32_t* __restrict__ flag) {
+    __shared__ double2 lcol[kPanelThreads * Q / kPanel + 1];
+    __shared__ double2 dsh;
+    const BandSys S = sys[blockIdx.x];
+    if (k0 >= S.n) return;
+    const int ld = S.bw + 1;
+    const int ncols = min(kPanel, S.n - k0);
+    const int total = ncols * ld;
+    double2* P = F + S.off + (int64_t)k0 * ld;
+    double2 v[Q];
+    int cj[Q], ce[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int f = threadIdx.x + kPanelThreads * q;
+        cj[q] = f < total ? f / ld : kPanel;   // kPanel: no entry
+        ce[q] = f < total ? f - cj[q] * ld : 0;
+        v[q] = f < total ? P[f] : make_double2(0.0, 0.0);
+    }
+    for (int jj = 0; jj < ncols; ++jj) {
+        const int j = k0 + jj;
+        const int emax = min(S.bw, S.n - 1 - j);
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if (cj[q] == jj && ce[q] == 0) dsh = v[q];
+        __syncthreads();
+        const double2 d = dsh;
+        const double m2 = d.x * d.x + d.y * d.y;
+        if (threadIdx.x == 0 && (!(m2 > 0.0) || !isfinite(m2))) flag[blockIdx.x] = 1;
+        const double2 inv = make_double2(d.x / m2, -d.y / m2);
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if (cj[q] == jj && ce[q] >= 1 && ce[q] <= emax) {
+                v[q] = cmul(v[q], inv);
+                lcol[ce[q]] = v[q];
+            }
+        __syncthreads();
+        // entries (jj + t, e2) with 1 <= t <= emax, e2 <= emax - t:
+        // a_{j+t+e2, j+t} -= l_{j+t+e2, j} d l_{j+t, j}
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int t = cj[q] - jj;
+            if (t >= 1 && t <= emax && ce[q] <= emax - t && cj[q] < ncols) {
+                const double2 f = cmul(d, lcol[t]);
+                cfms(v[q], lcol[t + ce[q]], f);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int f = threadIdx.x + kPanelThreads * q;
+        if (f < total) P[f] = v[q];
     }
 }
 
@@ -381,6 +449,187 @@ __global__ __launch_bounds__(256) void k_band_axpy(TileGeom geom, const double2*
     }
 }
 
+
+// ---- register-window sweeps ---------------------------------------------
+// Each column of a chunk of CPW columns (one system) is owned by a half
+// wavefront.  Lane l keeps K registers: register k holds row p + l + 32 k,
+// where p advances (forward) or retreats (backward) by 32 every 32 rows and
+// the registers rotate by one; K * 32 >= bw + 32 covers rows i .. i + bw.
+// The L columns of R consecutive rows are staged in LDS (double buffered,
+// the next block loaded into registers while the current one is used) as
+// 32 K entries: entry 0 and the entries past bw are zero, so every register
+// reads entry max(row - i, 0) with no other test; the diagonal is staged
+// apart.  One work-group barrier per R rows, none per row.
+//   forward: the lane holding row i broadcasts y_i = pending + b_i by a
+//     shuffle, writes y_i / d_i, and every register subtracts l_{row,i} y_i;
+//   backward: every register adds l_{row,i} x_row, the half wave reduces
+//     the sum, and the lane holding row i keeps x_i = z_i - sum.
+constexpr int kStageLds = 61440;   // bytes of LDS for the staged blocks
+
+template <int K, int CPW, bool FWD>
+__global__ __launch_bounds__(CPW * 32) void k_band_sweep(const BandSys* __restrict__ sys,
+                                                         const int32_t* __restrict__ colsys,
+                                                         const double2* __restrict__ F,
+                                                         TileGeom geom, double2* __restrict__ X,
+                                                         int R) {
+    constexpr int T = CPW * 32;
+    constexpr int W = 32 * K;   // staged entries per row
+    extern __shared__ double2 sh[];
+    const int tile = blockIdx.y;
+    const int c0 = blockIdx.x * CPW;
+    const int s0 = colsys[tile * kTile + c0];
+    if (s0 < 0) return;   // padding chunk (chunks never straddle systems)
+    const BandSys S = sys[s0];
+    const int n = S.n, bw = S.bw, ld = bw + 1;
+    const int64_t base = geom.base[tile];
+    const int lane = threadIdx.x & 31;
+    const int c = threadIdx.x >> 5;
+    const int RW = R * W, RC = R * CPW;
+    const int stage = RW + R + RC;     // entries per staged block
+    double2* Ls = sh;                  // [2][R][W]
+    double2* Ds = sh + 2 * RW;         // [2][R]
+    double2* bs = Ds + 2 * R;          // [2][R][CPW]
+    const double2* Fs = F + S.off;
+    const int nblk = (n + R - 1) / R;
+    constexpr int PF = (kStageLds / (2 * (int)sizeof(double2)) + T - 1) / T;
+    double2 pf[PF];
+    auto issue = [&](int blk) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int idx = threadIdx.x + q * T;
+            double2 v = make_double2(0.0, 0.0);
+            if (idx < RW) {
+                const int r = idx / W, d = idx - r * W;
+                const int i = blk * R + r;
+                if (i < n && d >= 1 && d <= bw) v = Fs[(int64_t)i * ld + d];
+            } else if (idx < RW + R) {
+                const int i = blk * R + (idx - RW);
+                if (i < n) v = Fs[(int64_t)i * ld];
+            } else if (idx < stage) {
+                const int r = (idx - RW - R) / CPW, cc = (idx - RW - R) - r * CPW;
+                const int i = blk * R + r;
+                if (i < n) v = X[base + (int64_t)i * kTile + c0 + cc];
+            }
+            pf[q] = v;
+        }
+    };
+    auto commit = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int idx = threadIdx.x + q * T;
+            if (idx < RW)
+                Ls[buf * RW + idx] = pf[q];
+            else if (idx < RW + R)
+                Ds[buf * R + idx - RW] = pf[q];
+            else if (idx < stage)
+                bs[buf * RC + idx - RW - R] = pf[q];
+        }
+    };
+    double2 win[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) win[k] = make_double2(0.0, 0.0);
+    int p = FWD ? 0 : ((n - 1) / 32) * 32;
+    issue(FWD ? 0 : nblk - 1);
+    commit(0);
+    __syncthreads();
+    for (int t = 0; t < nblk; ++t) {
+        const int blk = FWD ? t : nblk - 1 - t;
+        const int buf = t & 1;
+        if (t + 1 < nblk) issue(FWD ? blk + 1 : blk - 1);
+        for (int rr = 0; rr < R; ++rr) {
+            const int r = FWD ? rr : R - 1 - rr;
+            const int i = blk * R + r;
+            if (i >= n) continue;
+            const double2* Lr = Ls + buf * RW + r * W;
+            if (FWD) {
+                if (i - p == 32) {
+#pragma unroll
+                    for (int k = 0; k + 1 < K; ++k) win[k] = win[k + 1];
+                    win[K - 1] = make_double2(0.0, 0.0);
+                    p += 32;
+                }
+                const int ol = i - p;
+                double2 y;
+                y.x = __shfl(win[0].x, ol, 32);
+                y.y = __shfl(win[0].y, ol, 32);
+                const double2 b = bs[buf * RC + r * CPW + c];
+                y.x += b.x;
+                y.y += b.y;
+                if (lane == ol) {
+                    const double2 d = Ds[buf * R + r];
+                    const double m2 = d.x * d.x + d.y * d.y;
+                    X[base + (int64_t)i * kTile + c0 + c] =
+                        make_double2((y.x * d.x + y.y * d.y) / m2, (y.y * d.x - y.x * d.y) / m2);
+                }
+                const int b0 = p - i + lane;
+                double2 lv[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) lv[k] = Lr[max(b0 + 32 * k, 0)];
+#pragma unroll
+                for (int k = 0; k < K; ++k) cfms(win[k], lv[k], y);
+                if (lane == ol) win[0] = make_double2(0.0, 0.0);
+            } else {
+                if (i < p) {
+#pragma unroll
+                    for (int k = K - 1; k > 0; --k) win[k] = win[k - 1];
+                    win[0] = make_double2(0.0, 0.0);
+                    p -= 32;
+                }
+                const int b0 = p - i + lane;
+                double2 lv[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) lv[k] = Lr[max(b0 + 32 * k, 0)];
+                double2 part = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    part.x = fma(lv[k].x, win[k].x, fma(-lv[k].y, win[k].y, part.x));
+                    part.y = fma(lv[k].x, win[k].y, fma(lv[k].y, win[k].x, part.y));
+                }
+#pragma unroll
+                for (int o = 16; o > 0; o >>= 1) {
+                    part.x += __shfl_xor(part.x, o, 32);
+                    part.y += __shfl_xor(part.y, o, 32);
+                }
+                const double2 z = bs[buf * RC + r * CPW + c];
+                const double2 xv = make_double2(z.x - part.x, z.y - part.y);
+                if (lane == i - p) {
+                    X[base + (int64_t)i * kTile + c0 + c] = xv;
+                    win[0] = xv;
+                }
+            }
+        }
+        if (t + 1 < nblk) commit(buf ^ 1);
+        __syncthreads();
+    }
+}
+
+template <int K, int CPW>
+static hipError_t sweep_reg(const BandSys* sys, const int32_t* colsys, const double2* F,
+                            const TileGeom& g, int ntiles, double2* X, hipStream_t s) {
+    constexpr int W = 32 * K;
+    // R staged rows: 2 buffers of R * (W + 1 + CPW) entries within kStageLds
+    const int R = std::max(1, std::min(8, kStageLds / (2 * (W + 1 + CPW) * (int)sizeof(double2))));
+    const size_t lds = (size_t)2 * R * (W + 1 + CPW) * sizeof(double2);
+    hipLaunchKernelGGL((k_band_sweep<K, CPW, true>), dim3(kTile / CPW, ntiles), dim3(CPW * 32), lds, s,
+                       sys, colsys, F, g, X, R);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_band_sweep<K, CPW, false>), dim3(kTile / CPW, ntiles), dim3(CPW * 32), lds,
+                       s, sys, colsys, F, g, X, R);
+    return hipGetLastError();
+}
+
+template <int CPW>
+static hipError_t sweep_reg_k(const BandSys* sys, const int32_t* colsys, const double2* F,
+                              const TileGeom& g, int ntiles, int bw, double2* X, hipStream_t s) {
+    const int need = (bw + 32 + 31) / 32;   // K * 32 >= bw + 32
+    if (need <= 2) return sweep_reg<2, CPW>(sys, colsys, F, g, ntiles, X, s);
+    if (need <= 4) return sweep_reg<4, CPW>(sys, colsys, F, g, ntiles, X, s);
+    if (need <= 8) return sweep_reg<8, CPW>(sys, colsys, F, g, ntiles, X, s);
+    if (need <= 11) return sweep_reg<11, CPW>(sys, colsys, F, g, ntiles, X, s);
+    return sweep_reg<17, CPW>(sys, colsys, F, g, ntiles, X, s);
+}
+
 // ---- launchers ---------------------------------------------------------
 
 hipError_t band_form(const BandSys* sys, int nsys, const double2* AB, double2* F, hipStream_t s) {
@@ -388,9 +637,23 @@ hipError_t band_form(const BandSys* sys, int nsys, const double2* AB, double2* F
     return hipGetLastError();
 }
 
-hipError_t band_panel(const BandSys* sys, int nsys, double2* F, int k0, int32_t* flag,
+hipError_t band_panel(const BandSys* sys, int nsys, int bwmax, double2* F, int k0, int32_t* flag,
                       hipStream_t s) {
-    hipLaunchKernelGGL(k_band_panel, dim3(nsys), dim3(256), 0, s, sys, F, k0, flag);
+    // registers per thread for a kPanel x (bw + 1) panel over 1024 threads
+    const int need = (kPanel * (bwmax + 1) + kPanelThreads - 1) / kPanelThreads;
+    const dim3 b(kPanelThreads);
+    if (need <= 2)
+        hipLaunchKernelGGL(k_band_panel_reg<2>, dim3(nsys), b, 0, s, sys, F, k0, flag);
+    else if (need <= 4)
+        hipLaunchKernelGGL(k_band_panel_reg<4>, dim3(nsys), b, 0, s, sys, F, k0, flag);
+    else if (need <= 6)
+        hipLaunchKernelGGL(k_band_panel_reg<6>, dim3(nsys), b, 0, s, sys, F, k0, flag);
+    else if (need <= 8)
+        hipLaunchKernelGGL(k_band_panel_reg<8>, dim3(nsys), b, 0, s, sys, F, k0, flag);
+    else if (need <= 10)
+        hipLaunchKernelGGL(k_band_panel_reg<10>, dim3(nsys), b, 0, s, sys, F, k0, flag);
+    else   // wider bands: the panel stays in global memory (more registers would spill)
+        hipLaunchKernelGGL(k_band_panel, dim3(nsys), dim3(256), 0, s, sys, F, k0, flag);
     return hipGetLastError();
 }
 
@@ -423,7 +686,14 @@ static hipError_t solve_cw(const BandSys* sys, const int32_t* colsys, const doub
 }
 
 hipError_t band_solve(const BandSys* sys, const int32_t* colsys, const double2* F,
-                      const TileGeom& g, int ntiles, int bwmax, double2* X, hipStream_t s) {
+                      const TileGeom& g, int ntiles, int bwmax, double2* X, hipStream_t s,
+                      int chunk) {
+    // register-window sweeps when every chunk of `chunk` columns is one
+    // system and the window fits 16 slots per lane
+    if ((chunk == 16 || chunk == 8) && bwmax + 32 <= 32 * 17) {
+        if (chunk == 16) return sweep_reg_k<16>(sys, colsys, F, g, ntiles, bwmax, X, s);
+        return sweep_reg_k<8>(sys, colsys, F, g, ntiles, bwmax, X, s);
+    }
     switch (band_chunk_columns(bwmax)) {
         case 16: return solve_cw<16>(sys, colsys, F, g, ntiles, bwmax, X, s);
         case 8: return solve_cw<8>(sys, colsys, F, g, ntiles, bwmax, X, s);

@@ -167,8 +167,10 @@ struct BandSys {
     int32_t n = 0, bw = 0;
     double2 z{0.0, 0.0};
 };
-// Panel width of the banded factorisation and the LDS budget of the solves.
-constexpr int kPanel = 16;
+// Panel width of the banded factorisation (every step re-reads and re-writes
+// the trailing bw x bw window, so wider panels cut that traffic) and the LDS
+// budget of the generic solves.
+constexpr int kPanel = 32;
 // Widest half bandwidth for which a pencil's band is kept (the automatic
 // solver choice takes the band path up to kBandAutoBw).
 constexpr int64_t kBandMaxBw = 4096;
@@ -180,14 +182,17 @@ constexpr size_t kBandLds = 64 * 1024;
 hipError_t band_form(const BandSys* sys, int nsys, const double2* AB, double2* F, hipStream_t s);
 // One panel step: factor panel [k0, k0 + kPanel) (flag: zero or non-finite
 // pivot per system), then update the trailing window.
-hipError_t band_panel(const BandSys* sys, int nsys, double2* F, int k0, int32_t* flag,
+hipError_t band_panel(const BandSys* sys, int nsys, int bwmax, double2* F, int k0, int32_t* flag,
                       hipStream_t s);
 hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int k0, hipStream_t s);
 // Columns per work-group of the solves for a half bandwidth bw.
 int band_chunk_columns(int bw);
-// In place: X <- K^-1 X for every column (colsys: system of each tiled column, -1 = none).
+// In place: X <- K^-1 X for every column (colsys: system of each tiled column,
+// -1 = none).  chunk = 8 or 16 when every aligned chunk of that many columns
+// belongs to one system (register-window sweeps), else 0.
 hipError_t band_solve(const BandSys* sys, const int32_t* colsys, const double2* F,
-                      const TileGeom& g, int ntiles, int bwmax, double2* X, hipStream_t s);
+                      const TileGeom& g, int ntiles, int bwmax, double2* X, hipStream_t s,
+                      int chunk);
 hipError_t band_rhs(const TileGeom& g, const int64_t* bsrc, const double* BV, int64_t ldbv,
                     int ntiles, double2* X, hipStream_t s);
 // R = b - K X, rel[col] = ||R|| / ||b||; part holds ntiles * nrb_cap * 64 entries.

@@ -631,7 +631,7 @@ class Solver {
             int steps = 0;
             for (int64_t k0 = 0; k0 < nmax; k0 += kPanel, ++steps) {
                 tm_.begin(T_BAND_PANEL);
-                HIPCHK(band_panel(dsys.get(), nsys, band_F_->get(), (int)k0, flags.get(), s_));
+                HIPCHK(band_panel(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, flags.get(), s_));
                 tm_.end();
                 if (k0 + kPanel < nmax) {
                     tm_.begin(T_BAND_UPDATE);
@@ -659,7 +659,9 @@ class Solver {
                 (double)NH * L * band_solve_flops(jobs[k].n, P_->h.prob_bw[jobs[k].prob]);
         tm_.begin(T_BAND_SOLVE);
         HIPCHK(band_rhs(S.geom, S.bsrc, BV, ldbv, ntiles, X, s_));
-        HIPCHK(band_solve(dsys.get(), dcol.get(), band_F_->get(), S.geom, ntiles, bwmax, X, s_));
+        // chunks of 16 (or 8) columns belong to one system when L is a multiple
+        const int chunk = L % 16 == 0 ? 16 : (L % 8 == 0 ? 8 : 0);
+        HIPCHK(band_solve(dsys.get(), dcol.get(), band_F_->get(), S.geom, ntiles, bwmax, X, s_, chunk));
         tm_.end();
         // FP64 residual of every column, iterative refinement with the factors
         constexpr int kCap = 4096;
@@ -682,7 +684,8 @@ class Solver {
                 break;
             }
             tm_.begin(T_BAND_SOLVE);
-            HIPCHK(band_solve(dsys.get(), dcol.get(), band_F_->get(), S.geom, ntiles, bwmax, R.get(), s_));
+            HIPCHK(band_solve(dsys.get(), dcol.get(), band_F_->get(), S.geom, ntiles, bwmax, R.get(), s_,
+                              chunk));
             HIPCHK(band_axpy(S.geom, R.get(), ntiles, X, s_));
             for (int k = 0; k < K; ++k)
                 stats_.band_solve_flops +=
