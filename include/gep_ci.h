@@ -219,10 +219,13 @@ int gep_gram(const double* X, int64_t ld1, const double* Y, int64_t ld2, int64_t
 int gep_gemm_tall(const double* X, int64_t ldx, const double* T, int64_t ldt, int64_t n, int64_t k,
                   int64_t m, double* C, int64_t ldc, void* stream);
 
-/* Symmetric eigen-decomposition of `batch` k x k row-major matrices (cyclic
- * Jacobi, parallel ordering, one work-group per matrix): eigenvalues
- * ascending into w[batch*k], orthonormal eigenvectors as columns of
- * V[batch*k*k] (row-major).  A is overwritten. */
+/* Symmetric eigen-decomposition of `batch` k x k row-major matrices, k <= 1024
+ * (two-sided block Jacobi: 32-index blocks paired round robin, each 64 x 64
+ * subproblem diagonalised in LDS, the rotations applied to the block rows and
+ * columns as small products): eigenvalues ascending into w[batch*k],
+ * orthonormal eigenvectors as columns of V[batch*k*k] (row-major).  A is
+ * overwritten; a device work area is allocated per call; the stream is
+ * synchronised once per sweep.  GEP_EINVAL for bad sizes. */
 int gep_sym_eig(double* A, double* w, double* V, int64_t k, int batch, void* stream);
 
 /* Counter-based Gaussian block (the V of the solve): row-major n x L with

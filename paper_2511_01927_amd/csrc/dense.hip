@@ -2,6 +2,9 @@
 // (orthonormalisation and the reduced GEP A_k u = lambda B_k u, Alg.
 // "Standard CI pipeline").  Matrices are k x k, k <= 1024, row-major, one
 // work-group per matrix of a batch.
+#include <algorithm>
+#include <vector>
+
 #include "internal.h"
 
 namespace gep {
@@ -21,110 +24,328 @@ __device__ inline double block_sum(double v, double* red) {
     return s;
 }
 
-// ---- symmetric eigensolver: cyclic Jacobi, parallel (round-robin) order --
-// Each sweep visits all k(k-1)/2 pairs in kp-1 steps of kp/2 disjoint pairs
-// (kp = k rounded up to even; the padding index never rotates).  A rotation
-// (c, s) zeroes a_pq with t = sgn(tau)/(|tau| + sqrt(1 + tau^2)),
-// tau = (a_qq - a_pp)/(2 a_pq) (Golub and Van Loan, symmetric Schur 2x2);
-// rows then columns of A, and columns of V, are rotated.  Stops when the
-// off-diagonal Frobenius norm is <= 1e-15 ||A||_F or after 40 sweeps.
-__global__ __launch_bounds__(kDenseThreads) void k_jacobi(double* __restrict__ Aall,
-                                                          double* __restrict__ wout,
-                                                          double* __restrict__ Vout,
-                                                          double* __restrict__ Vwork, int kmax,
-                                                          const int32_t* __restrict__ ks) {
+// ---- symmetric eigensolver: block Jacobi, parallel (round-robin) order ---
+// Two-sided block Jacobi with blocks of kBJ = 32 indices (Golub and Van Loan,
+// block Jacobi for the symmetric eigenproblem).  The nbp blocks (k / 32
+// rounded up, plus one empty block when odd) are paired round robin: a sweep
+// is nbp - 1 rounds of nbp / 2 disjoint block pairs.  In a round every pair
+// (I, J) runs one cyclic sweep of element rotations on its 64 x 64 subproblem
+// S = A[I u J, I u J] in LDS (all index pairs in the first round of a sweep,
+// the pairs coupling I with J in the others) and accumulates the rotation R; then A[P, Q] <- R_P^T A[P, Q] R_Q for every two pairs P, Q of the round
+// (the diagonal blocks take S itself) and V[:, P] <- V[:, P] R_P.  An element
+// rotation zeroes s_pq with t = sgn(tau)/(|tau| + sqrt(1 + tau^2)),
+// tau = (s_qq - s_pp)/(2 s_pq) (symmetric Schur 2 x 2); s_pq, s_qp are set to
+// zero and s_pp -= t s_pq, s_qq += t s_pq.  Indices past k are padding: their
+// rows and columns are zero and never rotate.  Sweeps stop when the
+// off-diagonal Frobenius norm is <= 1e-15 ||A||_F, after at most 60 sweeps
+// (graded spectra converge linearly, about one decade per sweep).
+constexpr int kBJ = 32;
+constexpr int kBJ2 = 2 * kBJ;
+constexpr int kBJThreads = 256;
+constexpr int kBJMaxSweeps = 60;
+
+__device__ inline void bj_pair(int nbp, int r, int t, int& I, int& J) {
+    if (t == 0) {
+        I = nbp - 1;
+        J = r;
+    } else {
+        I = (r + t) % (nbp - 1);
+        J = (r - t + (nbp - 1)) % (nbp - 1);
+    }
+    if (I > J) {
+        const int x = I;
+        I = J;
+        J = x;
+    }
+}
+
+// global index of local index s of block pair (I, J)
+__device__ inline int bj_index(int I, int J, int s) { return s < kBJ ? I * kBJ + s : J * kBJ + (s - kBJ); }
+
+// Frobenius norm squared (whole or off-diagonal) of each matrix.
+__global__ __launch_bounds__(kDenseThreads) void k_bj_norm(const double* __restrict__ Aall, int kmax,
+                                                           const int32_t* __restrict__ ks, int offdiag,
+                                                           double* __restrict__ out) {
     __shared__ double red[kDenseThreads];
-    __shared__ int pp[kDenseThreads / 2], qq[kDenseThreads / 2];
-    __shared__ double cs[kDenseThreads / 2], sn[kDenseThreads / 2];
-    __shared__ double wl[kDenseThreads];
     const int b = blockIdx.x;
-    const int t = threadIdx.x;
-    const int nt = blockDim.x;
-    const int k = ks ? ks[b] : kmax;   // matrix b is k x k, stored with stride kmax * kmax
-    double* A = Aall + (int64_t)b * kmax * kmax;
-    double* V = Vwork + (int64_t)b * kmax * kmax;
-    if (k <= 0) return;
-    const int kp = k + (k & 1);
-    const int np = kp / 2;
-    for (int e = t; e < k * k; e += nt) V[e] = (e / k == e % k) ? 1.0 : 0.0;
+    const int k = ks ? ks[b] : kmax;
+    const double* A = Aall + (int64_t)b * kmax * kmax;
     double f = 0.0;
-    for (int e = t; e < k * k; e += nt) f += A[e] * A[e];
+    for (int i = threadIdx.y; i < k; i += blockDim.y)
+        for (int j = threadIdx.x; j < k; j += blockDim.x)
+            if (!offdiag || i != j) f += A[(int64_t)i * k + j] * A[(int64_t)i * k + j];
+    const int t = threadIdx.y * blockDim.x + threadIdx.x;
+    red[t] = f;
     __syncthreads();
-    const double fro2 = block_sum(f, red);
-    for (int sweep = 0; sweep < 40 && k > 1; ++sweep) {
-        double off = 0.0;
-        for (int e = t; e < k * k; e += nt)
-            if (e / k != e % k) off += A[e] * A[e];
-        const double off2 = block_sum(off, red);
-        if (!(off2 > 1e-30 * fro2)) break;
-        for (int step = 0; step < kp - 1; ++step) {
-            if (t < np) {
-                int p, q;
-                if (t == 0) {
-                    p = kp - 1;
-                    q = step;
+    for (int o = kDenseThreads / 2; o > 0; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+    }
+    if (t == 0) out[b] = red[0];
+}
+
+__global__ __launch_bounds__(kDenseThreads) void k_bj_identity(double* __restrict__ Vall, int kmax,
+                                                               const int32_t* __restrict__ ks) {
+    const int b = blockIdx.x;
+    const int k = ks ? ks[b] : kmax;
+    double* V = Vall + (int64_t)b * kmax * kmax;
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x) V[e] = (e / k == e % k) ? 1.0 : 0.0;
+}
+
+// One rotation sweep on the subproblem of block pair blockIdx.x of round r of
+// matrix blockIdx.y; R and S of the pair go to Rall and Sall.  full != 0:
+// all 64 * 63 / 2 index pairs (63 steps of 32 disjoint pairs, round robin);
+// else only the 32 * 32 pairs that couple I with J (step s pairs local index
+// p with 32 + (p + s) mod 32).  A sweep uses full on its first round, so that
+// every index pair of the matrix is visited at least once per sweep.
+__global__ __launch_bounds__(kBJThreads) void k_bj_solve(const double* __restrict__ Aall, int kmax,
+                                                         const int32_t* __restrict__ ks, int nbp, int r,
+                                                         int full, double* __restrict__ Rall,
+                                                         double* __restrict__ Sall) {
+    constexpr int kPer = kBJ * kBJ2 / kBJThreads;   // element pairs per thread and phase
+    constexpr int kLanes = kBJThreads / kBJ;        // threads per rotation
+    __shared__ double S[kBJ2][kBJ2 + 1];
+    __shared__ double Rm[kBJ2][kBJ2 + 1];
+    __shared__ int pp[kBJ], qq[kBJ];
+    __shared__ double cs[kBJ], sn[kBJ], dp[kBJ], dq[kBJ];
+    const int b = blockIdx.y;
+    const int k = ks ? ks[b] : kmax;
+    const int t = threadIdx.x;
+    int I, J;
+    bj_pair(nbp, r, blockIdx.x, I, J);
+    const double* A = Aall + (int64_t)b * kmax * kmax;
+    for (int e = t; e < kBJ2 * kBJ2; e += kBJThreads) {
+        const int s1 = e / kBJ2, s2 = e % kBJ2;
+        const int g1 = bj_index(I, J, s1), g2 = bj_index(I, J, s2);
+        S[s1][s2] = (g1 < k && g2 < k) ? A[(int64_t)g1 * k + g2] : 0.0;
+        Rm[s1][s2] = s1 == s2 ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int pr = t / kLanes, l0 = t % kLanes;   // this thread's rotation and first row / column
+    const int nsteps = full ? kBJ2 - 1 : kBJ;
+    for (int step = 0; step < nsteps; ++step) {
+        if (t < kBJ) {
+            int p, q;
+            if (!full) {
+                p = t;
+                q = kBJ + (t + step) % kBJ;
+            } else if (t == 0) {
+                p = kBJ2 - 1;
+                q = step;
+            } else {
+                p = (step + t) % (kBJ2 - 1);
+                q = (step - t + (kBJ2 - 1)) % (kBJ2 - 1);
+            }
+            if (p > q) {
+                const int x = p;
+                p = q;
+                q = x;
+            }
+            double c = 1.0, sv = 0.0, tt = 0.0;
+            const double apq = S[p][q], app = S[p][p], aqq = S[q][q];
+            if (apq != 0.0) {
+                const double diff = aqq - app;
+                if (fabs(diff) > 1e150 * fabs(apq)) {
+                    tt = apq / diff;
                 } else {
-                    p = (step + t) % (kp - 1);
-                    q = (step - t + (kp - 1)) % (kp - 1);
+                    const double tau = diff / (2.0 * apq);
+                    tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                 }
-                if (p > q) {
-                    const int tmp = p;
-                    p = q;
-                    q = tmp;
-                }
-                double c = 1.0, s = 0.0;
-                if (q < k) {
-                    const double apq = A[(int64_t)p * k + q];
-                    if (apq != 0.0) {
-                        const double diff = A[(int64_t)q * k + q] - A[(int64_t)p * k + p];
-                        double tt;
-                        if (fabs(diff) > 1e150 * fabs(apq)) {
-                            tt = apq / diff;
-                        } else {
-                            const double tau = diff / (2.0 * apq);
-                            tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        }
-                        c = 1.0 / sqrt(1.0 + tt * tt);
-                        s = tt * c;
-                    }
-                }
-                pp[t] = p;
-                qq[t] = q;
-                cs[t] = c;
-                sn[t] = s;
+                c = 1.0 / sqrt(1.0 + tt * tt);
+                sv = tt * c;
             }
-            __syncthreads();
-            // rows p, q of A
-            for (int e = t; e < np * k; e += nt) {
-                const int pr = e / k, j = e - pr * k;
-                const int p = pp[pr], q = qq[pr];
-                if (q >= k || sn[pr] == 0.0) continue;
-                const double c = cs[pr], s = sn[pr];
-                const double ap = A[(int64_t)p * k + j], aq = A[(int64_t)q * k + j];
-                A[(int64_t)p * k + j] = c * ap - s * aq;
-                A[(int64_t)q * k + j] = s * ap + c * aq;
+            pp[t] = p;
+            qq[t] = q;
+            cs[t] = c;
+            sn[t] = sv;
+            dp[t] = app - tt * apq;
+            dq[t] = aqq + tt * apq;
+        }
+        __syncthreads();
+        const int p = pp[pr], q = qq[pr];
+        const double c = cs[pr], sv = sn[pr];
+        {   // rows p, q of S (an unrotated pair has c = 1, sv = 0 and is rewritten unchanged)
+            double ap[kPer], aq[kPer];
+#pragma unroll
+            for (int m = 0; m < kPer; ++m) {
+                ap[m] = S[p][l0 + kLanes * m];
+                aq[m] = S[q][l0 + kLanes * m];
             }
-            __syncthreads();
-            // columns p, q of A and V
-            for (int e = t; e < np * k; e += nt) {
-                const int i = e / np, pr = e - i * np;
-                const int p = pp[pr], q = qq[pr];
-                if (q >= k || sn[pr] == 0.0) continue;
-                const double c = cs[pr], s = sn[pr];
-                const double ap = A[(int64_t)i * k + p], aq = A[(int64_t)i * k + q];
-                A[(int64_t)i * k + p] = c * ap - s * aq;
-                A[(int64_t)i * k + q] = s * ap + c * aq;
-                const double vp = V[(int64_t)i * k + p], vq = V[(int64_t)i * k + q];
-                V[(int64_t)i * k + p] = c * vp - s * vq;
-                V[(int64_t)i * k + q] = s * vp + c * vq;
+#pragma unroll
+            for (int m = 0; m < kPer; ++m) {
+                S[p][l0 + kLanes * m] = c * ap[m] - sv * aq[m];
+                S[q][l0 + kLanes * m] = sv * ap[m] + c * aq[m];
             }
-            __syncthreads();
+        }
+        __syncthreads();
+        {   // columns p, q of S and R; entries (p,p), (p,q), (q,p), (q,q) take the 2 x 2 result
+            double sp[kPer], sq[kPer], rp[kPer], rq[kPer];
+#pragma unroll
+            for (int m = 0; m < kPer; ++m) {
+                const int i = l0 + kLanes * m;
+                sp[m] = S[i][p];
+                sq[m] = S[i][q];
+                rp[m] = Rm[i][p];
+                rq[m] = Rm[i][q];
+            }
+            const double dpp = dp[pr], dqq = dq[pr];
+#pragma unroll
+            for (int m = 0; m < kPer; ++m) {
+                const int i = l0 + kLanes * m;
+                double np = c * sp[m] - sv * sq[m];
+                double nq = sv * sp[m] + c * sq[m];
+                np = i == p ? dpp : (i == q ? 0.0 : np);
+                nq = i == q ? dqq : (i == p ? 0.0 : nq);
+                S[i][p] = np;
+                S[i][q] = nq;
+                Rm[i][p] = c * rp[m] - sv * rq[m];
+                Rm[i][q] = sv * rp[m] + c * rq[m];
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t off = ((int64_t)b * (nbp / 2) + blockIdx.x) * kBJ2 * kBJ2;
+    for (int e = t; e < kBJ2 * kBJ2; e += kBJThreads) {
+        Rall[off + e] = Rm[e / kBJ2][e % kBJ2];
+        Sall[off + e] = S[e / kBJ2][e % kBJ2];
+    }
+}
+
+// C (64 x 64 per work-group, 4 x 4 per thread) = X^T Y or X Y for LDS tiles.
+template <bool TRANS_X>
+__device__ inline void bj_tile_product(const double (*X)[kBJ2 + 1], const double (*Y)[kBJ2 + 1],
+                                       double (&acc)[4][4], int tr, int tc) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[a][q] = 0.0;
+    for (int u = 0; u < kBJ2; ++u) {
+        double xv[4], yv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) xv[a] = TRANS_X ? X[u][tr * 4 + a] : X[tr * 4 + a][u];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) yv[q] = Y[u][tc + 16 * q];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[a][q] = fma(xv[a], yv[q], acc[a][q]);
+    }
+}
+
+// Apply the round's rotations.  Work-groups [0, nA) take the pair blocks
+// (P <= Q) of A: A[P, Q] <- R_P^T A[P, Q] R_Q and A[Q, P] its transpose, or S
+// when P == Q; the rest take 64-row chunks of V: V[c, P] <- V[c, P] R_P.
+__global__ __launch_bounds__(kBJThreads) void k_bj_apply(double* __restrict__ Aall,
+                                                         double* __restrict__ Vall, int kmax,
+                                                         const int32_t* __restrict__ ks, int nbp,
+                                                         int r, const double* __restrict__ Rall,
+                                                         const double* __restrict__ Sall) {
+    __shared__ double X[kBJ2][kBJ2 + 1];
+    __shared__ double Y[kBJ2][kBJ2 + 1];
+    __shared__ double Z[kBJ2][kBJ2 + 1];
+    const int b = blockIdx.y;
+    const int k = ks ? ks[b] : kmax;
+    const int npair = nbp / 2;
+    const int nA = npair * (npair + 1) / 2;
+    const int t = threadIdx.x;
+    const int tc = t & 15, tr = t >> 4;
+    double* A = Aall + (int64_t)b * kmax * kmax;
+    const double* Rb = Rall + (int64_t)b * npair * kBJ2 * kBJ2;
+    int w = blockIdx.x;
+    if (w < nA) {
+        int P = 0;
+        while (w >= npair - P) {   // upper-triangular enumeration of (P, Q)
+            w -= npair - P;
+            ++P;
+        }
+        const int Q = P + w;
+        int I1, J1, I2, J2;
+        bj_pair(nbp, r, P, I1, J1);
+        bj_pair(nbp, r, Q, I2, J2);
+        if (P == Q) {
+            const double* Sp = Sall + ((int64_t)b * npair + P) * kBJ2 * kBJ2;
+            for (int e = t; e < kBJ2 * kBJ2; e += kBJThreads) {
+                const int g1 = bj_index(I1, J1, e / kBJ2), g2 = bj_index(I1, J1, e % kBJ2);
+                if (g1 < k && g2 < k) A[(int64_t)g1 * k + g2] = Sp[e];
+            }
+            return;
+        }
+        const double* R1 = Rb + (int64_t)P * kBJ2 * kBJ2;
+        const double* R2 = Rb + (int64_t)Q * kBJ2 * kBJ2;
+        for (int e = t; e < kBJ2 * kBJ2; e += kBJThreads) {
+            const int s1 = e / kBJ2, s2 = e % kBJ2;
+            const int g1 = bj_index(I1, J1, s1), g2 = bj_index(I2, J2, s2);
+            X[s1][s2] = R1[e];
+            Y[s1][s2] = (g1 < k && g2 < k) ? A[(int64_t)g1 * k + g2] : 0.0;
+            Z[s1][s2] = R2[e];
+        }
+        __syncthreads();
+        double acc[4][4];
+        bj_tile_product<true>(X, Y, acc, tr, tc);   // R_P^T A[P, Q]
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Y[tr * 4 + a][tc + 16 * q] = acc[a][q];
+        __syncthreads();
+        bj_tile_product<false>(Y, Z, acc, tr, tc);   // (R_P^T A[P, Q]) R_Q
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int g1 = bj_index(I1, J1, tr * 4 + a);
+            if (g1 >= k) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int g2 = bj_index(I2, J2, tc + 16 * q);
+                if (g2 >= k) continue;
+                A[(int64_t)g1 * k + g2] = acc[a][q];
+                A[(int64_t)g2 * k + g1] = acc[a][q];
+            }
+        }
+        return;
+    }
+    w -= nA;
+    const int P = w % npair;
+    const int r0 = (w / npair) * kBJ2;
+    if (r0 >= k) return;
+    int I, J;
+    bj_pair(nbp, r, P, I, J);
+    double* V = Vall + (int64_t)b * kmax * kmax;
+    const double* R = Rb + (int64_t)P * kBJ2 * kBJ2;
+    for (int e = t; e < kBJ2 * kBJ2; e += kBJThreads) {
+        const int i = e / kBJ2, s2 = e % kBJ2;
+        const int g = bj_index(I, J, s2);
+        X[i][s2] = (g < k && r0 + i < k) ? V[(int64_t)(r0 + i) * k + g] : 0.0;
+        Y[i][s2] = R[e];
+    }
+    __syncthreads();
+    double acc[4][4];
+    bj_tile_product<false>(X, Y, acc, tr, tc);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int i = r0 + tr * 4 + a;
+        if (i >= k) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int g = bj_index(I, J, tc + 16 * q);
+            if (g < k) V[(int64_t)i * k + g] = acc[a][q];
         }
     }
-    // ascending order by rank (ties broken by index)
-    for (int j = t; j < k; j += nt) wl[j] = A[(int64_t)j * k + j];
+}
+
+// Eigenvalues ascending by rank (ties broken by index), eigenvector columns with them.
+__global__ __launch_bounds__(kDenseThreads) void k_bj_sort(const double* __restrict__ Aall,
+                                                           const double* __restrict__ Vall,
+                                                           double* __restrict__ wout,
+                                                           double* __restrict__ Vout, int kmax,
+                                                           const int32_t* __restrict__ ks) {
+    __shared__ double wl[kDenseThreads];
+    const int b = blockIdx.x;
+    const int k = ks ? ks[b] : kmax;
+    const double* A = Aall + (int64_t)b * kmax * kmax;
+    const double* V = Vall + (int64_t)b * kmax * kmax;
+    for (int j = threadIdx.x; j < k; j += blockDim.x) wl[j] = A[(int64_t)j * k + j];
     __syncthreads();
-    for (int j = t; j < k; j += nt) {
+    for (int j = threadIdx.x; j < k; j += blockDim.x) {
         const double wj = wl[j];
         int rank = 0;
         for (int i = 0; i < k; ++i) rank += (wl[i] < wj) || (wl[i] == wj && i < j);
@@ -134,12 +355,52 @@ __global__ __launch_bounds__(kDenseThreads) void k_jacobi(double* __restrict__ A
     }
 }
 
+size_t sym_eig_work_elems(int64_t kmax, int batch) {
+    const int64_t nb = (kmax + kBJ - 1) / kBJ;
+    const int64_t nbp = std::max<int64_t>(2, nb + (nb & 1));
+    return (size_t)batch * kmax * kmax + 2 * (size_t)batch * (nbp / 2) * kBJ2 * kBJ2 + 2 * (size_t)batch;
+}
+
 hipError_t launch_sym_eig(double* A, double* w, double* V, int64_t kmax, int batch,
                           const int32_t* ks, double* work, hipStream_t s) {
     if (kmax <= 0 || batch <= 0) return hipSuccess;
     if (kmax > kDenseThreads) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_jacobi, dim3(batch), dim3(kDenseThreads), 0, s, A, w, V, work, (int)kmax,
-                       ks);
+    const int nb = (int)((kmax + kBJ - 1) / kBJ);
+    const int nbp = std::max(2, nb + (nb & 1));
+    const int npair = nbp / 2;
+    const int nA = npair * (npair + 1) / 2;
+    const int nV = npair * (int)((kmax + kBJ2 - 1) / kBJ2);
+    double* Vw = work;
+    double* Rw = Vw + (size_t)batch * kmax * kmax;
+    double* Sw = Rw + (size_t)batch * npair * kBJ2 * kBJ2;
+    double* fro = Sw + (size_t)batch * npair * kBJ2 * kBJ2;
+    double* off = fro + batch;
+    hipLaunchKernelGGL(k_bj_identity, dim3(batch), dim3(kDenseThreads), 0, s, Vw, (int)kmax, ks);
+    hipLaunchKernelGGL(k_bj_norm, dim3(batch), dim3(32, 32), 0, s, A, (int)kmax, ks, 0, fro);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    std::vector<double> fh(batch), oh(batch);
+    e = hipMemcpyAsync(fh.data(), fro, sizeof(double) * batch, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    for (int sweep = 0; sweep < kBJMaxSweeps; ++sweep) {
+        hipLaunchKernelGGL(k_bj_norm, dim3(batch), dim3(32, 32), 0, s, A, (int)kmax, ks, 1, off);
+        e = hipMemcpyAsync(oh.data(), off, sizeof(double) * batch, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        bool done = true;
+        for (int b = 0; b < batch; ++b) done &= !(oh[b] > 1e-30 * fh[b]);
+        if (done) break;
+        for (int r = 0; r < nbp - 1; ++r) {
+            hipLaunchKernelGGL(k_bj_solve, dim3(npair, batch), dim3(kBJThreads), 0, s, A, (int)kmax, ks,
+                               nbp, r, (int)(r == 0), Rw, Sw);
+            hipLaunchKernelGGL(k_bj_apply, dim3(nA + nV, batch), dim3(kBJThreads), 0, s, A, Vw, (int)kmax,
+                               ks, nbp, r, Rw, Sw);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_bj_sort, dim3(batch), dim3(kDenseThreads), 0, s, A, Vw, w, V, (int)kmax, ks);
     return hipGetLastError();
 }
 

@@ -214,8 +214,11 @@ hipError_t launch_gemm_tall(const double* X, int64_t ldx, const double* T, int64
                             int64_t k, int64_t m, double* C, int64_t ldc, hipStream_t s);
 // Batched symmetric eigensolver; matrix b is ks[b] x ks[b] (row-major, leading
 // dimension ks[b]) at offset b * kmax^2; ks == NULL means all kmax.
+// work holds sym_eig_work_elems(kmax, batch) doubles.  Synchronises the
+// stream once per Jacobi sweep (convergence test on the host).
 hipError_t launch_sym_eig(double* A, double* w, double* V, int64_t kmax, int batch,
                           const int32_t* ks, double* work, hipStream_t s);
+size_t sym_eig_work_elems(int64_t kmax, int batch);
 // Cholesky of SPD matrices (same batching); writes L^-T (upper) into LinvT;
 // status[b] = 0 ok, j+1 if pivot j failed.
 hipError_t launch_chol_inv(const double* G, double* LinvT, int64_t kmax, int batch,

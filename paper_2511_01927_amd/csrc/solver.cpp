@@ -1070,7 +1070,7 @@ class Solver {
         const size_t tot = (size_t)soff[K], rr2 = (size_t)r0 * r0;
         int64_t nmax = 0;
         for (const Job& j : jobs) nmax = std::max(nmax, j.n);
-        DBuf<double> T(tot), Q1(tot), G(rr2 * K), U(rr2 * K), w((size_t)r0 * K), jw(rr2 * K);
+        DBuf<double> T(tot), Q1(tot), G(rr2 * K), U(rr2 * K), w((size_t)r0 * K), jw(std::max(rr2 * K, sym_eig_work_elems(r0, K)));
         DBuf<double> gw(gram_work_elems(nmax, r0, r0));
         DBuf<int32_t> ks(K), st(K);
         // pass 1: SVQB on the B-Gram G = S^T B S
@@ -1846,7 +1846,7 @@ int gep_gemm_tall(const double* X, int64_t ldx, const double* T, int64_t ldt, in
 int gep_sym_eig(double* A, double* w, double* V, int64_t k, int batch, void* stream) {
     if (!A || !w || !V || k <= 0 || k > 1024 || batch <= 0) { gep::set_error("bad sym_eig arguments"); return GEP_EINVAL; }
     try {
-        gep::DBuf<double> work((size_t)batch * k * k);
+        gep::DBuf<double> work(gep::sym_eig_work_elems(k, batch));
         HIPCHK(gep::launch_sym_eig(A, w, V, k, batch, nullptr, work.get(), (hipStream_t)stream));
         HIPCHK(hipStreamSynchronize((hipStream_t)stream));
     } catch (const gep::Fail& f) {

@@ -121,7 +121,7 @@ def test_gemm_tall_mfma(dev, n, k, m):
     assert np.abs(Cm.cpu().numpy() - ref).max() <= 1e-13 * np.sqrt(k) * 10
 
 
-@pytest.mark.parametrize("k", [1, 2, 17, 100, 256])
+@pytest.mark.parametrize("k", [1, 2, 17, 33, 65, 100, 256, 500])
 def test_sym_eig_jacobi(dev, k):
     import torch
     from paper_2511_01927_amd import gep_ci
@@ -143,6 +143,34 @@ def test_sym_eig_jacobi(dev, k):
     assert np.abs(wh - ref).max() <= 1e-14 * scale * max(1, k) ** 0.5
     assert np.abs(Vh.T @ Vh - np.eye(k)).max() <= 1e-13 * max(1, k)
     assert np.abs(A @ Vh - Vh * wh[None, :]).max() <= 1e-13 * scale * max(1, k)
+
+
+def test_sym_eig_batch_and_clusters(dev):
+    """Three matrices in one call: exactly repeated eigenvalues (clusters of
+    four), a diagonal matrix (nothing to rotate) and a graded spectrum; per
+    matrix the eigenvalues match, V is orthonormal and A V = V diag(w)."""
+    import torch
+    from paper_2511_01927_amd import gep_ci
+    k = 96
+    rng = np.random.default_rng(7)
+    Q, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    lam = np.repeat(np.arange(1.0, k // 4 + 1), 4)
+    A0 = Q @ np.diag(lam) @ Q.T
+    A1 = np.diag(rng.uniform(-1, 1, k))
+    Q2, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    A2 = Q2 @ np.diag(10.0 ** rng.uniform(-12, 0, k)) @ Q2.T
+    mats = [0.5 * (M + M.T) for M in (A0, A1, A2)]
+    Ad = _t(np.stack(mats), dev)
+    w = torch.zeros(3 * k, dtype=torch.float64, device=dev)
+    V = torch.zeros((3, k, k), dtype=torch.float64, device=dev)
+    gep_ci.gep_sym_eig(Ad, w, V, k, 3, stream=0)
+    wh, Vh = w.cpu().numpy().reshape(3, k), V.cpu().numpy()
+    for b, A in enumerate(mats):
+        ref = np.linalg.eigvalsh(A)
+        scale = np.abs(ref).max()
+        assert np.abs(wh[b] - ref).max() <= 1e-14 * scale * k ** 0.5
+        assert np.abs(Vh[b].T @ Vh[b] - np.eye(k)).max() <= 1e-13 * k
+        assert np.abs(A @ Vh[b] - Vh[b] * wh[b][None, :]).max() <= 1e-13 * scale * k
 
 
 def test_gaussian_block_matches_oracle_generator(dev):
