@@ -203,6 +203,7 @@ def main():
             "cocg_update": ("hbm", st["update_alg_bytes"]),
             "cocg_replace": ("hbm", st["replace_alg_bytes"]),
             "band_update": ("alu", st["band_update_flops"]),
+            "band_update_next": ("alu", st["band_update_next_flops"]),
             "band_panel": ("alu", st["band_panel_flops"]),
             "band_solve": ("alu", st["band_solve_flops"])}
     # dominant kernel by measured time

@@ -17,7 +17,11 @@
 //                  (k_band_panel_reg: the same with the panel in registers);
 //   k_band_update  the trailing window of bw rows and columns after the
 //                  panel: C -= W diag(d) W^T, lower triangle, in 64 x 64
-//                  tiles staged through LDS.
+//                  tiles staged through LDS; split into the next panel's
+//                  columns (with the contributions of this panel and the
+//                  one before) and the window past the panel after next,
+//                  so that the rest can run on a second stream beside the
+//                  next two panel steps (lookahead).
 // Solves, in place on the tiled multivector (element (i, c) at
 // (tile * n + i) * 64 + lane), a work-group per (tile, chunk of columns):
 //   k_band_forward   L y = b by columns of L (axpy form), the pending rows
@@ -163,38 +167,87 @@ __global__ __launch_bounds__(kPanelThreads) void k_band_panel_reg(const BandSys*
     }
 }
 
-// Trailing update after panel [k0, k0 + kPanel): rows and columns
-// [k0 + kPanel, min(n, k0 + kPanel + bw)), lower triangle.  blockIdx.x is
-// a lower-triangular tile index (bi >= bj) of 64 x 64 tiles, blockIdx.y
-// the system.
+// Panel factorisation with one thread per row: thread t holds row k0 + t of
+// the panel (its kPanel entries, column c at slot c - k0) in registers; the
+// panel's rows are k0 .. k0 + ncols - 1 + bw, so NT >= kPanel + bw.  For
+// column j the rows k0 .. k0 + ncols - 1 publish a_kj (the diagonal one also
+// 1 / d_j) in LDS; every row i in (j, j + bw] then forms l_ij = a_ij / d_j
+// and a_ik -= l_ij a_kj for the later panel columns k.  Slots above the
+// diagonal or past the last column may collect garbage: they are never
+// published, used or stored.  One barrier per column (double-buffered LDS).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_band_panel_rows(const BandSys* __restrict__ sys, double2* F,
+                                                        int k0, int32_t* __restrict__ flag) {
+    __shared__ double2 cb[2][kPanel + 1];
+    const BandSys S = sys[blockIdx.x];
+    if (k0 >= S.n) return;
+    const int ld = S.bw + 1;
+    const int ncols = min(kPanel, S.n - k0);
+    const int t = threadIdx.x;
+    const int i = k0 + t;
+    const bool row_ok = t < ncols + S.bw && i < S.n;
+    double2* Fs = F + S.off;
+    double2 a[kPanel];
+#pragma unroll
+    for (int k = 0; k < kPanel; ++k) {
+        const bool ok = row_ok && k < ncols && t >= k && t - k <= S.bw;
+        a[k] = ok ? Fs[(int64_t)(k0 + k) * ld + (t - k)] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int jj = 0; jj < kPanel; ++jj) {
+        if (jj < ncols) {   // uniform
+            double2* c = cb[jj & 1];
+            if (t >= jj && t < ncols) c[t] = a[jj];
+            if (t == jj) {
+                const double2 d = a[jj];
+                const double m2 = d.x * d.x + d.y * d.y;
+                if (!(m2 > 0.0) || !isfinite(m2)) flag[blockIdx.x] = 1;
+                c[kPanel] = make_double2(d.x / m2, -d.y / m2);
+            }
+            __syncthreads();
+            if (row_ok && t > jj && t - jj <= S.bw) {
+                const double2 l = cmul(a[jj], c[kPanel]);
+                a[jj] = l;
+#pragma unroll
+                for (int k = jj + 1; k < kPanel; ++k) cfms(a[k], l, c[k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kPanel; ++k) {
+        const bool ok = row_ok && k < ncols && t >= k && t - k <= S.bw;
+        if (ok) Fs[(int64_t)(k0 + k) * ld + (t - k)] = a[k];
+    }
+}
+
+// Trailing update after panel [k0, k0 + kPanel) on the window
+// [k0 + kPanel, wend), wend = min(n, k0 + kPanel + bw), lower triangle,
+// restricted to columns [c0, c1) (rows [c0, wend)).  strip != 0: blockIdx.x
+// is the row tile of the single tile column at c0 (c1 - c0 <= 64); else a
+// lower-triangular tile index (bi >= bj) of 64 x 64 tiles from (c0, c0).
+// npan = 2 adds the contributions of the panel before k0 as well (entries
+// it does not reach are zero).  blockIdx.y is the system.
 __global__ __launch_bounds__(256) void k_band_update(const BandSys* __restrict__ sys,
-                                                     double2* F, int k0) {
+                                                     double2* F, int k0, int c0, int c1,
+                                                     int strip, int npan) {
     __shared__ double2 Wi[64][kPanel + 1];
     __shared__ double2 Wj[64][kPanel + 1];
     const BandSys S = sys[blockIdx.y];
-    const int w0 = k0 + kPanel;
-    if (w0 >= S.n) return;
     const int wend = min(S.n, k0 + kPanel + S.bw);
+    const int cend = min(c1, wend);
+    if (c0 >= cend) return;
     const int x = blockIdx.x;
-    int bi = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
-    while ((bi + 1) * (bi + 2) / 2 <= x) ++bi;
-    while (bi * (bi + 1) / 2 > x) --bi;
-    const int bj = x - bi * (bi + 1) / 2;
-    const int i0 = w0 + 64 * bi, j0 = w0 + 64 * bj;
-    if (i0 >= wend) return;
+    int bi = x, bj = 0;
+    if (!strip) {
+        bi = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
+        while ((bi + 1) * (bi + 2) / 2 <= x) ++bi;
+        while (bi * (bi + 1) / 2 > x) --bi;
+        bj = x - bi * (bi + 1) / 2;
+    }
+    const int i0 = c0 + 64 * bi, j0 = c0 + 64 * bj;
+    if (i0 >= wend || j0 >= cend) return;
     const int ld = S.bw + 1;
     const double2* Fs = F + S.off;   // panel columns (read) and window columns (written) of one band
-    for (int idx = threadIdx.x; idx < 64 * kPanel; idx += blockDim.x) {
-        const int r = idx / kPanel, kk = idx - r * kPanel;
-        const int k = k0 + kk;
-        const int i = i0 + r, j = j0 + r;
-        double2 wi = make_double2(0.0, 0.0), wj = make_double2(0.0, 0.0);
-        if (i < wend && i - k <= S.bw) wi = Fs[(int64_t)k * ld + (i - k)];
-        if (j < wend && j - k <= S.bw) wj = cmul(Fs[(int64_t)k * ld + (j - k)], Fs[(int64_t)k * ld]);
-        Wi[r][kk] = wi;
-        Wj[r][kk] = wj;
-    }
-    __syncthreads();
     // thread: 4 consecutive rows x 4 columns (columns strided by 16)
     const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
     double2 acc[4][4];
@@ -202,30 +255,113 @@ __global__ __launch_bounds__(256) void k_band_update(const BandSys* __restrict__
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
-    for (int kk = 0; kk < kPanel; ++kk) {
-        double2 wi[4], wj[4];
+    for (int pp = 0; pp < npan; ++pp) {   // contributions of panel k0 (and of the one before it)
+        const int kp = k0 - kPanel * pp;
+        if (kp < 0) break;
+        if (pp > 0) __syncthreads();
+        for (int idx = threadIdx.x; idx < 64 * kPanel; idx += blockDim.x) {
+            const int r = idx / kPanel, kk = idx - r * kPanel;
+            const int k = kp + kk;
+            const int i = i0 + r, j = j0 + r;
+            double2 wi = make_double2(0.0, 0.0), wj = make_double2(0.0, 0.0);
+            if (i < wend && i - k <= S.bw) wi = Fs[(int64_t)k * ld + (i - k)];
+            if (j < cend && j - k <= S.bw) wj = cmul(Fs[(int64_t)k * ld + (j - k)], Fs[(int64_t)k * ld]);
+            Wi[r][kk] = wi;
+            Wj[r][kk] = wj;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < kPanel; ++kk) {
+            double2 wi[4], wj[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) wi[a] = Wi[tr * 4 + a][kk];
+            for (int a = 0; a < 4; ++a) wi[a] = Wi[tr * 4 + a][kk];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) wj[b] = Wj[tc + 16 * b][kk];
+            for (int b = 0; b < 4; ++b) wj[b] = Wj[tc + 16 * b][kk];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                acc[a][b].x = fma(wi[a].x, wj[b].x, fma(-wi[a].y, wj[b].y, acc[a][b].x));
-                acc[a][b].y = fma(wi[a].x, wj[b].y, fma(wi[a].y, wj[b].x, acc[a][b].y));
-            }
+                for (int b = 0; b < 4; ++b) {
+                    acc[a][b].x = fma(wi[a].x, wj[b].x, fma(-wi[a].y, wj[b].y, acc[a][b].x));
+                    acc[a][b].y = fma(wi[a].x, wj[b].y, fma(wi[a].y, wj[b].x, acc[a][b].y));
+                }
+        }
     }
     double2* Fw = F + S.off;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const int j = j0 + tc + 16 * b;
-        if (j >= wend) continue;
+        if (j >= cend) continue;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             const int i = i0 + tr * 4 + a;
             if (i >= wend || i < j) continue;
             double2& c = Fw[(int64_t)j * ld + (i - j)];
+            c.x -= acc[a][b].x;
+            c.y -= acc[a][b].y;
+        }
+    }
+}
+
+// Strip update of the next panel's columns [w0, w0 + kPanel), w0 = k0 +
+// kPanel, with the contributions of panel k0 and (npan = 2) of the panel
+// before it: rows [w0, wend) in 32-row tiles (blockIdx.x), 32 x 32 outputs
+// per work-group, 2 x 2 per thread; blockIdx.y is the system.  Short and on
+// the critical path of the factorisation, so many small work-groups.
+__global__ __launch_bounds__(256) void k_band_strip(const BandSys* __restrict__ sys, double2* F,
+                                                    int k0, int npan) {
+    __shared__ double2 Wi[32][kPanel + 1];
+    __shared__ double2 Wj[32][kPanel + 1];
+    const BandSys S = sys[blockIdx.y];
+    const int w0 = k0 + kPanel;
+    const int wend = min(S.n, k0 + kPanel + S.bw);
+    const int cend = min(w0 + kPanel, wend);
+    const int i0 = w0 + 32 * blockIdx.x;
+    if (w0 >= cend || i0 >= wend) return;
+    const int ld = S.bw + 1;
+    double2* Fs = F + S.off;
+    const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;   // rows 2 tr, 2 tr + 1; columns tc, tc + 16
+    double2 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = make_double2(0.0, 0.0);
+    for (int pp = 0; pp < npan; ++pp) {
+        const int kp = k0 - kPanel * pp;
+        if (kp < 0) break;
+        if (pp > 0) __syncthreads();
+        for (int idx = threadIdx.x; idx < 32 * kPanel; idx += 256) {
+            const int r = idx / kPanel, kk = idx - r * kPanel;
+            const int k = kp + kk;
+            const int i = i0 + r, j = w0 + r;
+            double2 wi = make_double2(0.0, 0.0), wj = make_double2(0.0, 0.0);
+            if (i < wend && i - k <= S.bw) wi = Fs[(int64_t)k * ld + (i - k)];
+            if (j < cend && j - k <= S.bw) wj = cmul(Fs[(int64_t)k * ld + (j - k)], Fs[(int64_t)k * ld]);
+            Wi[r][kk] = wi;
+            Wj[r][kk] = wj;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < kPanel; ++kk) {
+            const double2 wi0 = Wi[2 * tr][kk], wi1 = Wi[2 * tr + 1][kk];
+            const double2 wj0 = Wj[tc][kk], wj1 = Wj[tc + 16][kk];
+            const double2 wi[2] = {wi0, wi1}, wj[2] = {wj0, wj1};
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    acc[a][b].x = fma(wi[a].x, wj[b].x, fma(-wi[a].y, wj[b].y, acc[a][b].x));
+                    acc[a][b].y = fma(wi[a].x, wj[b].y, fma(wi[a].y, wj[b].x, acc[a][b].y));
+                }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int j = w0 + tc + 16 * b;
+        if (j >= cend) continue;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int i = i0 + 2 * tr + a;
+            if (i >= wend || i < j) continue;
+            double2& c = Fs[(int64_t)j * ld + (i - j)];
             c.x -= acc[a][b].x;
             c.y -= acc[a][b].y;
         }
@@ -639,6 +775,24 @@ hipError_t band_form(const BandSys* sys, int nsys, const double2* AB, double2* F
 
 hipError_t band_panel(const BandSys* sys, int nsys, int bwmax, double2* F, int k0, int32_t* flag,
                       hipStream_t s) {
+    // one thread per panel row while kPanel + bw rows fit 512 threads
+    const int rows = kPanel + bwmax;
+    if (rows <= 64) {
+        hipLaunchKernelGGL(k_band_panel_rows<64>, dim3(nsys), dim3(64), 0, s, sys, F, k0, flag);
+        return hipGetLastError();
+    } else if (rows <= 128) {
+        hipLaunchKernelGGL(k_band_panel_rows<128>, dim3(nsys), dim3(128), 0, s, sys, F, k0, flag);
+        return hipGetLastError();
+    } else if (rows <= 256) {
+        hipLaunchKernelGGL(k_band_panel_rows<256>, dim3(nsys), dim3(256), 0, s, sys, F, k0, flag);
+        return hipGetLastError();
+    } else if (rows <= 384) {
+        hipLaunchKernelGGL(k_band_panel_rows<384>, dim3(nsys), dim3(384), 0, s, sys, F, k0, flag);
+        return hipGetLastError();
+    } else if (rows <= 512) {
+        hipLaunchKernelGGL(k_band_panel_rows<512>, dim3(nsys), dim3(512), 0, s, sys, F, k0, flag);
+        return hipGetLastError();
+    }
     // registers per thread for a kPanel x (bw + 1) panel over 1024 threads
     const int need = (kPanel * (bwmax + 1) + kPanelThreads - 1) / kPanelThreads;
     const dim3 b(kPanelThreads);
@@ -657,11 +811,23 @@ hipError_t band_panel(const BandSys* sys, int nsys, int bwmax, double2* F, int k
     return hipGetLastError();
 }
 
-hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int k0, hipStream_t s) {
-    const int T = (bwmax + 63) / 64;
-    const int tiles = T * (T + 1) / 2;
-    if (tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_band_update, dim3(tiles, nsys), dim3(256), 0, s, sys, F, k0);
+hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int k0, int part,
+                       hipStream_t s) {
+    const int w0 = k0 + kPanel;
+    if (part == 1) {
+        const int T = (bwmax + 31) / 32;
+        hipLaunchKernelGGL(k_band_strip, dim3(T, nsys), dim3(256), 0, s, sys, F, k0, k0 >= kPanel ? 2 : 1);
+        return hipGetLastError();
+    }
+    int c0 = w0, c1 = w0 + bwmax, strip = 0, npan = 1;
+    if (part == 2) {
+        c0 = w0 + 2 * kPanel;
+    }
+    const int T = (w0 + bwmax - c0 + 63) / 64;
+    const int tiles = strip ? T : T * (T + 1) / 2;
+    if (tiles <= 0 || c0 >= c1) return hipSuccess;
+    hipLaunchKernelGGL(k_band_update, dim3(tiles, nsys), dim3(256), 0, s, sys, F, k0, c0, c1, strip,
+                       npan);
     return hipGetLastError();
 }
 

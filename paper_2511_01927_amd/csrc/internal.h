@@ -184,7 +184,11 @@ hipError_t band_form(const BandSys* sys, int nsys, const double2* AB, double2* F
 // pivot per system), then update the trailing window.
 hipError_t band_panel(const BandSys* sys, int nsys, int bwmax, double2* F, int k0, int32_t* flag,
                       hipStream_t s);
-hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int k0, hipStream_t s);
+// part 0: the whole trailing window; 1: only the next panel's columns
+// [k0 + kPanel, k0 + 2 kPanel), with the contributions of panel k0 and of
+// panel k0 - kPanel; 2: the window from k0 + 3 kPanel on (panel k0 only).
+hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int k0, int part,
+                       hipStream_t s);
 // Columns per work-group of the solves for a half bandwidth bw.
 int band_chunk_columns(int bw);
 // In place: X <- K^-1 X for every column (colsys: system of each tiled column,

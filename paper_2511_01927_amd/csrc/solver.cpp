@@ -128,9 +128,13 @@ struct Timer {
     };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
-    static constexpr int kClasses = 11;
+    static constexpr int kClasses = 12;
     double ms[kClasses] = {0};
-    long count[kClasses] = {0};
+    long count[kClasses] = {0};   // timed brackets
+    long seen[kClasses] = {0};    // all brackets
+    int stride[kClasses] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};   // time every stride-th bracket
+    // per-class totals: the timed mean times the number of brackets
+    double total_ms(int c) const { return count[c] ? ms[c] * (double)seen[c] / (double)count[c] : 0.0; }
     hipEvent_t get() {
         if (!pool.empty()) {
             hipEvent_t e = pool.back();
@@ -143,16 +147,24 @@ struct Timer {
     }
     int open_cls = -1;
     hipEvent_t open_a = nullptr;
-    void begin(int cls) {
+    hipStream_t open_s = nullptr;
+    // begin / end bracket one launch (or a run of launches) on stream st
+    // (the solver's stream by default)
+    void begin(int cls, hipStream_t st = nullptr) {
         if (!on) return;
+        if (seen[cls]++ % stride[cls] != 0) {
+            open_cls = -1;
+            return;
+        }
         open_cls = cls;
+        open_s = st ? st : s;
         open_a = get();
-        HIPCHK(hipEventRecord(open_a, s));
+        HIPCHK(hipEventRecord(open_a, open_s));
     }
     void end() {
-        if (!on) return;
+        if (!on || open_cls < 0) return;
         hipEvent_t b = get();
-        HIPCHK(hipEventRecord(b, s));
+        HIPCHK(hipEventRecord(b, open_s));
         pending.push_back({open_cls, open_a, b});
     }
     // call after a stream synchronisation
@@ -176,19 +188,21 @@ struct Timer {
     }
 };
 enum { T_SPMM = 0, T_UPDATE, T_REPLACE, T_REDUCE, T_MOMENTS, T_GRAM, T_GEMM, T_DENSE, T_BAND_PANEL,
-       T_BAND_UPDATE, T_BAND_SOLVE };
+       T_BAND_UPDATE, T_BAND_SOLVE, T_BAND_NEXT };
 static const char* kTimerNames[Timer::kClasses] = {"cocg_spmm_dir", "cocg_update", "cocg_replace",
                                                    "cocg_reduce", "moments", "gram",
                                                    "gemm_tall", "dense_small", "band_panel",
-                                                   "band_update", "band_solve"};
+                                                   "band_update", "band_solve", "band_update_next"};
 
 // Algorithmic real flops of the banded L D L^T of one n x n complex
 // symmetric system of half bandwidth bw, split between the panel kernel
 // (column scaling, 6 flops per complex product, and the updates inside a
 // panel) and the trailing-window kernel (8 flops per complex multiply-add
 // l_ik d_k l_jk, counted only where l_ik is inside the band).
-static void band_factor_flops(int64_t n, int64_t bw, double& panel, double& update) {
-    panel = update = 0.0;
+// update: the contributions to the two columns panels after each panel
+// (strip updates, next) and to the rest of its window (rest).
+static void band_factor_flops(int64_t n, int64_t bw, double& panel, double& next, double& rest) {
+    panel = next = rest = 0.0;
     for (int64_t k0 = 0; k0 < n; k0 += kPanel) {
         const int64_t nc = std::min<int64_t>(kPanel, n - k0);
         for (int64_t jj = 0; jj < nc; ++jj) {
@@ -201,7 +215,10 @@ static void band_factor_flops(int64_t n, int64_t bw, double& panel, double& upda
         for (int64_t i = w0; i < wend; ++i) {
             const int64_t kmin = std::max<int64_t>(k0, i - bw);
             const int64_t c = std::max<int64_t>(0, k0 + kPanel - kmin);
-            update += 8.0 * (double)c * (double)(i - w0 + 1);
+            const int64_t cols = i - w0 + 1;   // target columns w0 .. i
+            const int64_t near = std::min<int64_t>(cols, 2 * kPanel);
+            next += 8.0 * (double)c * (double)near;
+            rest += 8.0 * (double)c * (double)(cols - near);
         }
     }
 }
@@ -533,7 +550,7 @@ struct Stats {
     long band_pivot_flags = 0;    // systems with a zero or non-finite pivot
     long band_unconverged = 0;    // passes whose band residual stayed above solve_tol
     double band_relres_max = 0.0; // largest ||b - K x|| / ||b|| after refinement
-    double band_panel_flops = 0.0, band_update_flops = 0.0, band_solve_flops = 0.0;
+    double band_panel_flops = 0.0, band_next_flops = 0.0, band_update_flops = 0.0, band_solve_flops = 0.0;
 };
 
 static void choose_nrb(int64_t n, int n_active, int nrb_max, int& nrb) {
@@ -555,10 +572,20 @@ class Solver {
         }
         tm_.on = c.o.timing != 0;
         tm_.s = s_;
+        // thousands of short factorisation launches: time one in 16 (the
+        // event pairs would otherwise add to the gaps between launches)
+        tm_.stride[T_BAND_PANEL] = tm_.stride[T_BAND_NEXT] = tm_.stride[T_BAND_UPDATE] = 16;
         HIPCHK(hipHostMalloc((void**)&counts_h_, sizeof(int32_t) * 4, 0));
     }
     ~Solver() {
         if (counts_h_) (void)hipHostFree(counts_h_);
+        if (s2_) {
+            (void)hipStreamSynchronize(s2_);
+            (void)hipStreamDestroy(s2_);
+        }
+        if (ev_panel_) (void)hipEventDestroy(ev_panel_);
+        for (hipEvent_t e : ev_rest_)
+            if (e) (void)hipEventDestroy(e);
         if (own_) {
             (void)hipStreamSynchronize(own_);
             (void)hipStreamDestroy(own_);
@@ -628,22 +655,44 @@ class Solver {
             DBuf<int32_t> flags(nsys);
             HIPCHK(hipMemsetAsync(flags.get(), 0, sizeof(int32_t) * nsys, s_));
             HIPCHK(band_form(dsys.get(), nsys, dv_.band, band_F_->get(), s_));
+            // Lookahead over two panel steps.  Step k updates, on s_, the next
+            // panel's columns with panels k - 1 and k (they gate panel k + 1),
+            // then, on s2, the window from panel k + 3 on with panel k, beside
+            // the next two panel steps.  The rest of step k writes the columns
+            // of panel k + 3, so the strip update of step k + 2 waits for it;
+            // concurrent launches touch disjoint columns.
+            if (!s2_) HIPCHK(hipStreamCreateWithFlags(&s2_, hipStreamNonBlocking));
+            if (!ev_panel_) HIPCHK(hipEventCreateWithFlags(&ev_panel_, hipEventDisableTiming));
+            for (hipEvent_t& e : ev_rest_)
+                if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
             int steps = 0;
             for (int64_t k0 = 0; k0 < nmax; k0 += kPanel, ++steps) {
                 tm_.begin(T_BAND_PANEL);
                 HIPCHK(band_panel(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, flags.get(), s_));
                 tm_.end();
                 if (k0 + kPanel < nmax) {
-                    tm_.begin(T_BAND_UPDATE);
-                    HIPCHK(band_update(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, s_));
+                    if (steps >= 2) HIPCHK(hipStreamWaitEvent(s_, ev_rest_[steps & 1], 0));
+                    tm_.begin(T_BAND_NEXT);
+                    HIPCHK(band_update(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, 1, s_));
                     tm_.end();
+                    HIPCHK(hipEventRecord(ev_panel_, s_));
+                    HIPCHK(hipStreamWaitEvent(s2_, ev_panel_, 0));
+                    tm_.begin(T_BAND_UPDATE, s2_);
+                    HIPCHK(band_update(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, 2, s2_));
+                    tm_.end();
+                    HIPCHK(hipEventRecord(ev_rest_[steps & 1], s2_));
                 }
             }
+            if (steps >= 2) {
+                HIPCHK(hipEventRecord(ev_panel_, s2_));
+                HIPCHK(hipStreamWaitEvent(s_, ev_panel_, 0));
+            }
             for (int k = 0; k < K; ++k) {
-                double fp, fu;
-                band_factor_flops(jobs[k].n, P_->h.prob_bw[jobs[k].prob], fp, fu);
+                double fp, fn, fr;
+                band_factor_flops(jobs[k].n, P_->h.prob_bw[jobs[k].prob], fp, fn, fr);
                 stats_.band_panel_flops += NH * fp;
-                stats_.band_update_flops += NH * fu;
+                stats_.band_next_flops += NH * fn;
+                stats_.band_update_flops += NH * fr;
             }
             std::vector<int32_t> fh(nsys);
             HIPCHK(hipMemcpyAsync(fh.data(), flags.get(), sizeof(int32_t) * nsys, hipMemcpyDeviceToHost, s_));
@@ -1224,6 +1273,8 @@ class Solver {
     DevPencil dv_;   // the pencil with the row-group view of this solve
     // banded factors of the last pass and the (problem, z) list they belong to
     std::unique_ptr<DBuf<double2>> band_F_;
+    hipStream_t s2_ = nullptr;           // second stream of the factorisation (lookahead)
+    hipEvent_t ev_panel_ = nullptr, ev_rest_[2] = {nullptr, nullptr};
     std::vector<double> band_keys_;
     hipStream_t s_ = nullptr;
     hipStream_t own_ = nullptr;
@@ -1273,6 +1324,7 @@ static std::string json_stats(const Solver& s, double wall_ms, const std::vector
       << ",\"band_relres_max\":" << s.stats_.band_relres_max
       << ",\"band_panel_flops\":" << s.stats_.band_panel_flops
       << ",\"band_update_flops\":" << s.stats_.band_update_flops
+      << ",\"band_update_next_flops\":" << s.stats_.band_next_flops
       << ",\"band_solve_flops\":" << s.stats_.band_solve_flops
       << ",\"graph_captures\":" << s.stats_.graph_captures
       << ",\"spmm_alg_bytes\":" << s.stats_.spmm_alg_bytes
@@ -1281,8 +1333,11 @@ static std::string json_stats(const Solver& s, double wall_ms, const std::vector
       << ",\"gram_flops\":" << s.gram_flops_ << ",\"gemm_flops\":" << s.gemm_flops_
       << ",\"kernel_ms\":{";
     for (int c = 0; c < Timer::kClasses; ++c)
-        o << (c ? "," : "") << "\"" << kTimerNames[c] << "\":" << s.tm_.ms[c];
+        o << (c ? "," : "") << "\"" << kTimerNames[c] << "\":" << s.tm_.total_ms(c);
     o << "},\"kernel_launches\":{";
+    for (int c = 0; c < Timer::kClasses; ++c)
+        o << (c ? "," : "") << "\"" << kTimerNames[c] << "\":" << s.tm_.seen[c];
+    o << "},\"kernel_timed_launches\":{";
     for (int c = 0; c < Timer::kClasses; ++c)
         o << (c ? "," : "") << "\"" << kTimerNames[c] << "\":" << s.tm_.count[c];
     o << "},\"contours\":[";
