@@ -812,7 +812,7 @@ __global__ __launch_bounds__(CPW * 32 / CPL) void k_band_sweep(const BandSys* __
 typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kBlkRows = 32;
 constexpr int kBlkThreads = 256;
-constexpr int kBlkMaxBw = 416;
+constexpr int kBlkMaxBw = 384;
 
 __host__ __device__ constexpr int blk_ring_rows(int bw) { return kBlkRows * ((bw + kBlkRows + kBlkRows - 1) / kBlkRows); }
 
@@ -975,6 +975,152 @@ __global__ __launch_bounds__(kBlkThreads) void k_band_fwd_blocked(const BandSys*
     }
 }
 
+// ---- blocked backward sweep -----------------------------------------------
+// L^T x = z (z = D^-1 y from the forward sweep, in X), 32-row blocks from the
+// bottom.  For block [J0, J0 + 32) the solved rows r in [J0 + 32, J0 + 32 +
+// bw) contribute G[i, :] = sum_r L[r, i] x[r, :] (a 32 x 16 product with
+// K = bw on v_mfma_f64_16x16x4: the K steps are dealt to the four waves and
+// their partial sums added through LDS); then x_i = z_i - G_i - sum over the
+// block's later rows, solved from the last row up (half wave per two
+// columns, readlane broadcast).  Solved rows enter an LDS ring (WS >= bw + 32
+// rows) that holds the rows later blocks read.
+__global__ __launch_bounds__(kBlkThreads) void k_band_bwd_blocked(const BandSys* __restrict__ sys,
+                                                                  const int32_t* __restrict__ colsys,
+                                                                  const double2* __restrict__ F,
+                                                                  TileGeom geom, double2* __restrict__ X,
+                                                                  int xcd_map) {
+    constexpr int CPW = 16, CPT = kTile / CPW, NW = kBlkThreads / 64;
+    __shared__ double2 Ld[kBlkRows][kBlkRows + 1];   // L[J0 + r][J0 + c], r > c
+    __shared__ double red[NW * 16 * 64];               // [wave][tile][re,im][v][lane]
+    extern __shared__ double2 ring[];                  // [WS][CPW]
+    int tile, chunk;
+    if (xcd_map) {
+        const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+        tile = (slot / CPT) * 8 + xcd;
+        chunk = slot % CPT;
+    } else {
+        tile = blockIdx.x / CPT;
+        chunk = blockIdx.x % CPT;
+    }
+    const int c0 = chunk * CPW;
+    const int s0 = colsys[tile * kTile + c0];
+    if (s0 < 0) return;
+    const BandSys S = sys[s0];
+    const int n = S.n, bw = S.bw, ld = bw + 1;
+    const int WS = blk_ring_rows(bw);
+    const int64_t base = geom.base[tile];
+    const double2* Fs = F + S.off;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int hl = t & 31, hw = t >> 5;
+    const bool upper = (t & 32) != 0;
+    for (int e = t; e < WS * CPW; e += kBlkThreads) ring[e] = make_double2(0.0, 0.0);
+    const int nblk = (n + kBlkRows - 1) / kBlkRows;
+    constexpr int kLdPer = kBlkRows * kBlkRows / kBlkThreads;
+    auto load_ld = [&](int J0, double2 (&pl)[kLdPer]) {
+#pragma unroll
+        for (int m = 0; m < kLdPer; ++m) {
+            const int e = t + kBlkThreads * m, r = e / kBlkRows, c = e % kBlkRows;
+            pl[m] = (r > c && r - c <= bw && J0 + r < n) ? Fs[(int64_t)(J0 + c) * ld + (r - c)]
+                                                         : make_double2(0.0, 0.0);
+        }
+    };
+    // A operands of K step s (rows r = J0 + 32 + 4 s + lane / 16) for both tiles
+    auto load_a = [&](int J0, int s, int kend, double2& a0, double2& a1) {
+        const int r = J0 + kBlkRows + 4 * s + (lane >> 4);
+        const int i0 = J0 + (lane & 15), i1 = i0 + 16;
+        a0 = (r < kend && r - i0 <= bw) ? Fs[(int64_t)i0 * ld + (r - i0)] : make_double2(0.0, 0.0);
+        a1 = (r < kend && r - i1 <= bw) ? Fs[(int64_t)i1 * ld + (r - i1)] : make_double2(0.0, 0.0);
+    };
+    double2 pl[kLdPer];
+    load_ld((nblk - 1) * kBlkRows, pl);
+    __syncthreads();
+    for (int j = nblk - 1; j >= 0; --j) {
+        const int J0 = j * kBlkRows;
+        const int kend = min(n, J0 + kBlkRows + bw);
+        const int nks = max(0, (kend - (J0 + kBlkRows) + 3) / 4);
+#pragma unroll
+        for (int m = 0; m < kLdPer; ++m) {
+            const int e = t + kBlkThreads * m;
+            Ld[e / kBlkRows][e % kBlkRows] = pl[m];
+        }
+        if (j > 0) load_ld(J0 - kBlkRows, pl);
+        double2 z0 = make_double2(0.0, 0.0), z1 = make_double2(0.0, 0.0);
+        if (J0 + hl < n) {
+            const double2* xi = X + base + (int64_t)(J0 + hl) * kTile + c0 + 2 * hw;
+            z0 = xi[0];
+            z1 = xi[1];
+        }
+        // (a) partial products of this wave's K steps
+        mfma_f64x4 acc[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
+        double2 a0, a1;
+        if (wave < nks) load_a(J0, wave, kend, a0, a1);
+        for (int ks = wave; ks < nks; ks += NW) {
+            double2 n0, n1;
+            if (ks + NW < nks) load_a(J0, ks + NW, kend, n0, n1);
+            const int r = J0 + kBlkRows + 4 * ks + (lane >> 4);
+            const double2 xb = r < kend ? ring[(r % WS) * CPW + (lane & 15)] : make_double2(0.0, 0.0);
+            // G_re += A_re x_re - A_im x_im, G_im += A_re x_im + A_im x_re
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, xb.x, acc[0][0], 0, 0, 0);
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, -xb.y, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, xb.y, acc[0][1], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, xb.x, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, xb.x, acc[1][0], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, -xb.y, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, xb.y, acc[1][1], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, xb.x, acc[1][1], 0, 0, 0);
+            a0 = n0;
+            a1 = n1;
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) red[(((wave * 2 + a) * 2 + b) * 4 + v) * 64 + lane] = acc[a][b][v];
+        __syncthreads();
+        // (b) the block's rows from the last up: half wave hw, columns 2 hw, 2 hw + 1
+        {
+            // G at row i = J0 + hl: tile hl / 16, row rr = hl % 16 -> lane 16 (rr % 4) + column, register rr / 4
+            const int tq = hl >> 4, rr = hl & 15;
+            double2 g0 = make_double2(0.0, 0.0), g1 = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const int bre = (((w * 2 + tq) * 2 + 0) * 4 + (rr >> 2)) * 64 + 16 * (rr & 3);
+                const int bim = (((w * 2 + tq) * 2 + 1) * 4 + (rr >> 2)) * 64 + 16 * (rr & 3);
+                g0.x += red[bre + 2 * hw];
+                g0.y += red[bim + 2 * hw];
+                g1.x += red[bre + 2 * hw + 1];
+                g1.y += red[bim + 2 * hw + 1];
+            }
+            double2 v0 = make_double2(z0.x - g0.x, z0.y - g0.y);
+            double2 v1 = make_double2(z1.x - g1.x, z1.y - g1.y);
+#pragma unroll 4
+            for (int i = kBlkRows - 1; i >= 0; --i) {
+                const double2 p0 = readlane2(v0, i), q0 = readlane2(v0, i + 32);
+                const double2 p1 = readlane2(v1, i), q1 = readlane2(v1, i + 32);
+                const double2 x0 = upper ? q0 : p0, x1 = upper ? q1 : p1;
+                const double2 l = Ld[i][hl];   // L[J0 + i][J0 + hl], zero unless i > hl
+                cfms(v0, l, x0);
+                cfms(v1, l, x1);
+            }
+            if (J0 + hl < n) {
+                double2* xo = X + base + (int64_t)(J0 + hl) * kTile + c0 + 2 * hw;
+                xo[0] = v0;
+                xo[1] = v1;
+            }
+            // the ring slots of rows [J0, J0 + 32) held rows >= J0 + WS, out of reach
+            const int slot = ((J0 + hl) % WS) * CPW + 2 * hw;
+            ring[slot] = J0 + hl < n ? v0 : make_double2(0.0, 0.0);
+            ring[slot + 1] = J0 + hl < n ? v1 : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+    }
+}
+
 template <int K, int CPW, int CPL>
 static hipError_t sweep_reg(const BandSys* sys, const int32_t* colsys, const double2* F,
                             const TileGeom& g, int ntiles, double2* X, hipStream_t s, int bwmax) {
@@ -1004,8 +1150,16 @@ static hipError_t sweep_reg(const BandSys* sys, const int32_t* colsys, const dou
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_band_sweep<K, CPW, CPL, false>), grid, dim3(T), lds, s, sys, colsys, F, g, X, R,
-                       xcd_map);
+    if (CPW == 16 && bwmax <= kBlkMaxBw) {
+        const size_t ring = (size_t)blk_ring_rows(bwmax) * 16 * sizeof(double2);
+        e = hipFuncSetAttribute((const void*)k_band_bwd_blocked, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)ring);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_band_bwd_blocked, grid, dim3(kBlkThreads), ring, s, sys, colsys, F, g, X, xcd_map);
+    } else {
+        hipLaunchKernelGGL((k_band_sweep<K, CPW, CPL, false>), grid, dim3(T), lds, s, sys, colsys, F, g, X, R,
+                           xcd_map);
+    }
     return hipGetLastError();
 }
 
