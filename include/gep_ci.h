@@ -156,7 +156,10 @@ int gep_result_count(const gep_result* res, int64_t* m, int64_t* n);
 
 /* Copy results to caller-owned HOST buffers (any may be NULL):
  * evals[m] ascending; evecs n x m column-major, B-normalised, largest-|.|
- * entry positive; resid[m]; contour_id[m]; converged[m] (1 if resid <= tol). */
+ * entry positive; resid[m]; contour_id[m]; converged[m] (1 if resid <= tol).
+ * The eigenvectors stay in device memory owned by the result until
+ * gep_result_free; evecs is filled by a synchronous device-to-host copy
+ * (GEP_EDEVICE if it fails). */
 int gep_result_copy(const gep_result* res, double* evals, double* evecs, double* resid,
                     int32_t* contour_id, uint8_t* converged);
 

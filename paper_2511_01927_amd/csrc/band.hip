@@ -814,6 +814,14 @@ constexpr int kBlkRows = 32;
 constexpr int kBlkThreads = 256;
 constexpr int kBlkMaxBw = 384;
 
+// Ring slot of row J0 + d (jb = J0 mod WS, 0 <= d < 2 WS): no division.
+__device__ inline int ring_slot(int jb, int d, int WS) {
+    int s = jb + d;
+    s -= s >= WS ? WS : 0;
+    s -= s >= WS ? WS : 0;
+    return s;
+}
+
 __host__ __device__ constexpr int blk_ring_rows(int bw) { return kBlkRows * ((bw + kBlkRows + kBlkRows - 1) / kBlkRows); }
 
 __global__ __launch_bounds__(kBlkThreads) void k_band_fwd_blocked(const BandSys* __restrict__ sys,
@@ -849,7 +857,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_band_fwd_blocked(const BandSys*
     // ring: rows [0, 32 + bw) from X (zero past n)
     for (int e = t; e < (kBlkRows + bw) * CPW; e += kBlkThreads) {
         const int r = e / CPW, c = e - r * CPW;
-        ring[(r % WS) * CPW + c] = r < n ? X[base + (int64_t)r * kTile + c0 + c] : make_double2(0.0, 0.0);
+        ring[ring_slot(0, r, WS) * CPW + c] = r < n ? X[base + (int64_t)r * kTile + c0 + c] : make_double2(0.0, 0.0);
     }
     const int nblk = (n + kBlkRows - 1) / kBlkRows;
     // Global loads are issued a step ahead of their use (registers): the
@@ -878,6 +886,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_band_fwd_blocked(const BandSys*
     load_ld(0, pl, pd);
     for (int j = 0; j < nblk; ++j) {
         const int J0 = j * kBlkRows;
+        const int jb = J0 % WS;
         const int wend = min(n, J0 + kBlkRows + bw);
         const int ntl = (wend - (J0 + kBlkRows) + 15) / 16;
         // (a) diagonal block of L and 1 / d from the registers
@@ -903,7 +912,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_band_fwd_blocked(const BandSys*
         if (wave < ntl) load_a(J0, J0 + kBlkRows + 16 * wave, wend, av);
         // (b) the block's rows: half wave hw solves columns 2 hw, 2 hw + 1
         {
-            const int slot = ((J0 + hl) % WS) * CPW + 2 * hw;
+            const int slot = ring_slot(jb, hl, WS) * CPW + 2 * hw;
             double2 v0 = ring[slot], v1 = ring[slot + 1];
 #pragma unroll 4
             for (int i = 0; i < kBlkRows; ++i) {
@@ -943,7 +952,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_band_fwd_blocked(const BandSys*
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = r0 + (lane >> 4) + 4 * v;
-                    const double2 w = r < wend ? ring[(r % WS) * CPW + (lane & 15)] : make_double2(0.0, 0.0);
+                    const double2 w = r < wend ? ring[ring_slot(jb, r - J0, WS) * CPW + (lane & 15)] : make_double2(0.0, 0.0);
                     cre[v] = w.x;
                     cim[v] = w.y;
                 }
@@ -957,7 +966,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_band_fwd_blocked(const BandSys*
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = r0 + (lane >> 4) + 4 * v;
-                    if (r < wend) ring[(r % WS) * CPW + (lane & 15)] = make_double2(cre[v], cim[v]);
+                    if (r < wend) ring[ring_slot(jb, r - J0, WS) * CPW + (lane & 15)] = make_double2(cre[v], cim[v]);
                 }
 #pragma unroll
                 for (int q = 0; q < 8; ++q) av[q] = an[q];
@@ -969,7 +978,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_band_fwd_blocked(const BandSys*
         for (int m = 0; m < kNewPer; ++m) {
             const int e = t + kBlkThreads * m;
             const int r = J0 + kBlkRows + bw + e / CPW, c = e % CPW;
-            ring[(r % WS) * CPW + c] = pn[m];
+            ring[ring_slot(jb, r - J0, WS) * CPW + c] = pn[m];
         }
         __syncthreads();
     }
@@ -1036,6 +1045,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_band_bwd_blocked(const BandSys*
     __syncthreads();
     for (int j = nblk - 1; j >= 0; --j) {
         const int J0 = j * kBlkRows;
+        const int jb = J0 % WS;
         const int kend = min(n, J0 + kBlkRows + bw);
         const int nks = max(0, (kend - (J0 + kBlkRows) + 3) / 4);
 #pragma unroll
@@ -1050,30 +1060,39 @@ __global__ __launch_bounds__(kBlkThreads) void k_band_bwd_blocked(const BandSys*
             z0 = xi[0];
             z1 = xi[1];
         }
-        // (a) partial products of this wave's K steps
+        // (a) partial products of this wave's K steps (ks = wave + NW u); the L
+        // operands are loaded four steps ahead
         mfma_f64x4 acc[2][2];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b) acc[a][b] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
-        double2 a0, a1;
-        if (wave < nks) load_a(J0, wave, kend, a0, a1);
-        for (int ks = wave; ks < nks; ks += NW) {
-            double2 n0, n1;
-            if (ks + NW < nks) load_a(J0, ks + NW, kend, n0, n1);
-            const int r = J0 + kBlkRows + 4 * ks + (lane >> 4);
-            const double2 xb = r < kend ? ring[(r % WS) * CPW + (lane & 15)] : make_double2(0.0, 0.0);
-            // G_re += A_re x_re - A_im x_im, G_im += A_re x_im + A_im x_re
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, xb.x, acc[0][0], 0, 0, 0);
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, -xb.y, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, xb.y, acc[0][1], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, xb.x, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, xb.x, acc[1][0], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, -xb.y, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, xb.y, acc[1][1], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, xb.x, acc[1][1], 0, 0, 0);
-            a0 = n0;
-            a1 = n1;
+        const int my = nks > wave ? (nks - wave + NW - 1) / NW : 0;
+        double2 A0[4], A1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (u < my) load_a(J0, wave + NW * u, kend, A0[u], A1[u]);
+        for (int it = 0; it < my; it += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (it + u < my) {
+                    const int ks = wave + NW * (it + u);
+                    const int r = J0 + kBlkRows + 4 * ks + (lane >> 4);
+                    const double2 xb =
+                        r < kend ? ring[ring_slot(jb, r - J0, WS) * CPW + (lane & 15)] : make_double2(0.0, 0.0);
+                    const double2 a0 = A0[u], a1 = A1[u];
+                    if (it + u + 4 < my) load_a(J0, ks + 4 * NW, kend, A0[u], A1[u]);
+                    // G_re += A_re x_re - A_im x_im, G_im += A_re x_im + A_im x_re
+                    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, xb.x, acc[0][0], 0, 0, 0);
+                    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, -xb.y, acc[0][0], 0, 0, 0);
+                    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, xb.y, acc[0][1], 0, 0, 0);
+                    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, xb.x, acc[0][1], 0, 0, 0);
+                    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, xb.x, acc[1][0], 0, 0, 0);
+                    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, -xb.y, acc[1][0], 0, 0, 0);
+                    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, xb.y, acc[1][1], 0, 0, 0);
+                    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, xb.x, acc[1][1], 0, 0, 0);
+                }
+            }
         }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -1113,7 +1132,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_band_bwd_blocked(const BandSys*
                 xo[1] = v1;
             }
             // the ring slots of rows [J0, J0 + 32) held rows >= J0 + WS, out of reach
-            const int slot = ((J0 + hl) % WS) * CPW + 2 * hw;
+            const int slot = ring_slot(jb, hl, WS) * CPW + 2 * hw;
             ring[slot] = J0 + hl < n ? v0 : make_double2(0.0, 0.0);
             ring[slot + 1] = J0 + hl < n ? v1 : make_double2(0.0, 0.0);
         }

@@ -245,7 +245,8 @@ struct gep_pencil {
 
 struct gep_result {
     int64_t n = 0, m = 0;
-    std::vector<double> evals, evecs, resid;
+    std::vector<double> evals, resid;
+    std::unique_ptr<gep::DBuf<double>> dvecs;   // eigenvectors on the device, n x m column-major
     std::vector<int32_t> cid;
     std::vector<uint8_t> conv;
     std::string stats;
@@ -1360,7 +1361,8 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
     auto t0 = std::chrono::steady_clock::now();
     const HostPencil& H = P->h;
     const int64_t ntot = P->d.n;
-    Solver sv(P, cfg);
+    auto svp = std::make_unique<Solver>(P, cfg);
+    Solver& sv = *svp;
     hipStream_t s = sv.s_;
     const int L = cfg.L;
     // V (problem p: counter-based stream of seed + p on its own rows) and B V
@@ -1495,7 +1497,8 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
             int col;
         };
         std::vector<Pair> pairs;
-        std::vector<std::vector<double>> vecs(K);
+        // selected Ritz vectors of contour k stay on the device: n x sel, column-major
+        std::vector<std::unique_ptr<DBuf<double>>> cms(K);
         bool saturated = false;
         std::vector<ContourOut> mine(finals.begin() + base, finals.begin() + base + K);
         for (int k = 0; k < K; ++k) {
@@ -1507,17 +1510,22 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
                 if (co.theta[j] >= cc.keep_lo && co.theta[j] < cc.keep_hi) sel.push_back(j);
             if (sel.empty()) continue;
             DBuf<int32_t> dsel(sel.size());
-            DBuf<double> cm((size_t)n * sel.size());
+            cms[k] = std::make_unique<DBuf<double>>((size_t)n * sel.size());
             HIPCHK(hipMemcpyAsync(dsel.get(), sel.data(), sizeof(int32_t) * sel.size(), hipMemcpyHostToDevice, s));
-            HIPCHK(launch_gather_cols(co.X, n, co.r, dsel.get(), (int)sel.size(), cm.get(), s));
-            vecs[k].resize((size_t)n * sel.size());
-            HIPCHK(hipMemcpyAsync(vecs[k].data(), cm.get(), sizeof(double) * n * sel.size(), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(launch_gather_cols(co.X, n, co.r, dsel.get(), (int)sel.size(), cms[k]->get(), s));
+            HIPCHK(hipStreamSynchronize(s));   // dsel is released at the end of this iteration
             for (size_t a = 0; a < sel.size(); ++a) pairs.push_back({co.theta[sel[a]], co.rho[sel[a]], k, (int)a});
         }
         std::stable_sort(pairs.begin(), pairs.end(), [](const Pair& a, const Pair& b) { return a.lam < b.lam; });
         // de-duplicate pairs found by different contours (same value within 1e-8
-        // relative and |x_a^T B x_b| >= 0.9): keep the smaller residual
+        // relative and |x_a^T B x_b| >= 0.9): keep the smaller residual; only
+        // such candidate vectors come to the host
+        auto fetch = [&](const Pair& q, std::vector<double>& h) {
+            h.resize((size_t)n);
+            HIPCHK(hipMemcpyAsync(h.data(), cms[q.cid]->get() + (size_t)q.col * n, sizeof(double) * n,
+                                  hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        };
         auto bdot = [&](const double* xa, const double* xb) {
             double sacc = 0.0;
             for (int64_t i = 0; i < n; ++i) {
@@ -1529,19 +1537,24 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
             return sacc;
         };
         std::vector<char> drop(pairs.size(), 0);
+        std::vector<double> ha, hb;
         for (size_t a = 0; a < pairs.size(); ++a) {
             if (drop[a]) continue;
             for (size_t b = a + 1; b < pairs.size(); ++b) {
                 if (pairs[b].lam - pairs[a].lam > 1e-8 * std::max(std::fabs(pairs[a].lam), std::fabs(pairs[b].lam))) break;
                 if (drop[b] || pairs[b].cid == pairs[a].cid) continue;
-                const double* xa = vecs[pairs[a].cid].data() + (size_t)pairs[a].col * n;
-                const double* xb = vecs[pairs[b].cid].data() + (size_t)pairs[b].col * n;
-                if (std::fabs(bdot(xa, xb)) >= 0.9) drop[pairs[b].rho >= pairs[a].rho ? b : a] = 1;
+                fetch(pairs[a], ha);
+                fetch(pairs[b], hb);
+                if (std::fabs(bdot(ha.data(), hb.data())) >= 0.9) drop[pairs[b].rho >= pairs[a].rho ? b : a] = 1;
             }
         }
         auto* R = new gep_result();
         R->n = n;
         bool noconv = false;
+        size_t kept = 0;
+        for (size_t a = 0; a < pairs.size(); ++a) kept += !drop[a];
+        if (kept) R->dvecs = std::make_unique<DBuf<double>>((size_t)n * kept);
+        size_t idx = 0;
         for (size_t a = 0; a < pairs.size(); ++a) {
             if (drop[a]) continue;
             const Pair& pr = pairs[a];
@@ -1551,16 +1564,27 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
             const bool ok = pr.rho <= cfg.tol;
             noconv |= !ok;
             R->conv.push_back(ok ? 1 : 0);
-            const double* x = vecs[pr.cid].data() + (size_t)pr.col * n;
-            R->evecs.insert(R->evecs.end(), x, x + n);
+            HIPCHK(hipMemcpyAsync(R->dvecs->get() + idx * n, cms[pr.cid]->get() + (size_t)pr.col * n,
+                                  sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+            ++idx;
         }
+        HIPCHK(hipStreamSynchronize(s));
         R->m = (int64_t)R->evals.size();
         R->stats = json_stats(sv, wall_solve, mine, cfg.o.precision);
+        R->stats.insert(1, "\"wall_select_ms\":" +
+                               std::to_string(std::chrono::duration<double, std::milli>(
+                                                  std::chrono::steady_clock::now() - t0).count() - wall_solve) + ",");
         out[p] = R;
         const int st = noconv ? GEP_WNOCONV : (saturated ? GEP_WSATURATED : GEP_OK);
         if (st == GEP_WNOCONV || (st == GEP_WSATURATED && worst == GEP_OK)) worst = st;
         base += K;
     }
+    // release the solver's device buffers; the time it takes is reported
+    const auto tf = std::chrono::steady_clock::now();
+    svp.reset();
+    const double free_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tf).count();
+    for (int p = 0; p < n_problems; ++p)
+        if (out[p]) out[p]->stats.insert(1, "\"wall_free_ms\":" + std::to_string(free_ms) + ",");
     return worst;
 }
 
@@ -1777,7 +1801,13 @@ int gep_result_copy(const gep_result* r, double* evals, double* evecs, double* r
                     uint8_t* conv) {
     if (!r) return GEP_EINVAL;
     if (evals) std::copy(r->evals.begin(), r->evals.end(), evals);
-    if (evecs) std::copy(r->evecs.begin(), r->evecs.end(), evecs);
+    if (evecs && r->dvecs && r->dvecs->n) {
+        hipError_t e = hipMemcpy(evecs, r->dvecs->get(), sizeof(double) * r->dvecs->n, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            gep::set_error(std::string("eigenvector copy failed: ") + hipGetErrorString(e));
+            return GEP_EDEVICE;
+        }
+    }
     if (resid) std::copy(r->resid.begin(), r->resid.end(), resid);
     if (cid) std::copy(r->cid.begin(), r->cid.end(), cid);
     if (conv) std::copy(r->conv.begin(), r->conv.end(), conv);

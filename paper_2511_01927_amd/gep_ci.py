@@ -210,7 +210,7 @@ def _collect(res_ptr, status):
     _check(lib.gep_result_count(res_ptr, C.byref(m), C.byref(n)))
     m, n = m.value, n.value
     ev = np.zeros(m)
-    vec = np.zeros((m, n))          # row j = eigenvector j  (column-major n x m)
+    vec = np.empty((m, n))          # row j = eigenvector j  (column-major n x m)
     rho = np.zeros(m)
     cid = np.zeros(m, dtype=np.int32)
     conv = np.zeros(m, dtype=np.uint8)
