@@ -42,27 +42,56 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # same process (FETCH_SIZE x2.0, WRITE_SIZE x1.0).  They hold only for the
 # kernel sources they were taken on; with any other source the traffic is
 # reported as null.
-TRAFFIC = {
-    "workload": "q1_2d_300",
-    "precision": "fp64",
-    "sources_sha256": {
-        "paper_2511_01927_amd/csrc/cocg.hip": "d77cbde59f14638d2c50f773f839a7be198170836066b48c624d8ac22f973ea1",
-        "paper_2511_01927_amd/csrc/internal.h": "36a2880ef095f14e3a5520d05cadf39eef28aa42705b1d4c2846e980470b638c",
+# Measured HBM bytes (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated) on
+# the default workload; valid only while the kernels' sources are the ones
+# measured (sha256), else `traffic` is null.
+TRAFFIC = [
+    {
+        "workload": "q1_2d_300",
+        "precision": "fp64",
+        "sources_sha256": {
+            "paper_2511_01927_amd/csrc/cocg.hip": "d77cbde59f14638d2c50f773f839a7be198170836066b48c624d8ac22f973ea1",
+            "paper_2511_01927_amd/csrc/internal.h": "c30d92585243f2cfe02ca74c2f069d1f0c053400ac3d36d757082ed7fa44c36c",
+        },
+        # bytes per tile-launch (scaled by the tiles a launch processes)
+        "per_tile_bytes": {"cocg_spmm_dir": 3.389801e+08, "cocg_update": 5.272175e+08},
+        "profile": "profiles/cocg_q1_300x300_fp64_hbm_traffic.md",
     },
-    "per_tile_bytes": {"cocg_spmm_dir": 3.389801e+08, "cocg_update": 5.272175e+08},
-    "profile": "profiles/cocg_q1_300x300_fp64_hbm_traffic.md",
-}
+    {
+        "workload": "q1_2d_300",
+        "precision": "fp64",
+        "sources_sha256": {
+            "paper_2511_01927_amd/csrc/band.hip": "7f2ac266967ae4020e6f048a8253f23af3f4acae371cf9197a7577359cb33c7f",
+            "paper_2511_01927_amd/csrc/internal.h": "c30d92585243f2cfe02ca74c2f069d1f0c053400ac3d36d757082ed7fa44c36c",
+        },
+        # bytes per launch (per timed bracket for band_solve: right-hand sides,
+        # forward and backward sweep)
+        "per_launch_bytes": {"band_update": 9.658853e+07, "band_update_next": 6.397361e+07,
+                             "band_panel": 2.041963e+07, "band_solve": 8.697910e+10},
+        "profile": "profiles/band_q1_300x300_fp64_hbm_traffic.md",
+    },
+]
+
+
+def _traffic(workload: str, precision: str, kernel: str, key: str):
+    import hashlib
+    for t in TRAFFIC:
+        if workload != t["workload"] or precision != t["precision"] or kernel not in t.get(key, {}):
+            continue
+        for rel, want in t["sources_sha256"].items():
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != want:
+                    return None
+        return t[key][kernel]
+    return None
 
 
 def traffic_per_tile(workload: str, precision: str, kernel: str):
-    import hashlib
-    if workload != TRAFFIC["workload"] or precision != TRAFFIC["precision"]:
-        return None
-    for rel, want in TRAFFIC["sources_sha256"].items():
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != want:
-                return None
-    return TRAFFIC["per_tile_bytes"].get(kernel)
+    return _traffic(workload, precision, kernel, "per_tile_bytes")
+
+
+def traffic_per_launch(workload: str, precision: str, kernel: str):
+    return _traffic(workload, precision, kernel, "per_launch_bytes")
 
 
 def workload(name: str):
@@ -228,10 +257,12 @@ def main():
                     "traffic_unit": "bytes per launch", "kernel": name,
                     "avg_launch_us": round(avg_s * 1e6, 2), "alg_bytes_per_launch": per_launch,
                     "launches": kl.get(name, 0)}
-        # plain FP64 vector arithmetic (no matrix cores): peak 78.6 TFLOP/s
+        # FP64 arithmetic: peak 78.6 TFLOP/s (vector and matrix cores alike on MI355X)
+        traffic = None if args.max_iter else traffic_per_launch(args.workload, args.precision, name)
         return {"bound": "alu", "achieved": round(rate / 1e12, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(rate / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": None, "kernel": name, "avg_launch_us": round(avg_s * 1e6, 2),
+                "traffic": round(traffic) if traffic is not None else None,
+                "traffic_unit": "bytes per launch", "kernel": name, "avg_launch_us": round(avg_s * 1e6, 2),
                 "alg_flops_per_launch": per_launch, "launches": kl.get(name, 0)}
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "eigenpairs/s", "n_gpus": 1,
