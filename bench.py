@@ -51,7 +51,7 @@ TRAFFIC = [
         "precision": "fp64",
         "sources_sha256": {
             "paper_2511_01927_amd/csrc/cocg.hip": "d77cbde59f14638d2c50f773f839a7be198170836066b48c624d8ac22f973ea1",
-            "paper_2511_01927_amd/csrc/internal.h": "c30d92585243f2cfe02ca74c2f069d1f0c053400ac3d36d757082ed7fa44c36c",
+            "paper_2511_01927_amd/csrc/internal.h": "ae891c2b4dae34136c3ed5abdca25bbfe2e22d05efb54a0029d384d680705d18",
         },
         # bytes per tile-launch (scaled by the tiles a launch processes)
         "per_tile_bytes": {"cocg_spmm_dir": 3.389801e+08, "cocg_update": 5.272175e+08},
@@ -61,13 +61,13 @@ TRAFFIC = [
         "workload": "q1_2d_300",
         "precision": "fp64",
         "sources_sha256": {
-            "paper_2511_01927_amd/csrc/band.hip": "7f2ac266967ae4020e6f048a8253f23af3f4acae371cf9197a7577359cb33c7f",
-            "paper_2511_01927_amd/csrc/internal.h": "c30d92585243f2cfe02ca74c2f069d1f0c053400ac3d36d757082ed7fa44c36c",
+            "paper_2511_01927_amd/csrc/band.hip": "4bb7498a7ba7d16fb3126aa39003a84412ff1909c0e1e5ddcbf5a9fb99f71b2f",
+            "paper_2511_01927_amd/csrc/internal.h": "ae891c2b4dae34136c3ed5abdca25bbfe2e22d05efb54a0029d384d680705d18",
         },
         # bytes per launch (per timed bracket for band_solve: right-hand sides,
         # forward and backward sweep)
-        "per_launch_bytes": {"band_update": 9.658853e+07, "band_update_next": 6.397361e+07,
-                             "band_panel": 2.041963e+07, "band_solve": 8.697910e+10},
+        "per_launch_bytes": {"band_update": 9.659020e+07, "band_update_next": 6.397550e+07,
+                             "band_panel": 2.041963e+07, "band_solve": 8.699347e+10},
         "profile": "profiles/band_q1_300x300_fp64_hbm_traffic.md",
     },
 ]

@@ -35,6 +35,8 @@
 // shifted Q1 systems); every solve is followed by an FP64 residual check and
 // iterative refinement with the same factors, and a zero or non-finite pivot
 // is flagged per system.
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 
 namespace gep {
@@ -1203,49 +1205,49 @@ hipError_t band_form(const BandSys* sys, int nsys, const double2* AB, double2* F
 }
 
 hipError_t band_panel(const BandSys* sys, int nsys, int bwmax, double2* F, int k0, int32_t* flag,
-                      hipStream_t s) {
+                      hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     // one thread per panel row while kPanel + bw rows fit 512 threads
     const int rows = kPanel + bwmax;
     if (rows <= 64) {
-        hipLaunchKernelGGL(k_band_panel_rows<64>, dim3(nsys), dim3(64), 0, s, sys, F, k0, flag);
+        hipExtLaunchKernelGGL(k_band_panel_rows<64>, dim3(nsys), dim3(64), 0, s, e0, e1, 0, sys, F, k0, flag);
         return hipGetLastError();
     } else if (rows <= 128) {
-        hipLaunchKernelGGL(k_band_panel_rows<128>, dim3(nsys), dim3(128), 0, s, sys, F, k0, flag);
+        hipExtLaunchKernelGGL(k_band_panel_rows<128>, dim3(nsys), dim3(128), 0, s, e0, e1, 0, sys, F, k0, flag);
         return hipGetLastError();
     } else if (rows <= 256) {
-        hipLaunchKernelGGL(k_band_panel_rows<256>, dim3(nsys), dim3(256), 0, s, sys, F, k0, flag);
+        hipExtLaunchKernelGGL(k_band_panel_rows<256>, dim3(nsys), dim3(256), 0, s, e0, e1, 0, sys, F, k0, flag);
         return hipGetLastError();
     } else if (rows <= 384) {
-        hipLaunchKernelGGL(k_band_panel_rows<384>, dim3(nsys), dim3(384), 0, s, sys, F, k0, flag);
+        hipExtLaunchKernelGGL(k_band_panel_rows<384>, dim3(nsys), dim3(384), 0, s, e0, e1, 0, sys, F, k0, flag);
         return hipGetLastError();
     } else if (rows <= 512) {
-        hipLaunchKernelGGL(k_band_panel_rows<512>, dim3(nsys), dim3(512), 0, s, sys, F, k0, flag);
+        hipExtLaunchKernelGGL(k_band_panel_rows<512>, dim3(nsys), dim3(512), 0, s, e0, e1, 0, sys, F, k0, flag);
         return hipGetLastError();
     }
     // registers per thread for a kPanel x (bw + 1) panel over 1024 threads
     const int need = (kPanel * (bwmax + 1) + kPanelThreads - 1) / kPanelThreads;
     const dim3 b(kPanelThreads);
     if (need <= 2)
-        hipLaunchKernelGGL(k_band_panel_reg<2>, dim3(nsys), b, 0, s, sys, F, k0, flag);
+        hipExtLaunchKernelGGL(k_band_panel_reg<2>, dim3(nsys), b, 0, s, e0, e1, 0, sys, F, k0, flag);
     else if (need <= 4)
-        hipLaunchKernelGGL(k_band_panel_reg<4>, dim3(nsys), b, 0, s, sys, F, k0, flag);
+        hipExtLaunchKernelGGL(k_band_panel_reg<4>, dim3(nsys), b, 0, s, e0, e1, 0, sys, F, k0, flag);
     else if (need <= 6)
-        hipLaunchKernelGGL(k_band_panel_reg<6>, dim3(nsys), b, 0, s, sys, F, k0, flag);
+        hipExtLaunchKernelGGL(k_band_panel_reg<6>, dim3(nsys), b, 0, s, e0, e1, 0, sys, F, k0, flag);
     else if (need <= 8)
-        hipLaunchKernelGGL(k_band_panel_reg<8>, dim3(nsys), b, 0, s, sys, F, k0, flag);
+        hipExtLaunchKernelGGL(k_band_panel_reg<8>, dim3(nsys), b, 0, s, e0, e1, 0, sys, F, k0, flag);
     else if (need <= 10)
-        hipLaunchKernelGGL(k_band_panel_reg<10>, dim3(nsys), b, 0, s, sys, F, k0, flag);
+        hipExtLaunchKernelGGL(k_band_panel_reg<10>, dim3(nsys), b, 0, s, e0, e1, 0, sys, F, k0, flag);
     else   // wider bands: the panel stays in global memory (more registers would spill)
-        hipLaunchKernelGGL(k_band_panel, dim3(nsys), dim3(256), 0, s, sys, F, k0, flag);
+        hipExtLaunchKernelGGL(k_band_panel, dim3(nsys), dim3(256), 0, s, e0, e1, 0, sys, F, k0, flag);
     return hipGetLastError();
 }
 
 hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int k0, int part,
-                       hipStream_t s) {
+                       hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const int w0 = k0 + kPanel;
     if (part == 1) {
         const int T = (bwmax + 31) / 32;
-        hipLaunchKernelGGL(k_band_strip, dim3(T, nsys), dim3(256), 0, s, sys, F, k0, k0 >= kPanel ? 2 : 1);
+        hipExtLaunchKernelGGL(k_band_strip, dim3(T, nsys), dim3(256), 0, s, e0, e1, 0, sys, F, k0, k0 >= kPanel ? 2 : 1);
         return hipGetLastError();
     }
     int c0 = w0, c1 = w0 + bwmax, strip = 0, npan = 1;
@@ -1255,7 +1257,7 @@ hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int 
     const int T = (w0 + bwmax - c0 + 63) / 64;
     const int tiles = strip ? T : T * (T + 1) / 2;
     if (tiles <= 0 || c0 >= c1) return hipSuccess;
-    hipLaunchKernelGGL(k_band_update, dim3(tiles, nsys), dim3(256), 0, s, sys, F, k0, c0, c1, strip,
+    hipExtLaunchKernelGGL(k_band_update, dim3(tiles, nsys), dim3(256), 0, s, e0, e1, 0, sys, F, k0, c0, c1, strip,
                        npan);
     return hipGetLastError();
 }

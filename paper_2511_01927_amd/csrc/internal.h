@@ -182,13 +182,15 @@ constexpr size_t kBandLds = 64 * 1024;
 hipError_t band_form(const BandSys* sys, int nsys, const double2* AB, double2* F, hipStream_t s);
 // One panel step: factor panel [k0, k0 + kPanel) (flag: zero or non-finite
 // pivot per system), then update the trailing window.
+// e0, e1 (optional, timing events): attached to the kernel's dispatch
+// (start and end of its execution).
 hipError_t band_panel(const BandSys* sys, int nsys, int bwmax, double2* F, int k0, int32_t* flag,
-                      hipStream_t s);
+                      hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // part 0: the whole trailing window; 1: only the next panel's columns
 // [k0 + kPanel, k0 + 2 kPanel), with the contributions of panel k0 and of
 // panel k0 - kPanel; 2: the window from k0 + 3 kPanel on (panel k0 only).
 hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int k0, int part,
-                       hipStream_t s);
+                       hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Columns per work-group of the solves for a half bandwidth bw.
 int band_chunk_columns(int bw);
 // In place: X <- K^-1 X for every column (colsys: system of each tiled column,

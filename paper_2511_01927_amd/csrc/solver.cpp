@@ -167,6 +167,16 @@ struct Timer {
         HIPCHK(hipEventRecord(b, open_s));
         pending.push_back({open_cls, open_a, b});
     }
+    // Events to attach to the next dispatch of class cls (hipExtLaunchKernel
+    // start / stop: the kernel's own execution), or null when this dispatch
+    // is not sampled.
+    void kernel_pair(int cls, hipEvent_t& a, hipEvent_t& b) {
+        a = b = nullptr;
+        if (!on || seen[cls]++ % stride[cls] != 0) return;
+        a = get();
+        b = get();
+        pending.push_back({cls, a, b});
+    }
     // call after a stream synchronisation
     void flush() {
         for (auto& r : pending) {
@@ -668,19 +678,17 @@ class Solver {
                 if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
             int steps = 0;
             for (int64_t k0 = 0; k0 < nmax; k0 += kPanel, ++steps) {
-                tm_.begin(T_BAND_PANEL);
-                HIPCHK(band_panel(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, flags.get(), s_));
-                tm_.end();
+                hipEvent_t ea, eb;
+                tm_.kernel_pair(T_BAND_PANEL, ea, eb);
+                HIPCHK(band_panel(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, flags.get(), s_, ea, eb));
                 if (k0 + kPanel < nmax) {
                     if (steps >= 2) HIPCHK(hipStreamWaitEvent(s_, ev_rest_[steps & 1], 0));
-                    tm_.begin(T_BAND_NEXT);
-                    HIPCHK(band_update(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, 1, s_));
-                    tm_.end();
+                    tm_.kernel_pair(T_BAND_NEXT, ea, eb);
+                    HIPCHK(band_update(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, 1, s_, ea, eb));
                     HIPCHK(hipEventRecord(ev_panel_, s_));
                     HIPCHK(hipStreamWaitEvent(s2_, ev_panel_, 0));
-                    tm_.begin(T_BAND_UPDATE, s2_);
-                    HIPCHK(band_update(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, 2, s2_));
-                    tm_.end();
+                    tm_.kernel_pair(T_BAND_UPDATE, ea, eb);
+                    HIPCHK(band_update(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, 2, s2_, ea, eb));
                     HIPCHK(hipEventRecord(ev_rest_[steps & 1], s2_));
                 }
             }
