@@ -65,16 +65,31 @@ constexpr int band_threads_per_column(int cw) { return 256 / cw > 64 ? 64 : 256 
 
 }  // namespace
 
-// F = z B - A on the band of each system.
-__global__ __launch_bounds__(256) void k_band_form(const BandSys* __restrict__ sys,
+// F = z B - A on the band of each system.  Work-group row blockIdx.y takes
+// systems y, y + gridDim.y, ...; consecutive systems of a pass share their
+// pencil, so each (a, b) pair is read once for all of them when they do
+// (aoff equal), and F is written with non-temporal stores (the factorisation
+// reaches most of it long after).
+__global__ __launch_bounds__(256) void k_band_form(const BandSys* __restrict__ sys, int nsys,
                                                    const double2* __restrict__ AB,
                                                    double2* __restrict__ F) {
-    const BandSys S = sys[blockIdx.y];
-    const int64_t total = (int64_t)S.n * (S.bw + 1);
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const double2 v = AB[S.aoff + e];
-        F[S.off + e] = make_double2(S.z.x * v.y - v.x, S.z.y * v.y);
+    for (int y = blockIdx.y; y < nsys;) {
+        const BandSys S = sys[y];
+        const int64_t total = (int64_t)S.n * (S.bw + 1);
+        // the run of systems after y (stride gridDim.y) on the same pencil band
+        int yend = y + gridDim.y;
+        while (yend < nsys && sys[yend].aoff == S.aoff && sys[yend].n == S.n && sys[yend].bw == S.bw)
+            yend += gridDim.y;
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+             e += (int64_t)gridDim.x * blockDim.x) {
+            const double2 v = AB[S.aoff + e];
+            for (int q = y; q < yend; q += gridDim.y) {
+                const BandSys Q = sys[q];
+                __builtin_nontemporal_store(Q.z.x * v.y - v.x, &F[Q.off + e].x);
+                __builtin_nontemporal_store(Q.z.y * v.y, &F[Q.off + e].y);
+            }
+        }
+        y = yend;
     }
 }
 
@@ -1200,7 +1215,9 @@ static hipError_t sweep_reg_k(const BandSys* sys, const int32_t* colsys, const d
 // ---- launchers ---------------------------------------------------------
 
 hipError_t band_form(const BandSys* sys, int nsys, const double2* AB, double2* F, hipStream_t s) {
-    hipLaunchKernelGGL(k_band_form, dim3(64, nsys), dim3(256), 0, s, sys, AB, F);
+    // 1024 work-groups: 128 along each band x 8 system lanes
+    const int ys = std::min(nsys, 8);
+    hipLaunchKernelGGL(k_band_form, dim3(1024 / ys, ys), dim3(256), 0, s, sys, nsys, AB, F);
     return hipGetLastError();
 }
 
