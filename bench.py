@@ -64,13 +64,13 @@ TRAFFIC = [
         "workload": "q1_2d_300",
         "precision": "fp64",
         "sources_sha256": {
-            "paper_2511_01927_amd/csrc/band.hip": "4bb7498a7ba7d16fb3126aa39003a84412ff1909c0e1e5ddcbf5a9fb99f71b2f",
+            "paper_2511_01927_amd/csrc/band.hip": "678f3e30f96ab7f4b8a7c6e3f3f29cbb0a35ef697939abc8c32f02749435b098",
             "paper_2511_01927_amd/csrc/internal.h": "ae891c2b4dae34136c3ed5abdca25bbfe2e22d05efb54a0029d384d680705d18",
         },
         # bytes per launch (per timed bracket for band_solve: right-hand sides,
         # forward and backward sweep)
-        "per_launch_bytes": {"band_update": 9.659020e+07, "band_update_next": 6.397550e+07,
-                             "band_panel": 2.041963e+07, "band_solve": 8.699347e+10},
+        "per_launch_bytes": {"band_update": 9.658702e+07, "band_update_next": 6.397094e+07,
+                             "band_panel": 2.041961e+07, "band_solve": 8.693837e+10},
         "profile": "profiles/band_q1_300x300_fp64_hbm_traffic.md",
     },
 ]
