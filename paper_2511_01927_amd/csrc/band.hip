@@ -1310,7 +1310,13 @@ hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int 
     }
     const int T = (w0 + bwmax - c0 + 63) / 64;
     const int tiles = strip ? T : T * (T + 1) / 2;
-    if (tiles <= 0 || c0 >= c1) return hipSuccess;
+    if (tiles <= 0 || c0 >= c1) {   // nothing to update (narrow band): the events still bracket a point
+        if (e0) {
+            hipError_t e = hipEventRecord(e0, s);
+            if (e != hipSuccess) return e;
+        }
+        return e1 ? hipEventRecord(e1, s) : hipSuccess;
+    }
     hipExtLaunchKernelGGL(k_band_update, dim3(tiles, nsys), dim3(256), 0, s, e0, e1, 0, sys, F, k0, c0, c1, strip,
                        npan);
     return hipGetLastError();

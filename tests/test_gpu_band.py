@@ -122,3 +122,24 @@ def test_band_automatic_choice_and_wide_band(lib):
     with pytest.raises(lib.GepError) as e:
         lib.gep_ci_solve(Aw, B, c, 16, 2, 8, 1e-8, seed=1, solver="band")
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("which", ["fem1d", "q1"])
+def test_band_timing_statistics(lib, which):
+    """Per-kernel timing on (the bench's mode): sampled HIP events around the
+    factorisation launches, including steps whose window update is empty
+    (half bandwidth 1), give finite per-class times and launch counts."""
+    if which == "fem1d":
+        w = configs.fem1d_2000()
+    else:
+        w = configs.config_q1_2d(nx=70, ny=12, first=21, last=40, k=1, n_nodes=16, moments=4, block=16, seed=4)
+    P = lib.Pencil(w.A, w.B)
+    got = P.solve(w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed, solver="band", timing=True)
+    st = got["stats"]
+    km, kl = st["kernel_ms"], st["kernel_launches"]
+    steps = st["band_panel_steps"]
+    assert kl["band_panel"] == steps and kl["band_update"] == steps - 1 and kl["band_update_next"] == steps - 1
+    for k in ("band_panel", "band_update", "band_update_next", "band_solve"):
+        assert np.isfinite(km[k]) and km[k] >= 0.0, (k, km[k])
+    assert km["band_panel"] > 0.0 and km["band_solve"] > 0.0
+    assert np.max(got["resid"]) <= 1e-8
