@@ -17,7 +17,8 @@
 //                  (k_band_panel_reg: the same with the panel in registers);
 //   k_band_update  the trailing window of bw rows and columns after the
 //                  panel: C -= W diag(d) W^T, lower triangle, in 64 x 64
-//                  tiles staged through LDS; split into the next panel's
+//                  tiles staged through LDS, products on the FP64 matrix
+//                  cores; split into the next panel's
 //                  columns (with the contributions of this panel and the
 //                  one before) and the window past the panel after next,
 //                  so that the rest can run on a second stream beside the
@@ -51,6 +52,8 @@ __device__ inline void cfms(double2& a, double2 b, double2 c) {
     a.x = fma(-b.x, c.x, fma(b.y, c.y, a.x));
     a.y = fma(-b.x, c.y, fma(-b.y, c.x, a.y));
 }
+
+typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
 
 // Value of v in lane l (wave-uniform l) of the wavefront, through SGPRs.
 __device__ inline double readlane_d(double v, int l) {
@@ -274,13 +277,18 @@ __global__ __launch_bounds__(256) void k_band_update(const BandSys* __restrict__
     if (i0 >= wend || j0 >= cend) return;
     const int ld = S.bw + 1;
     const double2* Fs = F + S.off;   // panel columns (read) and window columns (written) of one band
-    // thread: 4 consecutive rows x 4 columns (columns strided by 16)
-    const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
-    double2 acc[4][4];
+    // FP64 matrix cores: wave w owns the tile's 16-column block w and all
+    // four 16-row blocks; per 4-deep K step one B operand (W_j) serves four
+    // complex products (four v_mfma_f64_16x16x4 each).  Operand layouts
+    // (lane l): A(i, k) at i = l % 16, k = l / 16; B(k, j) at k = l / 16,
+    // j = l % 16; result register v is D(l / 16 + 4 v, l % 16).
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    mfma_f64x4 pre[4], pim[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
+    for (int rb = 0; rb < 4; ++rb) {
+        pre[rb] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
+        pim[rb] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
+    }
     for (int pp = 0; pp < npan; ++pp) {   // contributions of panel k0 (and of the one before it)
         const int kp = k0 - kPanel * pp;
         if (kp < 0) break;
@@ -296,35 +304,34 @@ __global__ __launch_bounds__(256) void k_band_update(const BandSys* __restrict__
             Wj[r][kk] = wj;
         }
         __syncthreads();
-        for (int kk = 0; kk < kPanel; ++kk) {
-            double2 wi[4], wj[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) wi[a] = Wi[tr * 4 + a][kk];
+        for (int st = 0; st < kPanel / 4; ++st) {
+            const int kk = 4 * st + (lane >> 4);
+            const double2 b = Wj[wave * 16 + (lane & 15)][kk];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) wj[b] = Wj[tc + 16 * b][kk];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    acc[a][b].x = fma(wi[a].x, wj[b].x, fma(-wi[a].y, wj[b].y, acc[a][b].x));
-                    acc[a][b].y = fma(wi[a].x, wj[b].y, fma(wi[a].y, wj[b].x, acc[a][b].y));
-                }
+            for (int rb = 0; rb < 4; ++rb) {
+                const double2 a = Wi[rb * 16 + (lane & 15)][kk];
+                // P += W_i W_j^T (complex): re = a.x b.x - a.y b.y, im = a.x b.y + a.y b.x
+                pre[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, pre[rb], 0, 0, 0);
+                pre[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, -b.y, pre[rb], 0, 0, 0);
+                pim[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, pim[rb], 0, 0, 0);
+                pim[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, pim[rb], 0, 0, 0);
+            }
         }
     }
     double2* Fw = F + S.off;
+    const int j = j0 + wave * 16 + (lane & 15);
+    if (j >= cend) return;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int j = j0 + tc + 16 * b;
-        if (j >= cend) continue;
+    for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int i = i0 + tr * 4 + a;
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + rb * 16 + (lane >> 4) + 4 * v;
             if (i >= wend || i < j) continue;
             double2& c = Fw[(int64_t)j * ld + (i - j)];
-            c.x -= acc[a][b].x;
-            c.y -= acc[a][b].y;
+            c.x -= pre[rb][v];
+            c.y -= pim[rb][v];
         }
-    }
 }
 
 // Strip update of the next panel's columns [w0, w0 + kPanel), w0 = k0 +
@@ -826,7 +833,6 @@ __global__ __launch_bounds__(CPW * 32 / CPL) void k_band_sweep(const BandSys* __
 // when they first come into reach of a block.  MFMA operand layouts (lane l):
 // A(i, k) at i = l % 16, k = l / 16; B(k, j) at k = l / 16, j = l % 16;
 // result register v of lane l is D(l / 16 + 4 v, l % 16).
-typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kBlkRows = 32;
 constexpr int kBlkFwdThreads = 512;   // 8 waves: two per SIMD for the MFMA chains
 constexpr int kBlkBwdThreads = 512;
