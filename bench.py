@@ -64,13 +64,13 @@ TRAFFIC = [
         "workload": "q1_2d_300",
         "precision": "fp64",
         "sources_sha256": {
-            "paper_2511_01927_amd/csrc/band.hip": "f0affd6846a90dc4833f5b735f256f61309f0f4dcfc0503f2c0d6b2ef64d5e92",
+            "paper_2511_01927_amd/csrc/band.hip": "6d08aa008a5e3590e1ee8dec707fa8d41748d5cc249f70f98cb01db8e4a44a21",
             "paper_2511_01927_amd/csrc/internal.h": "ae891c2b4dae34136c3ed5abdca25bbfe2e22d05efb54a0029d384d680705d18",
         },
         # bytes per launch (per timed bracket for band_solve: right-hand sides,
         # forward and backward sweep)
-        "per_launch_bytes": {"band_update": 9.658813e+07, "band_update_next": 6.396960e+07,
-                             "band_panel": 2.041960e+07, "band_solve": 8.691198e+10},
+        "per_launch_bytes": {"band_update": 9.608043e+07, "band_update_next": 6.397313e+07,
+                             "band_panel": 2.041042e+07, "band_solve": 8.699095e+10},
         "profile": "profiles/band_q1_300x300_fp64_hbm_traffic.md",
     },
 ]
