@@ -12,26 +12,30 @@
 //
 // Factorisation, right-looking by panels of kPanel columns, one step per
 // panel (all systems of a batch advance together):
-//   k_band_panel   one work-group per system: unblocked L D L^T of the
-//                  panel's kPanel columns (each (bw + 1) long) in place
-//                  (k_band_panel_reg: the same with the panel in registers);
-//   k_band_update  the trailing window of bw rows and columns after the
-//                  panel: C -= W diag(d) W^T, lower triangle, in 64 x 64
+//   k_band_panel_rows  one work-group per system, one thread per panel row
+//                  (kPanel + bw <= 512): unblocked L D L^T of the panel's
+//                  kPanel columns with each row's entries in registers
+//                  (k_band_panel_reg / k_band_panel: wider bands, the panel
+//                  spread over 1024 threads or in global memory);
+//   k_band_strip   the next panel's columns take the contributions of this
+//                  panel and the one before (critical path of the step);
+//   k_band_update  the rest of the trailing window, from the panel after
+//                  next on: C -= W diag(d) W^T, lower triangle, 64 x 64
 //                  tiles staged through LDS, products on the FP64 matrix
-//                  cores; split into the next panel's
-//                  columns (with the contributions of this panel and the
-//                  one before) and the window past the panel after next,
-//                  so that the rest can run on a second stream beside the
-//                  next two panel steps (lookahead).
+//                  cores; it runs on a second stream beside the next two
+//                  panel steps (lookahead).
 // Solves, in place on the tiled multivector (element (i, c) at
 // (tile * n + i) * 64 + lane), a work-group per (tile, chunk of columns):
-//   k_band_forward   L y = b by columns of L (axpy form), the pending rows
-//                    i+1 .. i+bw in a circular LDS window; writes y / d;
-//   k_band_backward  L^T x = z by columns of L (dot form), the solved rows
-//                    i+1 .. i+bw in the LDS window;
-//   k_band_sweep     the same two sweeps with the window in registers (one
-//                    half wavefront per column, see below), used when every
-//                    chunk of 8 or 16 columns belongs to one system.
+//   k_band_fwd_blocked / k_band_bwd_blocked  32-row blocks: a triangular
+//                    solve of the block's rows (readlane broadcasts) and
+//                    the block's coupling to the next (previous) bw rows as
+//                    v_mfma_f64_16x16x4 products, pending rows in an LDS
+//                    ring; used for 16-column chunks and bw <= 384;
+//   k_band_sweep     row-by-row sweeps with the window in registers (one
+//                    half wavefront per column), for 8-column chunks or
+//                    wider bands;
+//   k_band_forward / k_band_backward  the same with an LDS window, for the
+//                    remaining cases.
 // Unpivoted elimination is safe here in practice (growth ~1 measured on the
 // shifted Q1 systems); every solve is followed by an FP64 residual check and
 // iterative refinement with the same factors, and a zero or non-finite pivot
