@@ -64,7 +64,7 @@ TRAFFIC = [
         "workload": "q1_2d_300",
         "precision": "fp64",
         "sources_sha256": {
-            "paper_2511_01927_amd/csrc/band.hip": "f40386755b92666a6c16bf2be4cfbbaf265825e07bae564657998281e898f8be",
+            "paper_2511_01927_amd/csrc/band.hip": "d23744b33f08056a9e410e23fdaadf603689a0dd09fa8feeb1b4204d07a931c2",
             "paper_2511_01927_amd/csrc/internal.h": "ae891c2b4dae34136c3ed5abdca25bbfe2e22d05efb54a0029d384d680705d18",
         },
         # bytes per launch (per timed bracket for band_solve: right-hand sides,

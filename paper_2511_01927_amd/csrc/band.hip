@@ -1311,6 +1311,13 @@ hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int 
     const int w0 = k0 + kPanel;
     if (part == 1) {
         const int T = (bwmax + 31) / 32;
+        if (T == 0) {   // diagonal systems: nothing couples the panels
+            if (e0) {
+                hipError_t e = hipEventRecord(e0, s);
+                if (e != hipSuccess) return e;
+            }
+            return e1 ? hipEventRecord(e1, s) : hipSuccess;
+        }
         hipExtLaunchKernelGGL(k_band_strip, dim3(T, nsys), dim3(256), 0, s, e0, e1, 0, sys, F, k0, k0 >= kPanel ? 2 : 1);
         return hipGetLastError();
     }

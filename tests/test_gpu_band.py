@@ -143,3 +143,22 @@ def test_band_timing_statistics(lib, which):
         assert np.isfinite(km[k]) and km[k] >= 0.0, (k, km[k])
     assert km["band_panel"] > 0.0 and km["band_solve"] > 0.0
     assert np.max(got["resid"]) <= 1e-8
+
+
+def test_band_diagonal_pencil(lib):
+    """Half bandwidth 0 (diagonal A and B): no coupling between panels, the
+    factorisation is the diagonal itself; eigenvalues a_ii / b_ii exactly."""
+    n = 600
+    rng = np.random.default_rng(21)
+    lam = np.arange(1.0, n + 1.0)
+    b = rng.uniform(1.0, 2.0, n)
+    A = sp.diags(lam * b).tocsr()
+    B = sp.diags(b).tocsr()
+    lo, hi = configs.gap_window(lam, 101, 120)
+    c = configs.uniform_contours(lo, hi, 2, 0.1)
+    got = lib.gep_ci_solve(A, B, c, 16, 4, 8, 1e-8, seed=3, solver="band")
+    ref = lam[100:120]
+    assert got["evals"].size == ref.size
+    assert np.max(np.abs(got["evals"] - ref) / ref) <= 1e-10
+    assert np.max(got["resid"]) <= 1e-8
+    _check_band_stats(got, 2 * 8)
