@@ -221,7 +221,7 @@ def main():
         # within 1e-10 relative and its residual is <= tol
         used = np.zeros(ref.size, dtype=bool)
         for l, rr in zip(lam, rho):
-            j = int(np.argmin(np.abs(ref - l) + used * np.inf)) if ref.size else -1
+            j = int(np.argmin(np.where(used, np.inf, np.abs(ref - l)))) if ref.size else -1
             if j >= 0 and not used[j] and abs(ref[j] - l) <= 1e-10 * abs(ref[j]) and rr <= w.tol:
                 used[j] = True
                 good += 1
