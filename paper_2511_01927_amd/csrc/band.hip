@@ -205,8 +205,9 @@ __global__ __launch_bounds__(kPanelThreads) void k_band_panel_reg(const BandSys*
 // panel's rows are k0 .. k0 + ncols - 1 + bw, so NT >= kPanel + bw.  For
 // column j the rows k0 .. k0 + ncols - 1 publish a_kj (the diagonal one also
 // 1 / d_j) in LDS; every row i in (j, j + bw] then forms l_ij = a_ij / d_j
-// and a_ik -= l_ij a_kj for the later panel columns k.  Slots above the
-// diagonal or past the last column may collect garbage: they are never
+// and a_ik -= l_ij a_kj for the later panel columns k, column j + 1 first so
+// that column can be published before the others are updated.  Slots above
+// the diagonal or past the last column may collect garbage: they are never
 // published, used or stored.  One barrier per column (double-buffered LDS).
 template <int NT>
 __global__ __launch_bounds__(NT) void k_band_panel_rows(const BandSys* __restrict__ sys, double2* F,
@@ -226,24 +227,38 @@ __global__ __launch_bounds__(NT) void k_band_panel_rows(const BandSys* __restric
         const bool ok = row_ok && k < ncols && t >= k && t - k <= S.bw;
         a[k] = ok ? Fs[(int64_t)(k0 + k) * ld + (t - k)] : make_double2(0.0, 0.0);
     }
+    // rows k0 .. k0 + ncols - 1 publish column jj (slot jj) and the pivot
+    // row its inverse
+    auto publish = [&](double2* c, int jj, double2 v) {
+        if (t >= jj && t < ncols) c[t] = v;
+        if (t == jj) {
+            const double m2 = v.x * v.x + v.y * v.y;
+            if (!(m2 > 0.0) || !isfinite(m2)) flag[blockIdx.x] = 1;
+            c[kPanel] = make_double2(v.x / m2, -v.y / m2);
+        }
+    };
+    publish(cb[0], 0, a[0]);
+    __syncthreads();
 #pragma unroll
     for (int jj = 0; jj < kPanel; ++jj) {
         if (jj < ncols) {   // uniform
-            double2* c = cb[jj & 1];
-            if (t >= jj && t < ncols) c[t] = a[jj];
-            if (t == jj) {
-                const double2 d = a[jj];
-                const double m2 = d.x * d.x + d.y * d.y;
-                if (!(m2 > 0.0) || !isfinite(m2)) flag[blockIdx.x] = 1;
-                c[kPanel] = make_double2(d.x / m2, -d.y / m2);
+            const double2* c = cb[jj & 1];
+            const int jn = jj + 1 < kPanel ? jj + 1 : jj;
+            const bool upd = row_ok && t > jj && t - jj <= S.bw;
+            double2 l = make_double2(0.0, 0.0);
+            if (upd) {
+                l = cmul(a[jj], c[kPanel]);
+                a[jj] = l;
+                if (jj + 1 < kPanel) cfms(a[jn], l, c[jn]);
+            }
+            // column jj + 1 is final now: publish it (its pivot's division
+            // overlaps the rest of this column's updates)
+            if (jj + 1 < ncols) publish(cb[(jj + 1) & 1], jj + 1, a[jn]);
+            if (upd) {
+#pragma unroll
+                for (int k = jj + 2; k < kPanel; ++k) cfms(a[k], l, c[k]);
             }
             __syncthreads();
-            if (row_ok && t > jj && t - jj <= S.bw) {
-                const double2 l = cmul(a[jj], c[kPanel]);
-                a[jj] = l;
-#pragma unroll
-                for (int k = jj + 1; k < kPanel; ++k) cfms(a[k], l, c[k]);
-            }
         }
     }
 #pragma unroll
@@ -340,68 +355,76 @@ __global__ __launch_bounds__(256) void k_band_update(const BandSys* __restrict__
 
 // Strip update of the next panel's columns [w0, w0 + kPanel), w0 = k0 +
 // kPanel, with the contributions of panel k0 and (npan = 2) of the panel
-// before it: rows [w0, wend) in 32-row tiles (blockIdx.x), 32 x 32 outputs
-// per work-group, 2 x 2 per thread; blockIdx.y is the system.  Short and on
-// the critical path of the factorisation, so many small work-groups.
-__global__ __launch_bounds__(256) void k_band_strip(const BandSys* __restrict__ sys, double2* F,
+// before it: C[i, j] -= sum_k l_ik d_k l_jk for rows [w0, wend) in 32-row
+// tiles (blockIdx.x; blockIdx.y is the system).  Short and on the critical
+// path of the factorisation, so its loads are all issued at once: wave w
+// takes panel w >> 2 and the 16 x 16 output sub-tile (w & 1, (w >> 1) & 1),
+// reads its operands straight from the band into registers and forms the
+// product on v_mfma_f64_16x16x4 as D(j, i) = sum_k (l_jk d_k) l_ik (a
+// complex product is four real ones), so that each lane's outputs run down
+// a column and the read-modify-write of C is coalesced.  The second panel's
+// partial sums join the first's through LDS.
+__global__ __launch_bounds__(512) void k_band_strip(const BandSys* __restrict__ sys, double2* F,
                                                     int k0, int npan) {
-    __shared__ double2 Wi[32][kPanel + 1];
-    __shared__ double2 Wj[32][kPanel + 1];
+    __shared__ double2 dsh[2][kPanel];
+    __shared__ double part[4][2][4][64];   // [sub-tile][re, im][register][lane]
     const BandSys S = sys[blockIdx.y];
     const int w0 = k0 + kPanel;
     const int wend = min(S.n, k0 + kPanel + S.bw);
     const int cend = min(w0 + kPanel, wend);
     const int i0 = w0 + 32 * blockIdx.x;
-    if (w0 >= cend || i0 >= wend) return;
+    if (w0 >= cend || i0 >= wend) return;   // uniform over the work-group
     const int ld = S.bw + 1;
     double2* Fs = F + S.off;
-    const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;   // rows 2 tr, 2 tr + 1; columns tc, tc + 16
-    double2 acc[2][2];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int pp = wave >> 2, sub = wave & 3, rw = sub & 1, cw = sub >> 1;
+    const int kp = k0 - kPanel * pp;
+    const bool act = pp < npan && kp >= 0;   // uniform over the wave
+    if (t < 2 * kPanel) {
+        const int q = t / kPanel, k = k0 - kPanel * q + t % kPanel;
+        dsh[q][t % kPanel] = (q < npan && k >= 0 && k < S.n) ? Fs[(int64_t)k * ld] : make_double2(0.0, 0.0);
+    }
+    // A(j, k) = l_jk (column j of C, lane row j), B(k, i) = l_ik; every row
+    // here lies below the panels (j, i >= w0 > k), so only the band limits
+    // the entries read.
+    const int jr = w0 + 16 * cw + (lane & 15);
+    const int ir = i0 + 16 * rw + (lane & 15);
+    double2 la[kPanel / 4], lb[kPanel / 4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int q = 0; q < kPanel / 4; ++q) {
+        const int k = kp + 4 * q + (lane >> 4);
+        la[q] = act && jr < cend && jr - k <= S.bw ? Fs[(int64_t)k * ld + (jr - k)] : make_double2(0.0, 0.0);
+        lb[q] = act && ir < wend && ir - k <= S.bw ? Fs[(int64_t)k * ld + (ir - k)] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    mfma_f64x4 cre = {0.0, 0.0, 0.0, 0.0}, cim = {0.0, 0.0, 0.0, 0.0};
+    if (act) {
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = make_double2(0.0, 0.0);
-    for (int pp = 0; pp < npan; ++pp) {
-        const int kp = k0 - kPanel * pp;
-        if (kp < 0) break;
-        if (pp > 0) __syncthreads();
-        for (int idx = threadIdx.x; idx < 32 * kPanel; idx += 256) {
-            const int r = idx / kPanel, kk = idx - r * kPanel;
-            const int k = kp + kk;
-            const int i = i0 + r, j = w0 + r;
-            double2 wi = make_double2(0.0, 0.0), wj = make_double2(0.0, 0.0);
-            if (i < wend && i - k <= S.bw) wi = Fs[(int64_t)k * ld + (i - k)];
-            if (j < cend && j - k <= S.bw) wj = cmul(Fs[(int64_t)k * ld + (j - k)], Fs[(int64_t)k * ld]);
-            Wi[r][kk] = wi;
-            Wj[r][kk] = wj;
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int kk = 0; kk < kPanel; ++kk) {
-            const double2 wi0 = Wi[2 * tr][kk], wi1 = Wi[2 * tr + 1][kk];
-            const double2 wj0 = Wj[tc][kk], wj1 = Wj[tc + 16][kk];
-            const double2 wi[2] = {wi0, wi1}, wj[2] = {wj0, wj1};
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    acc[a][b].x = fma(wi[a].x, wj[b].x, fma(-wi[a].y, wj[b].y, acc[a][b].x));
-                    acc[a][b].y = fma(wi[a].x, wj[b].y, fma(wi[a].y, wj[b].x, acc[a][b].y));
-                }
+        for (int q = 0; q < kPanel / 4; ++q) {
+            const double2 a = cmul(la[q], dsh[pp][4 * q + (lane >> 4)]);
+            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, lb[q].x, cre, 0, 0, 0);
+            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, lb[q].y, cre, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, lb[q].y, cim, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, lb[q].x, cim, 0, 0, 0);
         }
     }
+    if (pp == 1) {
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        const int j = w0 + tc + 16 * b;
-        if (j >= cend) continue;
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const int i = i0 + 2 * tr + a;
-            if (i >= wend || i < j) continue;
-            double2& c = Fs[(int64_t)j * ld + (i - j)];
-            c.x -= acc[a][b].x;
-            c.y -= acc[a][b].y;
+        for (int v = 0; v < 4; ++v) {
+            part[sub][0][v][lane] = cre[v];
+            part[sub][1][v][lane] = cim[v];
         }
+    }
+    __syncthreads();
+    if (pp == 1) return;
+    // register v of lane l: j = 16 cw + l / 16 + 4 v, i = 16 rw + l % 16
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int j = w0 + 16 * cw + (lane >> 4) + 4 * v;
+        if (j >= cend || ir >= wend || ir < j) continue;
+        double2& c = Fs[(int64_t)j * ld + (ir - j)];
+        c.x -= cre[v] + part[sub][0][v][lane];
+        c.y -= cim[v] + part[sub][1][v][lane];
     }
 }
 
@@ -1318,7 +1341,7 @@ hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int 
             }
             return e1 ? hipEventRecord(e1, s) : hipSuccess;
         }
-        hipExtLaunchKernelGGL(k_band_strip, dim3(T, nsys), dim3(256), 0, s, e0, e1, 0, sys, F, k0, k0 >= kPanel ? 2 : 1);
+        hipExtLaunchKernelGGL(k_band_strip, dim3(T, nsys), dim3(512), 0, s, e0, e1, 0, sys, F, k0, k0 >= kPanel ? 2 : 1);
         return hipGetLastError();
     }
     int c0 = w0, c1 = w0 + bwmax, strip = 0, npan = 1;
