@@ -683,13 +683,17 @@ class Solver {
                 HIPCHK(band_panel(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, flags.get(), s_, ea, eb));
                 if (k0 + kPanel < nmax) {
                     if (steps >= 2) HIPCHK(hipStreamWaitEvent(s_, ev_rest_[steps & 1], 0));
+                    // The cross-stream events ride on the dispatches (no marker
+                    // packet of their own) unless the timer holds that launch.
                     tm_.kernel_pair(T_BAND_NEXT, ea, eb);
-                    HIPCHK(band_update(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, 1, s_, ea, eb));
-                    HIPCHK(hipEventRecord(ev_panel_, s_));
+                    HIPCHK(band_update(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, 1, s_, ea,
+                                       eb ? eb : ev_panel_));
+                    if (eb) HIPCHK(hipEventRecord(ev_panel_, s_));
                     HIPCHK(hipStreamWaitEvent(s2_, ev_panel_, 0));
                     tm_.kernel_pair(T_BAND_UPDATE, ea, eb);
-                    HIPCHK(band_update(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, 2, s2_, ea, eb));
-                    HIPCHK(hipEventRecord(ev_rest_[steps & 1], s2_));
+                    HIPCHK(band_update(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, 2, s2_, ea,
+                                       eb ? eb : ev_rest_[steps & 1]));
+                    if (eb) HIPCHK(hipEventRecord(ev_rest_[steps & 1], s2_));
                 }
             }
             if (steps >= 2) {
