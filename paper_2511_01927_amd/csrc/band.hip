@@ -297,8 +297,9 @@ __global__ __launch_bounds__(256) void k_band_update(const BandSys* __restrict__
     const int ld = S.bw + 1;
     const double2* Fs = F + S.off;   // panel columns (read) and window columns (written) of one band
     // FP64 matrix cores: wave w owns the tile's 16-column block w and all
-    // four 16-row blocks; per 4-deep K step one B operand (W_j) serves four
-    // complex products (four v_mfma_f64_16x16x4 each).  Operand layouts
+    // four 16-row blocks; per 4-deep K step one A operand (W_j) serves four
+    // complex products (four v_mfma_f64_16x16x4 each), formed transposed so
+    // that the read-modify-write of C is coalesced.  Operand layouts
     // (lane l): A(i, k) at i = l % 16, k = l / 16; B(k, j) at k = l / 16,
     // j = l % 16; result register v is D(l / 16 + 4 v, l % 16).
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -313,7 +314,7 @@ __global__ __launch_bounds__(256) void k_band_update(const BandSys* __restrict__
         if (kp < 0) break;
         if (pp > 0) __syncthreads();
         for (int idx = threadIdx.x; idx < 64 * kPanel; idx += blockDim.x) {
-            const int r = idx / kPanel, kk = idx - r * kPanel;
+            const int r = idx & 63, kk = idx >> 6;   // lanes run down a band column
             const int k = kp + kk;
             const int i = i0 + r, j = j0 + r;
             double2 wi = make_double2(0.0, 0.0), wj = make_double2(0.0, 0.0);
@@ -326,27 +327,28 @@ __global__ __launch_bounds__(256) void k_band_update(const BandSys* __restrict__
 #pragma unroll
         for (int st = 0; st < kPanel / 4; ++st) {
             const int kk = 4 * st + (lane >> 4);
-            const double2 b = Wj[wave * 16 + (lane & 15)][kk];
+            const double2 a = Wj[wave * 16 + (lane & 15)][kk];
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb) {
-                const double2 a = Wi[rb * 16 + (lane & 15)][kk];
-                // P += W_i W_j^T (complex): re = a.x b.x - a.y b.y, im = a.x b.y + a.y b.x
+                const double2 b = Wi[rb * 16 + (lane & 15)][kk];
+                // P^T += W_j W_i^T (complex): re = a.x b.x - a.y b.y, im = a.x b.y + a.y b.x
                 pre[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, pre[rb], 0, 0, 0);
-                pre[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, -b.y, pre[rb], 0, 0, 0);
+                pre[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, pre[rb], 0, 0, 0);
                 pim[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, pim[rb], 0, 0, 0);
                 pim[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, pim[rb], 0, 0, 0);
             }
         }
     }
+    // register v of lane l of row block rb: column j = 16 wave + l / 16 + 4 v,
+    // row i = 16 rb + l % 16 (lanes run down a column of C)
     double2* Fw = F + S.off;
-    const int j = j0 + wave * 16 + (lane & 15);
-    if (j >= cend) return;
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int i = i0 + rb * 16 + (lane >> 4) + 4 * v;
-            if (i >= wend || i < j) continue;
+            const int j = j0 + wave * 16 + (lane >> 4) + 4 * v;
+            const int i = i0 + rb * 16 + (lane & 15);
+            if (j >= cend || i >= wend || i < j) continue;
             double2& c = Fw[(int64_t)j * ld + (i - j)];
             c.x -= pre[rb][v];
             c.y -= pim[rb][v];
