@@ -64,13 +64,13 @@ TRAFFIC = [
         "workload": "q1_2d_300",
         "precision": "fp64",
         "sources_sha256": {
-            "paper_2511_01927_amd/csrc/band.hip": "d23744b33f08056a9e410e23fdaadf603689a0dd09fa8feeb1b4204d07a931c2",
+            "paper_2511_01927_amd/csrc/band.hip": "99fb3ebf7a325f050592fca28e7748a3d86d82b64240b727ab75b4dedf91e18b",
             "paper_2511_01927_amd/csrc/internal.h": "ae891c2b4dae34136c3ed5abdca25bbfe2e22d05efb54a0029d384d680705d18",
         },
         # bytes per launch (per timed bracket for band_solve: right-hand sides,
         # forward and backward sweep)
-        "per_launch_bytes": {"band_update": 9.608043e+07, "band_update_next": 6.397313e+07,
-                             "band_panel": 2.041042e+07, "band_solve": 8.699095e+10},
+        "per_launch_bytes": {"band_update": 9.613465e+07, "band_update_next": 6.408333e+07,
+                             "band_panel": 2.045190e+07, "band_solve": 8.696773e+10},
         "profile": "profiles/band_q1_300x300_fp64_hbm_traffic.md",
     },
 ]
