@@ -64,13 +64,13 @@ TRAFFIC = [
         "workload": "q1_2d_300",
         "precision": "fp64",
         "sources_sha256": {
-            "paper_2511_01927_amd/csrc/band.hip": "99fb3ebf7a325f050592fca28e7748a3d86d82b64240b727ab75b4dedf91e18b",
+            "paper_2511_01927_amd/csrc/band.hip": "204b92569fbda54b3a3c695bf37398235d027bda2589061c573d553983884e1c",
             "paper_2511_01927_amd/csrc/internal.h": "ae891c2b4dae34136c3ed5abdca25bbfe2e22d05efb54a0029d384d680705d18",
         },
         # bytes per launch (per timed bracket for band_solve: right-hand sides,
         # forward and backward sweep)
-        "per_launch_bytes": {"band_update": 9.613465e+07, "band_update_next": 6.408333e+07,
-                             "band_panel": 2.045190e+07, "band_solve": 8.696773e+10},
+        "per_launch_bytes": {"band_update": 9.613204e+07, "band_update_next": 6.408169e+07,
+                             "band_panel": 2.045193e+07, "band_solve": 8.697368e+10},
         "profile": "profiles/band_q1_300x300_fp64_hbm_traffic.md",
     },
 ]
@@ -241,8 +241,11 @@ def main():
             "band_update_next": ("alu", st["band_update_next_flops"]),
             "band_panel": ("alu", st["band_panel_flops"]),
             "band_solve": ("alu", st["band_solve_flops"])}
-    # dominant kernel by measured time
-    dom = max(spec, key=lambda k: km.get(k, 0.0))
+    # dominant kernel by measured time.  The panel's HIP events also bracket
+    # the dispatch gap behind the strip before it (about 46 us per launch
+    # against 30 us of kernel time in a rocprofv3 kernel trace), so the panel
+    # does not take part in the choice; its event figure stays under "kernels".
+    dom = max((k for k in spec if k != "band_panel"), key=lambda k: km.get(k, 0.0))
 
     def roof(name):
         bound, work = spec[name]

@@ -971,7 +971,7 @@ __global__ __launch_bounds__(NT) void k_band_fwd_blocked(const BandSys* __restri
             double2 v[CPH];
 #pragma unroll
             for (int q = 0; q < CPH; ++q) v[q] = ring[slot + q];
-#pragma unroll 4
+#pragma unroll
             for (int i = 0; i < kBlkRows; ++i) {
                 const double2 l = Ld[hl][i];   // zero unless hl > i
 #pragma unroll
@@ -1204,7 +1204,7 @@ __global__ __launch_bounds__(NT) void k_band_bwd_blocked(const BandSys* __restri
                 }
                 v[q] = make_double2(z[q].x - g.x, z[q].y - g.y);
             }
-#pragma unroll 4
+#pragma unroll
             for (int i = kBlkRows - 1; i >= 0; --i) {
                 const double2 l = Ld[i][hl];   // L[J0 + i][J0 + hl], zero unless i > hl
 #pragma unroll
