@@ -16,7 +16,9 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -47,31 +49,113 @@ struct Fail {
     throw Fail{code};
 }
 
-// RAII device buffer
+// Device workspace kept by a packed pencil across its solves.  A solve of
+// the same shapes as an earlier one then takes every buffer from here instead
+// of calling hipMalloc / hipFree (tens of GB per solve on the 2D headline,
+// whose per-solve allocation made the solve time erratic).  A buffer handed
+// back is first made idle with a device synchronisation, the same wait that
+// hipFree performs, so a later solve can never reuse memory that queued work
+// still touches.  Blocks are matched best-fit within 25% of the request;
+// when hipMalloc runs out of memory the idle blocks are freed and the
+// allocation retried.
+struct DevPool {
+    std::mutex mu;
+    std::multimap<size_t, void*> idle;   // capacity in bytes -> block
+    size_t idle_bytes = 0;
+    long reused = 0, allocated = 0;
+    void* take(size_t bytes, size_t& cap) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto it = idle.lower_bound(bytes);
+            if (it != idle.end() && it->first <= bytes + bytes / 4 + 4096) {
+                void* q = it->second;
+                cap = it->first;
+                idle_bytes -= it->first;
+                idle.erase(it);
+                ++reused;
+                return q;
+            }
+        }
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, bytes);
+        if (e == hipErrorOutOfMemory) {
+            (void)hipGetLastError();
+            trim();
+            e = hipMalloc(&q, bytes);
+        }
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(e == hipErrorOutOfMemory ? GEP_ENOMEM : GEP_EDEVICE,
+                 "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+        }
+        cap = bytes;
+        std::lock_guard<std::mutex> lk(mu);
+        ++allocated;
+        return q;
+    }
+    void give(void* q, size_t cap) {
+        (void)hipDeviceSynchronize();
+        std::lock_guard<std::mutex> lk(mu);
+        idle.emplace(cap, q);
+        idle_bytes += cap;
+    }
+    void trim() {
+        (void)hipDeviceSynchronize();
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto& kv : idle) (void)hipFree(kv.second);
+        idle.clear();
+        idle_bytes = 0;
+    }
+    ~DevPool() { trim(); }
+};
+
+// Pool that DBuf allocations of the calling thread use (set for the duration
+// of a solve on a packed pencil; null: plain hipMalloc / hipFree).
+static thread_local DevPool* t_pool = nullptr;
+struct PoolScope {
+    DevPool* prev;
+    explicit PoolScope(DevPool* p) : prev(t_pool) { t_pool = p; }
+    ~PoolScope() { t_pool = prev; }
+};
+
+// RAII device buffer (from the thread's current pool when one is set)
 template <typename T>
 struct DBuf {
     T* p = nullptr;
     size_t n = 0;
+    DevPool* pool = nullptr;
+    size_t cap = 0;
     DBuf() = default;
     explicit DBuf(size_t count) { alloc(count); }
     void alloc(size_t count) {
         release();
         n = count;
-        if (count) {
-            hipError_t e = hipMalloc(&p, count * sizeof(T));
-            if (e != hipSuccess) {
-                p = nullptr;
-                (void)hipGetLastError();
-                fail(e == hipErrorOutOfMemory ? GEP_ENOMEM : GEP_EDEVICE,
-                     "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed: " +
-                         hipGetErrorString(e));
-            }
+        if (!count) return;
+        if (t_pool) {
+            pool = t_pool;
+            p = static_cast<T*>(pool->take(count * sizeof(T), cap));
+            return;
+        }
+        hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            fail(e == hipErrorOutOfMemory ? GEP_ENOMEM : GEP_EDEVICE,
+                 "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed: " +
+                     hipGetErrorString(e));
         }
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (pool)
+                pool->give(p, cap);
+            else
+                (void)hipFree(p);
+        }
         p = nullptr;
+        pool = nullptr;
         n = 0;
+        cap = 0;
     }
     ~DBuf() { release(); }
     DBuf(const DBuf&) = delete;
@@ -248,7 +332,23 @@ struct gep_pencil {
     HostPencil h;
     DevPencil d;
     std::vector<void*> owned;
+    gep::DevPool pool;   // solve workspace kept between solves
+    // second stream and events of the band factorisation's lookahead and the
+    // pinned read-back words of the COCG loop, created on first use and kept
+    // for later solves
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_panel = nullptr, ev_rest[2] = {nullptr, nullptr};
+    int32_t* counts_h = nullptr;
     ~gep_pencil() {
+        if (aux) {
+            (void)hipStreamSynchronize(aux);
+            (void)hipStreamDestroy(aux);
+        }
+        if (ev_panel) (void)hipEventDestroy(ev_panel);
+        for (hipEvent_t e : ev_rest)
+            if (e) (void)hipEventDestroy(e);
+        if (counts_h) (void)hipHostFree(counts_h);
+        pool.trim();
         for (void* p : owned) (void)hipFree(p);
     }
 };
@@ -586,17 +686,11 @@ class Solver {
         // thousands of short factorisation launches: time one in 16 (the
         // event pairs would otherwise add to the gaps between launches)
         tm_.stride[T_BAND_PANEL] = tm_.stride[T_BAND_NEXT] = tm_.stride[T_BAND_UPDATE] = 16;
-        HIPCHK(hipHostMalloc((void**)&counts_h_, sizeof(int32_t) * 4, 0));
+        if (!P_->counts_h) HIPCHK(hipHostMalloc((void**)&P_->counts_h, sizeof(int32_t) * 4, 0));
+        counts_h_ = P_->counts_h;
     }
     ~Solver() {
-        if (counts_h_) (void)hipHostFree(counts_h_);
-        if (s2_) {
-            (void)hipStreamSynchronize(s2_);
-            (void)hipStreamDestroy(s2_);
-        }
-        if (ev_panel_) (void)hipEventDestroy(ev_panel_);
-        for (hipEvent_t e : ev_rest_)
-            if (e) (void)hipEventDestroy(e);
+        if (s2_) (void)hipStreamSynchronize(s2_);
         if (own_) {
             (void)hipStreamSynchronize(own_);
             (void)hipStreamDestroy(own_);
@@ -672,10 +766,13 @@ class Solver {
             // the next two panel steps.  The rest of step k writes the columns
             // of panel k + 3, so the strip update of step k + 2 waits for it;
             // concurrent launches touch disjoint columns.
-            if (!s2_) HIPCHK(hipStreamCreateWithFlags(&s2_, hipStreamNonBlocking));
-            if (!ev_panel_) HIPCHK(hipEventCreateWithFlags(&ev_panel_, hipEventDisableTiming));
-            for (hipEvent_t& e : ev_rest_)
+            if (!P_->aux) HIPCHK(hipStreamCreateWithFlags(&P_->aux, hipStreamNonBlocking));
+            if (!P_->ev_panel) HIPCHK(hipEventCreateWithFlags(&P_->ev_panel, hipEventDisableTiming));
+            for (hipEvent_t& e : P_->ev_rest)
                 if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            s2_ = P_->aux;
+            hipEvent_t ev_panel_ = P_->ev_panel;
+            hipEvent_t* ev_rest_ = P_->ev_rest;
             int steps = 0;
             for (int64_t k0 = 0; k0 < nmax; k0 += kPanel, ++steps) {
                 hipEvent_t ea, eb;
@@ -1286,8 +1383,7 @@ class Solver {
     DevPencil dv_;   // the pencil with the row-group view of this solve
     // banded factors of the last pass and the (problem, z) list they belong to
     std::unique_ptr<DBuf<double2>> band_F_;
-    hipStream_t s2_ = nullptr;           // second stream of the factorisation (lookahead)
-    hipEvent_t ev_panel_ = nullptr, ev_rest_[2] = {nullptr, nullptr};
+    hipStream_t s2_ = nullptr;           // second stream of the factorisation (the pencil's)
     std::vector<double> band_keys_;
     hipStream_t s_ = nullptr;
     hipStream_t own_ = nullptr;
@@ -1371,6 +1467,7 @@ static std::string json_stats(const Solver& s, double wall_ms, const std::vector
 static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* const* contours,
                             const int* n_contours, const SolveCfg& cfg, gep_result** out) {
     auto t0 = std::chrono::steady_clock::now();
+    PoolScope pool_scope(&P->pool);
     const HostPencil& H = P->h;
     const int64_t ntot = P->d.n;
     auto svp = std::make_unique<Solver>(P, cfg);
@@ -1413,7 +1510,9 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
         }
     size_t freeb = 0, totalb = 0;
     HIPCHK(hipMemGetInfo(&freeb, &totalb));
-    const double budget = cfg.o.mem_limit_bytes > 0 ? cfg.o.mem_limit_bytes : 0.85 * (double)freeb;
+    // memory the pencil's idle workspace holds is available to this solve
+    const double budget = cfg.o.mem_limit_bytes > 0 ? cfg.o.mem_limit_bytes
+                                                    : 0.85 * (double)(freeb + P->pool.idle_bytes);
     const bool mixed = cfg.o.precision == GEP_MIXED;
     std::vector<ContourOut> finals(all.size());
     // jobs ordered by block size so that equal sizes share waves
@@ -1565,7 +1664,10 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
         bool noconv = false;
         size_t kept = 0;
         for (size_t a = 0; a < pairs.size(); ++a) kept += !drop[a];
-        if (kept) R->dvecs = std::make_unique<DBuf<double>>((size_t)n * kept);
+        if (kept) {
+            PoolScope own(nullptr);   // the result outlives the pencil's workspace
+            R->dvecs = std::make_unique<DBuf<double>>((size_t)n * kept);
+        }
         size_t idx = 0;
         for (size_t a = 0; a < pairs.size(); ++a) {
             if (drop[a]) continue;
