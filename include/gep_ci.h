@@ -217,6 +217,19 @@ int gep_spmm_real(const gep_pencil* p, const double* X, int64_t k, int64_t ld, d
 int gep_gram(const double* X, int64_t ld1, const double* Y, int64_t ld2, int64_t n, int64_t k1,
              int64_t k2, double* G, void* stream);
 
+/* gep_gram without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results as gep_gram; the split-K
+ * partial tiles go to a static device array of the library, 8 Mi doubles
+ * (64 MiB) per GPU, held until the process ends.  GEP_EINVAL, with a message,
+ * when the partials of (n, k1, k2) need more than that (gep_gram plans
+ * splits * k1 * k2 doubles, about 4 Mi for k1, k2 <= 1024 and at most
+ * k1 * k2 beyond).  All calls on one GPU share the array: calls that overlap
+ * on one GPU (other streams or threads) race and must be serialised by the
+ * caller.  The stream is synchronised before the call returns. */
+int gep_gram_noalloc(const double* X, int64_t ld1, const double* Y, int64_t ld2, int64_t n,
+                     int64_t k1, int64_t k2, double* G, void* stream);
+
 /* C = X T for row-major X (n x k, ldx), T (k x m, row-major, ldt), C (n x m, ldc);
  * FP64 MFMA. */
 int gep_gemm_tall(const double* X, int64_t ldx, const double* T, int64_t ldt, int64_t n, int64_t k,

@@ -7,6 +7,8 @@
 // and holding D[(l / 16) + 4 v][l % 16] in accumulator element v.
 #include "internal.h"
 
+#include <mutex>
+
 namespace gep {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -115,6 +117,46 @@ hipError_t launch_gram(const double* X, int64_t ld1, const double* Y, int64_t ld
     hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, s, work,
                        splits, elems, G);
     return hipGetLastError();
+}
+
+// ---- allocation-free Gram (gep_gram_noalloc) --------------------------------
+// The split-K partial tiles of k_gram normally live in a buffer allocated per
+// call.  For callers that cannot allocate, they go to this file-scope device
+// array instead: kGramScratchElems doubles (64 MiB) per GPU, held from module
+// load until the process ends.  Its host-side name is only a stand-in for the
+// symbol; kernels get the device address that hipGetSymbolAddress returns,
+// looked up once per device with that device current.  Every call on one GPU
+// shares the array: calls that overlap on one GPU (different streams or
+// threads) race on it.  Each call overwrites every partial it later sums, so
+// nothing has to be cleared between calls.
+constexpr size_t kGramScratchElems = size_t(8) << 20;
+static __device__ __align__(256) double scratch[kGramScratchElems];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+size_t gram_scratch_elems() { return kGramScratchElems; }
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device).
+hipError_t gram_scratch(double** ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 // ---- tall GEMM: C = X T, X n x k (ldx), T k x m (ldt), C n x m (ldc) -----

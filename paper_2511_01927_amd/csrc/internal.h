@@ -216,6 +216,10 @@ hipError_t launch_gram(const double* X, int64_t ld1, const double* Y, int64_t ld
                        int64_t k1, int64_t k2, double* G, double* work, size_t work_elems,
                        hipStream_t s);
 size_t gram_work_elems(int64_t n, int64_t k1, int64_t k2);
+// Allocation-free Gram: device address of the library's static partial-tile
+// array on the current device, and its size in doubles.
+hipError_t gram_scratch(double** ptr);
+size_t gram_scratch_elems();
 hipError_t launch_gemm_tall(const double* X, int64_t ldx, const double* T, int64_t ldt, int64_t n,
                             int64_t k, int64_t m, double* C, int64_t ldc, hipStream_t s);
 // Batched symmetric eigensolver; matrix b is ks[b] x ks[b] (row-major, leading

@@ -2030,6 +2030,28 @@ int gep_gram(const double* X, int64_t ld1, const double* Y, int64_t ld2, int64_t
     return GEP_OK;
 }
 
+int gep_gram_noalloc(const double* X, int64_t ld1, const double* Y, int64_t ld2, int64_t n,
+                     int64_t k1, int64_t k2, double* G, void* stream) {
+    if (!X || !Y || !G || n < 0 || k1 <= 0 || k2 <= 0 || ld1 < k1 || ld2 < k2) { gep::set_error("bad gram arguments"); return GEP_EINVAL; }
+    const size_t we = gep::gram_work_elems(n, k1, k2);
+    if (we > gep::gram_scratch_elems()) {
+        gep::set_error("gep_gram_noalloc: the split-K partials need " + std::to_string(we) +
+                       " doubles, more than the " + std::to_string(gep::gram_scratch_elems()) +
+                       " of the library's static scratch (use gep_gram)");
+        return GEP_EINVAL;
+    }
+    try {
+        double* work = nullptr;
+        HIPCHK(gep::gram_scratch(&work));
+        HIPCHK(gep::launch_gram(X, ld1, Y, ld2, n, k1, k2, G, work, gep::gram_scratch_elems(),
+                                (hipStream_t)stream));
+        HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    } catch (const gep::Fail& f) {
+        return f.code;
+    }
+    return GEP_OK;
+}
+
 int gep_gemm_tall(const double* X, int64_t ldx, const double* T, int64_t ldt, int64_t n, int64_t k,
                   int64_t m, double* C, int64_t ldc, void* stream) {
     if (!X || !T || !C || n < 0 || k <= 0 || m <= 0 || ldx < k || ldt < m || ldc < m) { gep::set_error("bad gemm arguments"); return GEP_EINVAL; }

@@ -53,7 +53,8 @@ EXPORTS = [
     "gep_opts_default", "gep_ci_solve", "gep_result_count", "gep_result_copy",
     "gep_result_stats", "gep_result_free", "gep_strerror", "gep_last_error",
     "gep_pencil_create", "gep_pencil_free", "gep_pencil_info", "gep_ci_solve_pencil",
-    "gep_spmm_shifted", "gep_spmm_shifted_f32", "gep_spmm_real", "gep_gram", "gep_gemm_tall",
+    "gep_spmm_shifted", "gep_spmm_shifted_f32", "gep_spmm_real", "gep_gram", "gep_gram_noalloc",
+    "gep_gemm_tall",
     "gep_sym_eig", "gep_gaussian_block", "gep_ci_solve_batch", "gep_kde_contours",
     "gep_density_create", "gep_density_free", "gep_density_forward", "gep_density_grads",
     "gep_density_adam", "gep_density_param", "gep_gemm_bf16",
@@ -91,6 +92,7 @@ def load():
         "gep_spmm_shifted_f32": (i32, [P, P, P, P, i64, P]),
         "gep_spmm_real": (i32, [P, P, i64, i64, P, P, P]),
         "gep_gram": (i32, [P, i64, P, i64, i64, i64, i64, P, P]),
+        "gep_gram_noalloc": (i32, [P, i64, P, i64, i64, i64, i64, P, P]),
         "gep_gemm_tall": (i32, [P, i64, P, i64, i64, i64, i64, P, i64, P]),
         "gep_sym_eig": (i32, [P, P, P, i64, i32, P]),
         "gep_gaussian_block": (i32, [C.c_uint64, i64, i64, P, P]),
@@ -327,6 +329,11 @@ def gep_spmm_real(pencil: Pencil, X, k: int, ld: int, YA=None, YB=None, stream=N
 def gep_gram(X, ld1, Y, ld2, n, k1, k2, G, stream=None):
     _check(load().gep_gram(X.data_ptr(), ld1, Y.data_ptr(), ld2, n, k1, k2, G.data_ptr(),
                            _stream_ptr(stream)))
+
+
+def gep_gram_noalloc(X, ld1, Y, ld2, n, k1, k2, G, stream=None):
+    _check(load().gep_gram_noalloc(X.data_ptr(), ld1, Y.data_ptr(), ld2, n, k1, k2, G.data_ptr(),
+                                   _stream_ptr(stream)))
 
 
 def gep_gemm_tall(X, ldx, T, ldt, n, k, m, Cm, ldc, stream=None):
