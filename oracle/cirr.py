@@ -24,7 +24,8 @@ zeta^m = ((z - c)/R)^m instead of raw z^m (same span, better conditioned),
 real Gaussian V shared by all contours, residual
 ||A x - lambda B x||_2 / (||A||_inf ||x||_2), half-open keep windows,
 refinement V <- all Ritz vectors with one moment, sign: largest-|.| entry
-positive.
+positive (ties within 1e-8 relative go to the lowest index), duplicates
+across contours merged by value cluster and B-projection.
 """
 from __future__ import annotations
 
@@ -149,10 +150,21 @@ def rayleigh_ritz(A, B, Q):
     return theta, Q @ U
 
 
+SIGN_TIE = 1e-8
+
+
 def _normalise(X: np.ndarray, B) -> np.ndarray:
-    """B-normalise each column and make its largest-|.| entry (lowest index on ties) positive."""
+    """B-normalise each column and make its largest-|.| entry positive.
+
+    Entries whose modulus is within a relative SIGN_TIE of the column's
+    largest count as tied, and the lowest index among them decides the sign:
+    eigenvectors of mirror-symmetric pencils have pairs of entries of exactly
+    equal modulus, which rounding would otherwise order at random.
+    """
     X = X / np.sqrt(np.einsum("ij,ij->j", X, B @ X))[None, :]
-    idx = np.argmax(np.abs(X), axis=0)
+    a = np.abs(X)
+    top = a.max(axis=0)
+    idx = np.argmax(a >= (1.0 - SIGN_TIE) * top[None, :], axis=0)
     sgn = np.sign(X[idx, np.arange(X.shape[1])])
     sgn[sgn == 0] = 1.0
     return X * sgn[None, :]
@@ -178,24 +190,43 @@ def _solve_contour(A, B, V0, c, R, lo, hi, N, M, tol, max_refine, rank_tol, work
 
 
 def dedupe(lam, X, rho, cid, B, rel: float = 1e-8, overlap: float = 0.9):
-    """Merge pairs found by different contours: same value within rel*|lambda| and
-    |x_a^T B x_b| >= overlap; the pair with the smaller residual is kept."""
+    """Merge the pairs that several contours found for the same eigenvalue.
+
+    Values are grouped into clusters (ascending, consecutive values within
+    rel * |lambda| of each other).  In a cluster holding pairs of several
+    contours, the contour whose cluster pairs have the smallest worst
+    residual (lowest id on ties) keeps all of them; the other contours' pairs
+    follow in ascending residual, and a pair is dropped when its B-orthogonal
+    projection onto the span of the pairs kept so far has B-norm >= overlap
+    times its own (it repeats an eigenvector already returned).  Pairs of one
+    contour are never merged with each other: an exact multiple eigenvalue
+    keeps all its vectors.
+    """
     order = np.argsort(lam, kind="stable")
     lam, X, rho, cid = lam[order], X[:, order], rho[order], cid[order]
-    drop = np.zeros(lam.size, dtype=bool)
+    keep = np.ones(lam.size, dtype=bool)
     BX = B @ X
-    for a in range(lam.size):
-        if drop[a]:
-            continue
-        for b in range(a + 1, lam.size):
-            if lam[b] - lam[a] > rel * max(abs(lam[a]), abs(lam[b])):
-                break
-            if drop[b] or cid[b] == cid[a]:
-                continue
-            if abs(X[:, a] @ BX[:, b]) >= overlap:
-                drop[b if rho[b] >= rho[a] else a] = True
-    k = ~drop
-    return lam[k], X[:, k], rho[k], cid[k]
+    start = 0
+    while start < lam.size:
+        end = start + 1
+        while end < lam.size and lam[end] - lam[end - 1] <= rel * max(abs(lam[end]), abs(lam[end - 1])):
+            end += 1
+        idx = np.arange(start, end)
+        owners = sorted(set(cid[idx].tolist()), key=lambda k: (rho[idx][cid[idx] == k].max(), k))
+        if len(owners) > 1:
+            kept = [int(i) for i in idx if cid[i] == owners[0]]
+            for k in owners[1:]:
+                mine = sorted((int(i) for i in idx if cid[i] == k), key=lambda i: (rho[i], i))
+                for i in mine:
+                    G = X[:, kept].T @ BX[:, kept]
+                    b = X[:, kept].T @ BX[:, i]
+                    proj2 = float(b @ np.linalg.solve(G, b))
+                    if proj2 >= overlap ** 2 * float(X[:, i] @ BX[:, i]):
+                        keep[i] = False
+                    else:
+                        kept.append(i)
+        start = end
+    return lam[keep], X[:, keep], rho[keep], cid[keep]
 
 
 def oracle_ci_solve(A, B, contours, n_nodes: int, moments: int, block: int, tol: float = 1e-8,
