@@ -24,7 +24,7 @@ zeta^m = ((z - c)/R)^m instead of raw z^m (same span, better conditioned),
 real Gaussian V shared by all contours, residual
 ||A x - lambda B x||_2 / (||A||_inf ||x||_2), half-open keep windows,
 refinement V <- all Ritz vectors with one moment, sign: largest-|.| entry
-positive (ties within 1e-8 relative go to the lowest index), duplicates
+positive (ties within 1e-4 relative go to the lowest index), duplicates
 across contours merged by value cluster and B-projection.
 """
 from __future__ import annotations
@@ -150,7 +150,7 @@ def rayleigh_ritz(A, B, Q):
     return theta, Q @ U
 
 
-SIGN_TIE = 1e-8
+SIGN_TIE = 1e-4
 
 
 def _normalise(X: np.ndarray, B) -> np.ndarray:
@@ -159,7 +159,9 @@ def _normalise(X: np.ndarray, B) -> np.ndarray:
     Entries whose modulus is within a relative SIGN_TIE of the column's
     largest count as tied, and the lowest index among them decides the sign:
     eigenvectors of mirror-symmetric pencils have pairs of entries of exactly
-    equal modulus, which rounding would otherwise order at random.
+    equal modulus, which the errors of a computed eigenvector (about the
+    residual over the spectral gap, 1e-7 for pairs accepted at residual
+    1e-8) would otherwise order at random.
     """
     X = X / np.sqrt(np.einsum("ij,ij->j", X, B @ X))[None, :]
     a = np.abs(X)

@@ -155,7 +155,7 @@ def _sine_with_sign_rule(n, j, B):
     v = np.sin(i * j * np.pi / (n + 1))
     v /= np.sqrt(v @ (B @ v))
     a = np.abs(v)
-    first = int(np.nonzero(a >= (1 - 1e-8) * a.max())[0][0])
+    first = int(np.nonzero(a >= (1 - 1e-4) * a.max())[0][0])
     return v * np.sign(v[first])
 
 
@@ -177,9 +177,9 @@ def test_sign_rule_breaks_mirror_ties_by_lowest_index():
     top = np.flatnonzero(np.abs(v) >= np.abs(v).max() * (1 - 1e-12))
     assert top.size == 2
     lo, hi = top
-    for bump in (1 + 1e-14, 1 - 1e-14):
+    for bump in (1 + 1e-7, 1 - 1e-7):
         u = v.copy()
-        u[hi] *= bump                              # rounding picks either entry as the max
+        u[hi] *= bump                  # a computed vector's error picks either entry as the max
         out = cirr._normalise(u[:, None], B)[:, 0]
         assert out[lo] > 0
 
