@@ -203,6 +203,19 @@ int gep_ci_solve_pencil(gep_pencil* p, const gep_contour* contours, int n_contou
 int gep_spmm_shifted(const gep_pencil* p, const double* shifts, const double* X, double* Y,
                      int64_t W, double* pq, void* stream);
 
+/* The direction step that opens every iteration of the batched COCG solve
+ * of the shifted systems (quadrature equation's operator K_c = z_c B - A,
+ * Jacobi-preconditioned residual U): Pn[:, c] = U[:, c] + beta_c P[:, c] and
+ * pq[c] = sum_i Pn[i, c] (K_c Pn)[i, c] (bilinear, no conjugation); K_c Pn
+ * itself is not stored.  Same tiled FP64 complex layout as
+ * gep_spmm_shifted; shifts, beta and pq: W interleaved complex doubles;
+ * all pointers device.  row_group 4 walks groups of 4 rows sharing their
+ * neighbour gathers (the pencil's 4-row form), 1 plain CSR rows: the
+ * results agree to rounding.  GEP_EINVAL for other values. */
+int gep_cocg_direction(const gep_pencil* p, const double* shifts, const double* beta,
+                       const double* U, const double* P, double* Pn, int64_t W, double* pq,
+                       int row_group, void* stream);
+
 /* FP32 complex variant of gep_spmm_shifted (shifts stay FP64 complex). */
 int gep_spmm_shifted_f32(const gep_pencil* p, const double* shifts, const float* X, float* Y,
                          int64_t W, void* stream);

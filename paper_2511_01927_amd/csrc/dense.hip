@@ -591,6 +591,12 @@ hipError_t launch_resid_norms(const double* AX, const double* BX, const double* 
 }
 
 // ---- gather + sign normalisation -------------------------------------------
+// Column sel[b] of X (n x k, row-major) -> out[b] (n), with the sign that
+// makes its largest-modulus entry positive.  Entries within a relative 1e-4
+// of the largest modulus count as tied and the lowest index among them
+// decides (mirror-symmetric eigenvectors have exactly tied pairs whose
+// computed moduli differ by the eigenvector's error, about 1e-7 for pairs
+// accepted at residual 1e-8).
 __global__ __launch_bounds__(256) void k_gather_cols(const double* __restrict__ X, int64_t n,
                                                      int k, const int32_t* __restrict__ sel,
                                                      double* __restrict__ out) {
@@ -598,30 +604,29 @@ __global__ __launch_bounds__(256) void k_gather_cols(const double* __restrict__ 
     __shared__ int64_t bi[256];
     const int t = threadIdx.x;
     const int c = sel[blockIdx.x];
-    double best = -1.0;
-    int64_t idx = 0;
-    for (int64_t i = t; i < n; i += 256) {
-        const double a = fabs(X[i * k + c]);
-        if (a > best) {
-            best = a;
-            idx = i;
-        }
-    }
+    double best = 0.0;
+    for (int64_t i = t; i < n; i += 256) best = fmax(best, fabs(X[i * k + c]));
     bv[t] = best;
-    bi[t] = idx;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
-        if (t < off) {
-            const double o = bv[t + off];
-            const int64_t oi = bi[t + off];
-            if (o > bv[t] || (o == bv[t] && oi < bi[t])) {
-                bv[t] = o;
-                bi[t] = oi;
-            }
-        }
+        if (t < off) bv[t] = fmax(bv[t], bv[t + off]);
         __syncthreads();
     }
-    const double sgn = X[bi[0] * k + c] < 0.0 ? -1.0 : 1.0;
+    const double thr = (1.0 - 1e-4) * bv[0];
+    int64_t first = n;
+    for (int64_t i = t; i < n; i += 256)
+        if (fabs(X[i * k + c]) >= thr) {
+            first = i;
+            break;
+        }
+    bi[t] = first;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) bi[t] = min(bi[t], bi[t + off]);
+        __syncthreads();
+    }
+    const int64_t at = bi[0] < n ? bi[0] : 0;
+    const double sgn = X[at * k + c] < 0.0 ? -1.0 : 1.0;
     double* o = out + (int64_t)blockIdx.x * n;
     for (int64_t i = t; i < n; i += 256) o[i] = sgn * X[i * k + c];
 }

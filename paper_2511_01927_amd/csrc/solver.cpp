@@ -652,6 +652,7 @@ struct Stats {
     double replace_alg_bytes = 0.0;
     long columns = 0;
     int waves = 0;
+    long fp32_passes = 0;         // passes whose shifted solves ran in FP32 (mixed precision)
     long fp64_columns = 0;        // mixed: columns finished by the FP64 recurrence
     long fp64_iters = 0;          // mixed: iterations of that FP64 completion
     long band_factorisations = 0; // banded L D L^T of shifted systems
@@ -916,6 +917,7 @@ class Solver {
         CocgState S;
         S.ntiles = ntiles;
         const bool mixed = c_.o.precision == GEP_MIXED && !band;
+        if (mixed) stats_.fp32_passes += 1;
         // small row blocks keep the gathers of concurrently running
         // work-groups inside the caches; one row group per wave by default,
         // and a whole number of groups per work-group
@@ -1418,7 +1420,12 @@ static std::string json_stats(const Solver& s, double wall_ms, const std::vector
                               int precision) {
     std::ostringstream o;
     o.precision(10);
-    o << "{\"wall_ms\":" << wall_ms << ",\"precision\":\"" << (precision == GEP_MIXED ? "mixed" : "fp64")
+    // precision: what the shifted solves actually ran in ("mixed" when some
+    // pass solved in FP32); precision_requested: the caller's option
+    o << "{\"wall_ms\":" << wall_ms << ",\"precision\":\"" << (s.stats_.fp32_passes > 0 ? "mixed" : "fp64")
+      << "\",\"precision_requested\":\"" << (precision == GEP_MIXED ? "mixed" : "fp64")
+      << "\",\"fp32_passes\":" << s.stats_.fp32_passes << ",\"solver_run\":\""
+      << (s.stats_.band_factorisations > 0 ? (s.stats_.cocg_iters > 0 ? "band+cocg" : "band") : "cocg")
       << "\",\"cocg_iters\":" << s.stats_.cocg_iters << ",\"tile_iters\":" << s.stats_.tile_iters
       << ",\"columns\":" << s.stats_.columns << ",\"waves\":" << s.stats_.waves
       << ",\"spmm_launches\":" << s.stats_.spmm_launches
@@ -1628,36 +1635,110 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
             for (size_t a = 0; a < sel.size(); ++a) pairs.push_back({co.theta[sel[a]], co.rho[sel[a]], k, (int)a});
         }
         std::stable_sort(pairs.begin(), pairs.end(), [](const Pair& a, const Pair& b) { return a.lam < b.lam; });
-        // de-duplicate pairs found by different contours (same value within 1e-8
-        // relative and |x_a^T B x_b| >= 0.9): keep the smaller residual; only
-        // such candidate vectors come to the host
+        // Merge pairs that several contours found for one eigenvalue.  Values
+        // form clusters (consecutive values within 1e-8 relative).  In a
+        // cluster holding pairs of more than one contour, the contour whose
+        // cluster pairs have the smallest worst residual (lowest id on ties)
+        // keeps them all; the other contours' pairs follow in ascending
+        // residual and are dropped when their B-orthogonal projection onto the
+        // span of the pairs kept so far has B-norm >= 0.9 of their own.  Pairs
+        // of one contour are never merged (exact multiple eigenvalues keep all
+        // their vectors).  Only the vectors of such clusters come to the host.
         auto fetch = [&](const Pair& q, std::vector<double>& h) {
             h.resize((size_t)n);
             HIPCHK(hipMemcpyAsync(h.data(), cms[q.cid]->get() + (size_t)q.col * n, sizeof(double) * n,
                                   hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
         };
-        auto bdot = [&](const double* xa, const double* xb) {
-            double sacc = 0.0;
+        auto bmul = [&](const std::vector<double>& x, std::vector<double>& y) {
+            y.assign((size_t)n, 0.0);
             for (int64_t i = 0; i < n; ++i) {
                 double t = 0.0;
                 for (int32_t e = H.rowptr[row0 + i]; e < H.rowptr[row0 + i + 1]; ++e)
-                    t += H.b[e] * xb[H.colind[e] - row0];
-                sacc += xa[i] * t;
+                    t += H.b[e] * x[H.colind[e] - row0];
+                y[i] = t;
             }
-            return sacc;
+        };
+        auto dot = [&](const std::vector<double>& x, const std::vector<double>& y) {
+            double acc = 0.0;
+            for (int64_t i = 0; i < n; ++i) acc += x[i] * y[i];
+            return acc;
         };
         std::vector<char> drop(pairs.size(), 0);
-        std::vector<double> ha, hb;
-        for (size_t a = 0; a < pairs.size(); ++a) {
-            if (drop[a]) continue;
-            for (size_t b = a + 1; b < pairs.size(); ++b) {
-                if (pairs[b].lam - pairs[a].lam > 1e-8 * std::max(std::fabs(pairs[a].lam), std::fabs(pairs[b].lam))) break;
-                if (drop[b] || pairs[b].cid == pairs[a].cid) continue;
-                fetch(pairs[a], ha);
-                fetch(pairs[b], hb);
-                if (std::fabs(bdot(ha.data(), hb.data())) >= 0.9) drop[pairs[b].rho >= pairs[a].rho ? b : a] = 1;
+        for (size_t c0 = 0; c0 < pairs.size();) {
+            size_t c1 = c0 + 1;
+            while (c1 < pairs.size() &&
+                   pairs[c1].lam - pairs[c1 - 1].lam <=
+                       1e-8 * std::max(std::fabs(pairs[c1].lam), std::fabs(pairs[c1 - 1].lam)))
+                ++c1;
+            std::vector<std::pair<double, int>> owners;   // (worst residual, contour)
+            for (size_t a = c0; a < c1; ++a) {
+                auto it = std::find_if(owners.begin(), owners.end(),
+                                       [&](const std::pair<double, int>& o) { return o.second == pairs[a].cid; });
+                if (it == owners.end())
+                    owners.push_back({pairs[a].rho, pairs[a].cid});
+                else
+                    it->first = std::max(it->first, pairs[a].rho);
             }
+            if (owners.size() > 1) {
+                std::sort(owners.begin(), owners.end());
+                const size_t m = c1 - c0;
+                std::vector<std::vector<double>> xv(m), bx(m);
+                for (size_t a = 0; a < m; ++a) {
+                    fetch(pairs[c0 + a], xv[a]);
+                    bmul(xv[a], bx[a]);
+                }
+                std::vector<size_t> kept;
+                for (size_t a = 0; a < m; ++a)
+                    if (pairs[c0 + a].cid == owners[0].second) kept.push_back(a);
+                for (size_t o = 1; o < owners.size(); ++o) {
+                    std::vector<size_t> mine;
+                    for (size_t a = 0; a < m; ++a)
+                        if (pairs[c0 + a].cid == owners[o].second) mine.push_back(a);
+                    std::stable_sort(mine.begin(), mine.end(), [&](size_t u, size_t v) {
+                        return pairs[c0 + u].rho < pairs[c0 + v].rho;
+                    });
+                    for (size_t a : mine) {
+                        // proj2 = b^T G^{-1} b, G = K^T B K, b = K^T B x (Cholesky of G)
+                        const size_t q = kept.size();
+                        std::vector<double> G(q * q), rhs(q);
+                        for (size_t u = 0; u < q; ++u) {
+                            rhs[u] = dot(xv[kept[u]], bx[a]);
+                            for (size_t v = 0; v <= u; ++v) G[u * q + v] = dot(xv[kept[u]], bx[kept[v]]);
+                        }
+                        bool spd = true;
+                        for (size_t j = 0; j < q && spd; ++j) {
+                            double d = G[j * q + j];
+                            for (size_t t = 0; t < j; ++t) d -= G[j * q + t] * G[j * q + t];
+                            if (!(d > 0.0)) {
+                                spd = false;
+                                break;
+                            }
+                            d = std::sqrt(d);
+                            G[j * q + j] = d;
+                            for (size_t i = j + 1; i < q; ++i) {
+                                double v = G[i * q + j];
+                                for (size_t t = 0; t < j; ++t) v -= G[i * q + t] * G[j * q + t];
+                                G[i * q + j] = v / d;
+                            }
+                        }
+                        double proj2 = 0.0;
+                        if (spd) {
+                            for (size_t i = 0; i < q; ++i) {   // forward solve L y = b
+                                double v = rhs[i];
+                                for (size_t t = 0; t < i; ++t) v -= G[i * q + t] * rhs[t];
+                                rhs[i] = v / G[i * q + i];
+                                proj2 += rhs[i] * rhs[i];
+                            }
+                        }
+                        if (proj2 >= 0.81 * dot(xv[a], bx[a]))
+                            drop[c0 + a] = 1;
+                        else
+                            kept.push_back(a);
+                    }
+                }
+            }
+            c0 = c1;
         }
         auto* R = new gep_result();
         R->n = n;
@@ -1975,6 +2056,76 @@ int gep_spmm_shifted(const gep_pencil* p, const double* shifts, const double* X,
                 }
             HIPCHK(hipMemcpy(pq, out.data(), sizeof(double2) * W, hipMemcpyHostToDevice));
         }
+        HIPCHK(hipStreamSynchronize(s));
+    } catch (const gep::Fail& f) {
+        return f.code;
+    }
+    return GEP_OK;
+}
+
+int gep_cocg_direction(const gep_pencil* p, const double* shifts, const double* beta,
+                       const double* U, const double* P, double* Pn, int64_t W, double* pq,
+                       int row_group, void* stream) {
+    if (!p || !shifts || !beta || !U || !P || !Pn || !pq || W <= 0 || W % gep::kTile ||
+        (row_group != 1 && row_group != 4)) {
+        gep::set_error("bad cocg_direction arguments");
+        return GEP_EINVAL;
+    }
+    try {
+        const int ntiles = (int)(W / gep::kTile);
+        const int64_t n = p->d.n;
+        hipStream_t s = (hipStream_t)stream;
+        const gep::DevPencil dv = gep::group_view(p->d, row_group);
+        gep::CocgState S;
+        S.n = n;
+        S.ntiles = ntiles;
+        S.u = (double2*)U;
+        S.p = (double2*)P;
+        S.pn = (double2*)Pn;
+        S.shifts = (double2*)shifts;
+        S.beta = (double2*)beta;
+        S.rpb = dv.grp == 4 ? 4 * gep::kWaves : 2 * gep::kWaves;
+        const int nrb = (int)((n + S.rpb - 1) / S.rpb);
+        S.nrb = nrb;
+        std::vector<int64_t> tb(ntiles);
+        std::vector<int32_t> tn(ntiles, (int32_t)n), tr(ntiles, 0), tg(ntiles, dv.grp == 4 ? p->h.prob_g4[0] : 0),
+            tl(ntiles);
+        for (int t = 0; t < ntiles; ++t) {
+            tb[t] = (int64_t)t * n * gep::kTile;
+            tl[t] = t;
+        }
+        gep::DBuf<int64_t> dtb(ntiles);
+        gep::DBuf<int32_t> dtn(ntiles), dtr(ntiles), dtg(ntiles), tiles(ntiles), cnt(2);
+        gep::DBuf<double2> part((size_t)ntiles * nrb * gep::kTile);
+        const int32_t counts[2] = {ntiles, (int32_t)W};
+        HIPCHK(hipMemcpyAsync(dtb.get(), tb.data(), sizeof(int64_t) * ntiles, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(dtn.get(), tn.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(dtr.get(), tr.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(dtg.get(), tg.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(tiles.get(), tl.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(cnt.get(), counts, sizeof(counts), hipMemcpyHostToDevice, s));
+        S.geom.base = dtb.get();
+        S.geom.n = dtn.get();
+        S.geom.row0 = dtr.get();
+        S.geom.g0 = dtg.get();
+        S.tiles = tiles.get();
+        S.counts = cnt.get();
+        S.part_c = part.get();
+        HIPCHK(gep::cocg_spmm_dir(dv, S, ntiles, nrb, s));
+        std::vector<double2> ph((size_t)ntiles * nrb * gep::kTile), out(W);
+        HIPCHK(hipMemcpyAsync(ph.data(), part.get(), sizeof(double2) * ph.size(), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int t = 0; t < ntiles; ++t)
+            for (int l = 0; l < gep::kTile; ++l) {
+                double2 a = make_double2(0, 0);
+                for (int rb = 0; rb < nrb; ++rb) {
+                    const double2 v = ph[((size_t)t * nrb + rb) * gep::kTile + l];
+                    a.x += v.x;
+                    a.y += v.y;
+                }
+                out[(size_t)t * gep::kTile + l] = a;
+            }
+        HIPCHK(hipMemcpy(pq, out.data(), sizeof(double2) * W, hipMemcpyHostToDevice));
         HIPCHK(hipStreamSynchronize(s));
     } catch (const gep::Fail& f) {
         return f.code;

@@ -53,7 +53,7 @@ EXPORTS = [
     "gep_opts_default", "gep_ci_solve", "gep_result_count", "gep_result_copy",
     "gep_result_stats", "gep_result_free", "gep_strerror", "gep_last_error",
     "gep_pencil_create", "gep_pencil_free", "gep_pencil_info", "gep_ci_solve_pencil",
-    "gep_spmm_shifted", "gep_spmm_shifted_f32", "gep_spmm_real", "gep_gram", "gep_gram_noalloc",
+    "gep_spmm_shifted", "gep_cocg_direction", "gep_spmm_shifted_f32", "gep_spmm_real", "gep_gram", "gep_gram_noalloc",
     "gep_gemm_tall",
     "gep_sym_eig", "gep_gaussian_block", "gep_ci_solve_batch", "gep_kde_contours",
     "gep_density_create", "gep_density_free", "gep_density_forward", "gep_density_grads",
@@ -90,6 +90,7 @@ def load():
         "gep_pencil_info": (i32, [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(dbl)]),
         "gep_spmm_shifted": (i32, [P, P, P, P, i64, P, P]),
         "gep_spmm_shifted_f32": (i32, [P, P, P, P, i64, P]),
+        "gep_cocg_direction": (i32, [P, P, P, P, P, P, i64, P, i32, P]),
         "gep_spmm_real": (i32, [P, P, i64, i64, P, P, P]),
         "gep_gram": (i32, [P, i64, P, i64, i64, i64, i64, P, P]),
         "gep_gram_noalloc": (i32, [P, i64, P, i64, i64, i64, i64, P, P]),
@@ -313,6 +314,12 @@ class Pencil:
 def gep_spmm_shifted(pencil: Pencil, shifts, X, Y, W: int, pq=None, stream=None):
     _check(load().gep_spmm_shifted(pencil.h, shifts.data_ptr(), X.data_ptr(), Y.data_ptr(), W,
                                    pq.data_ptr() if pq is not None else None, _stream_ptr(stream)))
+
+
+def gep_cocg_direction(pencil: Pencil, shifts, beta, U, P, Pn, W: int, pq, row_group=4, stream=None):
+    _check(load().gep_cocg_direction(pencil.h, shifts.data_ptr(), beta.data_ptr(), U.data_ptr(),
+                                     P.data_ptr(), Pn.data_ptr(), W, pq.data_ptr(), row_group,
+                                     _stream_ptr(stream)))
 
 
 def gep_spmm_shifted_f32(pencil: Pencil, shifts, X, Y, W: int, stream=None):
