@@ -59,8 +59,10 @@ extern "C" {
 
 /* ---- precision of the shifted solves --------------------------------- */
 #define GEP_FP64 0          /* FP64 complex COCG throughout */
-#define GEP_MIXED 1         /* FP32 complex COCG with FP64 residual replacement;
-                               orthonormalisation, Rayleigh-Ritz and residuals FP64 */
+#define GEP_MIXED 1         /* shifted solves in FP32 complex (COCG with FP64
+                               residual replacement, or FP32 banded factors with
+                               FP64 residual refinement); orthonormalisation,
+                               Rayleigh-Ritz and residuals FP64 */
 
 /* Sparse matrix in CSR form, both triangles stored, column indices sorted
  * ascending within each row, 0-based.  rowptr has n+1 entries. */
@@ -116,11 +118,23 @@ typedef struct {
                                Results do not depend on it. */
     int solver;             /* shifted solves (z_j B - A) Y = B V: 2 = banded
                                L D L^T of every system (complex symmetric, no
-                               pivoting, FP64 residual check and up to 3
-                               iterative-refinement sweeps; pencils of half
-                               bandwidth <= 4096), 1 = batched Jacobi COCG,
-                               0 (default) = banded when every pencil's half
-                               bandwidth is <= 1024, else COCG */
+                               pivoting, FP64 residual check and iterative
+                               refinement with the factors: up to 3 sweeps
+                               with FP64 factors, 12 with FP32 ones; pencils
+                               of half bandwidth <= 4096), 1 = batched
+                               Jacobi COCG, 0 (default) = banded when every
+                               pencil's half bandwidth is <= 4096, else COCG.
+                               With precision GEP_MIXED the banded factors
+                               are FP32 (the residuals and the solution FP64). */
+    int band_kernels;       /* banded factorisation kernels: 0 (default) =
+                               register-panel kernels with lookahead for FP64
+                               factors of half bandwidth <= 1024, wide-band
+                               kernels otherwise; 2 = wide-band kernels always
+                               (1 is the same as 0).  Results agree to rounding. */
+    int band_group;         /* wide-band kernels: factor at most this many shifted
+                               systems at once (0, the default: as many as the
+                               device memory holds); each group is factored,
+                               solved and refined before the next */
 } gep_opts;
 
 typedef struct gep_result gep_result;

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgepci.so")
-SOURCES = ["spmm.hip", "cocg.hip", "band.hip", "moments.hip", "gemm.hip", "dense.hip", "density.hip",
+SOURCES = ["spmm.hip", "cocg.hip", "band.hip", "band_wide.hip", "moments.hip", "gemm.hip", "dense.hip", "density.hip",
            "kde.cpp", "solver.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

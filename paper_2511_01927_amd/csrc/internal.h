@@ -163,10 +163,18 @@ hipError_t launch_moments(const double2* X, const TileGeom& g, int64_t nmax, int
 // off + j * (bw + 1) + (i - j).
 struct BandSys {
     int64_t off = 0;    // element offset of the system's band in the factor array
-    int64_t aoff = 0;   // element offset of its pencil's real (a, b) band
+    int64_t aoff = 0;   // element offset of its pencil's real (a, b) band (-1: none kept)
     int32_t n = 0, bw = 0;
     double2 z{0.0, 0.0};
+    int32_t row0 = 0;   // first row of its pencil in the concatenated CSR
+    int32_t pad = 0;
 };
+// Up to 16 consecutive columns of one band system inside one tile of a
+// multivector (the unit of the wide-band solves).
+struct WbChunk {
+    int32_t sys = 0, tile = 0, lane0 = 0, cnt = 0;
+};
+
 // Panel width of the banded factorisation (every step re-reads and re-writes
 // the trailing bw x bw window, so wider panels cut that traffic) and the LDS
 // budget of the generic solves.
@@ -177,6 +185,8 @@ constexpr int64_t kBandMaxBw = 4096;
 constexpr int64_t kBandAutoBw = 1024;
 // Iterative-refinement sweeps after a banded solve at most.
 constexpr int kBandRefineMax = 3;
+// ... and with FP32 factors (each sweep gains about cond(K) * 6e-8).
+constexpr int kBandRefineMax32 = 12;
 constexpr size_t kBandLds = 64 * 1024;
 
 hipError_t band_form(const BandSys* sys, int nsys, const double2* AB, double2* F, hipStream_t s);
@@ -207,6 +217,26 @@ hipError_t band_residual(const DevPencil& P, const TileGeom& g, const double2* s
                          double2* R, int ntiles, int64_t nmax, double2* part, int nrb_cap,
                          double* rel, hipStream_t s);
 hipError_t band_axpy(const TileGeom& g, const double2* R, int ntiles, double2* X, hipStream_t s);
+
+// ---- wide-band and FP32 factors (band_wide.hip) ---------------------------
+// Half bandwidth from which the wide-band kernels factor a system (below it
+// the register-panel kernels of band.hip, FP64 only, are used).
+constexpr int64_t kBandWideBw = 1024;
+// F (factor array of `fp32 ? float2 : double2`) = z B - A from the CSR rows;
+// F must be zero beforehand.
+hipError_t wb_form(const DevPencil& P, const BandSys* sys, int nsys, void* F, bool fp32, hipStream_t s);
+// One panel step: panel [k0, k0 + kPanel) and the whole trailing window.
+hipError_t wb_step(const BandSys* sys, int nsys, int bwmax, void* F, bool fp32, int k0, int nmax,
+                   int32_t* flag, hipStream_t s);
+// In place X <- K^-1 X on the chunks' columns (X of the factor's type).
+hipError_t wb_solve(const BandSys* sys, const WbChunk* chunks, int nchunks, const void* F, bool fp32,
+                    const TileGeom& g, void* X, hipStream_t s);
+// D (FP32) = S (FP64) on the chunks' columns.
+hipError_t wb_narrow(const BandSys* sys, const WbChunk* chunks, int nchunks, const TileGeom& g,
+                     const double2* S, float2* D, hipStream_t s);
+// X += D (set: X = D) on the chunks' columns; D FP32 or FP64.
+hipError_t wb_accumulate(const BandSys* sys, const WbChunk* chunks, int nchunks, const TileGeom& g,
+                         const void* D, bool fp32, double2* X, int set, hipStream_t s);
 
 // RNG
 hipError_t launch_gaussian(uint64_t seed, int64_t n, int64_t L, double* V, hipStream_t s);

@@ -551,7 +551,7 @@ static void upload(const HostPencil& H, gep_pencil* P) {
                 for (int32_t e = H.rowptr[i]; e < H.rowptr[i + 1]; ++e)
                     bw = std::max<int64_t>(bw, std::llabs((int64_t)H.colind[e] - i));
             pbw[pi] = (int32_t)std::min<int64_t>(bw, INT32_MAX);
-            if (bw <= kBandMaxBw) {
+            if (bw <= kBandWideBw) {   // wider bands are formed from the CSR rows
                 poff[pi] = total;
                 total += H.prob_n[pi] * (bw + 1);
             }
@@ -698,24 +698,33 @@ class Solver {
         }
     }
 
-    // Shifted solves of a pass by banded L D L^T (band.hip)?  solver: 0 =
-    // automatic (every pencil of the pass has half bandwidth <= kBandAutoBw),
-    // 1 = COCG, 2 = band (error if a pencil's band is wider than kBandMaxBw).
+    // Shifted solves of a pass by banded L D L^T (band.hip, band_wide.hip)?
+    // solver: 0 = automatic (every pencil of the pass has half bandwidth
+    // <= kBandMaxBw), 1 = COCG, 2 = band (error if a pencil's band is wider).
     bool use_band(const std::vector<Job>& jobs) const {
         const int mode = c_.o.solver;
         if (mode == 1) return false;
         for (const Job& j : jobs) {
             const int p = j.prob;
-            if (P_->h.prob_boff[p] < 0) {
+            if (P_->h.prob_bw[p] > kBandMaxBw) {
                 if (mode == 2)
                     fail(GEP_EINVAL, "band solver: half bandwidth " + std::to_string(P_->h.prob_bw[p]) +
                                          " of problem " + std::to_string(p) + " exceeds " +
                                          std::to_string(kBandMaxBw));
                 return false;
             }
-            if (mode == 0 && P_->h.prob_bw[p] > kBandAutoBw) return false;
         }
         return true;
+    }
+
+    // The wide-band kernels factor the pass's systems when a band is wider
+    // than the register-panel kernels take, when the factors are FP32 (mixed
+    // precision), or when the caller asks for them (band_kernels = 2).
+    bool use_wide(const std::vector<Job>& jobs) const {
+        if (c_.o.precision == GEP_MIXED || c_.o.band_kernels == 2) return true;
+        for (const Job& j : jobs)
+            if (P_->h.prob_boff[j.prob] < 0) return true;
+        return false;
     }
 
     // Solutions of every (job, node, rhs) column by banded L D L^T: X (tiled)
@@ -724,7 +733,11 @@ class Solver {
     // refinement pass).
     void band_pass(const std::vector<Job>& jobs, CocgState& S, const double* BV, int64_t ldbv,
                    int L, const std::vector<int64_t>& coff, const std::vector<double2>& shifts,
-                   int64_t nmax, double2* X) {
+                   int64_t nmax, int64_t elems, double2* X) {
+        if (use_wide(jobs)) {
+            band_pass_wide(jobs, S, BV, ldbv, L, coff, shifts, nmax, elems, X);
+            return;
+        }
         const int K = (int)jobs.size();
         const int NH = c_.NH;
         const int nsys = K * NH;
@@ -825,7 +838,7 @@ class Solver {
         tm_.end();
         // FP64 residual of every column, iterative refinement with the factors
         constexpr int kCap = 4096;
-        DBuf<double2> R((size_t)Wp * std::max<int64_t>(nmax, 1));
+        DBuf<double2> R((size_t)std::max<int64_t>(elems, 1));
         DBuf<double2> part((size_t)ntiles * kCap * kTile);
         DBuf<double> rel(Wp);
         std::vector<double> relh(Wp);
@@ -838,8 +851,9 @@ class Solver {
             double mx = 0.0;
             for (int64_t c = 0; c < Wp; ++c)
                 if (colsys[c] >= 0) mx = std::max(mx, std::isfinite(relh[c]) ? relh[c] : INFINITY);
-            stats_.band_relres_max = std::max(stats_.band_relres_max, mx);
             if (mx <= c_.o.solve_tol || ref == kBandRefineMax) {
+                // the largest relative residual after refinement
+                stats_.band_relres_max = std::max(stats_.band_relres_max, mx);
                 if (mx > c_.o.solve_tol) stats_.band_unconverged += 1;
                 break;
             }
@@ -853,6 +867,175 @@ class Solver {
             tm_.end();
             stats_.band_refinements += 1;
         }
+        stats_.band_solves += Wp;
+    }
+
+    // Wide-band / FP32 pass (band_wide.hip).  The systems are factored in
+    // groups that fit the device memory left after the pass's multivectors
+    // (all at once when they fit, and then the factors are kept for a
+    // refinement pass of the same systems); each group's columns are solved
+    // and refined against the FP64 residual while its factors are held.
+    // FP32 factors (mixed precision): the right-hand sides and each residual
+    // are rounded to FP32 for the sweeps, the corrections accumulate in the
+    // FP64 solution.
+    void band_pass_wide(const std::vector<Job>& jobs, CocgState& S, const double* BV, int64_t ldbv,
+                        int L, const std::vector<int64_t>& coff, const std::vector<double2>& shifts,
+                        int64_t nmax, int64_t elems, double2* X) {
+        const bool fp32 = c_.o.precision == GEP_MIXED;
+        const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
+        const int K = (int)jobs.size();
+        const int NH = c_.NH;
+        const int nsys = K * NH;
+        const int ntiles = S.ntiles;
+        const int64_t Wp = (int64_t)ntiles * kTile;
+        if (fp32) stats_.fp32_passes += 1;
+        std::vector<BandSys> sys(nsys);
+        std::vector<std::vector<WbChunk>> chunks(nsys);
+        std::vector<std::vector<int64_t>> cols(nsys);
+        std::vector<double> keys;
+        for (int k = 0; k < K; ++k)
+            for (int j = 0; j < NH; ++j) {
+                const int q = k * NH + j;
+                BandSys& b = sys[q];
+                const int p = jobs[k].prob;
+                b.aoff = -1;
+                b.n = (int32_t)jobs[k].n;
+                b.bw = P_->h.prob_bw[p];
+                b.z = shifts[coff[k] + (int64_t)j * L];
+                b.row0 = (int32_t)jobs[k].row0;
+                keys.insert(keys.end(), {(double)p, b.z.x, b.z.y, fp32 ? 1.0 : 0.0});
+                for (int l = 0; l < L;) {
+                    const int64_t c = coff[k] + (int64_t)j * L + l;
+                    const int cnt = std::min<int>(16, std::min<int64_t>(L - l, kTile - c % kTile));
+                    chunks[q].push_back({q, (int32_t)(c / kTile), (int32_t)(c % kTile), cnt});
+                    for (int u = 0; u < cnt; ++u) cols[q].push_back(c + u);
+                    l += cnt;
+                }
+            }
+        HIPCHK(band_rhs(S.geom, S.bsrc, BV, ldbv, ntiles, X, s_));
+        const int refine_max = fp32 ? kBandRefineMax32 : kBandRefineMax;
+        constexpr int kCap = 4096;
+        DBuf<double2> R((size_t)std::max<int64_t>(elems, 1));
+        DBuf<double2> part((size_t)ntiles * kCap * kTile);
+        DBuf<double> rel(Wp);
+        DBuf<float2> X32;
+        if (fp32) X32.alloc((size_t)std::max<int64_t>(elems, 1));
+        std::vector<double> relh(Wp);
+        // systems per group: what the device can hold now
+        size_t per = 0;
+        for (const BandSys& b : sys) per = std::max(per, (size_t)b.n * (size_t)(b.bw + 1) * esz);
+        size_t freeb = 0, totalb = 0;
+        HIPCHK(hipMemGetInfo(&freeb, &totalb));
+        const bool keep = band_wF_ && keys == band_keys_;
+        double avail = 0.92 * (double)(freeb + P_->pool.idle_bytes) +
+                       (keep ? (double)band_wF_->n * sizeof(double2) : 0.0);
+        // a caller's memory budget caps the factors held at once
+        if (c_.o.mem_limit_bytes > 0) avail = std::min(avail, c_.o.mem_limit_bytes);
+        int G = (int)std::min<double>(nsys, std::floor(avail / (double)std::max<size_t>(per, 1)));
+        if (c_.o.band_group > 0) G = std::min(G, c_.o.band_group);
+        if (G < 1) fail(GEP_ENOMEM, "one banded factor needs " + std::to_string(per) + " bytes of device memory");
+        if (G < nsys) {
+            band_wF_.reset();
+            band_keys_.clear();
+        }
+        DBuf<int32_t> flags(nsys);
+        HIPCHK(hipMemsetAsync(flags.get(), 0, sizeof(int32_t) * nsys, s_));
+        for (int g0 = 0; g0 < nsys; g0 += G) {
+            const int g1 = std::min(nsys, g0 + G), ng = g1 - g0;
+            std::vector<BandSys> gs(sys.begin() + g0, sys.begin() + g1);
+            std::vector<WbChunk> gc;
+            int64_t total = 0, gmax = 0;
+            int bwmax = 0;
+            for (int q = 0; q < ng; ++q) {
+                gs[q].off = total;
+                total += (int64_t)gs[q].n * (gs[q].bw + 1);
+                gmax = std::max<int64_t>(gmax, gs[q].n);
+                bwmax = std::max(bwmax, gs[q].bw);
+                for (WbChunk c : chunks[g0 + q]) {
+                    c.sys = q;
+                    gc.push_back(c);
+                }
+            }
+            const size_t fbytes = (size_t)total * esz;
+            DBuf<BandSys> dsys(ng);
+            DBuf<WbChunk> dch(gc.size());
+            HIPCHK(hipMemcpyAsync(dsys.get(), gs.data(), sizeof(BandSys) * ng, hipMemcpyHostToDevice, s_));
+            HIPCHK(hipMemcpyAsync(dch.get(), gc.data(), sizeof(WbChunk) * gc.size(), hipMemcpyHostToDevice, s_));
+            const int nch = (int)gc.size();
+            std::unique_ptr<DBuf<double2>> Fown;
+            DBuf<double2>* F = nullptr;
+            if (ng == nsys && keep) {
+                F = band_wF_.get();
+            } else {
+                Fown = std::make_unique<DBuf<double2>>((fbytes + sizeof(double2) - 1) / sizeof(double2));
+                F = Fown.get();
+                HIPCHK(hipMemsetAsync(F->get(), 0, fbytes, s_));
+                HIPCHK(wb_form(P_->d, dsys.get(), ng, F->get(), fp32, s_));
+                int steps = 0;
+                tm_.begin(T_BAND_UPDATE);
+                for (int64_t k0 = 0; k0 < gmax; k0 += kPanel, ++steps)
+                    HIPCHK(wb_step(dsys.get(), ng, bwmax, F->get(), fp32, (int)k0, (int)gmax, flags.get() + g0, s_));
+                tm_.end();
+                for (int q = g0; q < g1; ++q) {
+                    double fp, fn, fr;
+                    band_factor_flops(sys[q].n, sys[q].bw, fp, fn, fr);
+                    stats_.band_panel_flops += fp;
+                    stats_.band_update_flops += fn + fr;
+                }
+                stats_.band_factorisations += ng;
+                stats_.band_panel_steps += steps;
+            }
+            auto sweep_flops = [&]() {
+                for (int q = g0; q < g1; ++q)
+                    stats_.band_solve_flops += (double)cols[q].size() * band_solve_flops(sys[q].n, sys[q].bw);
+            };
+            tm_.begin(T_BAND_SOLVE);
+            if (fp32) {
+                HIPCHK(wb_narrow(dsys.get(), dch.get(), nch, S.geom, X, X32.get(), s_));
+                HIPCHK(wb_solve(dsys.get(), dch.get(), nch, F->get(), true, S.geom, X32.get(), s_));
+                HIPCHK(wb_accumulate(dsys.get(), dch.get(), nch, S.geom, X32.get(), true, X, 1, s_));
+            } else {
+                HIPCHK(wb_solve(dsys.get(), dch.get(), nch, F->get(), false, S.geom, X, s_));
+            }
+            tm_.end();
+            sweep_flops();
+            for (int ref = 0;; ++ref) {
+                HIPCHK(band_residual(dv_, S.geom, S.shifts, S.bsrc, BV, ldbv, X, R.get(), ntiles, nmax,
+                                     part.get(), kCap, rel.get(), s_));
+                HIPCHK(hipMemcpyAsync(relh.data(), rel.get(), sizeof(double) * Wp, hipMemcpyDeviceToHost, s_));
+                HIPCHK(hipStreamSynchronize(s_));
+                tm_.flush();
+                double mx = 0.0;
+                for (int q = g0; q < g1; ++q)
+                    for (int64_t c : cols[q]) mx = std::max(mx, std::isfinite(relh[c]) ? relh[c] : INFINITY);
+                if (mx <= c_.o.solve_tol || ref == refine_max) {
+                    // the largest relative residual after refinement
+                    stats_.band_relres_max = std::max(stats_.band_relres_max, mx);
+                    if (mx > c_.o.solve_tol) stats_.band_unconverged += 1;
+                    break;
+                }
+                tm_.begin(T_BAND_SOLVE);
+                if (fp32) {
+                    HIPCHK(wb_narrow(dsys.get(), dch.get(), nch, S.geom, R.get(), X32.get(), s_));
+                    HIPCHK(wb_solve(dsys.get(), dch.get(), nch, F->get(), true, S.geom, X32.get(), s_));
+                    HIPCHK(wb_accumulate(dsys.get(), dch.get(), nch, S.geom, X32.get(), true, X, 0, s_));
+                } else {
+                    HIPCHK(wb_solve(dsys.get(), dch.get(), nch, F->get(), false, S.geom, R.get(), s_));
+                    HIPCHK(wb_accumulate(dsys.get(), dch.get(), nch, S.geom, R.get(), false, X, 0, s_));
+                }
+                tm_.end();
+                sweep_flops();
+                stats_.band_refinements += 1;
+            }
+            if (ng == nsys && !keep) {
+                band_wF_ = std::move(Fown);
+                band_keys_ = keys;
+            }
+        }
+        std::vector<int32_t> fh(nsys);
+        HIPCHK(hipMemcpyAsync(fh.data(), flags.get(), sizeof(int32_t) * nsys, hipMemcpyDeviceToHost, s_));
+        HIPCHK(hipStreamSynchronize(s_));
+        for (int32_t v : fh) stats_.band_pivot_flags += v != 0;
         stats_.band_solves += Wp;
     }
 
@@ -1005,7 +1188,7 @@ class Solver {
         HIPCHK(hipMemcpyAsync(d_coef.get(), coef.data(), sizeof(double2) * coef.size(), hipMemcpyHostToDevice, s_));
         std::vector<int32_t> its(Wp, 0), its0(Wp, 0);
         if (band) {
-            band_pass(jobs, S, BV, ldbv, L, coff, shifts, nmax, x.get());
+            band_pass(jobs, S, BV, ldbv, L, coff, shifts, nmax, elems, x.get());
         } else {
         if (mixed) {
             HIPCHK(hipMemsetAsync(S.x, 0, sizeof(double2) * mv, s_));
@@ -1387,6 +1570,7 @@ class Solver {
     std::unique_ptr<DBuf<double2>> band_F_;
     hipStream_t s2_ = nullptr;           // second stream of the factorisation (the pencil's)
     std::vector<double> band_keys_;
+    std::unique_ptr<DBuf<double2>> band_wF_;   // kept wide / FP32 factors (any precision, bytes / 16)
     hipStream_t s_ = nullptr;
     hipStream_t own_ = nullptr;
     Timer tm_;
@@ -1396,22 +1580,23 @@ class Solver {
 };
 
 // Device bytes of one job in a wave.  bw >= 0: the job may take the band
-// path (factors of its NH systems, x and the residual); the larger of the two
-// paths is planned.
-static size_t bytes_per_job(int64_t n, int NH, int L, int M, bool mixed, int64_t bw) {
+// path (factors of its NH systems, x and the residual; with min_factor only
+// one system's factor: the band path then factors its systems in groups);
+// the larger of the two paths is planned.
+static size_t bytes_per_job(int64_t n, int NH, int L, int M, bool mixed, int64_t bw, bool min_factor = false) {
     const size_t W = (size_t)((NH * L + kTile - 1) / kTile) * kTile;
     const size_t r = (size_t)L * M;
     // FP64: x, u, p, pn.  Mixed: x and four FP32 vectors, then (FP64
     // completion) x, u, p, pn again, so both are planned for the FP64 size.
-    (void)mixed;
     const size_t mv = (size_t)n * W * 16 * 4;
     // per-row-block partials: row blocks of at least 8 rows
     const size_t parts = W * (size_t)((n + 7) / 8) * 24;
     size_t solve = mv + parts;
     if (bw >= 0) {
-        const size_t bandb = (size_t)NH * n * (size_t)(bw + 1) * 16 + (size_t)n * W * 16 * 2 +
-                             W * 4096 * 16;
-        solve = std::max(solve, bandb);
+        const size_t esz = mixed ? 8 : 16;
+        const size_t fac = (size_t)(min_factor ? 1 : NH) * n * (size_t)(bw + 1) * esz;
+        const size_t bandb = fac + (size_t)n * W * 16 * 2 + (mixed ? (size_t)n * W * 8 : 0) + W * 4096 * 16;
+        solve = bw > kBandWideBw || mixed ? bandb : std::max(solve, bandb);
     }
     return solve + (size_t)n * r * 8 * 9 + (size_t)W * 160;
 }
@@ -1536,8 +1721,11 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
         const int Lw = sorted_jobs[k0].L;
         while (k1 < sorted_jobs.size() && sorted_jobs[k1].L == Lw) {
             const int pj = sorted_jobs[k1].prob;
-            const int64_t bwj = (cfg.o.solver != 1 && P->h.prob_boff[pj] >= 0) ? P->h.prob_bw[pj] : -1;
-            const double need = (double)bytes_per_job(sorted_jobs[k1].n, cfg.NH, Lw, cfg.M, mixed, bwj);
+            const int64_t bwj = (cfg.o.solver != 1 && P->h.prob_bw[pj] <= kBandMaxBw) ? P->h.prob_bw[pj] : -1;
+            double need = (double)bytes_per_job(sorted_jobs[k1].n, cfg.NH, Lw, cfg.M, mixed, bwj);
+            // a job whose factors alone exceed the budget factors its systems in groups
+            if (bwj >= 0 && need > budget)
+                need = (double)bytes_per_job(sorted_jobs[k1].n, cfg.NH, Lw, cfg.M, mixed, bwj, true);
             if (k1 > k0 && used + need > budget) break;
             used += need;
             ++k1;
@@ -1809,6 +1997,7 @@ void gep_opts_default(gep_opts* o) {
     o->rhs = nullptr;
     o->mem_limit_bytes = 0.0;
     o->timing = 0;
+    o->band_kernels = 0;
     o->rows_per_block = 0;
     o->verbose = 0;
     o->use_graph = 1;
@@ -1879,6 +2068,14 @@ static int validate_problem(const gep_contour* contours, int K, int N, int M, in
     }
     if (o->solver < 0 || o->solver > 2) {
         gep::set_error("solver must be 0 (automatic), 1 (COCG) or 2 (band)");
+        return GEP_EINVAL;
+    }
+    if (o->band_group < 0) {
+        gep::set_error("band_group must be >= 0");
+        return GEP_EINVAL;
+    }
+    if (o->band_kernels < 0 || o->band_kernels > 2) {
+        gep::set_error("band_kernels must be 0 (automatic), 1 or 2");
         return GEP_EINVAL;
     }
     for (int k = 0; k < K; ++k) {

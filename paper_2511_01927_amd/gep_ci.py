@@ -45,7 +45,8 @@ class gep_opts(C.Structure):
                 ("stream", C.c_void_p), ("inputs_on_device", C.c_int), ("rhs", C.c_void_p),
                 ("mem_limit_bytes", C.c_double), ("timing", C.c_int), ("rows_per_block", C.c_int),
                 ("verbose", C.c_int), ("use_graph", C.c_int), ("blocks", C.c_void_p),
-                ("row_group", C.c_int), ("solver", C.c_int)]
+                ("row_group", C.c_int), ("solver", C.c_int), ("band_kernels", C.c_int),
+                ("band_group", C.c_int)]
 
 
 # every symbol declared in include/gep_ci.h
@@ -171,7 +172,7 @@ def _contours(contours):
 
 def _opts(seed=1, precision="fp64", max_refine=1, solve_tol=1e-9, max_iter=100000, check_every=16,
           stream=None, on_device=0, rhs=None, mem_limit_bytes=0.0, timing=False, rows_per_block=0, verbose=0, use_graph=True, blocks=None,
-          row_group=0, solver="auto"):
+          row_group=0, solver="auto", band_kernels=0, band_group=0):
     lib = load()
     o = gep_opts()
     lib.gep_opts_default(C.byref(o))
@@ -199,6 +200,9 @@ def _opts(seed=1, precision="fp64", max_refine=1, solve_tol=1e-9, max_iter=10000
     o.use_graph = 1 if use_graph else 0
     o.row_group = row_group
     o.solver = {"auto": 0, "cocg": 1, "band": 2}[solver] if isinstance(solver, str) else int(solver)
+    o.band_kernels = {"auto": 0, "narrow": 1, "wide": 2}[band_kernels] if isinstance(band_kernels, str) \
+        else int(band_kernels)
+    o.band_group = band_group
     if blocks is not None:
         bl = np.ascontiguousarray(blocks, dtype=np.int32)
         o.blocks = bl.ctypes.data
