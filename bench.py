@@ -36,6 +36,7 @@ import numpy as np  # noqa: E402
 METRIC = "eigenpairs/s at residual ≤1e-8 (learned+mixed vs plain FP64); SpMM HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3
 
 # Measured HBM traffic of the two COCG kernels on the default workload (FP64),
 # per 64-column tile per launch: two rocprofv3 --pmc runs (FETCH_SIZE, then
@@ -149,6 +150,49 @@ def cpu_baseline(w, sample_contours: int):
                       f"{w.moments} moments): {ok} eigenpairs in {dt:.2f} s on {workers} processes"}
 
 
+def cpu_baseline_3d(w, sizes=(20, 24, 28)):
+    """The oracle on the 3D workload, extrapolated: a sparse LU of z B - A at
+    64^3 takes minutes, so the oracle's per-node work (factor + block solve of
+    one node pair of the first circle) is timed on smaller cubes of the same
+    recipe and extended to 64^3 by the power law through the two sizes;
+    every node of every circle is one such task, spread over the worker
+    processes.  The eigenpair count is filled in from the GPU run."""
+    import oracle  # noqa: F401  (the oracle's own LU path)
+    from oracle.cirr import default_workers, _pair_moments, _SHARED
+    from oracle.rng import gaussian_block
+    from workloads import configs
+    workers = default_workers()
+    per = {}
+    for m in sizes:
+        ws = configs.config_fd7_3d(m=m, first=max(20, (m ** 3) // 130), last=max(40, (m ** 3) // 105),
+                                   k=1, block=w.block, moments=w.moments)
+        V = gaussian_block(ws.n, ws.block, ws.seed)
+        _SHARED.update(A=ws.A, B=ws.B, BV=ws.B @ V)
+        c, R = ws.contours[0][0], ws.contours[0][1]
+        t0 = time.perf_counter()
+        _pair_moments((c, R, ws.n_nodes, ws.moments, (0, ws.n_nodes - 1)))
+        per[m] = (time.perf_counter() - t0) / 2.0
+        _SHARED.clear()
+        print(f"# cpu baseline: oracle node at {m}^3: {per[m]:.2f} s", flush=True)
+    ms = np.array(sorted(per), dtype=float)
+    ts = np.array([per[int(m)] for m in ms])
+    expo, logc = np.polyfit(np.log(ms), np.log(ts), 1)   # least squares in log-log
+    m_full = round(w.n ** (1 / 3))
+    t_node = float(np.exp(logc) * m_full ** expo)
+    m0, m1 = int(ms[0]), int(ms[-1])
+    t0_, t1_ = per[m0], per[m1]
+    nodes = w.n_nodes * len(w.contours)
+    t_total = t_node * nodes / workers
+    return {"value": None, "unit": "eigenpairs/s", "cores": workers, "kind": "oracle",
+            "host": {"cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(),
+                     "worker_processes": workers, "threads_per_worker": 1},
+            "extrapolated": True, "seconds_per_node": round(t_node, 1), "seconds_total": round(float(t_total), 1),
+            "sample": f"oracle node (sparse LU + {w.block}-column solve) timed on "
+                      + ", ".join(f"{int(m)}^3 ({per[int(m)]:.2f} s)" for m in ms)
+                      + f" pencils of the same recipe, extended to {m_full}^3 by the least-squares power "
+                        f"law t ~ m^{expo:.2f}: {t_node:.0f} s per node, {nodes} nodes on {workers} processes"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,7 +202,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--solver", default="auto", choices=["auto", "cocg", "band"],
                     help="shifted solves: banded L D L^T or batched COCG (auto: band when the "
-                         "pencil's half bandwidth is at most 1024)")
+                         "pencil's half bandwidth is at most 4096)")
     ap.add_argument("--solve-tol", type=float, default=1e-9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-contours", type=int, default=1)
@@ -174,6 +218,9 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the steps, copy a 1 GiB device buffer three times; hardware "
                          "counters of that copy calibrate the HBM byte counters")
+    ap.add_argument("--compare-fp64", action="store_true",
+                    help="after the timed steps, one FP64 solve of the same workload: per-eigenpair "
+                         "differences of the timed precision's pairs from it")
     ap.add_argument("--counters", action="store_true",
                     help="run for hardware-counter collection: no HIP-event timing around the "
                          "kernels (graph replay as in production), copy probe on; use with "
@@ -188,7 +235,10 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         # before the GPU is touched: the oracle forks worker processes
-        cpu = cpu_baseline(w, args.cpu_sample_contours)
+        if args.workload == "fd7_3d_64":
+            cpu = cpu_baseline_3d(w)
+        else:
+            cpu = cpu_baseline(w, args.cpu_sample_contours)
         print(f"# cpu baseline: {cpu['sample']}", flush=True)
 
     import torch
@@ -263,7 +313,13 @@ def main():
             "band_update": ("alu", st["band_update_flops"]),
             "band_update_next": ("alu", st["band_update_next_flops"]),
             "band_panel": ("alu", st["band_panel_flops"]),
-            "band_solve": ("alu", st["band_solve_flops"])}
+            "band_solve": ("alu", st["band_solve_flops"]),
+            "band_factor_wide": ("mfma", st.get("band_wide_flops", 0.0))}
+    # matrix-core peaks: the wide-band kernels and the sweeps run on the
+    # FP64 matrix cores, or on the FP32 ones when the factors are FP32
+    fp32_band = st["precision"] == "mixed" and st.get("band_factorisations", 0) > 0
+    peak_of = {k: (FP32_MFMA_PEAK_TFLOPS if fp32_band and k in ("band_factor_wide", "band_solve")
+                   else FP64_VECTOR_PEAK_TFLOPS) for k in spec}
     # dominant kernel by measured time.  The panel's HIP events also bracket
     # the dispatch gap behind the strip before it (about 46 us per launch
     # against 30 us of kernel time in a rocprofv3 kernel trace), so the panel
@@ -289,10 +345,12 @@ def main():
                     "traffic_unit": "bytes per launch", "kernel": name,
                     "avg_launch_us": round(avg_s * 1e6, 2), "alg_bytes_per_launch": per_launch,
                     "launches": kl.get(name, 0)}
-        # FP64 arithmetic: peak 78.6 TFLOP/s (vector and matrix cores alike on MI355X)
+        # FP64 arithmetic: peak 78.6 TFLOP/s (vector and matrix cores alike on
+        # MI355X); FP32 matrix cores 157.3 TFLOP/s
         traffic = None if args.max_iter else traffic_per_launch(args.workload, args.precision, name)
-        return {"bound": "alu", "achieved": round(rate / 1e12, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(rate / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 4),
+        pk = peak_of[name]
+        return {"bound": bound, "achieved": round(rate / 1e12, 3), "peak": pk,
+                "unit": "TFLOP/s", "frac": round(rate / 1e12 / pk, 4),
                 "traffic": round(traffic) if traffic is not None else None,
                 "traffic_unit": "bytes per launch", "kernel": name, "avg_launch_us": round(avg_s * 1e6, 2),
                 "alg_flops_per_launch": per_launch, "launches": kl.get(name, 0)}
@@ -300,11 +358,14 @@ def main():
         "metric": METRIC, "value": round(value, 3), "unit": "eigenpairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f64" if st["precision"] == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{w.name} Q1-FEM pencil n={w.n}, {len(w.contours)} uniform circles x "
-                               f"{w.n_nodes} nodes, {w.moments} moments, block {w.block}"
-                   if args.workload == "q1_2d_300" else f"{w.name} n={w.n}",
+        "config": {"workload": {"q1_2d_300": f"{w.name} Q1-FEM pencil n={w.n}, {len(w.contours)} uniform "
+                                             f"circles x {w.n_nodes} nodes, {w.moments} moments, block {w.block}",
+                                "fd7_3d_64": f"{w.name} 7-point variable-coefficient diffusion (log-normal "
+                                             f"kappa, sigma 1) n={w.n}, lumped mass, {len(w.contours)} uniform "
+                                             f"circles x {w.n_nodes} nodes, {w.moments} moments, block {w.block}"}
+                   .get(args.workload, f"{w.name} n={w.n}"),
                    "n": w.n, "contours": len(w.contours), "nodes": w.n_nodes,
                    "moments": w.moments, "block": w.block, "precision": args.precision,
                    "solve_tol": args.solve_tol,
@@ -330,6 +391,28 @@ def main():
                         "achieved_tflops": round(st[key] / t / 1e12, 3),
                         "frac_of_fp64_mfma_peak": round(st[key] / t / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 4)}
     out["mfma_projections"] = mf
+    if cpu is not None and cpu.get("extrapolated"):
+        cpu["value"] = good / args.steps / cpu["seconds_total"]
+        cpu["sample"] += f"; {good // args.steps} eigenpairs (the GPU run's count)"
+    if args.compare_fp64:
+        # one FP64 solve of the same workload, untimed: the timed precision's
+        # pairs against it, matched in order (equal counts required)
+        kw64 = dict(kw)
+        kw64["precision"] = "fp64"
+        r64 = pencil.solve(w.contours, w.n_nodes, w.moments, w.block, w.tol, **kw64)
+        a, b = results[-1], r64
+        cmp = {"fp64_pairs": int(b["evals"].size), "pairs": int(a["evals"].size),
+               "fp64_wall_ms": round(b["stats"]["wall_ms"], 1)}
+        if a["evals"].size == b["evals"].size and a["evals"].size:
+            rel = np.abs(a["evals"] - b["evals"]) / np.abs(b["evals"])
+            BX = w.B @ b["evecs"]
+            ov = np.abs(np.einsum("ij,ij->j", a["evecs"], BX))
+            cmp.update({"eigenvalue_rel_diff_max": float(rel.max()),
+                        "eigenvalue_rel_diff_median": float(np.median(rel)),
+                        "eigenvector_overlap_min": float(ov.min()),
+                        "resid_max": float(a["resid"].max()), "fp64_resid_max": float(b["resid"].max())})
+        out["vs_fp64"] = cmp
+        print(f"# FP64 comparison: {cmp}", flush=True)
     if st.get("band_factorisations", 0) > 0 and not args.no_spmm_probe and not args.counters:
         # The metric's second figure, the shifted-solve SpMM's HBM rate, comes
         # from the COCG path (the band path has no SpMM in its solves): after

@@ -19,17 +19,21 @@
 //                 32 pivot rows are factored redundantly in every chunk (one
 //                 thread per row, the row's panel entries in registers) and
 //                 each chunk applies the column eliminations to its rows;
-//   k_wb_update   the whole trailing window C -= W diag(d) W^T, lower
-//                 triangle, 64 x 64 tiles on the matrix cores
-//                 (v_mfma_f64_16x16x4 or v_mfma_f32_16x16x4).
-// Solves on the tiled multivector, one work-group per chunk of at most 16
-// columns of one system (k_wb_sweep): 32-row blocks, the block's coupling
-// to the rows already solved (forward: the bw rows above; backward: the bw
-// rows below) as a matrix-core product whose K dimension runs over those
-// rows in 64-row tiles staged through LDS (the forward tile is read down
-// the factor's columns, the backward one across them), then a triangular
-// solve of the block.  The forward sweep leaves y = L^-1 b; the backward
-// sweep divides by d on the fly.
+//   k_wb_update   the trailing window C -= W diag(d) W^T, lower triangle,
+//                 64 x 64 tiles on the matrix cores (v_mfma_f64_16x16x4 or
+//                 v_mfma_f32_16x16x4); panels go in pairs: the second
+//                 panel's columns take the first's contribution (a strip),
+//                 and the window beyond them takes both panels' in one
+//                 read-modify-write.
+// Solves on the tiled multivector by chunks of at most 16 columns of one
+// system: 32-row blocks grouped in big blocks of 256 rows; each block's
+// coupling to the rows solved before it (forward: the bw rows above;
+// backward: the bw rows below) is a matrix-core product whose K dimension
+// runs over those rows in 64-row tiles staged through LDS; the part that
+// reaches past the current big block is formed for its eight blocks in
+// parallel (k_wb_far), the rest and the blocks' triangles in order
+// (k_wb_near).  The forward sweep leaves y = L^-1 b; the backward sweep
+// divides by d on the fly.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -200,43 +204,39 @@ __global__ __launch_bounds__(256) void k_wb_panel(const BandSys* __restrict__ sy
 }
 
 // ---- trailing update ---------------------------------------------------------
-// After panel [k0, k0 + kPanel): the window [w0, wend), w0 = k0 + kPanel,
-// wend = min(n, w0 + bw), lower triangle, C[i, j] -= sum_k l_ik d_k l_jk.
-// blockIdx.x: lower-triangular index of a 64 x 64 tile (bi >= bj);
-// blockIdx.y: system.  Wave w forms D(j, i) for the tile's 16 columns j of
-// block w and all 64 rows i (four 16-row blocks): A = W_j = l_jk d_k,
-// B = l_ik, both staged in LDS with lanes running down band columns; the
-// result registers run down a column of C, so the read-modify-write is
-// coalesced.
+// Contributions of the npan panels starting at k0 (columns [k0, k0 + 32
+// npan)) to the window columns [c0, c1), rows [c0, wend), wend = min(n,
+// k0 + 32 npan + bw), lower triangle: C[i, j] -= sum_k l_ik d_k l_jk.
+// strip == 0: blockIdx.x is a lower-triangular index of 64 x 64 tiles
+// (bi >= bj) from (c0, c0); strip != 0: the row tile of the single tile
+// column at c0 (c1 - c0 <= 64).  blockIdx.y: system.  Wave w forms D(j, i)
+// for the tile's 16 columns j of block w and all 64 rows i (four 16-row
+// blocks): A = W_j = l_jk d_k, B = l_ik, each panel's 32 columns staged in
+// LDS in turn with lanes running down band columns; the result registers
+// run down a column of C, so the single read-modify-write per tile is
+// coalesced.  Entries a panel does not reach (past its band) are zero.
 template <typename C>
-__global__ __launch_bounds__(256) void k_wb_update(const BandSys* __restrict__ sys, C* F, int k0) {
+__global__ __launch_bounds__(256) void k_wb_update(const BandSys* __restrict__ sys, C* F, int k0, int npan,
+                                                   int c0, int c1, int strip) {
     using V = typename Mma<C>::V;
     __shared__ C Wi[64][kPanel + 1];
     __shared__ C Wj[64][kPanel + 1];
     const BandSys S = sys[blockIdx.y];
-    const int w0 = k0 + kPanel;
-    const int wend = min(S.n, k0 + kPanel + S.bw);
-    if (w0 >= wend) return;
+    const int wend = min(S.n, k0 + kPanel * npan + S.bw);
+    const int cend = min(c1, wend);
+    if (c0 >= cend) return;
     const int x = blockIdx.x;
-    int bi = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
-    while ((bi + 1) * (bi + 2) / 2 <= x) ++bi;
-    while (bi * (bi + 1) / 2 > x) --bi;
-    const int bj = x - bi * (bi + 1) / 2;
-    const int i0 = w0 + 64 * bi, j0 = w0 + 64 * bj;
-    if (i0 >= wend) return;   // uniform
+    int bi = x, bj = 0;
+    if (!strip) {
+        bi = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
+        while ((bi + 1) * (bi + 2) / 2 <= x) ++bi;
+        while (bi * (bi + 1) / 2 > x) --bi;
+        bj = x - bi * (bi + 1) / 2;
+    }
+    const int i0 = c0 + 64 * bi, j0 = c0 + 64 * bj;
+    if (i0 >= wend || j0 >= cend) return;   // uniform
     const int ld = S.bw + 1;
     C* Fs = F + S.off;
-    for (int idx = threadIdx.x; idx < 64 * kPanel; idx += blockDim.x) {
-        const int r = idx & 63, kk = idx >> 6;
-        const int k = k0 + kk;
-        const int i = i0 + r, j = j0 + r;
-        C wi = czero<C>(), wj = czero<C>();
-        if (i < wend && i - k <= S.bw) wi = Fs[(int64_t)k * ld + (i - k)];
-        if (j < wend && j - k <= S.bw) wj = cmulT(Fs[(int64_t)k * ld + (j - k)], Fs[(int64_t)k * ld]);
-        Wi[r][kk] = wi;
-        Wj[r][kk] = wj;
-    }
-    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     V pre[4], pim[4];
 #pragma unroll
@@ -244,12 +244,30 @@ __global__ __launch_bounds__(256) void k_wb_update(const BandSys* __restrict__ s
         pre[rb] = V{0, 0, 0, 0};
         pim[rb] = V{0, 0, 0, 0};
     }
+    for (int pp = 0; pp < npan; ++pp) {
+        const int kp = k0 + kPanel * pp;
+        if (kp >= S.n) break;   // uniform
+        if (pp > 0) __syncthreads();
+        for (int idx = threadIdx.x; idx < 64 * kPanel; idx += blockDim.x) {
+            const int r = idx & 63, kk = idx >> 6;
+            const int k = kp + kk;
+            const int i = i0 + r, j = j0 + r;
+            C wi = czero<C>(), wj = czero<C>();
+            if (k < S.n) {
+                if (i < wend && i - k <= S.bw) wi = Fs[(int64_t)k * ld + (i - k)];
+                if (j < cend && j - k <= S.bw) wj = cmulT(Fs[(int64_t)k * ld + (j - k)], Fs[(int64_t)k * ld]);
+            }
+            Wi[r][kk] = wi;
+            Wj[r][kk] = wj;
+        }
+        __syncthreads();
 #pragma unroll
-    for (int st = 0; st < kPanel / 4; ++st) {
-        const int kk = 4 * st + (lane >> 4);
-        const C a = Wj[wave * 16 + (lane & 15)][kk];
+        for (int st = 0; st < kPanel / 4; ++st) {
+            const int kk = 4 * st + (lane >> 4);
+            const C a = Wj[wave * 16 + (lane & 15)][kk];
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) cmma<C>(a, Wi[rb * 16 + (lane & 15)][kk], pre[rb], pim[rb]);
+            for (int rb = 0; rb < 4; ++rb) cmma<C>(a, Wi[rb * 16 + (lane & 15)][kk], pre[rb], pim[rb]);
+        }
     }
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
@@ -257,7 +275,7 @@ __global__ __launch_bounds__(256) void k_wb_update(const BandSys* __restrict__ s
         for (int v = 0; v < 4; ++v) {
             const int j = j0 + wave * 16 + Mma<C>::row(lane, v);
             const int i = i0 + rb * 16 + (lane & 15);
-            if (j >= wend || i >= wend || i < j) continue;
+            if (j >= cend || i >= wend || i < j) continue;
             C& c = Fs[(int64_t)j * ld + (i - j)];
             c.x -= pre[rb][v];
             c.y -= pim[rb][v];
@@ -265,27 +283,129 @@ __global__ __launch_bounds__(256) void k_wb_update(const BandSys* __restrict__ s
 }
 
 // ---- blocked sweeps --------------------------------------------------------------
-// One work-group (4 waves) per chunk: up to 16 consecutive columns of one
-// system inside one tile of the multivector X (element (i, c) of the chunk
-// at base + i * 64 + lane0 + c, base the tile's).  Blocks of 32 rows, in
-// order (forward) or in reverse (backward).  For block rows [i0, i0 + 32):
-//   forward:  D(i, c) = sum_{j < i0} l_ij y_jc, then y_i = b_i - D_i -
-//             sum_{i0 <= j < i} l_ij y_j;
-//   backward: D(i, c) = sum_{j >= i0 + 32} l_ji x_jc, then x_i = y_i / d_i -
-//             D_i - sum_{i < j < i0 + 32} l_ji x_j.
-// The K dimension of D runs over 64-row tiles of the coupled rows; a tile of
-// L (64 x 32) is staged in LDS as Lt[k][i] (forward: l_{i0+i, j0+k}, read
-// down the factor's columns j; backward: l_{j0+k, i0+i}, read down columns
-// i), and the four waves take interleaved K steps of 4, their partial D
-// summed through LDS.  The block's triangle is solved by 16 lanes, one per
-// column, from LDS.
+// The solves walk a system's rows in big blocks of kWbBig = 256 rows (in
+// order for L y = b, in reverse for L^T x = D^-1 y), each split into eight
+// 32-row blocks.  For the 32-row block at rows [i0, i0 + 32):
+//   forward:  y_i = b_i - sum_{j < i0} l_ij y_j - sum_{i0 <= j < i} l_ij y_j;
+//   backward: x_i = y_i / d_i - sum_{j >= i0 + 32} l_ji x_j - sum_{i < j < i0 + 32} l_ji x_j.
+// The coupling to the rows outside the current big block ("far") only needs
+// rows solved in earlier big blocks, so it is formed for all eight blocks at
+// once by k_wb_far, one work-group per (chunk, block), into a scratch D.  The
+// coupling inside the big block ("near", at most 224 rows) and the block's
+// triangle are then done in order by k_wb_near, one work-group per chunk.
+// A chunk is up to 16 consecutive columns of one system inside one tile of
+// the multivector X (element (i, c) at base + i * 64 + lane0 + c).
+//
+// Coupling products: D(i, c) = sum_k A(i, k) Y(k, c) over 64-row tiles of
+// the coupled rows; the L tile is staged in LDS as Lt[k][i] (forward:
+// l_{i0+i, j0+k}, read down the factor's columns j; backward:
+// l_{j0+k, i0+i}, read down columns i), the next tile prefetched into
+// registers; the four waves take interleaved K steps of 4 on the matrix
+// cores and their partial D meet in LDS.
+constexpr int kWbBig = 256;
+
 template <typename C, bool FWD>
-__global__ __launch_bounds__(256) void k_wb_sweep(const BandSys* __restrict__ sys,
-                                                  const WbChunk* __restrict__ chunks,
-                                                  const C* __restrict__ F, TileGeom geom,
-                                                  C* __restrict__ X) {
-    using R = typename Real<C>::T;
+__device__ inline void wb_coupling(const C* __restrict__ Fs, int ld, int bw, int i0, int rows, int jlo,
+                                   int jhi, const C* __restrict__ Xc, int cnt, C (*Lt)[33],
+                                   C (*part)[32][16]) {
     using V = typename Mma<C>::V;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int cb = lane & 15;
+    const bool cok = cb < cnt;
+    V re[2], im[2];
+    re[0] = re[1] = im[0] = im[1] = V{0, 0, 0, 0};
+    auto fetch = [&](int j0, C* v) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = t + 256 * q;
+            const int k = FWD ? (e >> 5) : (e & 63);
+            const int i = FWD ? (e & 31) : (e >> 6);
+            const int j = j0 + k, r = i0 + i;
+            v[q] = czero<C>();
+            if (FWD) {
+                if (j < jhi && i < rows && r - j <= bw) v[q] = Fs[(int64_t)j * ld + (r - j)];
+            } else {
+                if (j < jhi && i < rows && j - r <= bw) v[q] = Fs[(int64_t)r * ld + (j - r)];
+            }
+        }
+    };
+    C nxt[8];
+    if (jlo < jhi) fetch(jlo, nxt);
+    for (int j0 = jlo; j0 < jhi; j0 += 64) {
+        __syncthreads();   // the previous tile has been consumed
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = t + 256 * q;
+            const int k = FWD ? (e >> 5) : (e & 63);
+            const int i = FWD ? (e & 31) : (e >> 6);
+            Lt[k][i] = nxt[q];
+        }
+        C xb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = 4 * (wave + 4 * u) + (lane >> 4);
+            xb[u] = (j0 + k < jhi && cok) ? Xc[(int64_t)(j0 + k) * 64 + cb] : czero<C>();
+        }
+        __syncthreads();
+        if (j0 + 64 < jhi) fetch(j0 + 64, nxt);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = 4 * (wave + 4 * u) + (lane >> 4);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) cmma<C>(Lt[k][16 * h + (lane & 15)], xb[u], re[h], im[h]);
+        }
+    }
+    // register v of lane l holds D(16 h + row(l, v), l % 16)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part[wave][16 * h + Mma<C>::row(lane, v)][lane & 15] = mkc<C>(re[h][v], im[h][v]);
+}
+
+// Far coupling of block blockIdx.y of big block `big` for chunk blockIdx.x,
+// the four waves' partials summed into Dfar[chunk][32 y + r][c].
+template <typename C, bool FWD>
+__global__ __launch_bounds__(256) void k_wb_far(const BandSys* __restrict__ sys,
+                                                const WbChunk* __restrict__ chunks, const C* __restrict__ F,
+                                                TileGeom geom, const C* __restrict__ X, C* __restrict__ Dfar,
+                                                int big) {
+    __shared__ C Lt[64][33];
+    __shared__ C part[4][32][16];
+    const WbChunk ch = chunks[blockIdx.x];
+    const BandSys S = sys[ch.sys];
+    const int n = S.n, bw = S.bw, ld = bw + 1;
+    const int b0 = big * kWbBig;
+    const int i0 = b0 + 32 * blockIdx.y;
+    if (i0 >= n) return;   // uniform
+    const int rows = min(32, n - i0);
+    const int jlo = FWD ? max(0, i0 - bw) : min(n, b0 + kWbBig);
+    const int jhi = FWD ? b0 : min(n, i0 + rows + bw);
+    const C* Xc = X + geom.base[ch.tile] + ch.lane0;
+    wb_coupling<C, FWD>(F + S.off, ld, bw, i0, rows, jlo, jhi, Xc, ch.cnt, Lt, part);
+    __syncthreads();
+    C* D = Dfar + ((int64_t)blockIdx.x * kWbBig + 32 * blockIdx.y) * 16;
+    for (int e = threadIdx.x; e < 32 * 16; e += 256) {
+        const int r = e >> 4, c = e & 15;
+        C v = part[0][r][c];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) {
+            v.x += part[w][r][c].x;
+            v.y += part[w][r][c].y;
+        }
+        D[r * 16 + c] = v;
+    }
+}
+
+// Near coupling and triangles of the eight blocks of big block `big`, in
+// order (forward) or reverse (backward), one work-group per chunk.  The
+// triangle is solved right-looking by all threads: thread t owns column
+// t % 16 and rows t / 16 and t / 16 + 16.
+template <typename C, bool FWD>
+__global__ __launch_bounds__(256) void k_wb_near(const BandSys* __restrict__ sys,
+                                                 const WbChunk* __restrict__ chunks, const C* __restrict__ F,
+                                                 TileGeom geom, C* __restrict__ X, const C* __restrict__ Dfar,
+                                                 int big) {
+    using R = typename Real<C>::T;
     __shared__ C Lt[64][33];
     __shared__ C Ld[32][33];      // Ld[r][q] = l_{i0+r, i0+q}, q < r; Ld[r][r] = d
     __shared__ C part[4][32][16];
@@ -293,105 +413,82 @@ __global__ __launch_bounds__(256) void k_wb_sweep(const BandSys* __restrict__ sy
     const WbChunk ch = chunks[blockIdx.x];
     const BandSys S = sys[ch.sys];
     const int n = S.n, bw = S.bw, ld = bw + 1;
+    const int b0 = big * kWbBig;
+    if (b0 >= n) return;   // uniform
     const C* Fs = F + S.off;
-    C* Xc = X + geom.base[ch.tile] + ch.lane0;   // element (i, c) at Xc[i * 64 + c]
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int cb = lane & 15;
-    const bool cok = cb < ch.cnt;
-    const int nblk = (n + 31) / 32;
-    for (int bb = 0; bb < nblk; ++bb) {
-        const int blk = FWD ? bb : nblk - 1 - bb;
-        const int i0 = blk * 32;
+    C* Xc = X + geom.base[ch.tile] + ch.lane0;
+    const C* Dc = Dfar + (int64_t)blockIdx.x * kWbBig * 16;
+    const int t = threadIdx.x;
+    const int tc = t & 15, tr = t >> 4;
+    const int bend = min(n, b0 + kWbBig);
+    const int nb = (bend - b0 + 31) / 32;
+    for (int u = 0; u < nb; ++u) {
+        const int blk = FWD ? u : nb - 1 - u;
+        const int i0 = b0 + 32 * blk;
         const int rows = min(32, n - i0);
-        const int jlo = FWD ? max(0, i0 - bw) : i0 + 32;
-        const int jhi = FWD ? i0 : min(n, i0 + rows + bw);
-        V re[2], im[2];
-        re[0] = re[1] = im[0] = im[1] = V{0, 0, 0, 0};
-        for (int j0 = jlo; j0 < jhi; j0 += 64) {
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int e = t + 256 * q;
-                int k, i;
-                if (FWD) {
-                    k = e >> 5;
-                    i = e & 31;
-                } else {
-                    i = e >> 6;
-                    k = e & 63;
-                }
-                const int j = j0 + k, r = i0 + i;
-                C v = czero<C>();
-                if (FWD) {
-                    if (j < jhi && i < rows && r - j <= bw) v = Fs[(int64_t)j * ld + (r - j)];
-                } else {
-                    if (j < jhi && i < rows && j - r <= bw) v = Fs[(int64_t)r * ld + (j - r)];
-                }
-                Lt[k][i] = v;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int s = wave; s < 16; s += 4) {
-                const int k = 4 * s + (lane >> 4);
-                const C xb = (j0 + k < jhi && cok) ? Xc[(int64_t)(j0 + k) * 64 + cb] : czero<C>();
-#pragma unroll
-                for (int h = 0; h < 2; ++h) cmma<C>(Lt[k][16 * h + (lane & 15)], xb, re[h], im[h]);
-            }
-        }
-        // A(i, k) = Lt[k][16 h + i], B(k, c) = X rows: register v of lane l
-        // holds D(16 h + row(l, v), c = l % 16); the waves' partials go to LDS
-        __syncthreads();
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) part[wave][16 * h + Mma<C>::row(lane, v)][lane & 15] = mkc<C>(re[h][v], im[h][v]);
-        // diagonal block and right-hand sides
+        const int jlo = FWD ? max(b0, i0 - bw) : i0 + 32;
+        const int jhi = FWD ? i0 : min(bend, i0 + rows + bw);
+        wb_coupling<C, FWD>(Fs, ld, bw, i0, rows, jlo, jhi, Xc, ch.cnt, Lt, part);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int e = t + 256 * q;
-            const int col = e >> 5, r = e & 31;   // Ld[r][col] = l_{i0+r, i0+col}
+            const int col = e >> 5, r = e & 31;
             C v = czero<C>();
             if (r >= col && r < rows && col < rows && r - col <= bw) v = Fs[(int64_t)(i0 + col) * ld + (r - col)];
             Ld[r][col] = v;
         }
-        for (int e = t; e < 32 * 16; e += 256) {
-            const int r = e >> 4, c = e & 15;
-            rhs[r][c] = (r < rows && c < ch.cnt) ? Xc[(int64_t)(i0 + r) * 64 + c] : czero<C>();
-        }
         __syncthreads();
-        if (t < 16) {
-            const int c = t;
-            if (FWD) {
-                for (int r = 0; r < rows; ++r) {
-                    C v = rhs[r][c];
+        // right-hand side of the block's triangle: b (or y / d) - far - near
 #pragma unroll
-                    for (int w = 0; w < 4; ++w) {
-                        v.x -= part[w][r][c].x;
-                        v.y -= part[w][r][c].y;
-                    }
-                    for (int q = 0; q < r; ++q) cfmsT(v, Ld[r][q], rhs[q][c]);
-                    rhs[r][c] = v;
-                }
-            } else {
-                for (int r = rows - 1; r >= 0; --r) {
+        for (int h = 0; h < 2; ++h) {
+            const int r = tr + 16 * h;
+            C v = czero<C>();
+            if (r < rows && tc < ch.cnt) {
+                v = Xc[(int64_t)(i0 + r) * 64 + tc];
+                if (!FWD) {
                     const C d = Ld[r][r];
                     const R m2 = d.x * d.x + d.y * d.y;
-                    C v = cmulT(rhs[r][c], mkc<C>(d.x / m2, -d.y / m2));
+                    v = cmulT(v, mkc<C>(d.x / m2, -d.y / m2));
+                }
+                const C f = Dc[(32 * blk + r) * 16 + tc];
+                v.x -= f.x;
+                v.y -= f.y;
 #pragma unroll
-                    for (int w = 0; w < 4; ++w) {
-                        v.x -= part[w][r][c].x;
-                        v.y -= part[w][r][c].y;
-                    }
-                    for (int q = r + 1; q < rows; ++q) cfmsT(v, Ld[q][r], rhs[q][c]);
-                    rhs[r][c] = v;
+                for (int w = 0; w < 4; ++w) {
+                    v.x -= part[w][r][tc].x;
+                    v.y -= part[w][r][tc].y;
                 }
             }
+            rhs[r][tc] = v;
         }
         __syncthreads();
-        for (int e = t; e < 32 * 16; e += 256) {
-            const int r = e >> 4, c = e & 15;
-            if (r < rows && c < ch.cnt) Xc[(int64_t)(i0 + r) * 64 + c] = rhs[r][c];
+        if (FWD) {
+            for (int q = 0; q < rows - 1; ++q) {
+                const C yq = rhs[q][tc];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = tr + 16 * h;
+                    if (r > q && r < rows) cfmsT(rhs[r][tc], Ld[r][q], yq);
+                }
+                __syncthreads();
+            }
+        } else {
+            for (int q = rows - 1; q > 0; --q) {
+                const C xq = rhs[q][tc];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = tr + 16 * h;
+                    if (r < q) cfmsT(rhs[r][tc], Ld[q][r], xq);
+                }
+                __syncthreads();
+            }
         }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = tr + 16 * h;
+            if (r < rows && tc < ch.cnt) Xc[(int64_t)(i0 + r) * 64 + tc] = rhs[r][tc];
+        }
+        __syncthreads();
     }
 }
 
@@ -439,27 +536,48 @@ static hipError_t wb_form_t(const DevPencil& P, const BandSys* sys, int nsys, C*
     return hipGetLastError();
 }
 
+// One step of two panels: panel k0, the next panel's columns updated with
+// it (a 32-column strip), panel k0 + kPanel, then the trailing window from
+// k0 + 2 kPanel with both panels (one read-modify-write of the window per
+// two panels).
 template <typename C>
 static hipError_t wb_step_t(const BandSys* sys, int nsys, int bwmax, C* F, int k0, int nmax, int32_t* flag,
                             hipStream_t s) {
     const int chunks = std::max(1, (bwmax + kWbRows - 1) / kWbRows);
-    hipLaunchKernelGGL(k_wb_panel<C>, dim3(chunks, nsys), dim3(256), 0, s, sys, F, k0, flag);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || k0 + kPanel >= nmax || bwmax == 0) return e;
     const int T = (bwmax + 63) / 64;
-    hipLaunchKernelGGL(k_wb_update<C>, dim3(T * (T + 1) / 2, nsys), dim3(256), 0, s, sys, F, k0);
+    hipLaunchKernelGGL(k_wb_panel<C>, dim3(chunks, nsys), dim3(256), 0, s, sys, F, k0, flag);
+    if (k0 + kPanel >= nmax) return hipGetLastError();
+    if (bwmax > 0)
+        hipLaunchKernelGGL(k_wb_update<C>, dim3(T + 1, nsys), dim3(256), 0, s, sys, F, k0, 1, k0 + kPanel,
+                           k0 + 2 * kPanel, 1);
+    hipLaunchKernelGGL(k_wb_panel<C>, dim3(chunks, nsys), dim3(256), 0, s, sys, F, k0 + kPanel, flag);
+    if (k0 + 2 * kPanel >= nmax || bwmax == 0) return hipGetLastError();
+    hipLaunchKernelGGL(k_wb_update<C>, dim3(T * (T + 1) / 2, nsys), dim3(256), 0, s, sys, F, k0, 2,
+                       k0 + 2 * kPanel, k0 + 2 * kPanel + bwmax, 0);
     return hipGetLastError();
 }
 
 template <typename C>
 static hipError_t wb_solve_t(const BandSys* sys, const WbChunk* chunks, int nchunks, const C* F,
-                             const TileGeom& g, C* X, hipStream_t s) {
+                             const TileGeom& g, C* X, int nmax, C* Dfar, hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_wb_sweep<C, true>), dim3(nchunks), dim3(256), 0, s, sys, chunks, F, g, X);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_wb_sweep<C, false>), dim3(nchunks), dim3(256), 0, s, sys, chunks, F, g, X);
-    return hipGetLastError();
+    const int nbig = (nmax + kWbBig - 1) / kWbBig;
+    for (int b = 0; b < nbig; ++b) {
+        // (big block 0 has nothing above it: the far kernel writes zeros)
+        hipLaunchKernelGGL((k_wb_far<C, true>), dim3(nchunks, kWbBig / 32), dim3(256), 0, s, sys, chunks, F, g,
+                           X, Dfar, b);
+        hipLaunchKernelGGL((k_wb_near<C, true>), dim3(nchunks), dim3(256), 0, s, sys, chunks, F, g, X, Dfar, b);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    for (int b = nbig - 1; b >= 0; --b) {
+        hipLaunchKernelGGL((k_wb_far<C, false>), dim3(nchunks, kWbBig / 32), dim3(256), 0, s, sys, chunks, F, g,
+                           X, Dfar, b);
+        hipLaunchKernelGGL((k_wb_near<C, false>), dim3(nchunks), dim3(256), 0, s, sys, chunks, F, g, X, Dfar, b);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t wb_form(const DevPencil& P, const BandSys* sys, int nsys, void* F, bool fp32, hipStream_t s) {
@@ -473,10 +591,13 @@ hipError_t wb_step(const BandSys* sys, int nsys, int bwmax, void* F, bool fp32, 
 }
 
 hipError_t wb_solve(const BandSys* sys, const WbChunk* chunks, int nchunks, const void* F, bool fp32,
-                    const TileGeom& g, void* X, hipStream_t s) {
-    return fp32 ? wb_solve_t<float2>(sys, chunks, nchunks, (const float2*)F, g, (float2*)X, s)
-                : wb_solve_t<double2>(sys, chunks, nchunks, (const double2*)F, g, (double2*)X, s);
+                    const TileGeom& g, void* X, int nmax, void* Dfar, hipStream_t s) {
+    return fp32 ? wb_solve_t<float2>(sys, chunks, nchunks, (const float2*)F, g, (float2*)X, nmax, (float2*)Dfar, s)
+                : wb_solve_t<double2>(sys, chunks, nchunks, (const double2*)F, g, (double2*)X, nmax,
+                                      (double2*)Dfar, s);
 }
+
+size_t wb_scratch_bytes(int nchunks) { return sizeof(double2) * (size_t)nchunks * kWbBig * 16; }
 
 hipError_t wb_narrow(const BandSys* sys, const WbChunk* chunks, int nchunks, const TileGeom& g,
                      const double2* Sx, float2* D, hipStream_t s) {

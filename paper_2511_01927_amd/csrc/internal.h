@@ -225,12 +225,14 @@ constexpr int64_t kBandWideBw = 1024;
 // F (factor array of `fp32 ? float2 : double2`) = z B - A from the CSR rows;
 // F must be zero beforehand.
 hipError_t wb_form(const DevPencil& P, const BandSys* sys, int nsys, void* F, bool fp32, hipStream_t s);
-// One panel step: panel [k0, k0 + kPanel) and the whole trailing window.
+// One step of two panels: [k0, k0 + 2 kPanel) and the trailing window.
 hipError_t wb_step(const BandSys* sys, int nsys, int bwmax, void* F, bool fp32, int k0, int nmax,
                    int32_t* flag, hipStream_t s);
-// In place X <- K^-1 X on the chunks' columns (X of the factor's type).
+// In place X <- K^-1 X on the chunks' columns (X of the factor's type);
+// nmax: the largest system size; Dfar: wb_scratch_bytes(nchunks) of scratch.
 hipError_t wb_solve(const BandSys* sys, const WbChunk* chunks, int nchunks, const void* F, bool fp32,
-                    const TileGeom& g, void* X, hipStream_t s);
+                    const TileGeom& g, void* X, int nmax, void* Dfar, hipStream_t s);
+size_t wb_scratch_bytes(int nchunks);
 // D (FP32) = S (FP64) on the chunks' columns.
 hipError_t wb_narrow(const BandSys* sys, const WbChunk* chunks, int nchunks, const TileGeom& g,
                      const double2* S, float2* D, hipStream_t s);

@@ -212,11 +212,11 @@ struct Timer {
     };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
-    static constexpr int kClasses = 12;
+    static constexpr int kClasses = 13;
     double ms[kClasses] = {0};
     long count[kClasses] = {0};   // timed brackets
     long seen[kClasses] = {0};    // all brackets
-    int stride[kClasses] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};   // time every stride-th bracket
+    int stride[kClasses] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};   // time every stride-th bracket
     // per-class totals: the timed mean times the number of brackets
     double total_ms(int c) const { return count[c] ? ms[c] * (double)seen[c] / (double)count[c] : 0.0; }
     hipEvent_t get() {
@@ -282,11 +282,12 @@ struct Timer {
     }
 };
 enum { T_SPMM = 0, T_UPDATE, T_REPLACE, T_REDUCE, T_MOMENTS, T_GRAM, T_GEMM, T_DENSE, T_BAND_PANEL,
-       T_BAND_UPDATE, T_BAND_SOLVE, T_BAND_NEXT };
+       T_BAND_UPDATE, T_BAND_SOLVE, T_BAND_NEXT, T_BAND_WIDE };
 static const char* kTimerNames[Timer::kClasses] = {"cocg_spmm_dir", "cocg_update", "cocg_replace",
                                                    "cocg_reduce", "moments", "gram",
                                                    "gemm_tall", "dense_small", "band_panel",
-                                                   "band_update", "band_solve", "band_update_next"};
+                                                   "band_update", "band_solve", "band_update_next",
+                                                   "band_factor_wide"};
 
 // Algorithmic real flops of the banded L D L^T of one n x n complex
 // symmetric system of half bandwidth bw, split between the panel kernel
@@ -663,6 +664,7 @@ struct Stats {
     long band_unconverged = 0;    // passes whose band residual stayed above solve_tol
     double band_relres_max = 0.0; // largest ||b - K x|| / ||b|| after refinement
     double band_panel_flops = 0.0, band_next_flops = 0.0, band_update_flops = 0.0, band_solve_flops = 0.0;
+    double band_wide_flops = 0.0;   // whole wide-band factorisations (panels, strips and windows)
 };
 
 static void choose_nrb(int64_t n, int n_active, int nrb_max, int& nrb) {
@@ -962,6 +964,7 @@ class Solver {
             HIPCHK(hipMemcpyAsync(dsys.get(), gs.data(), sizeof(BandSys) * ng, hipMemcpyHostToDevice, s_));
             HIPCHK(hipMemcpyAsync(dch.get(), gc.data(), sizeof(WbChunk) * gc.size(), hipMemcpyHostToDevice, s_));
             const int nch = (int)gc.size();
+            DBuf<double2> Dfar((wb_scratch_bytes(nch) + sizeof(double2) - 1) / sizeof(double2));
             std::unique_ptr<DBuf<double2>> Fown;
             DBuf<double2>* F = nullptr;
             if (ng == nsys && keep) {
@@ -972,15 +975,14 @@ class Solver {
                 HIPCHK(hipMemsetAsync(F->get(), 0, fbytes, s_));
                 HIPCHK(wb_form(P_->d, dsys.get(), ng, F->get(), fp32, s_));
                 int steps = 0;
-                tm_.begin(T_BAND_UPDATE);
-                for (int64_t k0 = 0; k0 < gmax; k0 += kPanel, ++steps)
+                tm_.begin(T_BAND_WIDE);
+                for (int64_t k0 = 0; k0 < gmax; k0 += 2 * kPanel, steps += 2)
                     HIPCHK(wb_step(dsys.get(), ng, bwmax, F->get(), fp32, (int)k0, (int)gmax, flags.get() + g0, s_));
                 tm_.end();
                 for (int q = g0; q < g1; ++q) {
                     double fp, fn, fr;
                     band_factor_flops(sys[q].n, sys[q].bw, fp, fn, fr);
-                    stats_.band_panel_flops += fp;
-                    stats_.band_update_flops += fn + fr;
+                    stats_.band_wide_flops += fp + fn + fr;
                 }
                 stats_.band_factorisations += ng;
                 stats_.band_panel_steps += steps;
@@ -992,10 +994,10 @@ class Solver {
             tm_.begin(T_BAND_SOLVE);
             if (fp32) {
                 HIPCHK(wb_narrow(dsys.get(), dch.get(), nch, S.geom, X, X32.get(), s_));
-                HIPCHK(wb_solve(dsys.get(), dch.get(), nch, F->get(), true, S.geom, X32.get(), s_));
+                HIPCHK(wb_solve(dsys.get(), dch.get(), nch, F->get(), true, S.geom, X32.get(), (int)gmax, Dfar.get(), s_));
                 HIPCHK(wb_accumulate(dsys.get(), dch.get(), nch, S.geom, X32.get(), true, X, 1, s_));
             } else {
-                HIPCHK(wb_solve(dsys.get(), dch.get(), nch, F->get(), false, S.geom, X, s_));
+                HIPCHK(wb_solve(dsys.get(), dch.get(), nch, F->get(), false, S.geom, X, (int)gmax, Dfar.get(), s_));
             }
             tm_.end();
             sweep_flops();
@@ -1017,10 +1019,10 @@ class Solver {
                 tm_.begin(T_BAND_SOLVE);
                 if (fp32) {
                     HIPCHK(wb_narrow(dsys.get(), dch.get(), nch, S.geom, R.get(), X32.get(), s_));
-                    HIPCHK(wb_solve(dsys.get(), dch.get(), nch, F->get(), true, S.geom, X32.get(), s_));
+                    HIPCHK(wb_solve(dsys.get(), dch.get(), nch, F->get(), true, S.geom, X32.get(), (int)gmax, Dfar.get(), s_));
                     HIPCHK(wb_accumulate(dsys.get(), dch.get(), nch, S.geom, X32.get(), true, X, 0, s_));
                 } else {
-                    HIPCHK(wb_solve(dsys.get(), dch.get(), nch, F->get(), false, S.geom, R.get(), s_));
+                    HIPCHK(wb_solve(dsys.get(), dch.get(), nch, F->get(), false, S.geom, R.get(), (int)gmax, Dfar.get(), s_));
                     HIPCHK(wb_accumulate(dsys.get(), dch.get(), nch, S.geom, R.get(), false, X, 0, s_));
                 }
                 tm_.end();
@@ -1627,6 +1629,7 @@ static std::string json_stats(const Solver& s, double wall_ms, const std::vector
       << ",\"band_update_flops\":" << s.stats_.band_update_flops
       << ",\"band_update_next_flops\":" << s.stats_.band_next_flops
       << ",\"band_solve_flops\":" << s.stats_.band_solve_flops
+      << ",\"band_wide_flops\":" << s.stats_.band_wide_flops
       << ",\"graph_captures\":" << s.stats_.graph_captures
       << ",\"spmm_alg_bytes\":" << s.stats_.spmm_alg_bytes
       << ",\"update_alg_bytes\":" << s.stats_.update_alg_bytes
