@@ -208,6 +208,23 @@ int gep_ci_solve_pencil(gep_pencil* p, const gep_contour* contours, int n_contou
                         int moments, int block, double tol, const gep_opts* opts,
                         gep_result** out);
 
+/* Batch form of gep_pencil_create: n_problems independent pencils packed
+ * once, device-resident, into one block-diagonal pencil (problem p owns the
+ * rows after those of problems 0..p-1).  Inputs host or device per
+ * inputs_on_device; errors name the failing problem. */
+int gep_pencil_create_batch(int n_problems, const gep_csr* A, const gep_csr* B, int inputs_on_device,
+                            void* stream, gep_pencil** out);
+/* Number of problems packed in a pencil (1 for gep_pencil_create). */
+int gep_pencil_problems(const gep_pencil* p, int* n_problems);
+
+/* gep_ci_solve_batch on a pencil from gep_pencil_create_batch: contours[p],
+ * n_contours[p] for each of its problems, results in out[p] (same
+ * conventions); the pencil keeps its device workspace between calls.  A
+ * pencil of several problems must be solved with this entry point. */
+int gep_ci_solve_pencil_batch(gep_pencil* p, const gep_contour* const* contours, const int* n_contours,
+                              int n_nodes, int moments, int block, double tol, const gep_opts* opts,
+                              gep_result** out);
+
 /* Shifted complex SpMM, Y[:, c] = z_c B X[:, c] - A X[:, c] (quadrature
  * equation's operator), FP64 complex, on the tiled layout: column c of an
  * n x W multivector lives at element ((c / 64) * n + i) * 64 + c % 64,

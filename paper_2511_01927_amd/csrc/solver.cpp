@@ -52,59 +52,175 @@ struct Fail {
 // Device workspace kept by a packed pencil across its solves.  A solve of
 // the same shapes as an earlier one then takes every buffer from here instead
 // of calling hipMalloc / hipFree (tens of GB per solve on the 2D headline,
-// whose per-solve allocation made the solve time erratic).  A buffer handed
-// back is first made idle with a device synchronisation, the same wait that
-// hipFree performs, so a later solve can never reuse memory that queued work
-// still touches.  Blocks are matched best-fit within 25% of the request;
-// when hipMalloc runs out of memory the idle blocks are freed and the
-// allocation retried.
+// whose per-solve allocation made the solve time erratic).  The pool is a
+// best-fit allocator over the chunks it has obtained from hipMalloc: a
+// request is carved from the smallest free range that holds it (256-byte
+// granules), a freed range merges with its free neighbours in its chunk,
+// and a new chunk is allocated only when no free range is large enough.
+// Chunks are kept until the pencil is freed (memory given back with
+// hipFree was measured not to become allocatable again right away, so a
+// multi-wave solve whose waves have different shapes must reuse it).  A
+// buffer handed back is first made idle with a device synchronisation, the
+// same wait that hipFree performs, so a later request can never reuse
+// memory that queued work still touches.
 struct DevPool {
     std::mutex mu;
-    std::multimap<size_t, void*> idle;   // capacity in bytes -> block
-    size_t idle_bytes = 0;
+    std::map<char*, size_t> chunks;              // hipMalloc'd regions: start -> bytes
+    std::map<char*, size_t> free_at;             // free ranges: start -> bytes
+    std::multimap<size_t, char*> free_by_size;   // the same ranges by size
+    size_t idle_bytes = 0;   // in free ranges
+    size_t live_bytes = 0;   // handed out and not given back
     long reused = 0, allocated = 0;
-    void* take(size_t bytes, size_t& cap) {
+    int verbose = 0;   // > 1: log requests of 1 GB and more on stderr
+    static constexpr size_t kGranule = 256;
+
+    void erase_free(char* a, size_t sz) {
+        free_at.erase(a);
+        auto r = free_by_size.equal_range(sz);
+        for (auto it = r.first; it != r.second; ++it)
+            if (it->second == a) {
+                free_by_size.erase(it);
+                break;
+            }
+        idle_bytes -= sz;
+    }
+    void insert_free(char* a, size_t sz) {
+        free_at[a] = sz;
+        free_by_size.emplace(sz, a);
+        idle_bytes += sz;
+    }
+    // start of the chunk holding address a
+    char* chunk_of(char* a) const {
+        auto it = chunks.upper_bound(a);
+        return std::prev(it)->first;
+    }
+    size_t largest_free() {
+        std::lock_guard<std::mutex> lk(mu);
+        return free_by_size.empty() ? 0 : free_by_size.rbegin()->first;
+    }
+    // One chunk of `bytes` unless a free range that large exists already
+    // (called at the start of a solve with what its largest wave needs, so
+    // that every wave is carved from one region).  Failure is not an error:
+    // requests then get chunks of their own.
+    void reserve(size_t bytes) {
+        bytes = (bytes + kGranule - 1) / kGranule * kGranule;
+        if (bytes == 0 || largest_free() >= bytes) return;
+        void* q = nullptr;
+        if (hipMalloc(&q, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return;
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        chunks[(char*)q] = bytes;
+        insert_free((char*)q, bytes);
+        ++allocated;
+    }
+    // top != 0: carve from the top end of the highest free range that holds
+    // the request (buffers that outlive a wave stay out of the way of the
+    // next wave's large requests)
+    void* take(size_t bytes, size_t& cap, bool top = false) {
+        const size_t need = (std::max<size_t>(bytes, 1) + kGranule - 1) / kGranule * kGranule;
+        if (top) {
+            std::lock_guard<std::mutex> lk(mu);
+            for (auto it = free_at.rbegin(); it != free_at.rend(); ++it) {
+                if (it->second < need) continue;
+                char* start = it->first;
+                const size_t sz = it->second;
+                erase_free(start, sz);
+                if (sz > need) insert_free(start, sz - need);
+                cap = need;
+                live_bytes += need;
+                ++reused;
+                return start + (sz - need);
+            }
+        }
         {
             std::lock_guard<std::mutex> lk(mu);
-            auto it = idle.lower_bound(bytes);
-            if (it != idle.end() && it->first <= bytes + bytes / 4 + 4096) {
-                void* q = it->second;
-                cap = it->first;
-                idle_bytes -= it->first;
-                idle.erase(it);
+            auto it = free_by_size.lower_bound(need);
+            if (verbose > 1 && need >= (size_t(1) << 30))
+                std::fprintf(stderr, "[gep] pool take %.2f GB: %s (live %.2f GB, free ranges %.2f GB, largest %.2f GB)\n",
+                             need / 1e9, it != free_by_size.end() ? "reuse" : "new chunk", live_bytes / 1e9,
+                             idle_bytes / 1e9, free_by_size.empty() ? 0.0 : free_by_size.rbegin()->first / 1e9);
+            if (it != free_by_size.end()) {
+                char* a = it->second;
+                const size_t sz = it->first;
+                erase_free(a, sz);
+                if (sz > need) insert_free(a + need, sz - need);
+                cap = need;
+                live_bytes += need;
                 ++reused;
-                return q;
+                return a;
             }
         }
         void* q = nullptr;
-        hipError_t e = hipMalloc(&q, bytes);
+        hipError_t e = hipMalloc(&q, need);
         if (e == hipErrorOutOfMemory) {
             (void)hipGetLastError();
             trim();
-            e = hipMalloc(&q, bytes);
+            e = hipMalloc(&q, need);
         }
         if (e != hipSuccess) {
             (void)hipGetLastError();
+            size_t fb = 0, tb = 0;
+            (void)hipMemGetInfo(&fb, &tb);
             fail(e == hipErrorOutOfMemory ? GEP_ENOMEM : GEP_EDEVICE,
-                 "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+                 "hipMalloc of " + std::to_string(need) + " bytes failed: " + hipGetErrorString(e) +
+                     " (workspace pool: " + std::to_string(live_bytes) + " bytes in use, " +
+                     std::to_string(idle_bytes) + " free in its chunks; device free " + std::to_string(fb) + ")");
         }
-        cap = bytes;
         std::lock_guard<std::mutex> lk(mu);
+        chunks[(char*)q] = need;
+        cap = need;
+        live_bytes += need;
         ++allocated;
         return q;
     }
     void give(void* q, size_t cap) {
         (void)hipDeviceSynchronize();
         std::lock_guard<std::mutex> lk(mu);
-        idle.emplace(cap, q);
-        idle_bytes += cap;
+        char* a = (char*)q;
+        size_t sz = cap;
+        live_bytes -= cap;
+        char* c0 = chunk_of(a);
+        char* c1 = c0 + chunks[c0];
+        // merge with the free range after it and the one before it (same chunk)
+        auto nx = free_at.find(a + sz);
+        if (nx != free_at.end() && nx->first < c1) {
+            const size_t s2 = nx->second;
+            erase_free(nx->first, s2);
+            sz += s2;
+        }
+        auto pv = free_at.lower_bound(a);
+        if (pv != free_at.begin()) {
+            --pv;
+            if (pv->first >= c0 && pv->first + pv->second == a) {
+                char* pa = pv->first;
+                const size_t s2 = pv->second;
+                erase_free(pa, s2);
+                a = pa;
+                sz += s2;
+            }
+        }
+        insert_free(a, sz);
     }
+    // give back to the runtime every chunk that is entirely free
     void trim() {
         (void)hipDeviceSynchronize();
-        std::lock_guard<std::mutex> lk(mu);
-        for (auto& kv : idle) (void)hipFree(kv.second);
-        idle.clear();
-        idle_bytes = 0;
+        if (verbose > 1) std::fprintf(stderr, "[gep] pool trim (free ranges %.2f GB)\n", idle_bytes / 1e9);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (auto it = chunks.begin(); it != chunks.end();) {
+                auto f = free_at.find(it->first);
+                if (f != free_at.end() && f->second == it->second) {
+                    erase_free(it->first, it->second);
+                    (void)hipFree(it->first);
+                    it = chunks.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+        }
+        (void)hipDeviceSynchronize();
     }
     ~DevPool() { trim(); }
 };
@@ -112,10 +228,17 @@ struct DevPool {
 // Pool that DBuf allocations of the calling thread use (set for the duration
 // of a solve on a packed pencil; null: plain hipMalloc / hipFree).
 static thread_local DevPool* t_pool = nullptr;
+static thread_local bool t_pool_top = false;
 struct PoolScope {
     DevPool* prev;
     explicit PoolScope(DevPool* p) : prev(t_pool) { t_pool = p; }
     ~PoolScope() { t_pool = prev; }
+};
+// Buffers allocated in this scope outlive the current wave of a solve.
+struct LongLived {
+    bool prev;
+    LongLived() : prev(t_pool_top) { t_pool_top = true; }
+    ~LongLived() { t_pool_top = prev; }
 };
 
 // RAII device buffer (from the thread's current pool when one is set)
@@ -133,7 +256,7 @@ struct DBuf {
         if (!count) return;
         if (t_pool) {
             pool = t_pool;
-            p = static_cast<T*>(pool->take(count * sizeof(T), cap));
+            p = static_cast<T*>(pool->take(count * sizeof(T), cap, t_pool_top));
             return;
         }
         hipError_t e = hipMalloc(&p, count * sizeof(T));
@@ -142,7 +265,7 @@ struct DBuf {
             (void)hipGetLastError();
             fail(e == hipErrorOutOfMemory ? GEP_ENOMEM : GEP_EDEVICE,
                  "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed: " +
-                     hipGetErrorString(e));
+                     hipGetErrorString(e) + " (outside the workspace pool)");
         }
     }
     void release() {
@@ -772,7 +895,16 @@ class Solver {
         HIPCHK(hipMemcpyAsync(dcol.get(), colsys.data(), sizeof(int32_t) * Wp, hipMemcpyHostToDevice, s_));
         if (!band_F_ || keys != band_keys_) {
             band_F_.reset();
-            band_F_ = std::make_unique<DBuf<double2>>(total);
+            try {
+                band_F_ = std::make_unique<DBuf<double2>>(total);
+            } catch (const Fail& f) {
+                // the wave's factors do not fit beside the rest of the pass:
+                // the wide-band path factors the systems in groups that do
+                if (f.code != GEP_ENOMEM) throw;
+                band_keys_.clear();
+                band_pass_wide(jobs, S, BV, ldbv, L, coff, shifts, nmax, elems, X);
+                return;
+            }
             DBuf<int32_t> flags(nsys);
             HIPCHK(hipMemsetAsync(flags.get(), 0, sizeof(int32_t) * nsys, s_));
             HIPCHK(band_form(dsys.get(), nsys, dv_.band, band_F_->get(), s_));
@@ -929,7 +1061,9 @@ class Solver {
         size_t freeb = 0, totalb = 0;
         HIPCHK(hipMemGetInfo(&freeb, &totalb));
         const bool keep = band_wF_ && keys == band_keys_;
-        double avail = 0.92 * (double)(freeb + P_->pool.idle_bytes) +
+        // the factors of a group are one buffer: the largest free range of
+        // the workspace, or a new chunk from the device's free memory
+        double avail = std::max(0.98 * (double)P_->pool.largest_free(), 0.92 * (double)freeb) +
                        (keep ? (double)band_wF_->n * sizeof(double2) : 0.0);
         // a caller's memory budget caps the factors held at once
         if (c_.o.mem_limit_bytes > 0) avail = std::min(avail, c_.o.mem_limit_bytes);
@@ -1455,7 +1589,11 @@ class Solver {
             co.rho.assign(keep[k], 0.0);
             kmax = std::max(kmax, keep[k]);
         }
-        auto Xbuf = std::make_shared<DBuf<double>>(std::max<size_t>(tot, 1));
+        std::shared_ptr<DBuf<double>> Xbuf;
+        {
+            LongLived ll;   // the Ritz vectors are kept until the solve's merge
+            Xbuf = std::make_shared<DBuf<double>>(std::max<size_t>(tot, 1));
+        }
         for (int k = 0; k < K; ++k) {
             outs[k].Xbuf = Xbuf;
             outs[k].X = Xbuf->get() + soff[k];
@@ -1542,6 +1680,10 @@ class Solver {
 
     void gram(const double* X, int64_t ld1, const double* Y, int64_t ld2, int64_t n, int64_t k1,
               int64_t k2, double* G, DBuf<double>& work) {
+        // the split plan depends on (n, k1, k2): grow the partial buffer when a
+        // call needs more than the pass planned
+        const size_t need = gram_work_elems(n, k1, k2);
+        if (need > work.n) work.alloc(need);
         tm_.begin(T_GRAM);
         HIPCHK(launch_gram(X, ld1, Y, ld2, n, k1, k2, G, work.get(), work.n, s_));
         tm_.end();
@@ -1663,6 +1805,7 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
                             const int* n_contours, const SolveCfg& cfg, gep_result** out) {
     auto t0 = std::chrono::steady_clock::now();
     PoolScope pool_scope(&P->pool);
+    P->pool.verbose = cfg.o.verbose;
     const HostPencil& H = P->h;
     const int64_t ntot = P->d.n;
     auto svp = std::make_unique<Solver>(P, cfg);
@@ -1713,12 +1856,22 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
     // jobs ordered by block size so that equal sizes share waves
     std::vector<size_t> ord(all.size());
     for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
-    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return all[a].L < all[b].L; });
+    // (larger problems first among equal block sizes, so that a wave holds
+    // problems of similar size and its banded factorisation no more steps
+    // than its largest problem needs)
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+        return all[a].L != all[b].L ? all[a].L < all[b].L : all[a].n > all[b].n;
+    });
     std::vector<Job> sorted_jobs;
     for (size_t i : ord) sorted_jobs.push_back(all[i]);
-    size_t k0 = 0;
-    while (k0 < sorted_jobs.size()) {
-        // a wave holds consecutive jobs with the same block size
+    // waves: consecutive jobs with the same block size within the budget
+    struct Wave {
+        size_t k0, k1;
+        double used;
+    };
+    std::vector<Wave> plan;
+    double long_lived = 0.0, max_used = 0.0;
+    for (size_t k0 = 0; k0 < sorted_jobs.size();) {
         size_t k1 = k0;
         double used = 0.0;
         const int Lw = sorted_jobs[k0].L;
@@ -1731,13 +1884,36 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
                 need = (double)bytes_per_job(sorted_jobs[k1].n, cfg.NH, Lw, cfg.M, mixed, bwj, true);
             if (k1 > k0 && used + need > budget) break;
             used += need;
+            long_lived += (double)sorted_jobs[k1].n * Lw * cfg.M * 8.0;   // Ritz vectors kept to the merge
             ++k1;
         }
         if (used > budget)
             fail(GEP_ENOMEM, "one contour needs " + std::to_string((long long)used) + " bytes of device memory");
+        plan.push_back({k0, k1, used});
+        max_used = std::max(max_used, used);
+        k0 = k1;
+    }
+    // one region for every wave (memory given back with hipFree does not
+    // become allocatable again right away, so waves of different shapes
+    // must share what the first one obtained)
+    P->pool.reserve((size_t)std::min(1.06 * max_used + long_lived + (double)(1 << 30),
+                                     0.95 * (double)(freeb + P->pool.largest_free())));
+    for (const Wave& wv : plan) {
+        const size_t k0 = wv.k0, k1 = wv.k1;
+        const double used = wv.used;
+        const int Lw = sorted_jobs[k0].L;
         std::vector<Job> jobs(sorted_jobs.begin() + k0, sorted_jobs.begin() + k1);
         std::vector<ContourOut> res;
         sv.stats_.waves += 1;
+        if (cfg.o.verbose > 0) {
+            size_t fb = 0, tb = 0;
+            (void)hipMemGetInfo(&fb, &tb);
+            std::fprintf(stderr,
+                         "[gep] wave %d: jobs %zu..%zu, planned %.2f GB of budget %.2f GB; free %.2f GB, "
+                         "pool live %.2f GB idle %.2f GB\n",
+                         sv.stats_.waves, k0, k1 - 1, used / 1e9, budget / 1e9, fb / 1e9,
+                         P->pool.live_bytes / 1e9, P->pool.idle_bytes / 1e9);
+        }
         sv.run_pass(jobs, BV.get(), L, Lw, cfg.M, res);
         for (auto& r : res) r.passes = 1;
         // refinement: jobs whose kept pairs miss tol (FEAST-type pass, V <- all Ritz vectors)
@@ -1790,7 +1966,10 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
             }
         }
         for (size_t i = 0; i < res.size(); ++i) finals[ord[k0 + i]] = res[i];
-        k0 = k1;
+        // this wave's factors are no longer needed: free them for the next wave
+        sv.band_F_.reset();
+        sv.band_wF_.reset();
+        sv.band_keys_.clear();
     }
     // per problem: selection, gather, merge
     const double wall_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -2097,6 +2276,10 @@ int gep_ci_solve_pencil(gep_pencil* P, const gep_contour* contours, int K, int N
                         double tol, const gep_opts* opts, gep_result** out) {
     if (!out || !P) { gep::set_error("NULL pencil or out"); return GEP_EINVAL; }
     *out = nullptr;
+    if (P->h.prob_n.size() != 1) {
+        gep::set_error("a batch pencil is solved with gep_ci_solve_pencil_batch");
+        return GEP_EINVAL;
+    }
     gep_opts o;
     if (opts) o = *opts; else gep_opts_default(&o);
     int st = validate_problem(contours, K, N, M, L, tol, &o);
@@ -2138,13 +2321,50 @@ int gep_ci_solve(const gep_csr* A, const gep_csr* B, const gep_contour* contours
     return st;
 }
 
-int gep_ci_solve_batch(int n_problems, const gep_csr* A, const gep_csr* B,
-                       const gep_contour* const* contours, const int* n_contours, int n_nodes,
-                       int moments, int block, double tol, const gep_opts* opts, gep_result** out) {
-    if (!out || n_problems <= 0 || !A || !B || !contours || !n_contours) {
+int gep_pencil_create_batch(int n_problems, const gep_csr* A, const gep_csr* B, int on_dev, void* stream,
+                            gep_pencil** out) {
+    (void)stream;
+    if (!out || n_problems <= 0 || !A || !B) {
+        gep::set_error("bad batch pencil arguments");
+        return GEP_EINVAL;
+    }
+    *out = nullptr;
+    auto* P = new gep_pencil();
+    try {
+        for (int p = 0; p < n_problems; ++p) {
+            gep::HostPencil h;
+            try {
+                gep::pack(&A[p], &B[p], on_dev != 0, h);
+            } catch (const gep::Fail& f) {
+                gep::set_error("problem " + std::to_string(p) + ": " + gep::g_err);
+                throw;
+            }
+            gep::append_pencil(P->h, h);
+        }
+        if (P->h.nnz >= (1ll << 31) - 1) gep::fail(GEP_EINVAL, "batch nnz >= 2^31");
+        gep::upload(P->h, P);
+    } catch (const gep::Fail& f) {
+        delete P;
+        return f.code;
+    }
+    *out = P;
+    return GEP_OK;
+}
+
+int gep_pencil_problems(const gep_pencil* p, int* n_problems) {
+    if (!p || !n_problems) return GEP_EINVAL;
+    *n_problems = (int)p->h.prob_n.size();
+    return GEP_OK;
+}
+
+int gep_ci_solve_pencil_batch(gep_pencil* P, const gep_contour* const* contours, const int* n_contours,
+                              int n_nodes, int moments, int block, double tol, const gep_opts* opts,
+                              gep_result** out) {
+    if (!out || !P || !contours || !n_contours) {
         gep::set_error("bad batch arguments");
         return GEP_EINVAL;
     }
+    const int n_problems = (int)P->h.prob_n.size();
     for (int p = 0; p < n_problems; ++p) out[p] = nullptr;
     gep_opts o;
     if (opts) o = *opts; else gep_opts_default(&o);
@@ -2156,7 +2376,6 @@ int gep_ci_solve_batch(int n_problems, const gep_csr* A, const gep_csr* B,
             return st;
         }
     }
-    auto* P = new gep_pencil();
     gep::SolveCfg cfg;
     cfg.N = n_nodes;
     cfg.NH = n_nodes / 2;
@@ -2164,24 +2383,39 @@ int gep_ci_solve_batch(int n_problems, const gep_csr* A, const gep_csr* B,
     cfg.L = block;
     cfg.tol = tol;
     cfg.o = o;
-    int st = GEP_OK;
     try {
-        for (int p = 0; p < n_problems; ++p) {
-            gep::HostPencil h;
-            gep::pack(&A[p], &B[p], o.inputs_on_device != 0, h);
-            gep::append_pencil(P->h, h);
-        }
-        if (P->h.nnz >= (1ll << 31) - 1) gep::fail(GEP_EINVAL, "batch nnz >= 2^31");
-        gep::upload(P->h, P);
-        st = gep::solve_batch_impl(P, n_problems, contours, n_contours, cfg, out);
+        return gep::solve_batch_impl(P, n_problems, contours, n_contours, cfg, out);
     } catch (const gep::Fail& f) {
         for (int p = 0; p < n_problems; ++p) {
             delete out[p];
             out[p] = nullptr;
         }
-        st = f.code;
+        return f.code;
     }
-    delete P;
+}
+
+int gep_ci_solve_batch(int n_problems, const gep_csr* A, const gep_csr* B,
+                       const gep_contour* const* contours, const int* n_contours, int n_nodes,
+                       int moments, int block, double tol, const gep_opts* opts, gep_result** out) {
+    if (!out || n_problems <= 0 || !A || !B || !contours || !n_contours) {
+        gep::set_error("bad batch arguments");
+        return GEP_EINVAL;
+    }
+    for (int p = 0; p < n_problems; ++p) out[p] = nullptr;
+    gep_opts o;
+    if (opts) o = *opts; else gep_opts_default(&o);
+    for (int p = 0; p < n_problems; ++p) {
+        int st = validate_problem(contours[p], n_contours[p], n_nodes, moments, block, tol, &o);
+        if (st) {
+            gep::set_error("problem " + std::to_string(p) + ": " + gep::g_err);
+            return st;
+        }
+    }
+    gep_pencil* P = nullptr;
+    int st = gep_pencil_create_batch(n_problems, A, B, o.inputs_on_device, o.stream, &P);
+    if (st) return st;
+    st = gep_ci_solve_pencil_batch(P, contours, n_contours, n_nodes, moments, block, tol, &o, out);
+    gep_pencil_free(P);
     return st;
 }
 

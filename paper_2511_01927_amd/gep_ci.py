@@ -58,7 +58,8 @@ EXPORTS = [
     "gep_gemm_tall",
     "gep_sym_eig", "gep_gaussian_block", "gep_ci_solve_batch", "gep_kde_contours",
     "gep_density_create", "gep_density_free", "gep_density_forward", "gep_density_grads",
-    "gep_density_adam", "gep_density_param", "gep_gemm_bf16",
+    "gep_density_adam", "gep_density_param", "gep_gemm_bf16", "gep_pencil_create_batch",
+    "gep_pencil_problems", "gep_ci_solve_pencil_batch",
 ]
 
 _lib = None
@@ -107,6 +108,10 @@ def load():
         "gep_density_adam": (i32, [P, C.c_float, C.c_float, C.c_float, C.c_float, P]),
         "gep_density_param": (i32, [P, i32, i32, P, i32]),
         "gep_gemm_bf16": (i32, [P, i64, i64, P, i64, i64, P, i64, i32, i32, i32, P]),
+        "gep_pencil_create_batch": (i32, [i32, C.POINTER(gep_csr), C.POINTER(gep_csr), i32, P, C.POINTER(P)]),
+        "gep_pencil_problems": (i32, [P, C.POINTER(C.c_int)]),
+        "gep_ci_solve_pencil_batch": (i32, [P, C.POINTER(C.POINTER(gep_contour)), C.POINTER(C.c_int), i32, i32,
+                                            i32, dbl, C.POINTER(gep_opts), C.POINTER(P)]),
         "gep_ci_solve_batch": (i32, [i32, C.POINTER(gep_csr), C.POINTER(gep_csr),
                                      C.POINTER(C.POINTER(gep_contour)), C.POINTER(C.c_int), i32, i32,
                                      i32, dbl, C.POINTER(gep_opts), C.POINTER(P)]),
@@ -274,6 +279,49 @@ def gep_ci_solve_batch(problems, n_nodes, moments, block, tol, **kw):
     st = lib.gep_ci_solve_batch(P, As, Bs, cptr, nks, n_nodes, moments, block, tol, C.byref(o), outs)
     _check(st, allow_warn=True)
     return [_collect(C.c_void_p(outs[p]), st) for p in range(P)]
+
+
+class BatchPencil:
+    """Several pencils packed once, device-resident (gep_pencil_create_batch)."""
+
+    def __init__(self, pairs, stream=None):
+        lib = load()
+        hosts = [(_HostCSR(a), _HostCSR(b)) for a, b in pairs]
+        P = len(hosts)
+        As = (gep_csr * P)(*[h[0].s for h in hosts])
+        Bs = (gep_csr * P)(*[h[1].s for h in hosts])
+        h = C.c_void_p()
+        _check(lib.gep_pencil_create_batch(P, As, Bs, 0, _stream_ptr(stream), C.byref(h)))
+        self.h = h
+        cnt = C.c_int()
+        _check(lib.gep_pencil_problems(h, C.byref(cnt)))
+        self.n_problems = cnt.value
+
+    def solve(self, contours_list, n_nodes, moments, block, tol, **kw):
+        """contours_list[p]: the circles of problem p; returns a list of result dicts."""
+        lib = load()
+        P = self.n_problems
+        if len(contours_list) != P:
+            raise ValueError(f"{P} problems, {len(contours_list)} contour sets")
+        conts = [_contours(c) for c in contours_list]
+        cptr = (C.POINTER(gep_contour) * P)(*[C.cast(c[0], C.POINTER(gep_contour)) for c in conts])
+        nks = (C.c_int * P)(*[c[1] for c in conts])
+        o, keep = _opts(**kw)
+        outs = (C.c_void_p * P)()
+        st = lib.gep_ci_solve_pencil_batch(self.h, cptr, nks, n_nodes, moments, block, tol, C.byref(o), outs)
+        _check(st, allow_warn=True)
+        return [_collect(C.c_void_p(outs[p]), st) for p in range(P)]
+
+    def free(self):
+        if getattr(self, "h", None):
+            load().gep_pencil_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 class Pencil:

@@ -142,3 +142,57 @@ def config_fd7_3d(m: int = 64, first: int = 2000, last: int = 2500, k: int = 4,
 # 8 moments give each a 512-dimensional subspace at no extra solve cost).
 def fd7_3d_64() -> Workload:
     return config_fd7_3d()
+
+
+@dataclass
+class Batch:
+    """A batch of independent pencils, each with its own circles."""
+    name: str
+    problems: list                # list of Workload
+    n_nodes: int
+    moments: int
+    block: int
+    seed: int                     # problem p draws its right-hand sides from seed + p
+    tol: float = 1e-8
+    meta: dict = field(default_factory=dict)
+
+
+def config_q1_batch(count: int = 64, seed0: int = 4000, nmin: int = 5000, nmax: int = 200000,
+                    cmin: int = 20, cmax: int = 300, per_contour: int = 50, alpha: float = 0.1,
+                    sigma: float = 1.0, n_nodes: int = 32, moments: int = 4, block: int = 32,
+                    seed: int = 1004) -> Batch:
+    """Batch of variable-coefficient 2D Q1 pencils of uneven sizes.
+
+    Instance b (generator seeded with seed0 + b): n log-uniform in
+    [nmin, nmax], aspect ratio nx / ny uniform in [0.5, 2], element
+    coefficient exp(GRF) with standard deviation sigma (field seed seed0 + b),
+    a target count c ~ U{cmin..cmax} of eigenvalues placed by Weyl's law at
+    the interior indices [2c, 3c), and ceil(c / per_contour) uniform circles.
+    """
+    probs = []
+    for b in range(count):
+        rng = np.random.default_rng(seed0 + b)
+        n = float(np.exp(rng.uniform(np.log(nmin), np.log(nmax))))
+        ar = float(rng.uniform(0.5, 2.0))
+        nx = max(8, int(round(np.sqrt(n * ar))))
+        ny = max(8, int(round(n / nx)))
+        c = int(rng.integers(cmin, cmax + 1))
+        g = pencils.grf((ny + 1, nx + 1), seed=seed0 + b, sigma=sigma)
+        kap = np.exp(g)
+        A, B = pencils.q1_2d(nx, ny, kap)
+        lo = weyl_index_to_lambda(kap, 2 * c, dim=2)
+        hi = weyl_index_to_lambda(kap, 3 * c, dim=2)
+        k = int(np.ceil(c / per_contour))
+        cont = uniform_contours(lo, hi, k, alpha)
+        probs.append(Workload(f"q1_{nx}x{ny}_b{b}", A, B, cont, n_nodes, moments, block, seed + b,
+                              window=(lo, hi), meta={"target_count": c, "nx": nx, "ny": ny}))
+    return Batch(f"q1_batch{count}", probs, n_nodes, moments, block, seed,
+                 meta={"seed0": seed0, "nmin": nmin, "nmax": nmax})
+
+
+# Batch configuration: 64 uneven 2D Q1 pencils (n log-uniform in [5k, 200k],
+# log-normal coefficients with sigma 1), 20-300 eigenvalues each over
+# ceil(count / 50) circles, 32 nodes, 4 moments, 32 right-hand sides.
+def q1_batch64() -> Batch:
+    return config_q1_batch()
+
