@@ -57,6 +57,14 @@ extern "C" {
                                strongest): eigenvalues may be missed; split the
                                contour or raise block*moments */
 
+/* ---- method ------------------------------------------------------------ */
+#define GEP_CIRR 0          /* moment-based CI (the block V, M moments, one pass, then
+                               FEAST-type refinement passes if a kept pair misses tol) */
+#define GEP_FEAST 1         /* FEAST subspace iteration (paper appendix, "Algorithm
+                               Families"): one moment, and up to max_refine further
+                               passes with V <- the contour's Ritz vectors until every
+                               kept pair meets tol; block >= the contour's count */
+
 /* ---- precision of the shifted solves --------------------------------- */
 #define GEP_FP64 0          /* FP64 complex COCG throughout */
 #define GEP_MIXED 1         /* shifted solves in FP32 complex (COCG with FP64
@@ -131,6 +139,7 @@ typedef struct {
                                factors of half bandwidth <= 1024, wide-band
                                kernels otherwise; 2 = wide-band kernels always
                                (1 is the same as 0).  Results agree to rounding. */
+    int method;             /* GEP_CIRR (default) or GEP_FEAST */
     int band_group;         /* wide-band kernels: factor at most this many shifted
                                systems at once (0, the default: as many as the
                                device memory holds); each group is factored,
@@ -224,6 +233,24 @@ int gep_pencil_problems(const gep_pencil* p, int* n_problems);
 int gep_ci_solve_pencil_batch(gep_pencil* p, const gep_contour* const* contours, const int* n_contours,
                               int n_nodes, int moments, int block, double tol, const gep_opts* opts,
                               gep_result** out);
+
+/* The m smallest eigenpairs with eigenvalue >= lower (the paper's target of
+ * the M smallest eigenvalues, Sec. 5 "Experiment Settings"), on a pencil of
+ * one problem.  The upper end of the window is not known.  The first window
+ * is [lower, lower + (m / n)^2 (lmax - lower)), lmax from a power iteration
+ * on diag(B)^-1 A (the count grows no faster than (lambda / lmax)^(1/2) n
+ * on 1D-3D grids, so it holds at most about m); while fewer than m pairs are
+ * found the covered range is extended by the density found so far, in
+ * uniform circles of about per_contour expected eigenvalues (radius 1.1 x
+ * half the circle's interval).  A circle whose subspace is saturated or that
+ * leaves a kept pair above tol is solved again as three circles (at most
+ * four times).  Each round is solved as gep_ci_solve_pencil does.  *out
+ * holds the m smallest pairs found (fewer, with GEP_WNOCONV, if the rounds
+ * ran out); contour ids count the circles of all rounds; the statistics
+ * list each round's.  With equal eigenvalues at the cut, which of their
+ * vectors is returned is open. */
+int gep_ci_solve_smallest(gep_pencil* p, int64_t m, double lower, int per_contour, int n_nodes,
+                          int moments, int block, double tol, const gep_opts* opts, gep_result** out);
 
 /* Shifted complex SpMM, Y[:, c] = z_c B X[:, c] - A X[:, c] (quadrature
  * equation's operator), FP64 complex, on the tiled layout: column c of an

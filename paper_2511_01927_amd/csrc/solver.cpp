@@ -483,6 +483,7 @@ struct gep_result {
     std::unique_ptr<gep::DBuf<double>> dvecs;   // eigenvectors on the device, n x m column-major
     std::vector<int32_t> cid;
     std::vector<uint8_t> conv;
+    std::vector<uint8_t> csat;   // per contour: subspace saturated
     std::string stats;
 };
 
@@ -1753,6 +1754,7 @@ static std::string json_stats(const Solver& s, double wall_ms, const std::vector
     // pass solved in FP32); precision_requested: the caller's option
     o << "{\"wall_ms\":" << wall_ms << ",\"precision\":\"" << (s.stats_.fp32_passes > 0 ? "mixed" : "fp64")
       << "\",\"precision_requested\":\"" << (precision == GEP_MIXED ? "mixed" : "fp64")
+      << "\",\"method\":\"" << (s.c_.o.method == GEP_FEAST ? "feast" : "cirr")
       << "\",\"fp32_passes\":" << s.stats_.fp32_passes << ",\"solver_run\":\""
       << (s.stats_.band_factorisations > 0 ? (s.stats_.cocg_iters > 0 ? "band+cocg" : "band") : "cocg")
       << "\",\"cocg_iters\":" << s.stats_.cocg_iters << ",\"tile_iters\":" << s.stats_.tile_iters
@@ -2135,6 +2137,7 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
         }
         HIPCHK(hipStreamSynchronize(s));
         R->m = (int64_t)R->evals.size();
+        for (const ContourOut& co : mine) R->csat.push_back(co.saturated ? 1 : 0);
         R->stats = json_stats(sv, wall_solve, mine, cfg.o.precision);
         R->stats.insert(1, "\"wall_select_ms\":" +
                                std::to_string(std::chrono::duration<double, std::milli>(
@@ -2252,6 +2255,10 @@ static int validate_problem(const gep_contour* contours, int K, int N, int M, in
         gep::set_error("solver must be 0 (automatic), 1 (COCG) or 2 (band)");
         return GEP_EINVAL;
     }
+    if (o->method != GEP_CIRR && o->method != GEP_FEAST) {
+        gep::set_error("method must be GEP_CIRR (0) or GEP_FEAST (1)");
+        return GEP_EINVAL;
+    }
     if (o->band_group < 0) {
         gep::set_error("band_group must be >= 0");
         return GEP_EINVAL;
@@ -2293,7 +2300,7 @@ int gep_ci_solve_pencil(gep_pencil* P, const gep_contour* contours, int K, int N
     gep::SolveCfg cfg;
     cfg.N = N;
     cfg.NH = N / 2;
-    cfg.M = M;
+    cfg.M = o.method == GEP_FEAST ? 1 : M;
     cfg.L = L;
     cfg.tol = tol;
     cfg.o = o;
@@ -2379,7 +2386,7 @@ int gep_ci_solve_pencil_batch(gep_pencil* P, const gep_contour* const* contours,
     gep::SolveCfg cfg;
     cfg.N = n_nodes;
     cfg.NH = n_nodes / 2;
-    cfg.M = moments;
+    cfg.M = o.method == GEP_FEAST ? 1 : moments;
     cfg.L = block;
     cfg.tol = tol;
     cfg.o = o;
@@ -2417,6 +2424,164 @@ int gep_ci_solve_batch(int n_problems, const gep_csr* A, const gep_csr* B,
     st = gep_ci_solve_pencil_batch(P, contours, n_contours, n_nodes, moments, block, tol, &o, out);
     gep_pencil_free(P);
     return st;
+}
+
+int gep_ci_solve_smallest(gep_pencil* P, int64_t m, double lower, int per_contour, int n_nodes, int moments,
+                          int block, double tol, const gep_opts* opts, gep_result** out) {
+    if (!out || !P) { gep::set_error("NULL pencil or out"); return GEP_EINVAL; }
+    *out = nullptr;
+    if (P->h.prob_n.size() != 1) { gep::set_error("one pencil per call"); return GEP_EINVAL; }
+    const int64_t n = P->h.n;
+    if (m < 1 || m > n) { gep::set_error("m must be in [1, n]"); return GEP_EINVAL; }
+    if (per_contour < 1) { gep::set_error("per_contour must be >= 1"); return GEP_EINVAL; }
+    if (!std::isfinite(lower)) { gep::set_error("lower must be finite"); return GEP_EINVAL; }
+    gep_opts o;
+    if (opts) o = *opts; else gep_opts_default(&o);
+    o.blocks = nullptr;
+    const gep::HostPencil& H = P->h;
+    try {
+        // largest eigenvalue estimate: power iteration on diag(B)^-1 A, its
+        // Rayleigh quotient x^T A x / x^T B x (only the first window uses it)
+        std::vector<double> x((size_t)n), y((size_t)n);
+        uint64_t st = 0x9e3779b97f4a7c15ull;
+        for (int64_t i = 0; i < n; ++i) {
+            st ^= st << 13;
+            st ^= st >> 7;
+            st ^= st << 17;
+            x[i] = (double)(st >> 11) / 9007199254740992.0 - 0.5;
+        }
+        double lmax = 0.0;
+        for (int it = 0; it < 60; ++it) {
+            double xax = 0.0, xbx = 0.0, nrm = 0.0;
+            for (int64_t i = 0; i < n; ++i) {
+                double ax = 0.0, bx = 0.0;
+                for (int32_t e = H.rowptr[i]; e < H.rowptr[i + 1]; ++e) {
+                    ax += H.a[e] * x[H.colind[e]];
+                    bx += H.b[e] * x[H.colind[e]];
+                }
+                xax += x[i] * ax;
+                xbx += x[i] * bx;
+                y[i] = ax / H.dB[i];
+                nrm += y[i] * y[i];
+            }
+            if (xbx > 0) lmax = std::max(lmax, xax / xbx);
+            nrm = std::sqrt(nrm);
+            if (!(nrm > 0)) break;
+            for (int64_t i = 0; i < n; ++i) x[i] = y[i] / nrm;
+        }
+        if (!(lmax > lower)) gep::fail(GEP_EINVAL, "no spectrum above the lower bound");
+        struct Found {
+            double lam, rho;
+            int cid;
+            const gep_result* res;
+            int col;
+        };
+        struct Span {
+            double a, b;
+            int depth;
+        };
+        std::vector<std::unique_ptr<gep_result, void (*)(gep_result*)>> rounds;
+        std::vector<Found> found;
+        // The first window assumes the fastest growth of the count with the
+        // eigenvalue among 1D-3D Weyl laws (N ~ n (lambda / lmax)^(1/2)), so it
+        // holds at most about m; later windows are sized by the density found
+        // so far.  A circle whose subspace is saturated or that leaves a kept
+        // pair above tol is solved again as three circles.
+        double covered = lower;
+        double first = lower + (lmax - lower) * std::min(1.0, std::pow((double)m / (double)n, 2.0));
+        std::vector<Span> pending{{lower, first, 0}};
+        covered = first;
+        int circle0 = 0, worst = GEP_OK, windows = 1;
+        for (int round = 0; round < 40 && !pending.empty(); ++round) {
+            const int K = (int)pending.size();
+            std::vector<gep_contour> cs(K);
+            for (int k = 0; k < K; ++k) {
+                const double a = pending[k].a, b = pending[k].b;
+                cs[k] = {0.5 * (a + b), 0.55 * (b - a), a, b};
+            }
+            gep::SolveCfg cfg;
+            cfg.N = n_nodes;
+            cfg.NH = n_nodes / 2;
+            cfg.M = o.method == GEP_FEAST ? 1 : moments;
+            cfg.L = block;
+            cfg.tol = tol;
+            cfg.o = o;
+            int stv = validate_problem(cs.data(), K, n_nodes, moments, block, tol, &o);
+            if (stv) return stv;
+            gep_result* r = nullptr;
+            stv = gep::solve_impl(P, cs.data(), K, cfg, &r);
+            if (stv < 0) return stv;
+            rounds.emplace_back(r, gep_result_free);
+            std::vector<char> bad(K, 0);
+            for (int k = 0; k < K; ++k) bad[k] = k < (int)r->csat.size() && r->csat[k];
+            for (int64_t q = 0; q < r->m; ++q)
+                if (!r->conv[q]) bad[r->cid[q]] = 1;
+            std::vector<Span> next;
+            for (int k = 0; k < K; ++k) {
+                if (bad[k] && pending[k].depth < 4) {
+                    const double a = pending[k].a, w3 = (pending[k].b - a) / 3.0;
+                    for (int t = 0; t < 3; ++t) next.push_back({a + t * w3, a + (t + 1) * w3, pending[k].depth + 1});
+                    continue;
+                }
+                if (bad[k]) worst = GEP_WNOCONV;
+                for (int64_t q = 0; q < r->m; ++q)
+                    if (r->cid[q] == k) found.push_back({r->evals[q], r->resid[q], circle0 + k, r, (int)q});
+            }
+            circle0 += K;
+            if (next.empty() && (int64_t)found.size() < m && covered < lmax * 1.5) {
+                // extend the covered range by the density found so far
+                const double width = covered - lower;
+                double ext = found.empty() ? 2.0 * width
+                                           : 1.25 * (double)(m - (int64_t)found.size()) * width / (double)found.size();
+                ext = std::max(ext, 0.05 * width);
+                const double b = std::min(covered + ext, lmax * 1.5);
+                const double expect = found.empty() ? (double)m : (double)found.size() / width * (b - covered);
+                const int Kn = std::max(1, (int)std::ceil(expect / per_contour));
+                for (int k = 0; k < Kn; ++k)
+                    next.push_back({covered + (b - covered) * k / Kn, covered + (b - covered) * (k + 1) / Kn, 0});
+                covered = b;
+                ++windows;
+            }
+            pending = next;
+        }
+        double lo = covered;
+        std::stable_sort(found.begin(), found.end(), [](const Found& a, const Found& b) { return a.lam < b.lam; });
+        const int64_t keep = std::min<int64_t>(m, (int64_t)found.size());
+        auto* R = new gep_result();
+        R->n = n;
+        if (keep) {
+            gep::PoolScope own(nullptr);
+            R->dvecs = std::make_unique<gep::DBuf<double>>((size_t)n * keep);
+        }
+        bool noconv = false;
+        for (int64_t a = 0; a < keep; ++a) {
+            const Found& f = found[a];
+            R->evals.push_back(f.lam);
+            R->resid.push_back(f.rho);
+            R->cid.push_back(f.cid);
+            R->conv.push_back(f.rho <= tol ? 1 : 0);
+            noconv |= !(f.rho <= tol);
+            HIPCHK(hipMemcpy(R->dvecs->get() + a * n, f.res->dvecs->get() + (size_t)f.col * n, sizeof(double) * n,
+                             hipMemcpyDeviceToDevice));
+        }
+        R->m = keep;
+        std::ostringstream js;
+        js << "{\"rounds\":" << rounds.size() << ",\"windows\":" << windows << ",\"circles\":" << circle0
+           << ",\"found\":" << found.size() << ",\"lmax_estimate\":" << lmax << ",\"window_hi\":" << lo
+           << ",\"round_stats\":[";
+        for (size_t i = 0; i < rounds.size(); ++i) js << (i ? "," : "") << rounds[i]->stats;
+        js << "]}";
+        R->stats = js.str();
+        *out = R;
+        if ((int64_t)found.size() < m) {
+            gep::set_error("found only " + std::to_string(found.size()) + " of " + std::to_string(m) +
+                           " eigenpairs below " + std::to_string(lo));
+            return GEP_WNOCONV;
+        }
+        return noconv ? GEP_WNOCONV : worst;
+    } catch (const gep::Fail& f) {
+        return f.code;
+    }
 }
 
 int gep_result_count(const gep_result* r, int64_t* m, int64_t* n) {

@@ -46,7 +46,7 @@ class gep_opts(C.Structure):
                 ("mem_limit_bytes", C.c_double), ("timing", C.c_int), ("rows_per_block", C.c_int),
                 ("verbose", C.c_int), ("use_graph", C.c_int), ("blocks", C.c_void_p),
                 ("row_group", C.c_int), ("solver", C.c_int), ("band_kernels", C.c_int),
-                ("band_group", C.c_int)]
+                ("method", C.c_int), ("band_group", C.c_int)]
 
 
 # every symbol declared in include/gep_ci.h
@@ -59,7 +59,7 @@ EXPORTS = [
     "gep_sym_eig", "gep_gaussian_block", "gep_ci_solve_batch", "gep_kde_contours",
     "gep_density_create", "gep_density_free", "gep_density_forward", "gep_density_grads",
     "gep_density_adam", "gep_density_param", "gep_gemm_bf16", "gep_pencil_create_batch",
-    "gep_pencil_problems", "gep_ci_solve_pencil_batch",
+    "gep_pencil_problems", "gep_ci_solve_pencil_batch", "gep_ci_solve_smallest",
 ]
 
 _lib = None
@@ -110,6 +110,7 @@ def load():
         "gep_gemm_bf16": (i32, [P, i64, i64, P, i64, i64, P, i64, i32, i32, i32, P]),
         "gep_pencil_create_batch": (i32, [i32, C.POINTER(gep_csr), C.POINTER(gep_csr), i32, P, C.POINTER(P)]),
         "gep_pencil_problems": (i32, [P, C.POINTER(C.c_int)]),
+        "gep_ci_solve_smallest": (i32, [P, i64, dbl, i32, i32, i32, i32, dbl, C.POINTER(gep_opts), C.POINTER(P)]),
         "gep_ci_solve_pencil_batch": (i32, [P, C.POINTER(C.POINTER(gep_contour)), C.POINTER(C.c_int), i32, i32,
                                             i32, dbl, C.POINTER(gep_opts), C.POINTER(P)]),
         "gep_ci_solve_batch": (i32, [i32, C.POINTER(gep_csr), C.POINTER(gep_csr),
@@ -177,7 +178,7 @@ def _contours(contours):
 
 def _opts(seed=1, precision="fp64", max_refine=1, solve_tol=1e-9, max_iter=100000, check_every=16,
           stream=None, on_device=0, rhs=None, mem_limit_bytes=0.0, timing=False, rows_per_block=0, verbose=0, use_graph=True, blocks=None,
-          row_group=0, solver="auto", band_kernels=0, band_group=0):
+          row_group=0, solver="auto", band_kernels=0, band_group=0, method="cirr"):
     lib = load()
     o = gep_opts()
     lib.gep_opts_default(C.byref(o))
@@ -208,6 +209,7 @@ def _opts(seed=1, precision="fp64", max_refine=1, solve_tol=1e-9, max_iter=10000
     o.band_kernels = {"auto": 0, "narrow": 1, "wide": 2}[band_kernels] if isinstance(band_kernels, str) \
         else int(band_kernels)
     o.band_group = band_group
+    o.method = {"cirr": 0, "feast": 1}[method] if isinstance(method, str) else int(method)
     if blocks is not None:
         bl = np.ascontiguousarray(blocks, dtype=np.int32)
         o.blocks = bl.ctypes.data
@@ -347,6 +349,16 @@ class Pencil:
         out = C.c_void_p()
         st = lib.gep_ci_solve_pencil(self.h, cs, K, n_nodes, moments, block, tol, C.byref(o),
                                      C.byref(out))
+        _check(st, allow_warn=True)
+        return _collect(out, st)
+
+    def solve_smallest(self, m, lower=0.0, per_contour=50, n_nodes=32, moments=4, block=32, tol=1e-8, **kw):
+        """The m smallest eigenpairs with eigenvalue >= lower (gep_ci_solve_smallest)."""
+        lib = load()
+        o, keep = _opts(**kw)
+        out = C.c_void_p()
+        st = lib.gep_ci_solve_smallest(self.h, m, lower, per_contour, n_nodes, moments, block, tol,
+                                       C.byref(o), C.byref(out))
         _check(st, allow_warn=True)
         return _collect(out, st)
 

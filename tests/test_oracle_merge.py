@@ -207,3 +207,18 @@ def test_planted_mistakes_break_the_merge_pins(monkeypatch):
         monkeypatch.setattr(cirr, "dedupe", bad)
         res = oracle.oracle_ci_solve(A, B, cont, 32, 4, 24, 1e-8, seed=4)
         assert res["evals"].size != ref.size, bad.__name__
+
+
+def test_oracle_feast_iteration_reaches_closed_form():
+    """One moment and refinement passes (V <- Ritz vectors) is FEAST subspace
+    iteration; with a subspace larger than the window's count it converges
+    to the closed form, and a single pass does not."""
+    w = configs.config_fem1d(n=2000, n_nodes=16, moments=4, block=32)
+    ref = configs.line_eigs(2000)[100:120]
+    one = oracle.oracle_ci_solve(w.A, w.B, w.contours, 16, 1, 32, w.tol, seed=w.seed, max_refine=0)
+    assert one["evals"].size != 20 or np.max(one["resid"]) > w.tol
+    res = oracle.oracle_ci_solve(w.A, w.B, w.contours, 16, 1, 32, w.tol, seed=w.seed, max_refine=8)
+    assert res["info"][0]["passes"] >= 2
+    assert res["evals"].size == 20
+    assert np.max(np.abs(res["evals"] - ref) / ref) <= 1e-10
+    assert np.max(res["resid"]) <= w.tol
