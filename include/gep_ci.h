@@ -336,6 +336,14 @@ int gep_kde_contours(const double* lam_hat, int64_t m, int nmin, int nmax, doubl
                      double beta, double window_lo, double window_hi, gep_contour* out, int cap,
                      int* count);
 
+/* Input of the spectral-density network (paper Sec. 4.1: the predictor
+ * reads the discretised coefficient field): block averages of a row-major
+ * FP32 field g[nz][ny][nx] (DEVICE) onto a side^3 grid (side^2 when nz == 1)
+ * written to out (DEVICE, cells ordered [z][y][x]).  Cell c along an axis of
+ * n entries averages the entries a with floor(a side / n) == c.  Requires
+ * side <= each dimension (> 1).  The stream is synchronised. */
+int gep_field_downsample(const float* g, int nz, int ny, int nx, int side, float* out, void* stream);
+
 /* Spectral-density network: 3-layer MLP din -> dhidden -> dhidden -> dout,
  * GELU, BF16 matrix-core GEMMs with FP32 accumulation, FP32 master weights
  * and Adam state (paper Sec. 4.1: the learned spectral predictor, trained

@@ -223,7 +223,54 @@ int fwd(gep_density* N, const float* X, int B, hipStream_t s) {
 
 }  // namespace
 
+// Block averages of a 3D (or, with nz = 1, 2D) row-major field [z][y][x]
+// onto a side^3 (side^2) grid: cell (cz, cy, cx) averages the entries whose
+// index along each axis a maps to c = floor(a * side / n_axis).  One thread
+// per output cell; the sum runs over the cell's index ranges in order.
+__global__ void k_downsample(const float* __restrict__ g, int nz, int ny, int nx, int sz, int side,
+                             float* __restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int cells = sz * side * side;
+    if (c >= cells) return;
+    const int cz = c / (side * side), cy = (c / side) % side, cx = c % side;
+    // index ranges [lo, hi) of each axis mapping to the cell
+    auto range = [](int cidx, int n, int sd, int& lo, int& hi) {
+        lo = (int)(((int64_t)cidx * n + sd - 1) / sd);
+        hi = (int)(((int64_t)(cidx + 1) * n + sd - 1) / sd);
+    };
+    int z0, z1, y0, y1, x0, x1;
+    range(cz, nz, sz, z0, z1);
+    range(cy, ny, side, y0, y1);
+    range(cx, nx, side, x0, x1);
+    double acc = 0.0;
+    int64_t cnt = 0;
+    for (int z = z0; z < z1; ++z)
+        for (int y = y0; y < y1; ++y)
+            for (int x = x0; x < x1; ++x) {
+                acc += g[((int64_t)z * ny + y) * nx + x];
+                ++cnt;
+            }
+    out[c] = cnt ? (float)(acc / (double)cnt) : 0.0f;
+}
+
 extern "C" {
+
+int gep_field_downsample(const float* g, int nz, int ny, int nx, int side, float* out, void* stream) {
+    if (!g || !out || nz < 1 || ny < 1 || nx < 1 || side < 1 || side > ny || side > nx ||
+        (nz > 1 && side > nz)) {
+        set_error("bad downsample arguments");
+        return GEP_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int sz = nz > 1 ? side : 1;
+    const int cells = sz * side * side;
+    hipLaunchKernelGGL(k_downsample, dim3((cells + 255) / 256), dim3(256), 0, s, g, nz, ny, nx, sz, side, out);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        set_error("downsample kernel failed");
+        return GEP_EDEVICE;
+    }
+    return GEP_OK;
+}
 
 int gep_density_create(int din, int dhidden, int dout, int max_batch, uint64_t seed, gep_density** out) {
     if (!out || din <= 0 || dhidden <= 0 || dout <= 0 || max_batch <= 0) {

@@ -60,6 +60,7 @@ EXPORTS = [
     "gep_density_create", "gep_density_free", "gep_density_forward", "gep_density_grads",
     "gep_density_adam", "gep_density_param", "gep_gemm_bf16", "gep_pencil_create_batch",
     "gep_pencil_problems", "gep_ci_solve_pencil_batch", "gep_ci_solve_smallest",
+    "gep_field_downsample",
 ]
 
 _lib = None
@@ -102,6 +103,7 @@ def load():
         "gep_kde_contours": (i32, [P, i64, i32, i32, dbl, dbl, dbl, dbl, dbl, P, i32,
                                    C.POINTER(C.c_int)]),
         "gep_density_create": (i32, [i32, i32, i32, i32, C.c_uint64, C.POINTER(P)]),
+        "gep_field_downsample": (i32, [P, i32, i32, i32, i32, P, P]),
         "gep_density_free": (None, [P]),
         "gep_density_forward": (i32, [P, P, i32, P, P]),
         "gep_density_grads": (i32, [P, P, P, i32, C.POINTER(dbl), P]),
@@ -433,6 +435,13 @@ def gep_kde_contours(lam_hat, nmin=10, nmax=50, w=10.0, alpha=0.1, beta=0.0, win
     _check(lib.gep_kde_contours(lam.ctypes.data, lam.size, nmin, nmax, w, alpha, beta, lo, hi, buf,
                                 cnt.value, C.byref(cnt)))
     return np.array([[c.center, c.radius, c.keep_lo, c.keep_hi] for c in buf[:cnt.value]]).reshape(-1, 4)
+
+
+def gep_field_downsample(g, side, out, stream=None):
+    """Block averages of a device FP32 field (nz, ny, nx) or (ny, nx) onto side^3 (side^2) cells."""
+    shape = tuple(g.shape)
+    nz, ny, nx = (1,) + shape if len(shape) == 2 else shape
+    _check(load().gep_field_downsample(g.data_ptr(), nz, ny, nx, side, out.data_ptr(), _stream_ptr(stream)))
 
 
 class DensityNet:

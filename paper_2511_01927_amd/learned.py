@@ -6,8 +6,10 @@ network (Sec. 4.1), build contours with KDE (Sec. 4.2, Alg. "Adaptive
 Contour Construction via KDE"), then run the CI solver.  Here:
 
 * the network is the library's BF16-matrix-core MLP (``gep_density_*``) that
-  maps a 16 x 16 downsample of log(kappa) to a histogram of the eigenvalues
-  over a target window, in units of the mean count per bin;
+  maps a block-averaged downsample of log(kappa) (16 x 16 for 2D fields,
+  8^3 for 3D ones, the latter by ``gep_field_downsample`` on the GPU) to a
+  histogram of the eigenvalues over a target window, in units of the mean
+  count per bin;
 * labels come from this library's own CI solves (``gep_ci_solve_batch``);
 * predicted eigenvalue positions are the histogram's quantile points, fed to
   ``gep_kde_contours``;
@@ -43,6 +45,31 @@ def field_features(g: np.ndarray, side: int = FEATURE_SIDE) -> np.ndarray:
     return (out / np.maximum(cnt, 1)).astype(np.float32).ravel()
 
 
+def field_features_3d(g: np.ndarray, side: int = 8) -> np.ndarray:
+    """Block-average a 3D log-coefficient field onto side^3 cells on the GPU
+    (gep_field_downsample); returns float32 features ordered [z][y][x]."""
+    import torch
+    dev = torch.device("cuda:0")
+    gd = torch.from_numpy(np.ascontiguousarray(g, dtype=np.float32)).to(dev)
+    out = torch.zeros(side ** 3, dtype=torch.float32, device=dev)
+    gep_ci.gep_field_downsample(gd, side, out)
+    return out.cpu().numpy()
+
+
+def weyl_count_3d(kappa: np.ndarray, lam) -> np.ndarray:
+    """Weyl's law for -div(kappa grad u) = lambda u on the unit cube:
+    N(lambda) ~ lambda^(3/2) mean(kappa^(-3/2)) / (6 pi^2)."""
+    m = float(np.mean(np.asarray(kappa, dtype=np.float64) ** -1.5))
+    return np.asarray(lam, dtype=np.float64) ** 1.5 * m / (6.0 * math.pi ** 2)
+
+
+def weyl_window_3d(kappa: np.ndarray, first: int, last: int):
+    """Window [lambda(first), lambda(last)] by the 3D Weyl law."""
+    m = float(np.mean(np.asarray(kappa, dtype=np.float64) ** -1.5))
+    lam = lambda k: (6.0 * math.pi ** 2 * k / m) ** (2.0 / 3.0)
+    return lam(first), lam(last)
+
+
 def weyl_window_2d(kappa: np.ndarray, first: int, last: int):
     """Window [lambda(first), lambda(last)] by Weyl's law N(lam) ~ lam mean(1/kappa) / (4 pi)."""
     m = float(np.mean(1.0 / kappa))
@@ -71,12 +98,12 @@ def quantile_points(hist: np.ndarray, window, expected: float) -> np.ndarray:
 class SpectralPrior:
     """Density network + training loop on the library's kernels."""
 
-    def __init__(self, n_bins=32, hidden=256, max_batch=256, seed=1, device=None):
+    def __init__(self, n_bins=32, hidden=256, max_batch=256, seed=1, device=None, din=None):
         import torch
         self.torch = torch
         self.dev = device or torch.device("cuda:0")
         self.n_bins = n_bins
-        self.net = gep_ci.DensityNet(FEATURE_SIDE * FEATURE_SIDE, hidden, n_bins, max_batch, seed)
+        self.net = gep_ci.DensityNet(din or FEATURE_SIDE * FEATURE_SIDE, hidden, n_bins, max_batch, seed)
         self.max_batch = max_batch
 
     def train(self, X: np.ndarray, T: np.ndarray, epochs=200, batch=32, lr=1e-3, seed=0, log=None):
