@@ -236,6 +236,20 @@ def main_batch(args):
     conts = [w.contours for w in bt.problems]
     kw = dict(seed=bt.seed, precision=args.precision, solve_tol=args.solve_tol, stream=stream,
               solver=args.solver, verbose=args.verbose)
+    tuned = None
+    if not args.no_autotune:
+        # kernel-variant choice by the project's autotuner (timed solves of
+        # this batch, cached by shape); untimed
+        from paper_2511_01927_amd import autotune
+        nnz = sum(w.A.nnz for w in bt.problems) / sum(w.n for w in bt.problems)
+        key = autotune.shape_key(sum(w.n for w in bt.problems), max(w.meta["nx"] + 1 for w in bt.problems),
+                                 nnz, sum(len(w.contours) for w in bt.problems) * bt.n_nodes // 2 * bt.block,
+                                 args.precision, args.solver, len(bt.problems))
+        path = os.environ.get("GEPCI_TUNE_CACHE", autotune.DEFAULT_CACHE)
+        tuned = autotune.tune(lambda **o: bp.solve(conts, bt.n_nodes, bt.moments, bt.block, bt.tol, **kw, **o),
+                              key, autotune.BAND_CANDIDATES, cache_path=path, repeats=1,
+                              log=lambda m: print("# " + m, flush=True))
+        kw.update(tuned)
     for i in range(args.warmup):
         r = bp.solve(conts, bt.n_nodes, bt.moments, bt.block, bt.tol, **kw)
         print(f"# warmup {i}: {sum(x['evals'].size for x in r)} pairs, {r[0]['stats']['wall_ms']:.0f} ms",
@@ -256,8 +270,9 @@ def main_batch(args):
     inst = bp.solve(conts, bt.n_nodes, bt.moments, bt.block, bt.tol, timing=True, **kw)
     st = inst[0]["stats"]   # solve-wide statistics (shared by every problem's result)
     km = st["kernel_ms"]
-    fl = st["band_update_flops"] + st["band_update_next_flops"] + st["band_panel_flops"]
-    fms = km.get("band_update", 0) + km.get("band_update_next", 0) + km.get("band_panel", 0)
+    fl = st["band_update_flops"] + st["band_update_next_flops"] + st["band_panel_flops"] + st.get("band_wide_flops", 0)
+    fms = (km.get("band_update", 0) + km.get("band_update_next", 0) + km.get("band_panel", 0)
+           + km.get("band_factor_wide", 0))
     out = {
         "metric": METRIC, "value": round(good / dt, 3), "unit": "eigenpairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 1),
@@ -270,12 +285,14 @@ def main_batch(args):
                                f"{bt.moments} moments, block {bt.block}, one batched solve per step",
                    "problems": len(bt.problems), "precision": args.precision, "solve_tol": args.solve_tol,
                    "pairs_returned_per_step": returned},
-        "roofline": {"bound": "alu", "achieved": round(fl / fms / 1e9, 3) if fms else None,
+        "roofline": {"bound": "mfma" if st.get("band_wide_flops", 0) else "alu",
+                     "achieved": round(fl / fms / 1e9, 3) if fms else None,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(fl / fms / 1e9 / FP64_VECTOR_PEAK_TFLOPS, 4) if fms else None,
                      "traffic": None, "kernel": "band factorisation (panel, strip and window kernels)",
                      "note": "factorisation flops / sampled HIP-event time of its kernels"},
-        "cpu_baseline": cpu, "waves": st["waves"], "band_factorisations": st["band_factorisations"],
+        "cpu_baseline": cpu, "autotune": tuned, "waves": st["waves"],
+        "band_factorisations": st["band_factorisations"],
         "kernel_ms": km, "step_ms": [round(t, 1) for t in step_ms],
     }
     print(json.dumps(out), flush=True)
@@ -306,6 +323,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the steps, copy a 1 GiB device buffer three times; hardware "
                          "counters of that copy calibrate the HBM byte counters")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the kernel-variant autotuning before the timed steps (band solver)")
     ap.add_argument("--compare-fp64", action="store_true",
                     help="after the timed steps, one FP64 solve of the same workload: per-eigenpair "
                          "differences of the timed precision's pairs from it")
@@ -342,6 +361,18 @@ def main():
         kw["max_iter"] = args.max_iter
     if args.counters:
         args.copy_probe = True
+    tuned = None
+    if not args.no_autotune and not args.counters and args.solver != "cocg" and args.workload != "fd7_3d_64":
+        # banded kernel variant chosen by the project's autotuner (timed
+        # solves of this workload, cached by shape); untimed
+        from paper_2511_01927_amd import autotune
+        key = autotune.shape_key(w.n, w.meta.get("bw", 0), w.A.nnz / w.n,
+                                 len(w.contours) * w.n_nodes // 2 * w.block, args.precision, args.solver)
+        path = os.environ.get("GEPCI_TUNE_CACHE", autotune.DEFAULT_CACHE)
+        tuned = autotune.tune(lambda **o: pencil.solve(w.contours, w.n_nodes, w.moments, w.block, w.tol, **kw, **o),
+                              key, autotune.BAND_CANDIDATES, cache_path=path, repeats=2,
+                              log=lambda m: print("# " + m, flush=True))
+        kw.update(tuned)
     for i in range(args.warmup):
         r = pencil.solve(w.contours, w.n_nodes, w.moments, w.block, w.tol, **kw)
         print(f"# warmup {i}: {r['evals'].size} pairs, {r['stats']['wall_ms']:.0f} ms", flush=True)
@@ -463,6 +494,7 @@ def main():
         "roofline": roof(dom),
         "kernels": {k: roof(k) for k in spec if kl.get(k, 0) > 0 and k != dom},
         "solver": "band" if st.get("band_factorisations", 0) > 0 else "cocg",
+        "autotune": tuned,
         "cpu_baseline": cpu,
         "cocg_iters": st["cocg_iters"], "tile_iters": st["tile_iters"],
         "kernel_ms": km,

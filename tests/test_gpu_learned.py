@@ -140,10 +140,10 @@ def test_learned_contours_gain_over_uniform(lib):
     prior = learned.SpectralPrior(n_bins=nbins, hidden=256, max_batch=64, seed=7)
     hist = prior.train(X, T, epochs=150, batch=32, lr=1e-3)
     assert hist[-1] < hist[0]
-    # held-out fields.  Both strategies size the block
-    # for 2.5x their per-contour count estimate (moments = 4) and fall back to
-    # split contours when the solver flags a contour; the uniform one only
-    # knows the Weyl estimate of the total.
+    # held-out fields.  Both strategies size each circle's block for 2.5x
+    # its count estimate (moments = 4) and fall back to split contours when
+    # the solver flags a circle; the uniform circles take their counts from
+    # the Weyl law over their intervals, the learned ones from the prediction.
     import time
     tot = {"learned": [0, 0.0, 0, 0, 0], "uniform": [0, 0.0, 0, 0, 0]}   # pairs, s, columns, missed, fallbacks
     f = 2.5
@@ -158,11 +158,15 @@ def test_learned_contours_gain_over_uniform(lib):
         t0 = time.perf_counter()
         got, nfb = learned.solve_with_fallback(A, B, cont, pred, 32, 4, max(bl), 1e-8, seed=3, blocks=bl)
         dt = time.perf_counter() - t0
+        # uniform circles with per-circle counts from the 2D Weyl law over
+        # each circle's interval, sized by the same block rule
         ku = max(1, math.ceil(expected / 40))
-        pu = np.full(ku, expected / ku)
-        Lu = learned.blocks_for(pu, 4, factor=f)[0]
+        uc = learned.uniform_contours(win, ku)
+        mk = float(np.mean(1.0 / np.exp(g)))
+        pu = np.array([(b - a) * mk / (4.0 * math.pi) for _, _, a, b in uc])
+        bu = learned.blocks_for(pu, 4, factor=f)
         t1 = time.perf_counter()
-        uni, nfu = learned.solve_with_fallback(A, B, learned.uniform_contours(win, ku), pu, 32, 4, Lu, 1e-8, seed=3)
+        uni, nfu = learned.solve_with_fallback(A, B, uc, pu, 32, 4, max(bu), 1e-8, seed=3, blocks=bu)
         du = time.perf_counter() - t1
         for name, r_, d, nf in (("learned", got, dt, nfb), ("uniform", uni, du, nfu)):
             good = r_["evals"][r_["resid"] <= 1e-8]
@@ -175,6 +179,6 @@ def test_learned_contours_gain_over_uniform(lib):
     print("learned vs uniform:", tot)
     for name, v in tot.items():
         print(f"{name}: {v[0]} pairs, {v[0] / v[1]:.1f} eigenpairs/s, {v[2]} columns, {v[3]} missed, {v[4]} fallbacks")
-    # the prior must not lose eigenpairs, and must need fewer shifted-system columns
-    assert tot["learned"][3] == 0
+    # equal accuracy (no pair missed by either), fewer shifted-system columns
+    assert tot["learned"][3] == 0 and tot["uniform"][3] == 0
     assert tot["learned"][2] < tot["uniform"][2]
