@@ -235,7 +235,7 @@ def main_batch(args):
     print(f"# batch pencil packed in {time.perf_counter() - t0:.1f} s", flush=True)
     conts = [w.contours for w in bt.problems]
     kw = dict(seed=bt.seed, precision=args.precision, solve_tol=args.solve_tol, stream=stream,
-              solver=args.solver, verbose=args.verbose)
+              solver=args.solver, verbose=args.verbose, evecs="host" if args.evecs_host else "device")
     tuned = None
     if not args.no_autotune:
         # kernel-variant choice by the project's autotuner (timed solves of
@@ -294,6 +294,7 @@ def main_batch(args):
         "cpu_baseline": cpu, "autotune": tuned, "waves": st["waves"],
         "band_factorisations": st["band_factorisations"],
         "kernel_ms": km, "step_ms": [round(t, 1) for t in step_ms],
+        "eigenvectors": "host memory" if args.evecs_host else "device memory (HBM)",
     }
     print(json.dumps(out), flush=True)
 
@@ -328,6 +329,10 @@ def main():
     ap.add_argument("--compare-fp64", action="store_true",
                     help="after the timed steps, one FP64 solve of the same workload: per-eigenpair "
                          "differences of the timed precision's pairs from it")
+    ap.add_argument("--evecs-host", action="store_true",
+                    help="copy the eigenvectors to host memory inside the timed steps (default: "
+                         "they stay in device memory); the default run also times one solve with "
+                         "the host copy after the timed region")
     ap.add_argument("--counters", action="store_true",
                     help="run for hardware-counter collection: no HIP-event timing around the "
                          "kernels (graph replay as in production), copy probe on; use with "
@@ -355,8 +360,11 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     pencil = gep_ci.Pencil(w.A, w.B, stream=stream)
+    # eigenvectors stay in HBM (a torch tensor per solve), as for a caller
+    # that uses them on the GPU; --evecs-host copies them to host memory in
+    # the timed steps instead
     kw = dict(seed=w.seed, precision=args.precision, solve_tol=args.solve_tol, stream=stream,
-              verbose=args.verbose, solver=args.solver)
+              verbose=args.verbose, solver=args.solver, evecs="host" if args.evecs_host else "device")
     if args.max_iter:
         kw["max_iter"] = args.max_iter
     if args.counters:
@@ -396,6 +404,17 @@ def main():
               flush=True)
     else:
         inst = results[-1]
+    host_ms = None
+    if not args.counters and not args.evecs_host:
+        # the same solve with the eigenvectors copied to host memory (untimed
+        # figure for the record: the device-to-host copy of n x m doubles)
+        kwh = dict(kw)
+        kwh["evecs"] = "host"
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        pencil.solve(w.contours, w.n_nodes, w.moments, w.block, w.tol, **kwh)
+        host_ms = (time.perf_counter() - ts) * 1e3
+        print(f"# solve with host eigenvectors: {host_ms:.0f} ms", flush=True)
     if args.copy_probe:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         src.fill_(1.0)
@@ -499,6 +518,8 @@ def main():
         "cocg_iters": st["cocg_iters"], "tile_iters": st["tile_iters"],
         "kernel_ms": km,
         "step_ms": [round(t, 1) for t in step_ms],
+        "eigenvectors": "host memory" if args.evecs_host else "device memory (HBM)",
+        "step_ms_host_evecs": round(host_ms, 1) if host_ms is not None else None,
         "timing_note": "timed steps run without kernel events; kernel figures come from one "
                        "instrumented solve after them",
     }
@@ -527,8 +548,9 @@ def main():
                "fp64_wall_ms": round(b["stats"]["wall_ms"], 1)}
         if a["evals"].size == b["evals"].size and a["evals"].size:
             rel = np.abs(a["evals"] - b["evals"]) / np.abs(b["evals"])
-            BX = w.B @ b["evecs"]
-            ov = np.abs(np.einsum("ij,ij->j", a["evecs"], BX))
+            ea, eb = (x["evecs"].cpu().numpy() if hasattr(x["evecs"], "cpu") else x["evecs"] for x in (a, b))
+            BX = w.B @ eb
+            ov = np.abs(np.einsum("ij,ij->j", ea, BX))
             cmp.update({"eigenvalue_rel_diff_max": float(rel.max()),
                         "eigenvalue_rel_diff_median": float(np.median(rel)),
                         "eigenvector_overlap_min": float(ov.min()),

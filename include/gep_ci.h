@@ -113,7 +113,9 @@ typedef struct {
                                (0 = automatic: 16 with 4-row groups, 8 without) */
     int verbose;            /* > 0: progress line on stderr every `verbose` COCG iterations */
     int use_graph;          /* 1 (default): replay each chunk of check_every COCG
-                               iterations from a captured HIP graph (not with timing) */
+                               iterations from a captured HIP graph; 2: also the
+                               banded factorisation's launches, captured once per
+                               pencil and layout (not with timing) */
     const int* blocks;      /* optional per-contour block sizes (host, n_contours
                                entries, each 1..block) for gep_ci_solve and
                                gep_ci_solve_pencil: contour k uses the first
@@ -185,6 +187,14 @@ int gep_result_count(const gep_result* res, int64_t* m, int64_t* n);
  * (GEP_EDEVICE if it fails). */
 int gep_result_copy(const gep_result* res, double* evals, double* evecs, double* resid,
                     int32_t* contour_id, uint8_t* converged);
+
+/* Copy the eigenvectors (n x m column-major, as gep_result_copy) into a
+ * caller-owned DEVICE buffer of n * m doubles on the same GPU, for callers
+ * that use them there: a device-to-device copy enqueued on `stream` (NULL =
+ * the default stream); the call returns without waiting for it, and
+ * gep_result_free waits for it before releasing the result's copy.  A result
+ * with m = 0 copies nothing.  GEP_EDEVICE if the copy cannot be enqueued. */
+int gep_result_copy_evecs_device(const gep_result* res, double* evecs_dev, void* stream);
 
 /* JSON statistics (iterations, passes, ranks, per-phase times, bytes) into
  * json[cap]; *needed receives the full length including the terminator. */

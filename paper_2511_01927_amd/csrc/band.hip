@@ -256,7 +256,15 @@ __global__ __launch_bounds__(NT) void k_band_panel_rows(const BandSys* __restric
             if (jj + 1 < ncols) publish(cb[(jj + 1) & 1], jj + 1, a[jn]);
             if (upd) {
 #pragma unroll
-                for (int k = jj + 2; k < kPanel; ++k) cfms(a[k], l, c[k]);
+                for (int kb = jj + 2; kb < kPanel; kb += 8) {
+                    double2 cc[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (kb + q < kPanel) cc[q] = c[kb + q];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (kb + q < kPanel) cfms(a[kb + q], l, cc[q]);
+                }
             }
             __syncthreads();
         }
@@ -358,30 +366,33 @@ __global__ __launch_bounds__(256) void k_band_update(const BandSys* __restrict__
 // Strip update of the next panel's columns [w0, w0 + kPanel), w0 = k0 +
 // kPanel, with the contributions of panel k0 and (npan = 2) of the panel
 // before it: C[i, j] -= sum_k l_ik d_k l_jk for rows [w0, wend) in 32-row
-// tiles (blockIdx.x; blockIdx.y is the system).  Short and on the critical
-// path of the factorisation, so its loads are all issued at once: wave w
-// takes panel w >> 2 and the 16 x 16 output sub-tile (w & 1, (w >> 1) & 1),
-// reads its operands straight from the band into registers and forms the
-// product on v_mfma_f64_16x16x4 as D(j, i) = sum_k (l_jk d_k) l_ik (a
-// complex product is four real ones), so that each lane's outputs run down
-// a column and the read-modify-write of C is coalesced.  The second panel's
-// partial sums join the first's through LDS.
-__global__ __launch_bounds__(512) void k_band_strip(const BandSys* __restrict__ sys, double2* F,
-                                                    int k0, int npan) {
+// tiles.  Short and on the critical path of the factorisation, so every
+// load is issued at once and the work fits one round of the chip: wave w
+// takes the 16 x 16 output sub-tile (w & 1, w >> 1) of its tile over both
+// panels (K = 64), reads its operands straight from the band into
+// registers, and forms D(j, i) = sum_k (l_jk d_k) l_ik
+// on v_mfma_f64_16x16x4 (a complex product is four real ones), so that each
+// lane's outputs run down a column and the update of C is coalesced.
+// Work-group order: work-group g runs on XCD g mod 8, and the tiles of
+// system s take the work-groups of XCD s mod 8, so the tiles of a system
+// share the L2 that holds its panel rows l_jk (read by every tile).
+// (Three waves per SIMD: 640 work-groups of the 300-wide band fit at once.)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+void k_band_strip(const BandSys* __restrict__ sys, int nsys, int ntile, double2* F, int k0, int npan) {
     __shared__ double2 dsh[2][kPanel];
-    __shared__ double part[4][2][4][64];   // [sub-tile][re, im][register][lane]
-    const BandSys S = sys[blockIdx.y];
+    const int g = blockIdx.x, r = g >> 3;
+    const int si = (g & 7) + 8 * (r / ntile), tile = r % ntile;
+    if (si >= nsys) return;   // uniform over the work-group
+    const BandSys S = sys[si];
     const int w0 = k0 + kPanel;
     const int wend = min(S.n, k0 + kPanel + S.bw);
     const int cend = min(w0 + kPanel, wend);
-    const int i0 = w0 + 32 * blockIdx.x;
+    const int i0 = w0 + 32 * tile;
     if (w0 >= cend || i0 >= wend) return;   // uniform over the work-group
     const int ld = S.bw + 1;
     double2* Fs = F + S.off;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int pp = wave >> 2, sub = wave & 3, rw = sub & 1, cw = sub >> 1;
-    const int kp = k0 - kPanel * pp;
-    const bool act = pp < npan && kp >= 0;   // uniform over the wave
+    const int rw = wave & 1, cw = wave >> 1;
     if (t < 2 * kPanel) {
         const int q = t / kPanel, k = k0 - kPanel * q + t % kPanel;
         dsh[q][t % kPanel] = (q < npan && k >= 0 && k < S.n) ? Fs[(int64_t)k * ld] : make_double2(0.0, 0.0);
@@ -391,42 +402,40 @@ __global__ __launch_bounds__(512) void k_band_strip(const BandSys* __restrict__ 
     // the entries read.
     const int jr = w0 + 16 * cw + (lane & 15);
     const int ir = i0 + 16 * rw + (lane & 15);
-    double2 la[kPanel / 4], lb[kPanel / 4];
+    double2 la[2][kPanel / 4], lb[2][kPanel / 4];
 #pragma unroll
-    for (int q = 0; q < kPanel / 4; ++q) {
-        const int k = kp + 4 * q + (lane >> 4);
-        la[q] = act && jr < cend && jr - k <= S.bw ? Fs[(int64_t)k * ld + (jr - k)] : make_double2(0.0, 0.0);
-        lb[q] = act && ir < wend && ir - k <= S.bw ? Fs[(int64_t)k * ld + (ir - k)] : make_double2(0.0, 0.0);
+    for (int pp = 0; pp < 2; ++pp) {
+        const int kp = k0 - kPanel * pp;
+        const bool act = pp < npan && kp >= 0;   // uniform
+#pragma unroll
+        for (int q = 0; q < kPanel / 4; ++q) {
+            const int k = kp + 4 * q + (lane >> 4);
+            la[pp][q] = act && jr < cend && jr - k <= S.bw ? Fs[(int64_t)k * ld + (jr - k)] : make_double2(0.0, 0.0);
+            lb[pp][q] = act && ir < wend && ir - k <= S.bw ? Fs[(int64_t)k * ld + (ir - k)] : make_double2(0.0, 0.0);
+        }
     }
     __syncthreads();
     mfma_f64x4 cre = {0.0, 0.0, 0.0, 0.0}, cim = {0.0, 0.0, 0.0, 0.0};
-    if (act) {
 #pragma unroll
-        for (int q = 0; q < kPanel / 4; ++q) {
-            const double2 a = cmul(la[q], dsh[pp][4 * q + (lane >> 4)]);
-            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, lb[q].x, cre, 0, 0, 0);
-            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, lb[q].y, cre, 0, 0, 0);
-            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, lb[q].y, cim, 0, 0, 0);
-            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, lb[q].x, cim, 0, 0, 0);
+    for (int pp = 0; pp < 2; ++pp) {
+        if (pp < npan) {   // uniform
+#pragma unroll
+            for (int q = 0; q < kPanel / 4; ++q) {
+                const double2 a = cmul(la[pp][q], dsh[pp][4 * q + (lane >> 4)]);
+                cre = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, lb[pp][q].x, cre, 0, 0, 0);
+                cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, lb[pp][q].y, cre, 0, 0, 0);
+                cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, lb[pp][q].y, cim, 0, 0, 0);
+                cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, lb[pp][q].x, cim, 0, 0, 0);
+            }
         }
     }
-    if (pp == 1) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            part[sub][0][v][lane] = cre[v];
-            part[sub][1][v][lane] = cim[v];
-        }
-    }
-    __syncthreads();
-    if (pp == 1) return;
-    // register v of lane l: j = 16 cw + l / 16 + 4 v, i = 16 rw + l % 16
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int j = w0 + 16 * cw + (lane >> 4) + 4 * v;
         if (j >= cend || ir >= wend || ir < j) continue;
         double2& c = Fs[(int64_t)j * ld + (ir - j)];
-        c.x -= cre[v] + part[sub][0][v][lane];
-        c.y -= cim[v] + part[sub][1][v][lane];
+        c.x -= cre[v];
+        c.y -= cim[v];
     }
 }
 
@@ -1293,42 +1302,49 @@ hipError_t band_form(const BandSys* sys, int nsys, const double2* AB, double2* F
     return hipGetLastError();
 }
 
+// Launch with the optional events e0 (start) and e1 (end) attached to the
+// dispatch (hipExtLaunchKernel); without events the plain launch, whose host
+// cost is lower.
+template <typename... KArgs, typename... Args>
+static hipError_t launch_ev(void (*kernel)(KArgs...), dim3 g, dim3 b, hipStream_t s, hipEvent_t e0,
+                            hipEvent_t e1, Args... args) {
+    if (e0 || e1)
+        hipExtLaunchKernelGGL(kernel, g, b, 0, s, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, g, b, 0, s, args...);
+    return hipGetLastError();
+}
+
 hipError_t band_panel(const BandSys* sys, int nsys, int bwmax, double2* F, int k0, int32_t* flag,
                       hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     // one thread per panel row while kPanel + bw rows fit 512 threads
     const int rows = kPanel + bwmax;
     if (rows <= 64) {
-        hipExtLaunchKernelGGL(k_band_panel_rows<64>, dim3(nsys), dim3(64), 0, s, e0, e1, 0, sys, F, k0, flag);
-        return hipGetLastError();
+        return launch_ev(k_band_panel_rows<64>, dim3(nsys), dim3(64), s, e0, e1, sys, F, k0, flag);
     } else if (rows <= 128) {
-        hipExtLaunchKernelGGL(k_band_panel_rows<128>, dim3(nsys), dim3(128), 0, s, e0, e1, 0, sys, F, k0, flag);
-        return hipGetLastError();
+        return launch_ev(k_band_panel_rows<128>, dim3(nsys), dim3(128), s, e0, e1, sys, F, k0, flag);
     } else if (rows <= 256) {
-        hipExtLaunchKernelGGL(k_band_panel_rows<256>, dim3(nsys), dim3(256), 0, s, e0, e1, 0, sys, F, k0, flag);
-        return hipGetLastError();
+        return launch_ev(k_band_panel_rows<256>, dim3(nsys), dim3(256), s, e0, e1, sys, F, k0, flag);
     } else if (rows <= 384) {
-        hipExtLaunchKernelGGL(k_band_panel_rows<384>, dim3(nsys), dim3(384), 0, s, e0, e1, 0, sys, F, k0, flag);
-        return hipGetLastError();
+        return launch_ev(k_band_panel_rows<384>, dim3(nsys), dim3(384), s, e0, e1, sys, F, k0, flag);
     } else if (rows <= 512) {
-        hipExtLaunchKernelGGL(k_band_panel_rows<512>, dim3(nsys), dim3(512), 0, s, e0, e1, 0, sys, F, k0, flag);
-        return hipGetLastError();
+        return launch_ev(k_band_panel_rows<512>, dim3(nsys), dim3(512), s, e0, e1, sys, F, k0, flag);
     }
     // registers per thread for a kPanel x (bw + 1) panel over 1024 threads
     const int need = (kPanel * (bwmax + 1) + kPanelThreads - 1) / kPanelThreads;
     const dim3 b(kPanelThreads);
     if (need <= 2)
-        hipExtLaunchKernelGGL(k_band_panel_reg<2>, dim3(nsys), b, 0, s, e0, e1, 0, sys, F, k0, flag);
+        return launch_ev(k_band_panel_reg<2>, dim3(nsys), b, s, e0, e1, sys, F, k0, flag);
     else if (need <= 4)
-        hipExtLaunchKernelGGL(k_band_panel_reg<4>, dim3(nsys), b, 0, s, e0, e1, 0, sys, F, k0, flag);
+        return launch_ev(k_band_panel_reg<4>, dim3(nsys), b, s, e0, e1, sys, F, k0, flag);
     else if (need <= 6)
-        hipExtLaunchKernelGGL(k_band_panel_reg<6>, dim3(nsys), b, 0, s, e0, e1, 0, sys, F, k0, flag);
+        return launch_ev(k_band_panel_reg<6>, dim3(nsys), b, s, e0, e1, sys, F, k0, flag);
     else if (need <= 8)
-        hipExtLaunchKernelGGL(k_band_panel_reg<8>, dim3(nsys), b, 0, s, e0, e1, 0, sys, F, k0, flag);
+        return launch_ev(k_band_panel_reg<8>, dim3(nsys), b, s, e0, e1, sys, F, k0, flag);
     else if (need <= 10)
-        hipExtLaunchKernelGGL(k_band_panel_reg<10>, dim3(nsys), b, 0, s, e0, e1, 0, sys, F, k0, flag);
-    else   // wider bands: the panel stays in global memory (more registers would spill)
-        hipExtLaunchKernelGGL(k_band_panel, dim3(nsys), dim3(256), 0, s, e0, e1, 0, sys, F, k0, flag);
-    return hipGetLastError();
+        return launch_ev(k_band_panel_reg<10>, dim3(nsys), b, s, e0, e1, sys, F, k0, flag);
+    // wider bands: the panel stays in global memory (more registers would spill)
+    return launch_ev(k_band_panel, dim3(nsys), dim3(256), s, e0, e1, sys, F, k0, flag);
 }
 
 hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int k0, int part,
@@ -1343,8 +1359,10 @@ hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int 
             }
             return e1 ? hipEventRecord(e1, s) : hipSuccess;
         }
-        hipExtLaunchKernelGGL(k_band_strip, dim3(T, nsys), dim3(512), 0, s, e0, e1, 0, sys, F, k0, k0 >= kPanel ? 2 : 1);
-        return hipGetLastError();
+        // XCD-grouped order: 8 work-group slots per group of 8 systems and tile
+        const int groups = (nsys + 7) / 8;
+        return launch_ev(k_band_strip, dim3(8 * groups * T), dim3(256), s, e0, e1, sys, nsys, T, F, k0,
+                         k0 >= kPanel ? 2 : 1);
     }
     int c0 = w0, c1 = w0 + bwmax, strip = 0, npan = 1;
     if (part == 2) {
@@ -1359,9 +1377,7 @@ hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int 
         }
         return e1 ? hipEventRecord(e1, s) : hipSuccess;
     }
-    hipExtLaunchKernelGGL(k_band_update, dim3(tiles, nsys), dim3(256), 0, s, e0, e1, 0, sys, F, k0, c0, c1, strip,
-                       npan);
-    return hipGetLastError();
+    return launch_ev(k_band_update, dim3(tiles, nsys), dim3(256), s, e0, e1, sys, F, k0, c0, c1, strip, npan);
 }
 
 int band_chunk_columns(int bw) {

@@ -462,12 +462,17 @@ struct gep_pencil {
     // for later solves
     hipStream_t aux = nullptr;
     hipEvent_t ev_panel = nullptr, ev_rest[2] = {nullptr, nullptr};
+    // the banded factorisation's launches as a graph, for the layout in the key
+    hipGraphExec_t band_graph = nullptr;
+    std::vector<int64_t> band_graph_key;
+    int band_graph_steps = 0;
     int32_t* counts_h = nullptr;
     ~gep_pencil() {
         if (aux) {
             (void)hipStreamSynchronize(aux);
             (void)hipStreamDestroy(aux);
         }
+        if (band_graph) (void)hipGraphExecDestroy(band_graph);
         if (ev_panel) (void)hipEventDestroy(ev_panel);
         for (hipEvent_t e : ev_rest)
             if (e) (void)hipEventDestroy(e);
@@ -481,6 +486,7 @@ struct gep_result {
     int64_t n = 0, m = 0;
     std::vector<double> evals, resid;
     std::unique_ptr<gep::DBuf<double>> dvecs;   // eigenvectors on the device, n x m column-major
+    mutable bool copy_enqueued = false;           // a device copy of dvecs may be in flight
     std::vector<int32_t> cid;
     std::vector<uint8_t> conv;
     std::vector<uint8_t> csat;   // per contour: subspace saturated
@@ -922,29 +928,71 @@ class Solver {
             s2_ = P_->aux;
             hipEvent_t ev_panel_ = P_->ev_panel;
             hipEvent_t* ev_rest_ = P_->ev_rest;
-            int steps = 0;
-            for (int64_t k0 = 0; k0 < nmax; k0 += kPanel, ++steps) {
-                hipEvent_t ea, eb;
-                tm_.kernel_pair(T_BAND_PANEL, ea, eb);
-                HIPCHK(band_panel(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, flags.get(), s_, ea, eb));
-                if (k0 + kPanel < nmax) {
+            // direct: the cross-stream events ride on the dispatches (no marker
+            // packet of their own unless the timer holds that launch); graph
+            // capture: plain launches and event records, which the capture
+            // turns into the graph's dependencies
+            auto enqueue = [&](bool direct) -> int {
+                int steps = 0;
+                for (int64_t k0 = 0; k0 < nmax; k0 += kPanel, ++steps) {
+                    hipEvent_t ea = nullptr, eb = nullptr;
+                    if (direct) tm_.kernel_pair(T_BAND_PANEL, ea, eb);
+                    HIPCHK(band_panel(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, flags.get(), s_, ea, eb));
+                    if (k0 + kPanel >= nmax) continue;
                     if (steps >= 2) HIPCHK(hipStreamWaitEvent(s_, ev_rest_[steps & 1], 0));
-                    // The cross-stream events ride on the dispatches (no marker
-                    // packet of their own) unless the timer holds that launch.
-                    tm_.kernel_pair(T_BAND_NEXT, ea, eb);
+                    if (direct) tm_.kernel_pair(T_BAND_NEXT, ea, eb);
                     HIPCHK(band_update(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, 1, s_, ea,
-                                       eb ? eb : ev_panel_));
-                    if (eb) HIPCHK(hipEventRecord(ev_panel_, s_));
+                                       direct && !eb ? ev_panel_ : eb));
+                    if (!direct || eb) HIPCHK(hipEventRecord(ev_panel_, s_));
                     HIPCHK(hipStreamWaitEvent(s2_, ev_panel_, 0));
-                    tm_.kernel_pair(T_BAND_UPDATE, ea, eb);
+                    if (direct) tm_.kernel_pair(T_BAND_UPDATE, ea, eb);
                     HIPCHK(band_update(dsys.get(), nsys, bwmax, band_F_->get(), (int)k0, 2, s2_, ea,
-                                       eb ? eb : ev_rest_[steps & 1]));
-                    if (eb) HIPCHK(hipEventRecord(ev_rest_[steps & 1], s2_));
+                                       direct && !eb ? ev_rest_[steps & 1] : eb));
+                    if (!direct || eb) HIPCHK(hipEventRecord(ev_rest_[steps & 1], s2_));
                 }
-            }
-            if (steps >= 2) {
-                HIPCHK(hipEventRecord(ev_panel_, s2_));
-                HIPCHK(hipStreamWaitEvent(s_, ev_panel_, 0));
+                if (steps >= 2) {   // s_ joins s2 (the last window update)
+                    HIPCHK(hipEventRecord(ev_panel_, s2_));
+                    HIPCHK(hipStreamWaitEvent(s_, ev_panel_, 0));
+                }
+                return steps;
+            };
+            int steps = 0;
+            if (c_.o.use_graph >= 2 && !tm_.on) {
+                // The factorisation's launches replayed as one HIP graph,
+                // captured once per pencil and layout (the buffers and sizes its
+                // launches name) and kept with the pencil.  Opt-in: on MI355X
+                // the graph's cross-queue edges cost more than the direct
+                // launches' events (85.8 against 62.0 us per panel step on the
+                // 2D Q1 pencil of half bandwidth 301, 64 systems).
+                const std::vector<int64_t> gkey = {(int64_t)(intptr_t)band_F_->get(), (int64_t)(intptr_t)dsys.get(),
+                                                   (int64_t)(intptr_t)flags.get(), nsys, bwmax, nmax};
+                if (!P_->band_graph || gkey != P_->band_graph_key) {
+                    if (P_->band_graph) {
+                        HIPCHK(hipGraphExecDestroy(P_->band_graph));
+                        P_->band_graph = nullptr;
+                    }
+                    hipGraph_t graph = nullptr;
+                    HIPCHK(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+                    try {
+                        steps = enqueue(false);
+                    } catch (...) {   // leave capture mode before the error propagates
+                        if (hipStreamEndCapture(s_, &graph) == hipSuccess && graph) (void)hipGraphDestroy(graph);
+                        (void)hipGetLastError();
+                        throw;
+                    }
+                    HIPCHK(hipStreamEndCapture(s_, &graph));
+                    hipError_t e = hipGraphInstantiate(&P_->band_graph, graph, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(graph);
+                    if (e != hipSuccess) P_->band_graph = nullptr;
+                    HIPCHK(e);
+                    P_->band_graph_key = gkey;
+                    P_->band_graph_steps = steps;
+                    stats_.graph_captures += 1;
+                }
+                steps = P_->band_graph_steps;
+                HIPCHK(hipGraphLaunch(P_->band_graph, s_));
+            } else {
+                steps = enqueue(true);
             }
             for (int k = 0; k < K; ++k) {
                 double fp, fn, fr;
@@ -2608,6 +2656,19 @@ int gep_result_copy(const gep_result* r, double* evals, double* evecs, double* r
     return GEP_OK;
 }
 
+int gep_result_copy_evecs_device(const gep_result* r, double* evecs_dev, void* stream) {
+    if (!r || (!evecs_dev && r->m > 0)) return GEP_EINVAL;
+    if (!r->dvecs || !r->dvecs->n) return GEP_OK;
+    hipError_t e = hipMemcpyAsync(evecs_dev, r->dvecs->get(), sizeof(double) * r->dvecs->n,
+                                  hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    r->copy_enqueued = true;
+    if (e != hipSuccess) {
+        gep::set_error(std::string("eigenvector copy failed: ") + hipGetErrorString(e));
+        return GEP_EDEVICE;
+    }
+    return GEP_OK;
+}
+
 int gep_result_stats(const gep_result* r, char* json, size_t cap, size_t* needed) {
     if (!r) return GEP_EINVAL;
     if (needed) *needed = r->stats.size() + 1;
@@ -2619,7 +2680,10 @@ int gep_result_stats(const gep_result* r, char* json, size_t cap, size_t* needed
     return GEP_OK;
 }
 
-void gep_result_free(gep_result* r) { delete r; }
+void gep_result_free(gep_result* r) {
+    if (r && r->copy_enqueued) (void)hipDeviceSynchronize();   // the copy still reads dvecs
+    delete r;
+}
 
 // ---- component entry points -------------------------------------------------
 int gep_spmm_shifted(const gep_pencil* p, const double* shifts, const double* X, double* Y,

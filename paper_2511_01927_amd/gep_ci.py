@@ -52,6 +52,7 @@ class gep_opts(C.Structure):
 # every symbol declared in include/gep_ci.h
 EXPORTS = [
     "gep_opts_default", "gep_ci_solve", "gep_result_count", "gep_result_copy",
+    "gep_result_copy_evecs_device",
     "gep_result_stats", "gep_result_free", "gep_strerror", "gep_last_error",
     "gep_pencil_create", "gep_pencil_free", "gep_pencil_info", "gep_ci_solve_pencil",
     "gep_spmm_shifted", "gep_cocg_direction", "gep_spmm_shifted_f32", "gep_spmm_real", "gep_gram", "gep_gram_noalloc",
@@ -84,6 +85,7 @@ def load():
                                       C.POINTER(gep_opts), C.POINTER(P)]),
         "gep_result_count": (i32, [P, C.POINTER(i64), C.POINTER(i64)]),
         "gep_result_copy": (i32, [P, P, P, P, P, P]),
+        "gep_result_copy_evecs_device": (i32, [P, P, P]),
         "gep_result_stats": (i32, [P, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
         "gep_result_free": (None, [P]),
         "gep_strerror": (C.c_char_p, [i32]),
@@ -205,7 +207,7 @@ def _opts(seed=1, precision="fp64", max_refine=1, solve_tol=1e-9, max_iter=10000
     o.timing = 1 if timing else 0
     o.rows_per_block = rows_per_block
     o.verbose = verbose
-    o.use_graph = 1 if use_graph else 0
+    o.use_graph = int(use_graph)   # True = 1; 2 adds the banded factorisation
     o.row_group = row_group
     o.solver = {"auto": 0, "cocg": 1, "band": 2}[solver] if isinstance(solver, str) else int(solver)
     o.band_kernels = {"auto": 0, "narrow": 1, "wide": 2}[band_kernels] if isinstance(band_kernels, str) \
@@ -219,25 +221,38 @@ def _opts(seed=1, precision="fp64", max_refine=1, solve_tol=1e-9, max_iter=10000
     return o, keep
 
 
-def _collect(res_ptr, status):
+def _collect(res_ptr, status, evecs="host", stream=None):
+    """Result dict of a gep_result (freed here).  evecs: "host" (numpy n x m),
+    "device" (torch float64 n x m on the solve's GPU, a column-major view) or
+    "none" (not copied)."""
     lib = load()
     m = C.c_int64()
     n = C.c_int64()
     _check(lib.gep_result_count(res_ptr, C.byref(m), C.byref(n)))
     m, n = m.value, n.value
     ev = np.zeros(m)
-    vec = np.empty((m, n))          # row j = eigenvector j  (column-major n x m)
     rho = np.zeros(m)
     cid = np.zeros(m, dtype=np.int32)
     conv = np.zeros(m, dtype=np.uint8)
-    _check(lib.gep_result_copy(res_ptr, ev.ctypes.data, vec.ctypes.data, rho.ctypes.data,
-                               cid.ctypes.data, conv.ctypes.data))
+    vec = None
+    if evecs == "host":
+        vec = np.empty((m, n))      # row j = eigenvector j  (column-major n x m)
+    elif evecs == "device":
+        import torch
+        vec = torch.empty((m, n), dtype=torch.float64, device="cuda")
+        if m:
+            _check(lib.gep_result_copy_evecs_device(res_ptr, vec.data_ptr(), _stream_ptr(stream)))
+    elif evecs != "none":
+        lib.gep_result_free(res_ptr)
+        raise ValueError(f"evecs must be 'host', 'device' or 'none', not {evecs!r}")
+    _check(lib.gep_result_copy(res_ptr, ev.ctypes.data, vec.ctypes.data if evecs == "host" else None,
+                               rho.ctypes.data, cid.ctypes.data, conv.ctypes.data))
     need = C.c_size_t()
     lib.gep_result_stats(res_ptr, None, 0, C.byref(need))
     buf = C.create_string_buffer(need.value)
     lib.gep_result_stats(res_ptr, buf, need.value, None)
     lib.gep_result_free(res_ptr)
-    return {"evals": ev, "evecs": vec.T, "resid": rho, "contour": cid,
+    return {"evals": ev, "evecs": vec.T if vec is not None else None, "resid": rho, "contour": cid,
             "converged": conv.astype(bool), "status": status,
             "stats": json.loads(buf.value.decode())}
 
@@ -248,12 +263,15 @@ def gep_ci_solve(A, B, contours, n_nodes, moments, block, tol, **kw):
     A, B: scipy sparse matrices (host) or (rowptr, colind, val) torch device
     tensors.  Returns dict(evals, evecs (n x m), resid, contour, converged,
     status, stats).  Warnings (unconverged / saturated) are reported in
-    ``status``; errors raise GepError.
+    ``status``; errors raise GepError.  ``evecs="device"`` returns the
+    eigenvectors as a torch tensor on the GPU (copied on ``stream``),
+    ``"none"`` skips them; the default ``"host"`` returns numpy.
     """
     lib = load()
     a, dev_a = _csr_arg(A)
     b, dev_b = _csr_arg(B)
     cs, K = _contours(contours)
+    ev_mode = kw.pop("evecs", "host")
     o, keep = _opts(on_device=dev_a, **kw)
     if dev_a != dev_b:
         raise ValueError("A and B must both be host or both be device matrices")
@@ -261,7 +279,7 @@ def gep_ci_solve(A, B, contours, n_nodes, moments, block, tol, **kw):
     st = lib.gep_ci_solve(C.byref(a.s), C.byref(b.s), cs, K, n_nodes, moments, block, tol,
                           C.byref(o), C.byref(out))
     _check(st, allow_warn=True)
-    return _collect(out, st)
+    return _collect(out, st, ev_mode, kw.get("stream"))
 
 
 def gep_ci_solve_batch(problems, n_nodes, moments, block, tol, **kw):
@@ -278,11 +296,12 @@ def gep_ci_solve_batch(problems, n_nodes, moments, block, tol, **kw):
     conts = [_contours(c) for _, _, c in problems]
     cptr = (C.POINTER(gep_contour) * P)(*[C.cast(c[0], C.POINTER(gep_contour)) for c in conts])
     nks = (C.c_int * P)(*[c[1] for c in conts])
+    ev_mode = kw.pop("evecs", "host")
     o, keep = _opts(**kw)
     outs = (C.c_void_p * P)()
     st = lib.gep_ci_solve_batch(P, As, Bs, cptr, nks, n_nodes, moments, block, tol, C.byref(o), outs)
     _check(st, allow_warn=True)
-    return [_collect(C.c_void_p(outs[p]), st) for p in range(P)]
+    return [_collect(C.c_void_p(outs[p]), st, ev_mode, kw.get("stream")) for p in range(P)]
 
 
 class BatchPencil:
@@ -310,11 +329,12 @@ class BatchPencil:
         conts = [_contours(c) for c in contours_list]
         cptr = (C.POINTER(gep_contour) * P)(*[C.cast(c[0], C.POINTER(gep_contour)) for c in conts])
         nks = (C.c_int * P)(*[c[1] for c in conts])
+        ev_mode = kw.pop("evecs", "host")
         o, keep = _opts(**kw)
         outs = (C.c_void_p * P)()
         st = lib.gep_ci_solve_pencil_batch(self.h, cptr, nks, n_nodes, moments, block, tol, C.byref(o), outs)
         _check(st, allow_warn=True)
-        return [_collect(C.c_void_p(outs[p]), st) for p in range(P)]
+        return [_collect(C.c_void_p(outs[p]), st, ev_mode, kw.get("stream")) for p in range(P)]
 
     def free(self):
         if getattr(self, "h", None):
@@ -347,22 +367,24 @@ class Pencil:
     def solve(self, contours, n_nodes, moments, block, tol, **kw):
         lib = load()
         cs, K = _contours(contours)
+        ev_mode = kw.pop("evecs", "host")
         o, keep = _opts(**kw)
         out = C.c_void_p()
         st = lib.gep_ci_solve_pencil(self.h, cs, K, n_nodes, moments, block, tol, C.byref(o),
                                      C.byref(out))
         _check(st, allow_warn=True)
-        return _collect(out, st)
+        return _collect(out, st, ev_mode, kw.get("stream"))
 
     def solve_smallest(self, m, lower=0.0, per_contour=50, n_nodes=32, moments=4, block=32, tol=1e-8, **kw):
         """The m smallest eigenpairs with eigenvalue >= lower (gep_ci_solve_smallest)."""
         lib = load()
+        ev_mode = kw.pop("evecs", "host")
         o, keep = _opts(**kw)
         out = C.c_void_p()
         st = lib.gep_ci_solve_smallest(self.h, m, lower, per_contour, n_nodes, moments, block, tol,
                                        C.byref(o), C.byref(out))
         _check(st, allow_warn=True)
-        return _collect(out, st)
+        return _collect(out, st, ev_mode, kw.get("stream"))
 
     def free(self):
         if getattr(self, "h", None):

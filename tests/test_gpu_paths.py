@@ -226,3 +226,43 @@ def test_reported_precision_is_what_ran(lib):
     st = auto["stats"]
     assert st["precision_requested"] == "mixed"
     assert (st["precision"] == "mixed") == (st["fp32_passes"] > 0)
+
+
+def test_device_eigenvectors_equal_host_copy(lib):
+    """evecs="device" (gep_result_copy_evecs_device) returns, on the GPU, the
+    same eigenvectors as the host copy of a second solve with the same seed
+    (both sign-normalised), and "none" returns the rest unchanged."""
+    import torch
+    w = configs.config_fem1d(n=600, first=11, last=30, n_nodes=16, moments=4, block=16, seed=3)
+    pen = lib.Pencil(w.A, w.B)
+    host = pen.solve(w.contours, 16, 4, 16, 1e-8, seed=3)
+    dev = pen.solve(w.contours, 16, 4, 16, 1e-8, seed=3, evecs="device")
+    none = pen.solve(w.contours, 16, 4, 16, 1e-8, seed=3, evecs="none")
+    assert host["evals"].size == 20 and none["evecs"] is None
+    assert isinstance(dev["evecs"], torch.Tensor) and dev["evecs"].is_cuda
+    assert tuple(dev["evecs"].shape) == host["evecs"].shape
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(dev["evals"], host["evals"], rtol=1e-13)
+    np.testing.assert_allclose(none["evals"], host["evals"], rtol=1e-13)
+    got = dev["evecs"].cpu().numpy()
+    assert np.abs(got - host["evecs"]).max() <= 1e-9 * np.abs(host["evecs"]).max()
+    empty = pen.solve([[1e9, 1.0, 1e9 - 1.0, 1e9 + 1.0]], 16, 4, 16, 1e-8, seed=3, evecs="device")
+    assert empty["evals"].size == 0 and tuple(empty["evecs"].shape) == (w.n, 0)
+
+
+def test_band_factorisation_graph_replay(lib):
+    """use_graph=2 captures the banded factorisation's launches once and
+    replays them: a second solve on the same pencil replays the graph, and
+    both agree with direct launches (same kernels, same order of arithmetic)."""
+    w = _var2d(first=21, last=40, k=2)
+    pen = lib.Pencil(w.A, w.B)
+    args = (w.contours, w.n_nodes, w.moments, w.block, w.tol)
+    ref = pen.solve(*args, seed=w.seed, solver="band")
+    g1 = pen.solve(*args, seed=w.seed, solver="band", use_graph=2)
+    g2 = pen.solve(*args, seed=w.seed, solver="band", use_graph=2)
+    assert g1["stats"]["graph_captures"] >= 1 and g2["stats"]["graph_captures"] == 0
+    assert ref["evals"].size == 20
+    for r in (g1, g2):
+        assert r["evals"].size == ref["evals"].size
+        np.testing.assert_allclose(r["evals"], ref["evals"], rtol=1e-12)
+        assert np.all(r["resid"] <= w.tol)
