@@ -196,6 +196,15 @@ int gep_result_copy(const gep_result* res, double* evals, double* evecs, double*
  * with m = 0 copies nothing.  GEP_EDEVICE if the copy cannot be enqueued. */
 int gep_result_copy_evecs_device(const gep_result* res, double* evecs_dev, void* stream);
 
+/* Boundary-proximity check (the paper's robustness safeguards, appendix on
+ * mild distribution shifts): filter[m] receives, for each returned pair, the
+ * value at its eigenvalue of the rational filter that the N-node trapezoid rule
+ * of its contour applies, Re sum_j w_j / (z_j - lambda): 1 at the centre, 1/2
+ * on the circle.  Pairs below 0.9 lie in the filter's transition band (the
+ * statistics count them as near_boundary_pairs); a caller may enlarge or split
+ * such contours.  filter is a caller-owned HOST buffer of m doubles. */
+int gep_result_filter(const gep_result* res, double* filter);
+
 /* JSON statistics (iterations, passes, ranks, per-phase times, bytes) into
  * json[cap]; *needed receives the full length including the terminator. */
 int gep_result_stats(const gep_result* res, char* json, size_t cap, size_t* needed);

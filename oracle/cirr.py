@@ -53,6 +53,17 @@ def quadrature(center: float, radius: float, n_nodes: int):
     return center + radius * zeta, radius * zeta / n_nodes, zeta
 
 
+def filter_value(center: float, radius: float, n_nodes: int, lam) -> np.ndarray:
+    """Value at real lam of the rational filter that the quadrature applies to
+    the spectrum (Appendix, quadrature equation): f(lam) = Re sum_j w_j /
+    (z_j - lam), about 1 well inside the circle, 1/2 on it and about 0 outside.
+    Used for the boundary-proximity check of the robustness safeguards
+    (Appendix, robustness under mild distribution shifts)."""
+    z, w, _ = quadrature(center, radius, n_nodes)
+    lam = np.atleast_1d(np.asarray(lam, dtype=np.float64))
+    return np.real((w[None, :] / (z[None, :] - lam[:, None])).sum(axis=1))
+
+
 def inf_norm(A) -> float:
     """Maximum absolute row sum of a sparse matrix."""
     return float(np.max(np.asarray(abs(A).sum(axis=1)).ravel()))

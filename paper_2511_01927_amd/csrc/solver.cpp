@@ -490,6 +490,7 @@ struct gep_result {
     std::vector<int32_t> cid;
     std::vector<uint8_t> conv;
     std::vector<uint8_t> csat;   // per contour: subspace saturated
+    std::vector<double> filt;    // per pair: quadrature filter value at its eigenvalue
     std::string stats;
 };
 
@@ -1851,6 +1852,37 @@ static std::string json_stats(const Solver& s, double wall_ms, const std::vector
 
 // Solve every problem of a (possibly single-element) batch.  contours[p] and
 // n_contours[p] describe problem p's circles.  out[p] receives its result.
+// Boundary-proximity check (robustness safeguards of the paper's appendix on
+// mild distribution shifts): the value at lam of the rational filter that the
+// N-node trapezoid rule applies to the spectrum (quadrature equation of the
+// appendix on numerical quadrature), f(lam) = Re sum_j w_j / (z_j - lam),
+// z_j = c + r zeta_j, w_j = r zeta_j / N, zeta_j = e^{i pi (2j - 1) / N}:
+// 1 at the centre, 1/2 on the circle, about 0 outside.  Pairs with f below
+// kNearBoundary sit in the filter's transition band, where the subspace
+// holds them only weakly and eigenvalues just outside the circle leak in.
+constexpr double kNearBoundary = 0.9;
+static double quad_filter(const gep_contour& c, int N, double lam) {
+    double f = 0.0;
+    for (int j = 1; j <= N; ++j) {
+        const double th = M_PI * (2.0 * j - 1.0) / N;
+        const double zr = std::cos(th), zi = std::sin(th);
+        const double dr = c.radius * zr + (c.center - lam), di = c.radius * zi;   // z_j - lam
+        f += (c.radius * zr * dr + c.radius * zi * di) / (N * (dr * dr + di * di));
+    }
+    return f;
+}
+
+// "near_boundary_pairs" and "filter_min" of a result's pairs, for its JSON statistics.
+static std::string boundary_stats(const std::vector<double>& filt) {
+    int64_t near = 0;
+    double fmin = 1.0;
+    for (double f : filt) {
+        near += f < kNearBoundary;
+        fmin = std::min(fmin, f);
+    }
+    return "\"near_boundary_pairs\":" + std::to_string(near) + ",\"filter_min\":" + std::to_string(fmin) + ",";
+}
+
 static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* const* contours,
                             const int* n_contours, const SolveCfg& cfg, gep_result** out) {
     auto t0 = std::chrono::steady_clock::now();
@@ -2176,6 +2208,7 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
             R->evals.push_back(pr.lam);
             R->resid.push_back(pr.rho);
             R->cid.push_back(pr.cid);
+            R->filt.push_back(quad_filter(contours[p][pr.cid], cfg.N, pr.lam));
             const bool ok = pr.rho <= cfg.tol;
             noconv |= !ok;
             R->conv.push_back(ok ? 1 : 0);
@@ -2187,6 +2220,7 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
         R->m = (int64_t)R->evals.size();
         for (const ContourOut& co : mine) R->csat.push_back(co.saturated ? 1 : 0);
         R->stats = json_stats(sv, wall_solve, mine, cfg.o.precision);
+        R->stats.insert(1, boundary_stats(R->filt));
         R->stats.insert(1, "\"wall_select_ms\":" +
                                std::to_string(std::chrono::duration<double, std::milli>(
                                                   std::chrono::steady_clock::now() - t0).count() - wall_solve) + ",");
@@ -2607,6 +2641,7 @@ int gep_ci_solve_smallest(gep_pencil* P, int64_t m, double lower, int per_contou
             R->evals.push_back(f.lam);
             R->resid.push_back(f.rho);
             R->cid.push_back(f.cid);
+            R->filt.push_back(f.col < (int)f.res->filt.size() ? f.res->filt[f.col] : 1.0);
             R->conv.push_back(f.rho <= tol ? 1 : 0);
             noconv |= !(f.rho <= tol);
             HIPCHK(hipMemcpy(R->dvecs->get() + a * n, f.res->dvecs->get() + (size_t)f.col * n, sizeof(double) * n,
@@ -2614,7 +2649,8 @@ int gep_ci_solve_smallest(gep_pencil* P, int64_t m, double lower, int per_contou
         }
         R->m = keep;
         std::ostringstream js;
-        js << "{\"rounds\":" << rounds.size() << ",\"windows\":" << windows << ",\"circles\":" << circle0
+        js << "{" << gep::boundary_stats(R->filt) << "\"rounds\":" << rounds.size() << ",\"windows\":" << windows
+           << ",\"circles\":" << circle0
            << ",\"found\":" << found.size() << ",\"lmax_estimate\":" << lmax << ",\"window_hi\":" << lo
            << ",\"round_stats\":[";
         for (size_t i = 0; i < rounds.size(); ++i) js << (i ? "," : "") << rounds[i]->stats;
@@ -2666,6 +2702,12 @@ int gep_result_copy_evecs_device(const gep_result* r, double* evecs_dev, void* s
         gep::set_error(std::string("eigenvector copy failed: ") + hipGetErrorString(e));
         return GEP_EDEVICE;
     }
+    return GEP_OK;
+}
+
+int gep_result_filter(const gep_result* r, double* filter) {
+    if (!r || (!filter && r->m > 0)) return GEP_EINVAL;
+    std::copy(r->filt.begin(), r->filt.end(), filter);
     return GEP_OK;
 }
 

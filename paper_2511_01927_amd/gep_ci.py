@@ -52,7 +52,7 @@ class gep_opts(C.Structure):
 # every symbol declared in include/gep_ci.h
 EXPORTS = [
     "gep_opts_default", "gep_ci_solve", "gep_result_count", "gep_result_copy",
-    "gep_result_copy_evecs_device",
+    "gep_result_copy_evecs_device", "gep_result_filter",
     "gep_result_stats", "gep_result_free", "gep_strerror", "gep_last_error",
     "gep_pencil_create", "gep_pencil_free", "gep_pencil_info", "gep_ci_solve_pencil",
     "gep_spmm_shifted", "gep_cocg_direction", "gep_spmm_shifted_f32", "gep_spmm_real", "gep_gram", "gep_gram_noalloc",
@@ -86,6 +86,7 @@ def load():
         "gep_result_count": (i32, [P, C.POINTER(i64), C.POINTER(i64)]),
         "gep_result_copy": (i32, [P, P, P, P, P, P]),
         "gep_result_copy_evecs_device": (i32, [P, P, P]),
+        "gep_result_filter": (i32, [P, P]),
         "gep_result_stats": (i32, [P, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
         "gep_result_free": (None, [P]),
         "gep_strerror": (C.c_char_p, [i32]),
@@ -247,13 +248,15 @@ def _collect(res_ptr, status, evecs="host", stream=None):
         raise ValueError(f"evecs must be 'host', 'device' or 'none', not {evecs!r}")
     _check(lib.gep_result_copy(res_ptr, ev.ctypes.data, vec.ctypes.data if evecs == "host" else None,
                                rho.ctypes.data, cid.ctypes.data, conv.ctypes.data))
+    filt = np.ones(m)
+    _check(lib.gep_result_filter(res_ptr, filt.ctypes.data))
     need = C.c_size_t()
     lib.gep_result_stats(res_ptr, None, 0, C.byref(need))
     buf = C.create_string_buffer(need.value)
     lib.gep_result_stats(res_ptr, buf, need.value, None)
     lib.gep_result_free(res_ptr)
     return {"evals": ev, "evecs": vec.T if vec is not None else None, "resid": rho, "contour": cid,
-            "converged": conv.astype(bool), "status": status,
+            "converged": conv.astype(bool), "filter": filt, "status": status,
             "stats": json.loads(buf.value.decode())}
 
 

@@ -195,13 +195,14 @@ def solve_with_fallback(A, B, contours, predicted, n_nodes, moments, block, tol,
         "resid": np.concatenate([res["resid"][keep], res2["resid"]]),
         "contour": np.concatenate([res["contour"][keep], res2["contour"] + len(contours)]),
         "converged": np.concatenate([res["converged"][keep], res2["converged"]]),
+        "filter": np.concatenate([res["filter"][keep], res2["filter"]]),
         "status": max(res["status"], res2["status"]),
         "stats": {"first": res["stats"], "fallback": res2["stats"],
                   "cocg_iters": res["stats"]["cocg_iters"] + res2["stats"]["cocg_iters"],
                   "columns": res["stats"]["columns"] + res2["stats"]["columns"]},
     }
     order = np.argsort(merged["evals"], kind="stable")
-    for key in ("evals", "resid", "contour", "converged"):
+    for key in ("evals", "resid", "contour", "converged", "filter"):
         merged[key] = merged[key][order]
     merged["evecs"] = merged["evecs"][:, order]
     return merged, len(flagged)

@@ -266,3 +266,26 @@ def test_band_factorisation_graph_replay(lib):
         assert r["evals"].size == ref["evals"].size
         np.testing.assert_allclose(r["evals"], ref["evals"], rtol=1e-12)
         assert np.all(r["resid"] <= w.tol)
+
+
+@pytest.mark.parametrize("alpha,near", [(0.0, True), (0.25, False)])
+def test_boundary_proximity_filter(lib, alpha, near):
+    """Per-pair quadrature filter values (gep_result_filter) against the
+    oracle's filter at the returned eigenvalues, and the near-boundary count:
+    keep windows that reach the circle (alpha 0) put pairs in the filter's
+    transition band, a 25% margin keeps them out."""
+    from oracle.cirr import filter_value
+    n = 800
+    A, B = pencils.fem1d(n)
+    lam = configs.line_eigs(n)
+    lo, hi = configs.gap_window(lam, 21, 36)
+    cont = configs.uniform_contours(lo, hi, 1, alpha)
+    r = lib.gep_ci_solve(A, B, cont, 32, 4, 16, 1e-8, seed=4)
+    assert r["evals"].size == 16 and np.all(r["converged"])
+    c, rad = cont[0][0], cont[0][1]
+    want = filter_value(c, rad, 32, r["evals"])
+    np.testing.assert_allclose(r["filter"], want, rtol=0, atol=1e-12)
+    st = r["stats"]
+    assert st["near_boundary_pairs"] == int(np.sum(want < 0.9))
+    assert (st["near_boundary_pairs"] > 0) == near
+    assert abs(st["filter_min"] - want.min()) <= 1e-6
