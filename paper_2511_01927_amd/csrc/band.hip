@@ -278,86 +278,83 @@ __global__ __launch_bounds__(NT) void k_band_panel_rows(const BandSys* __restric
 
 // Trailing update after panel [k0, k0 + kPanel) on the window
 // [k0 + kPanel, wend), wend = min(n, k0 + kPanel + bw), lower triangle,
-// restricted to columns [c0, c1) (rows [c0, wend)).  strip != 0: blockIdx.x
-// is the row tile of the single tile column at c0 (c1 - c0 <= 64); else a
-// lower-triangular tile index (bi >= bj) of 64 x 64 tiles from (c0, c0).
-// npan = 2 adds the contributions of the panel before k0 as well (entries
-// it does not reach are zero).  blockIdx.y is the system.
-__global__ __launch_bounds__(256) void k_band_update(const BandSys* __restrict__ sys,
-                                                     double2* F, int k0, int c0, int c1,
-                                                     int strip, int npan) {
+// restricted to columns [c0, c1) (rows [c0, wend)): C -= W_i diag(d) W_j^T
+// over the lower-triangular set of 64 x 64 tiles (bi >= bj) from (c0, c0),
+// ntile tiles per system.  FP64 matrix cores: wave w owns the tile's 16-column
+// block w and all four 16-row blocks; per 4-deep K step one A operand
+// (l_jk d_k, from registers) serves four complex products (four
+// v_mfma_f64_16x16x4 each), formed transposed so that the read-modify-write
+// of C is coalesced.  Operand layouts (lane l): A(i, k) at i = l % 16,
+// k = l / 16; B(k, j) at k = l / 16, j = l % 16; result register v is
+// D(l / 16 + 4 v, l % 16).  Only the row operand W_i (shared by the four
+// waves) is staged in LDS; each wave reads its own column operand straight
+// into registers, so that four work-groups fit a CU and the launch one round
+// of the chip.  Work-group order as in k_band_strip: the
+// tiles of system s run on XCD s mod 8 and share its L2.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+void k_band_update(const BandSys* __restrict__ sys, int nsys, int ntile, double2* F, int k0, int c0, int c1) {
     __shared__ double2 Wi[64][kPanel + 1];
-    __shared__ double2 Wj[64][kPanel + 1];
-    const BandSys S = sys[blockIdx.y];
+    __shared__ double2 dsh[kPanel];
+    const int g = blockIdx.x, r = g >> 3;
+    const int si = (g & 7) + 8 * (r / ntile), x = r % ntile;
+    if (si >= nsys) return;   // uniform over the work-group
+    const BandSys S = sys[si];
     const int wend = min(S.n, k0 + kPanel + S.bw);
     const int cend = min(c1, wend);
     if (c0 >= cend) return;
-    const int x = blockIdx.x;
-    int bi = x, bj = 0;
-    if (!strip) {
-        bi = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
-        while ((bi + 1) * (bi + 2) / 2 <= x) ++bi;
-        while (bi * (bi + 1) / 2 > x) --bi;
-        bj = x - bi * (bi + 1) / 2;
-    }
+    int bi = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
+    while ((bi + 1) * (bi + 2) / 2 <= x) ++bi;
+    while (bi * (bi + 1) / 2 > x) --bi;
+    const int bj = x - bi * (bi + 1) / 2;
     const int i0 = c0 + 64 * bi, j0 = c0 + 64 * bj;
     if (i0 >= wend || j0 >= cend) return;
     const int ld = S.bw + 1;
-    const double2* Fs = F + S.off;   // panel columns (read) and window columns (written) of one band
-    // FP64 matrix cores: wave w owns the tile's 16-column block w and all
-    // four 16-row blocks; per 4-deep K step one A operand (W_j) serves four
-    // complex products (four v_mfma_f64_16x16x4 each), formed transposed so
-    // that the read-modify-write of C is coalesced.  Operand layouts
-    // (lane l): A(i, k) at i = l % 16, k = l / 16; B(k, j) at k = l / 16,
-    // j = l % 16; result register v is D(l / 16 + 4 v, l % 16).
+    double2* Fs = F + S.off;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x < kPanel) dsh[threadIdx.x] = k0 + threadIdx.x < S.n ? Fs[(int64_t)(k0 + threadIdx.x) * ld] : make_double2(0.0, 0.0);
+    for (int idx = threadIdx.x; idx < 64 * kPanel; idx += blockDim.x) {
+        const int rr = idx & 63, kk = idx >> 6;   // lanes run down a band column
+        const int k = k0 + kk, i = i0 + rr;
+        Wi[rr][kk] = i < wend && i - k <= S.bw ? Fs[(int64_t)k * ld + (i - k)] : make_double2(0.0, 0.0);
+    }
+    // A(j, k) = l_jk for this wave's 16 columns j; every row here lies below
+    // the panel (j >= c0 > k), so only the band limits the entries read
+    const int jr = j0 + 16 * wave + (lane & 15);
+    double2 wj[kPanel / 4];
+#pragma unroll
+    for (int q = 0; q < kPanel / 4; ++q) {
+        const int k = k0 + 4 * q + (lane >> 4);
+        wj[q] = jr < cend && jr - k <= S.bw ? Fs[(int64_t)k * ld + (jr - k)] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
     mfma_f64x4 pre[4], pim[4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
         pre[rb] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
         pim[rb] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
     }
-    for (int pp = 0; pp < npan; ++pp) {   // contributions of panel k0 (and of the one before it)
-        const int kp = k0 - kPanel * pp;
-        if (kp < 0) break;
-        if (pp > 0) __syncthreads();
-        for (int idx = threadIdx.x; idx < 64 * kPanel; idx += blockDim.x) {
-            const int r = idx & 63, kk = idx >> 6;   // lanes run down a band column
-            const int k = kp + kk;
-            const int i = i0 + r, j = j0 + r;
-            double2 wi = make_double2(0.0, 0.0), wj = make_double2(0.0, 0.0);
-            if (i < wend && i - k <= S.bw) wi = Fs[(int64_t)k * ld + (i - k)];
-            if (j < cend && j - k <= S.bw) wj = cmul(Fs[(int64_t)k * ld + (j - k)], Fs[(int64_t)k * ld]);
-            Wi[r][kk] = wi;
-            Wj[r][kk] = wj;
-        }
-        __syncthreads();
 #pragma unroll
-        for (int st = 0; st < kPanel / 4; ++st) {
-            const int kk = 4 * st + (lane >> 4);
-            const double2 a = Wj[wave * 16 + (lane & 15)][kk];
+    for (int q = 0; q < kPanel / 4; ++q) {
+        const int kk = 4 * q + (lane >> 4);
+        const double2 a = cmul(wj[q], dsh[kk]);
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) {
-                const double2 b = Wi[rb * 16 + (lane & 15)][kk];
-                // P^T += W_j W_i^T (complex): re = a.x b.x - a.y b.y, im = a.x b.y + a.y b.x
-                pre[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, pre[rb], 0, 0, 0);
-                pre[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, pre[rb], 0, 0, 0);
-                pim[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, pim[rb], 0, 0, 0);
-                pim[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, pim[rb], 0, 0, 0);
-            }
+        for (int rb = 0; rb < 4; ++rb) {
+            const double2 b = Wi[rb * 16 + (lane & 15)][kk];
+            // P^T += W_j W_i^T (complex): re = a.x b.x - a.y b.y, im = a.x b.y + a.y b.x
+            pre[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, pre[rb], 0, 0, 0);
+            pre[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, pre[rb], 0, 0, 0);
+            pim[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, pim[rb], 0, 0, 0);
+            pim[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, pim[rb], 0, 0, 0);
         }
     }
-    // register v of lane l of row block rb: column j = 16 wave + l / 16 + 4 v,
-    // row i = 16 rb + l % 16 (lanes run down a column of C)
-    double2* Fw = F + S.off;
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int j = j0 + wave * 16 + (lane >> 4) + 4 * v;
+            const int j = j0 + 16 * wave + (lane >> 4) + 4 * v;
             const int i = i0 + rb * 16 + (lane & 15);
             if (j >= cend || i >= wend || i < j) continue;
-            double2& c = Fw[(int64_t)j * ld + (i - j)];
+            double2& c = Fs[(int64_t)j * ld + (i - j)];
             c.x -= pre[rb][v];
             c.y -= pim[rb][v];
         }
@@ -1364,12 +1361,9 @@ hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int 
         return launch_ev(k_band_strip, dim3(8 * groups * T), dim3(256), s, e0, e1, sys, nsys, T, F, k0,
                          k0 >= kPanel ? 2 : 1);
     }
-    int c0 = w0, c1 = w0 + bwmax, strip = 0, npan = 1;
-    if (part == 2) {
-        c0 = w0 + 2 * kPanel;
-    }
+    const int c0 = part == 2 ? w0 + 2 * kPanel : w0, c1 = w0 + bwmax;
     const int T = (w0 + bwmax - c0 + 63) / 64;
-    const int tiles = strip ? T : T * (T + 1) / 2;
+    const int tiles = T * (T + 1) / 2;
     if (tiles <= 0 || c0 >= c1) {   // nothing to update (narrow band): the events still bracket a point
         if (e0) {
             hipError_t e = hipEventRecord(e0, s);
@@ -1377,7 +1371,9 @@ hipError_t band_update(const BandSys* sys, int nsys, int bwmax, double2* F, int 
         }
         return e1 ? hipEventRecord(e1, s) : hipSuccess;
     }
-    return launch_ev(k_band_update, dim3(tiles, nsys), dim3(256), s, e0, e1, sys, F, k0, c0, c1, strip, npan);
+    // XCD-grouped order: 8 work-group slots per group of 8 systems and tile
+    const int groups = (nsys + 7) / 8;
+    return launch_ev(k_band_update, dim3(8 * groups * tiles), dim3(256), s, e0, e1, sys, nsys, tiles, F, k0, c0, c1);
 }
 
 int band_chunk_columns(int bw) {
