@@ -55,23 +55,23 @@ TRAFFIC = [
         "precision": "fp64",
         "sources_sha256": {
             "paper_2511_01927_amd/csrc/cocg.hip": "d77cbde59f14638d2c50f773f839a7be198170836066b48c624d8ac22f973ea1",
-            "paper_2511_01927_amd/csrc/internal.h": "ae891c2b4dae34136c3ed5abdca25bbfe2e22d05efb54a0029d384d680705d18",
+            "paper_2511_01927_amd/csrc/internal.h": "fe02d87eab89e9f3ce3dc21207077ee00c5a24d8999c17071557d0a3182a8605",
         },
         # bytes per tile-launch (scaled by the tiles a launch processes)
-        "per_tile_bytes": {"cocg_spmm_dir": 3.389801e+08, "cocg_update": 5.272175e+08},
+        "per_tile_bytes": {"cocg_spmm_dir": 3.389832e+08, "cocg_update": 5.272176e+08},
         "profile": "profiles/cocg_q1_300x300_fp64_hbm_traffic.md",
     },
     {
         "workload": "q1_2d_300",
         "precision": "fp64",
         "sources_sha256": {
-            "paper_2511_01927_amd/csrc/band.hip": "a67899f49a241d37875eae62b3634d8fd6682921ecf3ae3875c9c2f5c7650b33",
+            "paper_2511_01927_amd/csrc/band.hip": "9cd99bf12c078fba7f11e7ee7cde5d615523474a314630f763a89ef522ec771a",
             "paper_2511_01927_amd/csrc/internal.h": "fe02d87eab89e9f3ce3dc21207077ee00c5a24d8999c17071557d0a3182a8605",
         },
         # bytes per launch (per timed bracket for band_solve: right-hand sides,
         # forward and backward sweep)
-        "per_launch_bytes": {"band_update": 9.614991e+07, "band_update_next": 3.717571e+07,
-                             "band_panel": 2.045747e+07, "band_solve": 8.696545e+10},
+        "per_launch_bytes": {"band_update": 6.795489e+07, "band_update_next": 3.717571e+07,
+                             "band_panel": 2.045747e+07, "band_solve": 8.697036e+10},
         "profile": "profiles/band_q1_300x300_fp64_hbm_traffic.md",
     },
 ]
