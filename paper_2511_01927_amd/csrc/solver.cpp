@@ -1880,7 +1880,8 @@ static std::string boundary_stats(const std::vector<double>& filt) {
         near += f < kNearBoundary;
         fmin = std::min(fmin, f);
     }
-    return "\"near_boundary_pairs\":" + std::to_string(near) + ",\"filter_min\":" + std::to_string(fmin) + ",";
+    return "\"near_boundary_pairs\":" + std::to_string(near) + ",\"filter_min\":" +
+           (std::isfinite(fmin) ? std::to_string(fmin) : std::string("null")) + ",";
 }
 
 static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* const* contours,
