@@ -299,6 +299,176 @@ def main_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def main_learned(args):
+    """Learned contours + mixed precision + one batched solve against plain FP64
+    uniform contours solved pencil by pencil, at equal accuracy, on held-out 3D
+    27-point FEM pencils (the prior trained on 16^3 fields, untimed)."""
+    import math
+    from workloads import configs
+    first, last = configs.LEARNED_FIRST, configs.LEARNED_LAST
+    nbins, side, M, factor, tol, N = 64, 8, 4, 2.5, 1e-8, 32
+    expected = last - first
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before the GPU is touched (the oracle forks worker processes): the
+        # oracle on the first held-out instance with its uniform circles
+        import oracle
+        from oracle.cirr import default_workers
+        from paper_2511_01927_amd.learned import uniform_contours, weyl_count_3d, blocks_for
+        m0, sd0 = configs.LEARNED_EVAL[0]
+        A0, B0, _, kap0, win0 = configs.learned_instance(m0, sd0)
+        uc0 = uniform_contours(win0, max(1, math.ceil(expected / 40)))
+        b0 = max(blocks_for([weyl_count_3d(kap0, b) - weyl_count_3d(kap0, a) for _, _, a, b in uc0], M, factor=factor))
+        workers = default_workers()
+        t0 = time.perf_counter()
+        ref = oracle.oracle_ci_solve(A0, B0, uc0[:2], N, M, b0, tol, seed=3, workers=workers)
+        dt = time.perf_counter() - t0
+        ok = int(np.sum(ref["resid"] <= tol))
+        cpu = {"value": ok / dt, "unit": "eigenpairs/s", "cores": workers, "kind": "oracle",
+               "host": {"cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(), "worker_processes": workers,
+                        "threads_per_worker": 1},
+               "sample": f"the first held-out instance (grid {m0}^3, n={A0.shape[0]}), the first 2 of its "
+                         f"{len(uc0)} uniform circles, every node by sparse LU, block {b0}: {ok} eigenpairs in "
+                         f"{dt:.2f} s on {workers} processes"}
+        print(f"# cpu baseline: {cpu['sample']}", flush=True)
+    import torch
+    from paper_2511_01927_amd import gep_ci, learned
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    # training (untimed): labels from this library's own batched FP64 solves
+    t0 = time.perf_counter()
+    feats, probs = [], []
+    for m, sd in configs.LEARNED_TRAIN:
+        A, B, g, kap, win = configs.learned_instance(m, sd)
+        probs.append((A, B, learned.uniform_contours(win, 5)))
+        feats.append(learned.field_features_3d(g, side))
+    res = gep_ci.gep_ci_solve_batch(probs, N, M, 48, tol, seed=1, max_refine=1, stream=stream)
+    targs = []
+    for (A, B, c), r in zip(probs, res):
+        targs.append(learned.histogram_target(r["evals"][r["resid"] <= tol], (c[0][2], c[-1][3]), nbins, expected))
+    prior = learned.SpectralPrior(n_bins=nbins, hidden=256, max_batch=64, seed=11, din=side ** 3)
+    hist = prior.train(np.array(feats), np.array(targs), epochs=200, batch=16, lr=1e-3)
+    train_s = time.perf_counter() - t0
+    print(f"# prior trained on {len(feats)} solved 16^3 fields in {train_s:.1f} s (loss {hist[0]:.3f} -> "
+          f"{hist[-1]:.3f})", flush=True)
+    # held-out instances: learned and uniform contours, block sizes by the same rule
+    inst, L_c, L_p, L_b, U_c, U_b = [], [], [], [], [], []
+    for m, sd in configs.LEARNED_EVAL:
+        A, B, g, kap, win = configs.learned_instance(m, sd)
+        inst.append((m, A, B))
+        h = prior.predict(learned.field_features_3d(g, side)[None, :])[0]
+        cont, pred = learned.learned_contours(h, win, expected, nmin=args.kde_nmin, nmax=args.kde_nmax, w=10.0,
+                                              alpha=0.1)
+        L_c.append(cont)
+        L_p.append(pred)
+        L_b.append(learned.blocks_for(pred, M, factor=factor))
+        uc = learned.uniform_contours(win, max(1, math.ceil(expected / 40)))
+        pu = [learned.weyl_count_3d(kap, b) - learned.weyl_count_3d(kap, a) for _, _, a, b in uc]
+        U_c.append(uc)
+        U_b.append(learned.blocks_for(pu, M, factor=factor))
+    pens = [gep_ci.Pencil(A, B, stream=stream) for _, A, B in inst]
+    bp = gep_ci.BatchPencil([(A, B) for _, A, B in inst], stream=stream)
+    bmax = max(max(b) for b in L_b + U_b)
+    common = dict(seed=3, stream=stream, evecs="device", solve_tol=args.solve_tol)
+
+    def plain():
+        return [pens[i].solve(U_c[i], N, M, max(U_b[i]), tol, blocks=U_b[i], precision="fp64", **common)
+                for i in range(len(pens))]
+
+    def learned_run():
+        return learned.batch_with_fallback(bp, pens, L_c, L_p, N, M, bmax, tol, blocks=L_b,
+                                           precision=args.precision if args.precision != "fp64" else "mixed",
+                                           **common)
+
+    def learned_fp64_single():   # ablation: the prediction alone
+        first = [pens[i].solve(L_c[i], N, M, max(L_b[i]), tol, blocks=L_b[i], precision="fp64", **common)
+                 for i in range(len(pens))]
+        return learned.resolve_flagged(first, pens, L_c, L_p, N, M, bmax, tol, precision="fp64", **common)[0]
+
+    def uniform_mixed_batched():   # ablation: precision and batching alone
+        return bp.solve(U_c, N, M, bmax, tol, blocks=U_b, precision="mixed", **common)
+
+    for _ in range(max(1, args.warmup)):
+        plain()
+        learned_run()
+    torch.cuda.synchronize()
+    abl = {}
+    for name, fn in (("learned_fp64_per_pencil", learned_fp64_single), ("uniform_mixed_batched", uniform_mixed_batched)):
+        fn()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        rr = fn()
+        torch.cuda.synchronize()
+        d = time.perf_counter() - ts
+        good = sum(int(np.sum(r["resid"] <= tol)) for r in rr)
+        abl[name] = {"eigenpairs_per_s": round(good / d, 3), "ms": round(d * 1e3, 1), "pairs": good}
+        print(f"# ablation {name}: {good} pairs in {d * 1e3:.0f} ms", flush=True)
+    tp, tl, rp, rl, nflag = [], [], None, None, 0
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        rp = plain()
+        torch.cuda.synchronize()
+        tp.append(time.perf_counter() - ts)
+        ts = time.perf_counter()
+        rl, nflag = learned_run()
+        torch.cuda.synchronize()
+        tl.append(time.perf_counter() - ts)
+        print(f"# step {i}: plain {tp[-1] * 1e3:.0f} ms, learned+mixed+batched {tl[-1] * 1e3:.0f} ms", flush=True)
+    # equal accuracy: the two strategies return the same converged eigenvalues
+    pairs_p = pairs_l = 0
+    worst = 0.0
+    missed = 0
+    for a, b in zip(rp, rl):
+        ea = np.sort(a["evals"][a["resid"] <= tol])
+        eb = np.sort(b["evals"][b["resid"] <= tol])
+        pairs_p += ea.size
+        pairs_l += eb.size
+        if ea.size == eb.size and ea.size:
+            worst = max(worst, float(np.max(np.abs(ea - eb) / np.abs(ea))))
+        missed += abs(int(ea.size) - int(eb.size))
+    rate_p = pairs_p * len(tp) / sum(tp)
+    rate_l = pairs_l * len(tl) / sum(tl)
+    inst_l = bp.solve(L_c, N, M, bmax, tol, blocks=L_b, timing=True, precision="mixed", seed=3, stream=stream,
+                      evecs="none")
+    st = inst_l[0]["stats"]
+    km = st["kernel_ms"]
+    fl = (st["band_update_flops"] + st["band_update_next_flops"] + st["band_panel_flops"]
+          + st.get("band_wide_flops", 0))
+    fms = (km.get("band_update", 0) + km.get("band_update_next", 0) + km.get("band_panel", 0)
+           + km.get("band_factor_wide", 0))
+    peak = FP32_MFMA_PEAK_TFLOPS if st.get("band_wide_flops", 0) and st["precision"] == "mixed" \
+        else FP64_VECTOR_PEAK_TFLOPS
+    out = {
+        "metric": METRIC, "value": round(rate_l, 3), "unit": "eigenpairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * sum(tl) / len(tl), 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "learned3d: 3D 27-point trilinear-FEM pencils, log-normal coefficients (sigma 1), "
+                               "held-out fields on " + ", ".join(f"{m}^3" for m, _ in configs.LEARNED_EVAL)
+                               + f", Weyl indices [{first}, {last}); learned contours (prior trained on 64 16^3 "
+                               f"fields; KDE with {args.kde_nmin}-{args.kde_nmax} predicted eigenvalues per circle) "
+                               "+ FP32 factors with FP64 refinement + one batched solve, against uniform circles "
+                               "in FP64 solved pencil by pencil",
+                   "instances": len(inst), "nodes": N, "moments": M, "precision": "mixed"},
+        "vs_plain_fp64": {"plain_fp64_eigenpairs_per_s": round(rate_p, 3),
+                          "speedup": round(rate_l / rate_p, 3) if rate_p > 0 else None,
+                          "plain_ms_per_step": round(1e3 * sum(tp) / len(tp), 1),
+                          "pairs_plain": pairs_p, "pairs_learned": pairs_l, "count_differences": missed,
+                          "eigenvalue_rel_diff_max": worst, "fallback_contours": nflag,
+                          "columns_learned": int(rl[0]["stats"]["columns"]),
+                          "columns_plain": sum(int(r["stats"]["columns"]) for r in rp)},
+        "roofline": {"bound": "mfma", "achieved": round(fl / fms / 1e9, 3) if fms else None, "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(fl / fms / 1e9 / peak, 4) if fms else None,
+                     "traffic": None, "kernel": "band factorisation of the learned batched solve",
+                     "note": "factorisation flops / sampled HIP-event time of its kernels"},
+        "ablation": abl,
+        "training_s": round(train_s, 1),
+        "cpu_baseline": cpu,
+        "step_ms": {"plain": [round(t * 1e3, 1) for t in tp], "learned": [round(t * 1e3, 1) for t in tl]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,6 +503,11 @@ def main():
                     help="copy the eigenvectors to host memory inside the timed steps (default: "
                          "they stay in device memory); the default run also times one solve with "
                          "the host copy after the timed region")
+    ap.add_argument("--kde-nmin", type=int, default=30,
+                    help="learned3d: fewest predicted eigenvalues per KDE contour")
+    ap.add_argument("--kde-nmax", type=int, default=120,
+                    help="learned3d: most predicted eigenvalues per KDE contour (the banded solves cost "
+                         "per circle, so fewer, fuller circles suit them)")
     ap.add_argument("--counters", action="store_true",
                     help="run for hardware-counter collection: no HIP-event timing around the "
                          "kernels (graph replay as in production), copy probe on; use with "
@@ -345,6 +520,8 @@ def main():
 
     if args.workload == "q1_batch64":
         return main_batch(args)
+    if args.workload == "learned3d":
+        return main_learned(args)
     w, ref = workload(args.workload)
     cpu = None
     if not args.no_cpu_baseline:

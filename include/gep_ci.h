@@ -116,11 +116,13 @@ typedef struct {
                                iterations from a captured HIP graph; 2: also the
                                banded factorisation's launches, captured once per
                                pencil and layout (not with timing) */
-    const int* blocks;      /* optional per-contour block sizes (host, n_contours
-                               entries, each 1..block) for gep_ci_solve and
-                               gep_ci_solve_pencil: contour k uses the first
-                               blocks[k] columns of V.  NULL: every contour uses
-                               `block`.  Ignored by gep_ci_solve_batch. */
+    const int* blocks;      /* optional per-contour block sizes (host, each
+                               1..block): contour k uses the first blocks[k]
+                               columns of V.  One entry per contour; for the
+                               batched entry points the problems' entries one
+                               after another (sum of n_contours entries).  NULL:
+                               every contour uses `block`.  Ignored by
+                               gep_ci_solve_smallest. */
     int row_group;          /* rows whose neighbour gathers the COCG kernels share:
                                4 (groups of 4 consecutive rows of one pencil, union
                                of their columns), 1 (plain CSR), 0 (default:

@@ -1917,7 +1917,8 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
     V.release();
     // jobs and memory plan: waves of jobs in order
     std::vector<Job> all;
-    for (int p = 0; p < n_problems; ++p)
+    int64_t boff = 0;   // problem p's first entry of cfg.o.blocks (problems in order)
+    for (int p = 0; p < n_problems; boff += n_contours[p], ++p)
         for (int k = 0; k < n_contours[p]; ++k) {
             Job j;
             j.c = contours[p][k];
@@ -1926,7 +1927,7 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
             j.row0 = H.prob_row0[p];
             j.n = H.prob_n[p];
             j.bsrc0 = H.prob_row0[p] * L;
-            j.L = (n_problems == 1 && cfg.o.blocks) ? cfg.o.blocks[k] : L;
+            j.L = cfg.o.blocks ? cfg.o.blocks[boff + k] : L;
             all.push_back(j);
         }
     size_t freeb = 0, totalb = 0;
@@ -2458,14 +2459,21 @@ int gep_ci_solve_pencil_batch(gep_pencil* P, const gep_contour* const* contours,
     for (int p = 0; p < n_problems; ++p) out[p] = nullptr;
     gep_opts o;
     if (opts) o = *opts; else gep_opts_default(&o);
-    o.blocks = nullptr;
+    int64_t nk = 0;
     for (int p = 0; p < n_problems; ++p) {
         int st = validate_problem(contours[p], n_contours[p], n_nodes, moments, block, tol, &o);
         if (st) {
             gep::set_error("problem " + std::to_string(p) + ": " + gep::g_err);
             return st;
         }
+        nk += n_contours[p];
     }
+    if (o.blocks)
+        for (int64_t k = 0; k < nk; ++k)
+            if (o.blocks[k] < 1 || o.blocks[k] > block) {
+                gep::set_error("blocks[" + std::to_string(k) + "] must be in [1, block]");
+                return GEP_EINVAL;
+            }
     gep::SolveCfg cfg;
     cfg.N = n_nodes;
     cfg.NH = n_nodes / 2;

@@ -324,11 +324,14 @@ class BatchPencil:
         self.n_problems = cnt.value
 
     def solve(self, contours_list, n_nodes, moments, block, tol, **kw):
-        """contours_list[p]: the circles of problem p; returns a list of result dicts."""
+        """contours_list[p]: the circles of problem p; returns a list of result dicts.
+        blocks (optional): per problem, its contours' block sizes."""
         lib = load()
         P = self.n_problems
         if len(contours_list) != P:
             raise ValueError(f"{P} problems, {len(contours_list)} contour sets")
+        if kw.get("blocks") is not None:
+            kw["blocks"] = np.concatenate([np.asarray(b, dtype=np.int32).ravel() for b in kw["blocks"]])
         conts = [_contours(c) for c in contours_list]
         cptr = (C.POINTER(gep_contour) * P)(*[C.cast(c[0], C.POINTER(gep_contour)) for c in conts])
         nks = (C.c_int * P)(*[c[1] for c in conts])

@@ -14,9 +14,9 @@ Contour Construction via KDE"), then run the CI solver.  Here:
 * predicted eigenvalue positions are the histogram's quantile points, fed to
   ``gep_kde_contours``;
 * every learned solve is judged by the solver: contours whose subspace is
-  saturated, whose pairs miss the residual bar, or whose eigenvalue count
-  differs from the prediction by more than 20% fall back to uniform
-  contours over their interval (the scouting-free baseline).
+  saturated, whose pairs miss the residual bar, or that found more than 20%
+  fewer eigenvalues than predicted fall back to uniform contours over their
+  interval (the scouting-free baseline).
 
 Only marshalling and O(#eigenvalues) bookkeeping run in Python; the solves,
 the network and KDE run in the library.
@@ -170,8 +170,11 @@ def solve_with_fallback(A, B, contours, predicted, n_nodes, moments, block, tol,
     """Solve on the given contours; re-solve flagged contours on uniform sub-contours.
 
     A contour is flagged when its subspace is saturated, when a kept pair
-    misses tol, or when its eigenvalue count differs from the predicted count
-    by more than 20% (and by more than 2).  Returns (result, n_fallback).
+    misses tol, or when it found fewer eigenvalues than predicted by more than
+    20% (and by more than 2): a missed eigenvalue shows as a shortfall, while
+    more pairs than predicted in an unsaturated subspace of converged pairs
+    means the prediction was low, not that the solve failed.  Returns (result,
+    n_fallback).
     """
     res = gep_ci.gep_ci_solve(A, B, contours, n_nodes, moments, block, tol, **kw)
     flagged = []
@@ -179,7 +182,7 @@ def solve_with_fallback(A, B, contours, predicted, n_nodes, moments, block, tol,
         mine = res["contour"] == k
         found = int(np.sum(mine))
         bad_pairs = bool(np.any(~res["converged"][mine]))
-        miss = predicted is not None and abs(found - predicted[k]) > max(2, 0.2 * predicted[k])
+        miss = predicted is not None and found < predicted[k] - max(2, 0.2 * predicted[k])
         if c["saturated"] or bad_pairs or miss:
             flagged.append(k)
     if not flagged:
@@ -206,3 +209,48 @@ def solve_with_fallback(A, B, contours, predicted, n_nodes, moments, block, tol,
         merged[key] = merged[key][order]
     merged["evecs"] = merged["evecs"][:, order]
     return merged, len(flagged)
+
+
+def resolve_flagged(res, pencils_, contours_list, predicted, n_nodes, moments, block, tol, fallback_k=2, **kw):
+    """Per problem p, the contours of the first-pass result res[p] that are
+    flagged (saturated, a kept pair above tol, or more than 20% and 2 fewer
+    eigenvalues than predicted) re-solved on uniform sub-contours on that
+    problem's Pencil.  Returns (per-problem dicts with evals, resid, contour,
+    converged, stats; number of flagged contours)."""
+    out, nflag = [], 0
+    for p, r in enumerate(res):
+        conts = np.asarray(contours_list[p])
+        flagged = []
+        cs = r["stats"].get("contours", [])
+        for k in range(len(conts)):
+            mine = r["contour"] == k
+            found = int(np.sum(mine))
+            sat = k < len(cs) and bool(cs[k]["saturated"])
+            bad = bool(np.any(~r["converged"][mine]))
+            miss = predicted is not None and found < predicted[p][k] - max(2, 0.2 * predicted[p][k])
+            if sat or bad or miss:
+                flagged.append(k)
+        nflag += len(flagged)
+        keep = ~np.isin(r["contour"], flagged)
+        ev, rs, cv, cid = r["evals"][keep], r["resid"][keep], r["converged"][keep], r["contour"][keep]
+        if flagged:
+            sub = np.concatenate([uniform_contours((conts[k][2], conts[k][3]), fallback_k) for k in flagged])
+            kw2 = {key: v for key, v in kw.items() if key != "blocks"}
+            r2 = pencils_[p].solve(sub, n_nodes, moments, block, tol, **kw2)
+            ev = np.concatenate([ev, r2["evals"]])
+            rs = np.concatenate([rs, r2["resid"]])
+            cv = np.concatenate([cv, r2["converged"]])
+            cid = np.concatenate([cid, r2["contour"] + len(conts)])
+        o = np.argsort(ev, kind="stable")
+        out.append({"evals": ev[o], "resid": rs[o], "converged": cv[o], "contour": cid[o], "stats": r["stats"]})
+    return out, nflag
+
+
+def batch_with_fallback(bp, pencils_, contours_list, predicted, n_nodes, moments, block, tol, blocks=None,
+                        fallback_k=2, **kw):
+    """Batched solve of every problem's contours on a BatchPencil, then the
+    flagged contours of each problem re-solved on its own Pencil
+    (resolve_flagged)."""
+    res = bp.solve(contours_list, n_nodes, moments, block, tol, blocks=blocks, **kw)
+    return resolve_flagged(res, pencils_, contours_list, predicted, n_nodes, moments, block, tol,
+                           fallback_k=fallback_k, **kw)

@@ -50,3 +50,27 @@ def test_batch_pencil_needs_the_batch_entry_point(lib):
     with pytest.raises(lib.GepError) as e:
         lib.Pencil.solve(bp, bt.problems[0].contours, 32, 4, 32, 1e-8)
     assert e.value.status == -1
+
+
+def test_batch_per_contour_blocks(lib):
+    """Per-contour block sizes in a batched solve (the problems' entries one
+    after another) give each problem the pairs of its own single-pencil solve
+    with the same block sizes, and the statistics count the smaller blocks'
+    columns."""
+    bt = configs.config_q1_batch(count=3, seed0=4200, nmin=1200, nmax=2500, cmin=20, cmax=50)
+    bp = lib.BatchPencil([(w.A, w.B) for w in bt.problems])
+    conts = [w.contours for w in bt.problems]
+    rng = np.random.default_rng(5)
+    blocks = [rng.integers(bt.block * 3 // 4, bt.block + 1, size=len(c)) for c in conts]
+    got = bp.solve(conts, bt.n_nodes, bt.moments, bt.block, bt.tol, seed=bt.seed, blocks=blocks)
+    full = bp.solve(conts, bt.n_nodes, bt.moments, bt.block, bt.tol, seed=bt.seed)
+    assert got[0]["stats"]["columns"] < full[0]["stats"]["columns"]
+    for p, w in enumerate(bt.problems):
+        one = lib.gep_ci_solve(w.A, w.B, w.contours, bt.n_nodes, bt.moments, bt.block, bt.tol,
+                               seed=bt.seed + p, blocks=blocks[p])
+        assert got[p]["evals"].size == one["evals"].size and np.all(got[p]["converged"])
+        np.testing.assert_allclose(got[p]["evals"], one["evals"], rtol=1e-10)
+    with pytest.raises(lib.GepError):
+        bad = [b.copy() for b in blocks]
+        bad[1][0] = bt.block + 1
+        bp.solve(conts, bt.n_nodes, bt.moments, bt.block, bt.tol, seed=bt.seed, blocks=bad)

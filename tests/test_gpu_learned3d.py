@@ -126,3 +126,30 @@ def test_learned_contours_3d_gain_over_uniform(lib):
     # the prediction's gain: fewer shifted-system columns and a higher rate
     assert tot["learned"]["columns"] < tot["uniform"]["columns"]
     assert tot["learned"]["pairs"] / tot["learned"]["s"] >= tot["uniform"]["pairs"] / tot["uniform"]["s"]
+
+
+def test_batched_fallback_matches_single_pencil_solves(lib):
+    """learned.batch_with_fallback (one batched mixed-precision solve, flagged
+    contours re-solved per pencil) returns the converged eigenvalues of plain
+    FP64 single-pencil solves of the same contours, pencil by pencil."""
+    from paper_2511_01927_amd import learned
+    from workloads import configs
+    insts = [configs.learned_instance(m, s, 60, 140) for m, s in ((12, 950), (14, 951))]
+    pens = [lib.Pencil(A, B) for A, B, *_ in insts]
+    bp = lib.BatchPencil([(A, B) for A, B, *_ in insts])
+    conts, preds, blocks = [], [], []
+    for A, B, g, kap, win in insts:
+        c = learned.uniform_contours(win, 2)
+        p = [learned.weyl_count_3d(kap, b) - learned.weyl_count_3d(kap, a) for _, _, a, b in c]
+        conts.append(c)
+        preds.append(p)
+        blocks.append(learned.blocks_for(p, 4, factor=2.5))
+    bmax = max(max(b) for b in blocks)
+    got, nflag = learned.batch_with_fallback(bp, pens, conts, preds, 32, 4, bmax, 1e-8, blocks=blocks,
+                                             precision="mixed", seed=3)
+    for i, pen in enumerate(pens):
+        ref = pen.solve(conts[i], 32, 4, bmax, 1e-8, seed=3, precision="fp64")
+        a = np.sort(ref["evals"][ref["resid"] <= 1e-8])
+        b = np.sort(got[i]["evals"][got[i]["resid"] <= 1e-8])
+        assert a.size > 20 and a.size == b.size, (i, a.size, b.size, nflag)
+        np.testing.assert_allclose(b, a, rtol=1e-10)

@@ -196,3 +196,24 @@ def config_q1_batch(count: int = 64, seed0: int = 4000, nmin: int = 5000, nmax: 
 def q1_batch64() -> Batch:
     return config_q1_batch()
 
+
+
+# Learned-contour comparison: 3D 27-point trilinear FEM pencils with
+# log-normal coefficients (sigma 1).  The spectral prior trains on 64 random
+# 16^3 fields (field seeds 300..363); the comparison runs on held-out fields
+# on finer grids (the prior's transfer to grids it never saw).  Every instance
+# targets the Weyl-law indices [60, 220) of its own coefficient field.
+LEARNED_TRAIN = [(16, s) for s in range(300, 364)]
+LEARNED_EVAL = [(24, 900), (24, 901), (28, 902), (28, 903), (32, 904), (32, 905)]
+LEARNED_FIRST, LEARNED_LAST = 60, 220
+
+
+def learned_instance(m: int, seed: int, first: int = LEARNED_FIRST, last: int = LEARNED_LAST):
+    """(A, B, log-coefficient field, coefficient field, Weyl window) of one
+    3D instance on an m^3 element grid."""
+    g = pencils.grf((m + 1,) * 3, seed=seed)
+    kap = np.exp(g)
+    A, B = pencils.q1_3d(m, kap)
+    m_ = float(np.mean(kap ** -1.5))
+    lam = lambda k: (6.0 * np.pi ** 2 * k / m_) ** (2.0 / 3.0)
+    return A, B, g, kap, (lam(first), lam(last))
