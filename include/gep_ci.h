@@ -137,7 +137,16 @@ typedef struct {
                                Jacobi COCG, 0 (default) = banded when every
                                pencil's half bandwidth is <= 4096, else COCG.
                                With precision GEP_MIXED the banded factors
-                               are FP32 (the residuals and the solution FP64). */
+                               are FP32 (the residuals and the solution FP64).
+                               3 = multi-shift COCG: for a single pencil (not
+                               a batch) whose B is beta I (no off-diagonal
+                               entries, constant diagonal, beta != 0; else
+                               GEP_EINVAL), each contour's nodes share one
+                               Krylov space per right-hand side, iterated on
+                               the node nearest the real axis; no
+                               preconditioner; FP64 regardless of precision.
+                               A column stops when its residual estimate
+                               ||r|| / |pi| is <= solve_tol ||B v||. */
     int band_kernels;       /* banded factorisation kernels: 0 (default) =
                                register-panel kernels with lookahead for FP64
                                factors of half bandwidth <= 1024, wide-band

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgepci.so")
 SOURCES = ["spmm.hip", "cocg.hip", "band.hip", "band_wide.hip", "moments.hip", "gemm.hip", "dense.hip", "density.hip",
-           "kde.cpp", "solver.cpp"]
+           "multishift.hip", "kde.cpp", "solver.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

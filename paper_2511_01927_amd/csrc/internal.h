@@ -209,6 +209,18 @@ int band_chunk_columns(int bw);
 hipError_t band_solve(const BandSys* sys, const int32_t* colsys, const double2* F,
                       const TileGeom& g, int ntiles, int bwmax, double2* X, hipStream_t s,
                       int chunk);
+// Multi-shift COCG (multishift.hip).  Seed vectors: nseed_tiles tiles of
+// 64 columns over n rows.  Seed residual update with the partials of r^T r
+// and ||r||^2 per seed tile, row block (nrb blocks) and column; the shifted
+// columns' solution and search-vector update (coef[3 c + 0..2] = alpha_c,
+// beta_c, 1 / pi_c; col_l[c] = seed column, -1 for padding); the seed search
+// vector p_s = r + beta p_s.
+hipError_t ms_seed_update(int n, int nseed_tiles, int nrb, const double2* alpha, const double2* q, double2* r,
+                          double2* part_rho, double* part_nrm, hipStream_t s);
+hipError_t ms_shift_update(const TileGeom& g, int ntiles, int64_t nmax, int n_seed, const int32_t* col_l,
+                           const int32_t* active, const double2* coef, const double2* r, double2* X, double2* P,
+                           hipStream_t s);
+hipError_t ms_seed_p(int n, int nseed_tiles, const double2* beta, const double2* r, double2* ps, hipStream_t s);
 hipError_t band_rhs(const TileGeom& g, const int64_t* bsrc, const double* BV, int64_t ldbv,
                     int ntiles, double2* X, hipStream_t s);
 // R = b - K X, rel[col] = ||R|| / ||b||; part holds ntiles * nrb_cap * 64 entries.

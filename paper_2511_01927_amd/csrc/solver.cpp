@@ -775,6 +775,8 @@ struct ContourOut {
 
 struct Stats {
     long cocg_iters = 0;          // iterations of the COCG loop (all passes)
+    long ms_iters = 0;            // iterations of the multi-shift COCG seed recurrences (all passes)
+    long ms_unconverged = 0;      // shifted columns above solve_tol when the multi-shift loop stopped
     long tile_iters = 0;          // sum over tiles of iterations run
     long spmm_launches = 0;
     long replacements = 0;
@@ -836,7 +838,7 @@ class Solver {
     // <= kBandMaxBw), 1 = COCG, 2 = band (error if a pencil's band is wider).
     bool use_band(const std::vector<Job>& jobs) const {
         const int mode = c_.o.solver;
-        if (mode == 1) return false;
+        if (mode == 1 || mode == 3) return false;
         for (const Job& j : jobs) {
             const int p = j.prob;
             if (P_->h.prob_bw[p] > kBandMaxBw) {
@@ -1228,6 +1230,200 @@ class Solver {
     // One pass of the pipeline for a set of jobs sharing (L, M).  Job k's
     // right-hand side l is the column of B V starting at offset
     // jobs[k].bsrc0 + l, rows of its pencil at stride ldbv.
+    // Shifted solves by multi-shift COCG (solver = 3, multishift.hip): one
+    // pencil whose B is beta I.  The nodes of one contour are shifts of one
+    // another and share a Krylov space per right-hand side: each contour's
+    // block column l is a seed column, iterated on the system of the
+    // contour's node nearest the real axis (the slowest to converge); every
+    // (node, l) column keeps scalar recurrences (on the host, from two small
+    // reads per iteration) and its own solution and search vector (updated
+    // on the device).  A column stops once ||r|| / |pi_c| <= solve_tol ||b||.
+    void ms_pass(const std::vector<Job>& jobs, CocgState& S, const double* BV, int64_t ldbv, int L,
+                 const std::vector<int64_t>& coff, const std::vector<double2>& shifts, int64_t Wp, size_t mv,
+                 double2* X) {
+        const int K = (int)jobs.size();
+        const int NH = c_.NH;
+        const HostPencil& H = P_->h;
+        if (H.prob_n.size() != 1) fail(GEP_EINVAL, "multi-shift COCG: single pencils only (no batches)");
+        const int64_t n = H.n;
+        double bB = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            for (int32_t e = H.rowptr[i]; e < H.rowptr[i + 1]; ++e) {
+                const double v = H.b[e];
+                if (H.colind[e] != i) {
+                    if (v != 0.0) fail(GEP_EINVAL, "multi-shift COCG needs B = beta I (B has off-diagonal entries)");
+                } else if (i == 0) {
+                    bB = v;
+                } else if (std::abs(v - bB) > 1e-14 * std::abs(bB)) {
+                    fail(GEP_EINVAL, "multi-shift COCG needs B = beta I (B's diagonal is not constant)");
+                }
+            }
+        if (!(bB != 0.0)) fail(GEP_EINVAL, "multi-shift COCG needs B = beta I with beta != 0");
+        // seed columns s = k L + l with the shift of contour k's node nearest
+        // the real axis; shifted column c -> seed column col_l[c], delta_c
+        const int ntiles = S.ntiles;
+        const int nseed = K * L, st = (nseed + kTile - 1) / kTile, ws = st * kTile;
+        std::vector<int32_t> col_l(Wp, -1);
+        std::vector<std::complex<double>> delta(Wp, 0.0);
+        std::vector<double2> zseed(ws, make_double2(0.0, 0.0));
+        std::vector<int64_t> bs(ws, -1);
+        for (int k = 0; k < K; ++k) {
+            int js = 0;
+            for (int j = 1; j < NH; ++j)
+                if (std::abs(shifts[coff[k] + (int64_t)j * L].y) < std::abs(shifts[coff[k] + (int64_t)js * L].y)) js = j;
+            const double2 z0 = shifts[coff[k] + (int64_t)js * L];
+            for (int l = 0; l < L; ++l) {
+                zseed[k * L + l] = z0;
+                bs[k * L + l] = jobs[k].bsrc0 + l;
+            }
+            for (int j = 0; j < NH; ++j)
+                for (int l = 0; l < L; ++l) {
+                    const int64_t c = coff[k] + (int64_t)j * L + l;
+                    col_l[c] = k * L + l;
+                    delta[c] = bB * std::complex<double>(shifts[c].x - z0.x, shifts[c].y - z0.y);
+                }
+        }
+        std::vector<std::complex<double>> pi(Wp, 1.0), pip(Wp, 1.0);
+        std::vector<int32_t> act(Wp, 0);
+        int64_t n_act = 0;
+        for (int64_t c = 0; c < Wp; ++c) n_act += (act[c] = col_l[c] >= 0);
+        // seed geometry: tile t at t n 64
+        std::vector<int64_t> sbase(st);
+        std::vector<int32_t> sn(st, (int32_t)n), stile(st);
+        for (int t = 0; t < st; ++t) {
+            sbase[t] = (int64_t)t * n * kTile;
+            stile[t] = t;
+        }
+        const size_t sv = (size_t)n * ws;
+        DBuf<double2> r(sv), ps(sv), q(sv), P(mv);
+        DBuf<double2> d_zs(ws), d_alpha(ws), d_beta(ws), d_coef((size_t)3 * Wp);
+        DBuf<int32_t> d_col(Wp), d_act(Wp), d_stile(st), d_cnt(1), d_sn(st);
+        DBuf<int64_t> d_sbase(st), d_bs(ws);
+        int nrb = 0;
+        choose_nrb(n, st, (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 31) / 32)), nrb);
+        DBuf<double2> part_mu((size_t)st * nrb * kTile), part_rho((size_t)st * nrb * kTile);
+        DBuf<double> part_nrm((size_t)st * nrb * kTile);
+        const int32_t st32 = st;
+        HIPCHK(hipMemcpyAsync(d_zs.get(), zseed.data(), sizeof(double2) * ws, hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(d_col.get(), col_l.data(), sizeof(int32_t) * Wp, hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(d_sbase.get(), sbase.data(), sizeof(int64_t) * st, hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(d_sn.get(), sn.data(), sizeof(int32_t) * st, hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(d_stile.get(), stile.data(), sizeof(int32_t) * st, hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(d_cnt.get(), &st32, sizeof(int32_t), hipMemcpyHostToDevice, s_));
+        HIPCHK(hipMemcpyAsync(d_bs.get(), bs.data(), sizeof(int64_t) * ws, hipMemcpyHostToDevice, s_));
+        TileGeom gs;
+        gs.base = d_sbase.get();
+        gs.n = d_sn.get();
+        // x = 0, every shifted p = b, seed r = p_s = b, q = 0
+        HIPCHK(hipMemsetAsync(X, 0, sizeof(double2) * mv, s_));
+        HIPCHK(band_rhs(S.geom, S.bsrc, BV, ldbv, ntiles, P.get(), s_));
+        HIPCHK(band_rhs(gs, d_bs.get(), BV, ldbv, st, r.get(), s_));
+        HIPCHK(hipMemcpyAsync(ps.get(), r.get(), sizeof(double2) * sv, hipMemcpyDeviceToDevice, s_));
+        HIPCHK(hipMemsetAsync(q.get(), 0, sizeof(double2) * sv, s_));
+        HIPCHK(hipMemsetAsync(d_alpha.get(), 0, sizeof(double2) * ws, s_));
+        const size_t np = (size_t)st * nrb * kTile;
+        std::vector<double2> hpart(np);
+        std::vector<double> hnrm(np);
+        // column sums over the row blocks of [tile][nrb][64] partials
+        auto col_sum = [&](const std::vector<double2>& pp, int s_col) {
+            const int t = s_col / kTile, l = s_col % kTile;
+            std::complex<double> a = 0.0;
+            for (int rb = 0; rb < nrb; ++rb) {
+                const double2 v = pp[((size_t)t * nrb + rb) * kTile + l];
+                a += std::complex<double>(v.x, v.y);
+            }
+            return a;
+        };
+        std::vector<std::complex<double>> rho(ws), rho_n(ws), alpha(ws, 0.0), beta(ws, 0.0), alpha_prev(ws, 1.0),
+            beta_prev(ws, 0.0);
+        std::vector<double> nrm(ws), bnorm(ws);
+        auto seed_sums = [&]() {
+            HIPCHK(hipMemcpyAsync(hpart.data(), part_rho.get(), sizeof(double2) * np, hipMemcpyDeviceToHost, s_));
+            HIPCHK(hipMemcpyAsync(hnrm.data(), part_nrm.get(), sizeof(double) * np, hipMemcpyDeviceToHost, s_));
+            HIPCHK(hipStreamSynchronize(s_));
+            for (int sc = 0; sc < ws; ++sc) {
+                rho_n[sc] = col_sum(hpart, sc);
+                double b = 0.0;
+                for (int rb = 0; rb < nrb; ++rb) b += hnrm[((size_t)(sc / kTile) * nrb + rb) * kTile + sc % kTile];
+                nrm[sc] = b;
+            }
+        };
+        HIPCHK(ms_seed_update((int)n, st, nrb, d_alpha.get(), q.get(), r.get(), part_rho.get(), part_nrm.get(), s_));
+        seed_sums();
+        for (int sc = 0; sc < ws; ++sc) {
+            rho[sc] = rho_n[sc];
+            bnorm[sc] = std::sqrt(nrm[sc]);
+        }
+        const double tol = c_.o.solve_tol;
+        std::vector<double2> coef((size_t)3 * Wp, make_double2(0.0, 0.0)), h_ab(ws);
+        long it = 0;
+        while (n_act > 0 && it < c_.o.max_iter) {
+            // q = K_s p_s with the column partials of p_s^T q
+            tm_.begin(T_SPMM);
+            HIPCHK(launch_spmm_c64(P_->d, d_zs.get(), ps.get(), q.get(), d_stile.get(), d_cnt.get(), st, nrb,
+                                   part_mu.get(), s_));
+            tm_.end();
+            HIPCHK(hipMemcpyAsync(hpart.data(), part_mu.get(), sizeof(double2) * np, hipMemcpyDeviceToHost, s_));
+            HIPCHK(hipStreamSynchronize(s_));
+            for (int sc = 0; sc < ws; ++sc) {
+                const std::complex<double> mu = col_sum(hpart, sc);
+                alpha[sc] = (sc < nseed && std::abs(mu) > 0.0) ? rho[sc] / mu : 0.0;
+                h_ab[sc] = make_double2(alpha[sc].real(), alpha[sc].imag());
+            }
+            HIPCHK(hipMemcpyAsync(d_alpha.get(), h_ab.data(), sizeof(double2) * ws, hipMemcpyHostToDevice, s_));
+            HIPCHK(ms_seed_update((int)n, st, nrb, d_alpha.get(), q.get(), r.get(), part_rho.get(), part_nrm.get(),
+                                  s_));
+            seed_sums();
+            for (int sc = 0; sc < ws; ++sc)
+                beta[sc] = (sc < nseed && std::abs(rho[sc]) > 0.0) ? rho_n[sc] / rho[sc] : 0.0;
+            // shifted scalars: pi_{k+1} = (1 + a b'/a' + a delta) pi_k - (a b'/a') pi_{k-1},
+            // alpha_c = a pi_k / pi_{k+1}, beta_c = (pi_k / pi_{k+1})^2 b
+            std::vector<int32_t> done;
+            for (int64_t c = 0; c < Wp; ++c) {
+                if (!act[c]) continue;
+                const int sc = col_l[c];
+                const std::complex<double> a = alpha[sc];
+                const std::complex<double> g =
+                    (it > 0 && std::abs(alpha_prev[sc]) > 0.0) ? a * beta_prev[sc] / alpha_prev[sc] : 0.0;
+                const std::complex<double> pn = (1.0 + g + a * delta[c]) * pi[c] - g * pip[c];
+                const std::complex<double> rat = pi[c] / pn;
+                const std::complex<double> ac = a * rat, bc = rat * rat * beta[sc], ip = 1.0 / pn;
+                coef[3 * c] = make_double2(ac.real(), ac.imag());
+                coef[3 * c + 1] = make_double2(bc.real(), bc.imag());
+                coef[3 * c + 2] = make_double2(ip.real(), ip.imag());
+                pip[c] = pi[c];
+                pi[c] = pn;
+                if (std::sqrt(nrm[sc]) <= tol * bnorm[sc] * std::abs(pn) || !std::isfinite(std::abs(pn)))
+                    done.push_back((int32_t)c);
+            }
+            HIPCHK(hipMemcpyAsync(d_coef.get(), coef.data(), sizeof(double2) * coef.size(), hipMemcpyHostToDevice, s_));
+            HIPCHK(hipMemcpyAsync(d_act.get(), act.data(), sizeof(int32_t) * Wp, hipMemcpyHostToDevice, s_));
+            tm_.begin(T_UPDATE);
+            HIPCHK(ms_shift_update(S.geom, ntiles, n, (int)n, d_col.get(), d_act.get(), d_coef.get(), r.get(), X,
+                                   P.get(), s_));
+            tm_.end();
+            for (int sc = 0; sc < ws; ++sc) h_ab[sc] = make_double2(beta[sc].real(), beta[sc].imag());
+            HIPCHK(hipMemcpyAsync(d_beta.get(), h_ab.data(), sizeof(double2) * ws, hipMemcpyHostToDevice, s_));
+            HIPCHK(ms_seed_p((int)n, st, d_beta.get(), r.get(), ps.get(), s_));
+            // host buffers read by the copies above must not change before they ran
+            HIPCHK(hipStreamSynchronize(s_));
+            tm_.flush();
+            for (int32_t c : done) {
+                act[c] = 0;
+                --n_act;
+            }
+            for (int sc = 0; sc < ws; ++sc) {
+                alpha_prev[sc] = alpha[sc];
+                beta_prev[sc] = beta[sc];
+                rho[sc] = rho_n[sc];
+            }
+            ++it;
+        }
+        HIPCHK(hipStreamSynchronize(s_));
+        stats_.ms_iters += it;
+        stats_.ms_unconverged += n_act;
+    }
+
     void run_pass(const std::vector<Job>& jobs, const double* BV, int64_t ldbv, int L, int M,
                   std::vector<ContourOut>& out) {
         const int K = (int)jobs.size();
@@ -1283,9 +1479,10 @@ class Solver {
         }
         // shifted solves: banded L D L^T (band.hip) or batched COCG
         const bool band = use_band(jobs);
+        const bool ms = c_.o.solver == 3;
         CocgState S;
         S.ntiles = ntiles;
-        const bool mixed = c_.o.precision == GEP_MIXED && !band;
+        const bool mixed = c_.o.precision == GEP_MIXED && !band && !ms;
         if (mixed) stats_.fp32_passes += 1;
         // small row blocks keep the gathers of concurrently running
         // work-groups inside the caches; one row group per wave by default,
@@ -1299,7 +1496,7 @@ class Solver {
         const size_t mv = (size_t)elems;
         DBuf<double2> x(mv), u, p, pn;
         DBuf<float2> x32, u32, p32, pn32;
-        if (band) {
+        if (band || ms) {
             // only x (the solutions); the COCG vectors are not needed
         } else if (mixed) {
             x32.alloc(mv);
@@ -1375,6 +1572,8 @@ class Solver {
         std::vector<int32_t> its(Wp, 0), its0(Wp, 0);
         if (band) {
             band_pass(jobs, S, BV, ldbv, L, coff, shifts, nmax, elems, x.get());
+        } else if (ms) {
+            ms_pass(jobs, S, BV, ldbv, L, coff, shifts, Wp, mv, x.get());
         } else {
         if (mixed) {
             HIPCHK(hipMemsetAsync(S.x, 0, sizeof(double2) * mv, s_));
@@ -1805,8 +2004,11 @@ static std::string json_stats(const Solver& s, double wall_ms, const std::vector
       << "\",\"precision_requested\":\"" << (precision == GEP_MIXED ? "mixed" : "fp64")
       << "\",\"method\":\"" << (s.c_.o.method == GEP_FEAST ? "feast" : "cirr")
       << "\",\"fp32_passes\":" << s.stats_.fp32_passes << ",\"solver_run\":\""
-      << (s.stats_.band_factorisations > 0 ? (s.stats_.cocg_iters > 0 ? "band+cocg" : "band") : "cocg")
+      << (s.stats_.ms_iters > 0 ? "multishift"
+                                : s.stats_.band_factorisations > 0 ? (s.stats_.cocg_iters > 0 ? "band+cocg" : "band")
+                                                                   : "cocg")
       << "\",\"cocg_iters\":" << s.stats_.cocg_iters << ",\"tile_iters\":" << s.stats_.tile_iters
+      << ",\"multishift_iters\":" << s.stats_.ms_iters << ",\"multishift_unconverged\":" << s.stats_.ms_unconverged
       << ",\"columns\":" << s.stats_.columns << ",\"waves\":" << s.stats_.waves
       << ",\"spmm_launches\":" << s.stats_.spmm_launches
       << ",\"replacements\":" << s.stats_.replacements
@@ -2335,8 +2537,8 @@ static int validate_problem(const gep_contour* contours, int K, int N, int M, in
         gep::set_error("row_group must be 0, 1 or 4");
         return GEP_EINVAL;
     }
-    if (o->solver < 0 || o->solver > 2) {
-        gep::set_error("solver must be 0 (automatic), 1 (COCG) or 2 (band)");
+    if (o->solver < 0 || o->solver > 3) {
+        gep::set_error("solver must be 0 (automatic), 1 (COCG), 2 (band) or 3 (multi-shift COCG)");
         return GEP_EINVAL;
     }
     if (o->method != GEP_CIRR && o->method != GEP_FEAST) {

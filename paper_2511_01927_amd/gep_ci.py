@@ -210,7 +210,7 @@ def _opts(seed=1, precision="fp64", max_refine=1, solve_tol=1e-9, max_iter=10000
     o.verbose = verbose
     o.use_graph = int(use_graph)   # True = 1; 2 adds the banded factorisation
     o.row_group = row_group
-    o.solver = {"auto": 0, "cocg": 1, "band": 2}[solver] if isinstance(solver, str) else int(solver)
+    o.solver = {"auto": 0, "cocg": 1, "band": 2, "multishift": 3}[solver] if isinstance(solver, str) else int(solver)
     o.band_kernels = {"auto": 0, "narrow": 1, "wide": 2}[band_kernels] if isinstance(band_kernels, str) \
         else int(band_kernels)
     o.band_group = band_group
