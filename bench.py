@@ -476,9 +476,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="q1_2d_300")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--solver", default="auto", choices=["auto", "cocg", "band"],
-                    help="shifted solves: banded L D L^T or batched COCG (auto: band when the "
-                         "pencil's half bandwidth is at most 4096)")
+    ap.add_argument("--solver", default="auto", choices=["auto", "cocg", "band", "multishift"],
+                    help="shifted solves: banded L D L^T, batched COCG or multi-shift COCG (B = beta I "
+                         "only; auto: band when the pencil's half bandwidth is at most 4096)")
     ap.add_argument("--solve-tol", type=float, default=1e-9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-contours", type=int, default=1)
@@ -547,7 +547,8 @@ def main():
     if args.counters:
         args.copy_probe = True
     tuned = None
-    if not args.no_autotune and not args.counters and args.solver != "cocg" and args.workload != "fd7_3d_64":
+    if (not args.no_autotune and not args.counters and args.solver in ("auto", "band")
+            and args.workload != "fd7_3d_64"):
         # banded kernel variant chosen by the project's autotuner (timed
         # solves of this workload, cached by shape); untimed
         from paper_2511_01927_amd import autotune

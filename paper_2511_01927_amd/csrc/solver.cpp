@@ -1418,6 +1418,11 @@ class Solver {
                 rho[sc] = rho_n[sc];
             }
             ++it;
+            if (c_.o.verbose > 0 && it % c_.o.verbose == 0) {
+                std::fprintf(stderr, "gep: multi-shift pass, iteration %ld, active columns %lld\n", it,
+                             (long long)n_act);
+                std::fflush(stderr);
+            }
         }
         HIPCHK(hipStreamSynchronize(s_));
         stats_.ms_iters += it;
