@@ -573,6 +573,7 @@ __global__ __launch_bounds__(256) void k_band_backward(const BandSys* __restrict
 
 // r = b - K x per column (FP64, CSR of the concatenated pencil), stored in
 // R; partials of ||r||^2 (x) and ||b||^2 (y) per row block.
+template <bool WRITE_R>
 __global__ __launch_bounds__(256) void k_band_residual(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
     const double2* __restrict__ ab, TileGeom geom, const double2* __restrict__ shifts,
@@ -596,7 +597,25 @@ __global__ __launch_bounds__(256) void k_band_residual(
     for (int i = r0 + wave; i < r1; i += 4) {
         const int g = row0 + i;
         double ar = 0, ai = 0, br = 0, bi = 0;
-        for (int k = rowptr[g]; k < rowptr[g + 1]; ++k) {
+        const int ke = rowptr[g + 1];
+        int k = rowptr[g];
+        // four gathers in flight; the products are summed in entry order
+        for (; k + 4 <= ke; k += 4) {
+            double2 v[4], xj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                v[u] = ab[k + u];
+                xj[u] = X[goff + (int64_t)colind[k + u] * kTile + lane];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                ar = fma(v[u].x, xj[u].x, ar);
+                ai = fma(v[u].x, xj[u].y, ai);
+                br = fma(v[u].y, xj[u].x, br);
+                bi = fma(v[u].y, xj[u].y, bi);
+            }
+        }
+        for (; k < ke; ++k) {
             const double2 v = ab[k];
             const double2 xj = X[goff + (int64_t)colind[k] * kTile + lane];
             ar = fma(v.x, xj.x, ar);
@@ -607,7 +626,7 @@ __global__ __launch_bounds__(256) void k_band_residual(
         const double b = bs >= 0 ? BV[bs + (int64_t)i * ldbv] : 0.0;
         const double rx = b - (z.x * br - z.y * bi - ar);
         const double ry = -(z.x * bi + z.y * br - ai);
-        R[base + (int64_t)i * kTile + lane] = make_double2(rx, ry);
+        if (WRITE_R) R[base + (int64_t)i * kTile + lane] = make_double2(rx, ry);
         rr += rx * rx + ry * ry;
         bb += b * b;
     }
@@ -624,16 +643,27 @@ __global__ __launch_bounds__(256) void k_band_residual(
 }
 
 // rel[col] = ||r|| / ||b|| from the row-block partials (fixed order).
-__global__ __launch_bounds__(64) void k_band_relres(int nrb, const double2* __restrict__ part,
-                                                    double* __restrict__ rel) {
-    const int tile = blockIdx.x, lane = threadIdx.x;
+__global__ __launch_bounds__(256) void k_band_relres(int nrb, const double2* __restrict__ part,
+                                                     double* __restrict__ rel) {
+    // wave w sums row blocks w, w + 4, ... and the four sums are added in
+    // wave order: a fixed order for every launch
+    __shared__ double2 red[4][kTile];
+    const int tile = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double rr = 0.0, bb = 0.0;
-    for (int rb = 0; rb < nrb; ++rb) {
+    for (int rb = wave; rb < nrb; rb += 4) {
         const double2 p = part[((int64_t)tile * nrb + rb) * kTile + lane];
         rr += p.x;
         bb += p.y;
     }
-    rel[tile * kTile + lane] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    red[wave][lane] = make_double2(rr, bb);
+    __syncthreads();
+    if (wave == 0) {
+        for (int w = 1; w < 4; ++w) {
+            rr += red[w][lane].x;
+            bb += red[w][lane].y;
+        }
+        rel[tile * kTile + lane] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    }
 }
 
 // X += R over the rows of every tile.
@@ -1453,11 +1483,15 @@ hipError_t band_residual(const DevPencil& P, const TileGeom& g, const double2* s
                          double* rel, hipStream_t s) {
     const int rpb = (int)std::max<int64_t>(16, (nmax + nrb_cap - 1) / nrb_cap);
     const int nrb = (int)((nmax + rpb - 1) / rpb);
-    hipLaunchKernelGGL(k_band_residual, dim3(ntiles * nrb), dim3(256), 0, s, P.rowptr, P.colind,
-                       P.ab, g, shifts, bsrc, BV, ldbv, X, R, ntiles, nrb, rpb, part);
+    if (R)
+        hipLaunchKernelGGL(k_band_residual<true>, dim3(ntiles * nrb), dim3(256), 0, s, P.rowptr, P.colind,
+                           P.ab, g, shifts, bsrc, BV, ldbv, X, R, ntiles, nrb, rpb, part);
+    else
+        hipLaunchKernelGGL(k_band_residual<false>, dim3(ntiles * nrb), dim3(256), 0, s, P.rowptr, P.colind,
+                           P.ab, g, shifts, bsrc, BV, ldbv, X, R, ntiles, nrb, rpb, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_band_relres, dim3(ntiles), dim3(64), 0, s, nrb, part, rel);
+    hipLaunchKernelGGL(k_band_relres, dim3(ntiles), dim3(256), 0, s, nrb, part, rel);
     return hipGetLastError();
 }
 

@@ -1022,9 +1022,11 @@ class Solver {
         const int chunk = L % 16 == 0 ? 16 : (L % 8 == 0 ? 8 : 0);
         HIPCHK(band_solve(dsys.get(), dcol.get(), band_F_->get(), S.geom, ntiles, bwmax, X, s_, chunk));
         tm_.end();
-        // FP64 residual of every column, iterative refinement with the factors
-        constexpr int kCap = 4096;
-        DBuf<double2> R((size_t)std::max<int64_t>(elems, 1));
+        // FP64 residual of every column, iterative refinement with the factors.
+        // The first check forms only the norms; the residual itself is
+        // written (and its buffer allocated) once a column needs refinement.
+        constexpr int kCap = 1024;   // row blocks of the residual norms per tile
+        DBuf<double2> R;
         DBuf<double2> part((size_t)ntiles * kCap * kTile);
         DBuf<double> rel(Wp);
         std::vector<double> relh(Wp);
@@ -1042,6 +1044,11 @@ class Solver {
                 stats_.band_relres_max = std::max(stats_.band_relres_max, mx);
                 if (mx > c_.o.solve_tol) stats_.band_unconverged += 1;
                 break;
+            }
+            if (!R.get()) {   // norms only so far: form the residual to solve against
+                R.alloc((size_t)std::max<int64_t>(elems, 1));
+                HIPCHK(band_residual(dv_, S.geom, S.shifts, S.bsrc, BV, ldbv, X, R.get(), ntiles, nmax,
+                                     part.get(), kCap, rel.get(), s_));
             }
             tm_.begin(T_BAND_SOLVE);
             HIPCHK(band_solve(dsys.get(), dcol.get(), band_F_->get(), S.geom, ntiles, bwmax, R.get(), s_,
@@ -1100,7 +1107,7 @@ class Solver {
             }
         HIPCHK(band_rhs(S.geom, S.bsrc, BV, ldbv, ntiles, X, s_));
         const int refine_max = fp32 ? kBandRefineMax32 : kBandRefineMax;
-        constexpr int kCap = 4096;
+        constexpr int kCap = 1024;   // row blocks of the residual norms per tile
         DBuf<double2> R((size_t)std::max<int64_t>(elems, 1));
         DBuf<double2> part((size_t)ntiles * kCap * kTile);
         DBuf<double> rel(Wp);
