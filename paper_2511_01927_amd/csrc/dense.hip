@@ -596,16 +596,53 @@ hipError_t launch_resid_norms(const double* AX, const double* BX, const double* 
 // of the largest modulus count as tied and the lowest index among them
 // decides (mirror-symmetric eigenvectors have exactly tied pairs whose
 // computed moduli differ by the eigenvector's error, about 1e-7 for pairs
-// accepted at residual 1e-8).
-__global__ __launch_bounds__(256) void k_gather_cols(const double* __restrict__ X, int64_t n,
-                                                     int k, const int32_t* __restrict__ sel,
-                                                     double* __restrict__ out) {
-    __shared__ double bv[256];
-    __shared__ int64_t bi[256];
-    const int t = threadIdx.x;
-    const int c = sel[blockIdx.x];
+// accepted at residual 1e-8).  Two kernels: the gather, then the sign rule
+// on the contiguous copies.
+
+// out (n x m, column-major) = the columns sel of X: 64 x 64 tiles through
+// LDS, so that both the reads along X's rows and the writes down out's
+// columns are coalesced.  pmax[j * nrt + row tile] = max |entry| of column j
+// over the tile's rows.
+__global__ __launch_bounds__(256) void k_gather_tile(const double* __restrict__ X, int64_t n, int k,
+                                                     const int32_t* __restrict__ sel, int m,
+                                                     double* __restrict__ out, double* __restrict__ pmax) {
+    __shared__ double tl[64][65];
+    __shared__ double mx[4][64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int j0 = blockIdx.y * 64;
+    const int j = j0 + lane;
+    const int c = j < m ? sel[j] : 0;
     double best = 0.0;
-    for (int64_t i = t; i < n; i += 256) best = fmax(best, fabs(X[i * k + c]));
+    for (int r = wave; r < 64; r += 4) {
+        const int64_t i = i0 + r;
+        const double x = (i < n && j < m) ? X[i * k + c] : 0.0;
+        tl[r][lane] = x;
+        best = fmax(best, fabs(x));
+    }
+    mx[wave][lane] = best;
+    __syncthreads();
+    if (wave == 0 && j < m)
+        pmax[(int64_t)j * gridDim.x + blockIdx.x] = fmax(fmax(mx[0][lane], mx[1][lane]), fmax(mx[2][lane], mx[3][lane]));
+    for (int q = wave; q < 64; q += 4) {
+        const int jj = j0 + q;
+        const int64_t i = i0 + lane;
+        if (jj < m && i < n) out[(int64_t)jj * n + i] = tl[lane][q];
+    }
+}
+
+// Sign of each gathered column (one work-group per column): the largest
+// modulus from the row tiles' maxima, then the first row tile that reaches
+// the tie threshold and, inside it, the first such row; sgn[j] = -1 when
+// that entry is negative.
+__global__ __launch_bounds__(256) void k_sign_cols(int64_t n, int nrt, const double* __restrict__ pmax,
+                                                   const double* __restrict__ out, double* __restrict__ sgn) {
+    __shared__ double bv[256];
+    __shared__ int bi[256];
+    const int t = threadIdx.x;
+    const double* pm = pmax + (int64_t)blockIdx.x * nrt;
+    double best = 0.0;
+    for (int b = t; b < nrt; b += 256) best = fmax(best, pm[b]);
     bv[t] = best;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
@@ -613,28 +650,60 @@ __global__ __launch_bounds__(256) void k_gather_cols(const double* __restrict__ 
         __syncthreads();
     }
     const double thr = (1.0 - 1e-4) * bv[0];
-    int64_t first = n;
-    for (int64_t i = t; i < n; i += 256)
-        if (fabs(X[i * k + c]) >= thr) {
-            first = i;
+    int fb = nrt;
+    for (int b = t; b < nrt; b += 256)
+        if (pm[b] >= thr) {
+            fb = b;
             break;
         }
-    bi[t] = first;
+    bi[t] = fb;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
         if (t < off) bi[t] = min(bi[t], bi[t + off]);
         __syncthreads();
     }
-    const int64_t at = bi[0] < n ? bi[0] : 0;
-    const double sgn = X[at * k + c] < 0.0 ? -1.0 : 1.0;
-    double* o = out + (int64_t)blockIdx.x * n;
-    for (int64_t i = t; i < n; i += 256) o[i] = sgn * X[i * k + c];
+    const int b0 = bi[0] < nrt ? bi[0] : 0;
+    __syncthreads();   // every thread has read bi[0]
+    const double* o = out + (int64_t)blockIdx.x * n;
+    const int64_t i = (int64_t)b0 * 64 + t;
+    bi[t] = (t < 64 && i < n && fabs(o[i]) >= thr) ? t : 64;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) bi[t] = min(bi[t], bi[t + off]);
+        __syncthreads();
+    }
+    if (t == 0) {
+        const int64_t at = (int64_t)b0 * 64 + (bi[0] < 64 ? bi[0] : 0);
+        sgn[blockIdx.x] = (at < n && o[at] < 0.0) ? -1.0 : 1.0;
+    }
 }
 
+// out[:, j] *= sgn[j] where sgn[j] < 0.
+__global__ __launch_bounds__(256) void k_flip_cols(int64_t n, const double* __restrict__ sgn,
+                                                   double* __restrict__ out) {
+    const int j = blockIdx.y;
+    if (sgn[j] > 0.0) return;   // uniform over the work-group
+    double* o = out + (int64_t)j * n;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) o[i] = -o[i];
+}
+
+size_t gather_cols_work(int64_t n, int m) { return (size_t)((n + 63) / 64) * m + m; }
+
 hipError_t launch_gather_cols(const double* X, int64_t n, int64_t k, const int32_t* sel, int m,
-                              double* out, hipStream_t s) {
+                              double* out, double* work, hipStream_t s) {
     if (m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_cols, dim3(m), dim3(256), 0, s, X, n, (int)k, sel, out);
+    const int nrt = (int)((n + 63) / 64);
+    double* pmax = work;
+    double* sg = work + (size_t)nrt * m;
+    hipLaunchKernelGGL(k_gather_tile, dim3((unsigned)nrt, (unsigned)((m + 63) / 64)), dim3(256), 0, s, X, n,
+                       (int)k, sel, m, out, pmax);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sign_cols, dim3(m), dim3(256), 0, s, n, nrt, pmax, out, sg);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_flip_cols, dim3((unsigned)std::min<int64_t>(64, (n + 255) / 256), m), dim3(256), 0, s, n,
+                       sg, out);
     return hipGetLastError();
 }
 

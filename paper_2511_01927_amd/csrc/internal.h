@@ -290,8 +290,10 @@ hipError_t launch_resid_norms(const double* AX, const double* BX, const double* 
                               const double* theta, int64_t n, int64_t k, double* num, double* den,
                               double* work, hipStream_t s);
 // gather selected columns of row-major X (n x k) into column-major out (n x m),
-// sign-normalised (largest-|.| entry positive, lowest index on ties)
+// sign-normalised (largest-|.| entry positive, lowest index on ties); work
+// holds gather_cols_work(n, m) doubles
+size_t gather_cols_work(int64_t n, int m);
 hipError_t launch_gather_cols(const double* X, int64_t n, int64_t k, const int32_t* sel, int m,
-                              double* out, hipStream_t s);
+                              double* out, double* work, hipStream_t s);
 
 }  // namespace gep

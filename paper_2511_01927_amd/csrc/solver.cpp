@@ -2298,8 +2298,9 @@ static int solve_batch_impl(gep_pencil* P, int n_problems, const gep_contour* co
             DBuf<int32_t> dsel(sel.size());
             cms[k] = std::make_unique<DBuf<double>>((size_t)n * sel.size());
             HIPCHK(hipMemcpyAsync(dsel.get(), sel.data(), sizeof(int32_t) * sel.size(), hipMemcpyHostToDevice, s));
-            HIPCHK(launch_gather_cols(co.X, n, co.r, dsel.get(), (int)sel.size(), cms[k]->get(), s));
-            HIPCHK(hipStreamSynchronize(s));   // dsel is released at the end of this iteration
+            DBuf<double> gwork(gather_cols_work(n, (int)sel.size()));
+            HIPCHK(launch_gather_cols(co.X, n, co.r, dsel.get(), (int)sel.size(), cms[k]->get(), gwork.get(), s));
+            HIPCHK(hipStreamSynchronize(s));   // dsel and gwork are released at the end of this iteration
             for (size_t a = 0; a < sel.size(); ++a) pairs.push_back({co.theta[sel[a]], co.rho[sel[a]], k, (int)a});
         }
         std::stable_sort(pairs.begin(), pairs.end(), [](const Pair& a, const Pair& b) { return a.lam < b.lam; });
