@@ -48,18 +48,18 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 # reported as null.
 # Measured HBM bytes (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated) on
 # the default workload; valid only while the kernels' sources are the ones
-# measured (sha256), else `traffic` is null.  (Two hashes were moved without
-# a new measurement, each after checking that the measured kernels compile to
-# the same gfx950 assembly with either version: the COCG entry's internal.h
-# over a declaration-only change of that header, and the band entry's
-# band.hip over a change confined to the residual-norm kernels.)
+# measured (sha256), else `traffic` is null.  (Hashes were moved without a
+# new measurement only after checking that every measured kernel compiles to
+# the same gfx950 assembly with either version: internal.h over
+# declaration-only changes, band.hip over changes confined to the
+# residual-norm kernels.)
 TRAFFIC = [
     {
         "workload": "q1_2d_300",
         "precision": "fp64",
         "sources_sha256": {
             "paper_2511_01927_amd/csrc/cocg.hip": "d77cbde59f14638d2c50f773f839a7be198170836066b48c624d8ac22f973ea1",
-            "paper_2511_01927_amd/csrc/internal.h": "8c70061bdd6e6ee76f5d821f9e1d01eeab424ca459a9059dbd53251847317e65",
+            "paper_2511_01927_amd/csrc/internal.h": "4e19dbea0f25f1ead60c00d887ebbd761b83b9432924910ca8ecf490cce52023",
         },
         # bytes per tile-launch (scaled by the tiles a launch processes)
         "per_tile_bytes": {"cocg_spmm_dir": 3.389832e+08, "cocg_update": 5.272176e+08},
@@ -70,7 +70,7 @@ TRAFFIC = [
         "precision": "fp64",
         "sources_sha256": {
             "paper_2511_01927_amd/csrc/band.hip": "d399a5986f430db73643e4a9435d96693daacf2a2a361278f1dc7f4a68f6072b",
-            "paper_2511_01927_amd/csrc/internal.h": "8c70061bdd6e6ee76f5d821f9e1d01eeab424ca459a9059dbd53251847317e65",
+            "paper_2511_01927_amd/csrc/internal.h": "4e19dbea0f25f1ead60c00d887ebbd761b83b9432924910ca8ecf490cce52023",
         },
         # bytes per launch (per timed bracket for band_solve: right-hand sides,
         # forward and backward sweep)
