@@ -26,11 +26,13 @@
 //                  panel steps (lookahead).
 // Solves, in place on the tiled multivector (element (i, c) at
 // (tile * n + i) * 64 + lane), a work-group per (tile, chunk of columns):
-//   k_band_fwd_pipe / k_band_bwd_blocked  32-row blocks: a triangular
+//   k_band_fwd_pipe / k_band_bwd_pipe  32-row blocks: a triangular
 //                    solve of the block's rows (readlane broadcasts) and
 //                    the block's coupling to the next (previous) bw rows as
-//                    v_mfma_f64_16x16x4 products, pending rows in an LDS
-//                    ring; used for 16-column chunks and bw <= 384;
+//                    v_mfma_f64_16x16x4 products, in two wave roles so that
+//                    the products of one block overlap the solve of the
+//                    next, pending rows in an LDS ring; used for 16-column
+//                    chunks and bw <= 384;
 //   k_band_sweep     row-by-row sweeps with the window in registers (one
 //                    half wavefront per column), for 8-column chunks or
 //                    wider bands;
@@ -900,7 +902,7 @@ __global__ __launch_bounds__(CPW * 32 / CPL) void k_band_sweep(const BandSys* __
 // result register v of lane l is D(l / 16 + 4 v, l % 16).
 constexpr int kBlkRows = 32;
 constexpr int kBlkFwdThreads = 512;   // 4 product waves + 4 solve waves
-constexpr int kBlkBwdThreads = 512;
+constexpr int kBlkBwdThreads = 512;   // 4 product waves + 4 solve waves
 constexpr int kBlkMaxBw = 384;
 
 // Ring slot of row J0 + d (jb = J0 mod WS, 0 <= d < 2 WS): no division.
@@ -1104,27 +1106,33 @@ __global__ __launch_bounds__(NT) void k_band_fwd_pipe(const BandSys* __restrict_
     }
 }
 
-// ---- blocked backward sweep -----------------------------------------------
+// ---- backward sweep in two wave roles ----------------------------------------
 // L^T x = z (z = D^-1 y from the forward sweep, in X), 32-row blocks from the
-// bottom.  For block [J0, J0 + 32) the solved rows r in [J0 + 32, J0 + 32 +
-// bw) contribute G[i, :] = sum_r L[r, i] x[r, :] (a 32 x 16 product with
-// K = bw on v_mfma_f64_16x16x4: the K steps are dealt to the four waves and
-// their partial sums added through LDS); then x_i = z_i - G_i - sum over the
-// block's later rows, solved from the last row up (half wave per two
-// columns, readlane broadcast).  Solved rows enter an LDS ring (WS >= bw + 32
-// rows) that holds the rows later blocks read.
+// bottom, right-looking: once block j's x is known, the rows above it within
+// the band take z_i -= sum_{r in block j} L[r, i] x_r (a 16-row tile per
+// matrix-core product, K = 32 over the block, operands L[r, i] read down
+// column i of the band and x from LDS).  Waves 0-3 (product waves) apply
+// block j to those rows in 16-row tiles dealt round robin, nearest first, so
+// that their first tiles (0-3) cover block j - 1's rows before the mid-block
+// barrier.  Waves 4-7 (solve waves) meanwhile insert the rows entering reach
+// and keep block j - 1's diagonal block of L; after the barrier they solve
+// block j - 1 from its last row up (half wave per two columns, readlane
+// broadcast) while the product waves finish block j's other tiles.  Pending
+// rows live in an LDS ring (row r in slot r mod WS, WS >= bw + 32); x of the
+// last solved block alternates between two LDS buffers.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_band_bwd_blocked(const BandSys* __restrict__ sys,
-                                                                  const int32_t* __restrict__ colsys,
-                                                                  const double2* __restrict__ F,
-                                                                  TileGeom geom, double2* __restrict__ X,
-                                                                  int xcd_map) {
-    constexpr int CPW = 16, CPT = kTile / CPW, NW = NT / 64;
-    constexpr int NR = NW < 4 ? NW : 4;   // partial-sum slots (waves 4..7 fold into 0..3 first)
-    constexpr int CPH = CPW * 32 / NT;    // columns per half wave in the block solve
+__global__ __launch_bounds__(NT) void k_band_bwd_pipe(const BandSys* __restrict__ sys,
+                                                      const int32_t* __restrict__ colsys,
+                                                      const double2* __restrict__ F, TileGeom geom,
+                                                      double2* __restrict__ X, int xcd_map) {
+    constexpr int CPW = 16, CPT = kTile / CPW;
+    constexpr int NS = 256;                      // solve threads (four waves)
+    constexpr int NP = (NT - NS) / 64;           // product waves
+    static_assert(NP >= 2 && NP * 64 + NS == NT, "two or more product waves, then four solve waves");
+    constexpr int CPH = CPW * 32 / NS;           // columns per solve half wave
     __shared__ double2 Ld[kBlkRows][kBlkRows + 1];   // L[J0 + r][J0 + c], r > c
-    __shared__ double red[NR * 16 * 64];               // [slot][tile][re,im][v][lane]
-    extern __shared__ double2 ring[];                  // [WS][CPW]
+    __shared__ double2 Yb[2][kBlkRows][CPW + 1];      // x of the last solved block
+    extern __shared__ double2 ring[];                 // [WS][CPW]
     int tile, chunk;
     if (xcd_map) {
         const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
@@ -1143,148 +1151,141 @@ __global__ __launch_bounds__(NT) void k_band_bwd_blocked(const BandSys* __restri
     const int64_t base = geom.base[tile];
     const double2* Fs = F + S.off;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int hl = t & 31, hw = t >> 5;
-    const bool upper = (t & 32) != 0;
-    for (int e = t; e < WS * CPW; e += NT) ring[e] = make_double2(0.0, 0.0);
+    const bool prod = wave < NP;                 // uniform over the wave
+    const int ts = t - 64 * NP;                  // solve thread index (solve waves)
+    const int hl = ts & 31, hw = ts >> 5;        // solve half-wave lane (block row) and index
+    const bool upper = (ts & 32) != 0;
     const int nblk = (n + kBlkRows - 1) / kBlkRows;
-    constexpr int kLdPer = kBlkRows * kBlkRows / NT;
+    const int Jl = (nblk - 1) * kBlkRows;
+    // the bottom block and the rows above it within reach; rows past n are zero
+    for (int e = t; e < (kBlkRows + bw) * CPW; e += NT) {
+        const int r = Jl - bw + e / CPW, c = e % CPW;
+        if (r >= 0) ring[(r % WS) * CPW + c] = r < n ? X[base + (int64_t)r * kTile + c0 + c] : make_double2(0.0, 0.0);
+    }
+    constexpr int kLdPer = kBlkRows * kBlkRows / NS;
+    constexpr int kNewPer = kBlkRows * CPW / NS;
     auto load_ld = [&](int J0, double2 (&pl)[kLdPer]) {
 #pragma unroll
         for (int m = 0; m < kLdPer; ++m) {
-            const int e = t + NT * m, r = e / kBlkRows, c = e % kBlkRows;
+            const int e = ts + NS * m, r = e / kBlkRows, c = e % kBlkRows;
             pl[m] = (r > c && r - c <= bw && J0 + r < n) ? Fs[(int64_t)(J0 + c) * ld + (r - c)]
                                                          : make_double2(0.0, 0.0);
         }
     };
-    // A operands of K step s (rows r = J0 + 32 + 4 s + lane / 16) for both tiles
-    auto load_a = [&](int J0, int s, int kend, double2& a0, double2& a1) {
-        const int r = J0 + kBlkRows + 4 * s + (lane >> 4);
-        const int i0 = J0 + (lane & 15), i1 = i0 + 16;
-        a0 = (r < kend && r - i0 <= bw) ? Fs[(int64_t)i0 * ld + (r - i0)] : make_double2(0.0, 0.0);
-        a1 = (r < kend && r - i1 <= bw) ? Fs[(int64_t)i1 * ld + (r - i1)] : make_double2(0.0, 0.0);
-    };
-    double2 pl[kLdPer];
-    load_ld((nblk - 1) * kBlkRows, pl);
-    __syncthreads();
-    for (int j = nblk - 1; j >= 0; --j) {
-        const int J0 = j * kBlkRows;
-        const int jb = J0 % WS;
-        const int kend = min(n, J0 + kBlkRows + bw);
-        const int nks = max(0, (kend - (J0 + kBlkRows) + 3) / 4);
+    auto store_ld = [&](const double2 (&pl)[kLdPer]) {
 #pragma unroll
         for (int m = 0; m < kLdPer; ++m) {
-            const int e = t + NT * m;
+            const int e = ts + NS * m;
             Ld[e / kBlkRows][e % kBlkRows] = pl[m];
         }
-        if (j > 0) load_ld(J0 - kBlkRows, pl);
-        double2 z[CPH];
+    };
+    // block J0's rows from the ring, solved from the last row up: x to X and Yb[buf]
+    auto solve_block = [&](int J0, int buf) {
+        const int slot = ((J0 + hl) % WS) * CPW + CPH * hw;
+        double2 v[CPH];
 #pragma unroll
-        for (int q = 0; q < CPH; ++q) z[q] = make_double2(0.0, 0.0);
-        if (J0 + hl < n) {
-            const double2* xi = X + base + (int64_t)(J0 + hl) * kTile + c0 + CPH * hw;
+        for (int q = 0; q < CPH; ++q) v[q] = ring[slot + q];
 #pragma unroll
-            for (int q = 0; q < CPH; ++q) z[q] = xi[q];
-        }
-        // (a) partial products of this wave's K steps (ks = wave + NW u); the L
-        // operands are loaded four steps ahead
-        mfma_f64x4 acc[2][2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) acc[a][b] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
-        const int my = nks > wave ? (nks - wave + NW - 1) / NW : 0;
-        double2 A0[4], A1[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (u < my) load_a(J0, wave + NW * u, kend, A0[u], A1[u]);
-        for (int it = 0; it < my; it += 4) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (it + u < my) {
-                    const int ks = wave + NW * (it + u);
-                    const int r = J0 + kBlkRows + 4 * ks + (lane >> 4);
-                    const double2 xb =
-                        r < kend ? ring[ring_slot(jb, r - J0, WS) * CPW + (lane & 15)] : make_double2(0.0, 0.0);
-                    const double2 a0 = A0[u], a1 = A1[u];
-                    if (it + u + 4 < my) load_a(J0, ks + 4 * NW, kend, A0[u], A1[u]);
-                    // G_re += A_re x_re - A_im x_im, G_im += A_re x_im + A_im x_re
-                    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, xb.x, acc[0][0], 0, 0, 0);
-                    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, -xb.y, acc[0][0], 0, 0, 0);
-                    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, xb.y, acc[0][1], 0, 0, 0);
-                    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, xb.x, acc[0][1], 0, 0, 0);
-                    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, xb.x, acc[1][0], 0, 0, 0);
-                    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, -xb.y, acc[1][0], 0, 0, 0);
-                    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, xb.y, acc[1][1], 0, 0, 0);
-                    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, xb.x, acc[1][1], 0, 0, 0);
-                }
-            }
-        }
-        if (NW > 4) {   // waves 4..7 hand their partial sums to waves 0..3
-            if (wave >= 4) {
-#pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int b = 0; b < 2; ++b)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            red[((((wave - 4) * 2 + a) * 2 + b) * 4 + v) * 64 + lane] = acc[a][b][v];
-            }
-            __syncthreads();
-            if (wave < 4) {
-#pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int b = 0; b < 2; ++b)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            acc[a][b][v] += red[(((wave * 2 + a) * 2 + b) * 4 + v) * 64 + lane];
-            }
-            __syncthreads();
-        }
-        if (wave < NR) {
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) red[(((wave * 2 + a) * 2 + b) * 4 + v) * 64 + lane] = acc[a][b][v];
-        }
-        __syncthreads();
-        // (b) the block's rows from the last up: half wave hw, columns CPH hw .. CPH hw + CPH - 1
-        {
-            // G at row i = J0 + hl: tile hl / 16, row rr = hl % 16 -> lane 16 (rr % 4) + column, register rr / 4
-            const int tq = hl >> 4, rr = hl & 15;
-            double2 v[CPH];
+        for (int i = kBlkRows - 1; i >= 0; --i) {
+            const double2 l = Ld[i][hl];   // L[J0 + i][J0 + hl], zero unless i > hl
 #pragma unroll
             for (int q = 0; q < CPH; ++q) {
-                double2 g = make_double2(0.0, 0.0);
+                const double2 a = readlane2(v[q], i), b = readlane2(v[q], i + 32);
+                cfms(v[q], l, upper ? b : a);
+            }
+        }
 #pragma unroll
-                for (int w = 0; w < NR; ++w) {
-                    const int bre = (((w * 2 + tq) * 2 + 0) * 4 + (rr >> 2)) * 64 + 16 * (rr & 3);
-                    const int bim = (((w * 2 + tq) * 2 + 1) * 4 + (rr >> 2)) * 64 + 16 * (rr & 3);
-                    g.x += red[bre + CPH * hw + q];
-                    g.y += red[bim + CPH * hw + q];
-                }
-                v[q] = make_double2(z[q].x - g.x, z[q].y - g.y);
+        for (int q = 0; q < CPH; ++q) Yb[buf][hl][CPH * hw + q] = J0 + hl < n ? v[q] : make_double2(0.0, 0.0);
+        if (J0 + hl < n) {
+            double2* xo = X + base + (int64_t)(J0 + hl) * kTile + c0 + CPH * hw;
+#pragma unroll
+            for (int q = 0; q < CPH; ++q) xo[q] = v[q];
+        }
+    };
+    // A operands of tile rows [I0, I0 + 16) for block J0: A(i, k) = L[J0 + k][I0 + i]
+    auto load_a = [&](int J0, int I0, int lo, double2 (&av)[8]) {
+        const int ia = I0 + (lane & 15);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int r = J0 + 4 * q + (lane >> 4);
+            av[q] = (ia >= lo && r < n && r - ia <= bw) ? Fs[(int64_t)ia * ld + (r - ia)] : make_double2(0.0, 0.0);
+        }
+    };
+    double2 pl[kLdPer];
+    double2 av[8];
+    if (!prod) load_ld(Jl, pl);
+    __syncthreads();   // ring filled
+    if (!prod) store_ld(pl);
+    __syncthreads();
+    if (!prod) {
+        solve_block(Jl, (nblk - 1) & 1);
+        if (nblk > 1) load_ld(Jl - kBlkRows, pl);
+    } else if (wave < (min(bw, Jl) + 15) / 16) {
+        load_a(Jl, Jl - 16 * (wave + 1), max(0, Jl - bw), av);
+    }
+    __syncthreads();   // x of the bottom block ready
+    for (int j = nblk - 1; j > 0; --j) {
+        const int J0 = j * kBlkRows;
+        const int lo = max(0, J0 - bw);
+        const int ntl = (J0 - lo + 15) / 16;
+        // one 16-row tile of block j's product (tile tl: rows [J0 - 16 (tl + 1), J0 - 16 tl),
+        // operands in av; the next tile of this wave, tl + NP, loaded meanwhile)
+        auto do_tile = [&](int tl) {
+            const int I0 = J0 - 16 * (tl + 1);
+            double2 an[8];
+            if (tl + NP < ntl) load_a(J0, I0 - 16 * NP, lo, an);
+            mfma_f64x4 cre, cim;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = I0 + (lane >> 4) + 4 * v;
+                const double2 w = r >= lo ? ring[(r % WS) * CPW + (lane & 15)] : make_double2(0.0, 0.0);
+                cre[v] = w.x;
+                cim[v] = w.y;
             }
 #pragma unroll
-            for (int i = kBlkRows - 1; i >= 0; --i) {
-                const double2 l = Ld[i][hl];   // L[J0 + i][J0 + hl], zero unless i > hl
-#pragma unroll
-                for (int q = 0; q < CPH; ++q) {
-                    const double2 pa = readlane2(v[q], i), pb = readlane2(v[q], i + 32);
-                    cfms(v[q], l, upper ? pb : pa);
-                }
+            for (int q = 0; q < 8; ++q) {
+                const double2 y = Yb[j & 1][4 * q + (lane >> 4)][lane & 15];
+                // C -= A x: re -= A_re x_re - A_im x_im, im -= A_re x_im + A_im x_re
+                cre = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q].x, -y.x, cre, 0, 0, 0);
+                cim = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q].x, -y.y, cim, 0, 0, 0);
+                cre = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q].y, y.y, cre, 0, 0, 0);
+                cim = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q].y, -y.x, cim, 0, 0, 0);
             }
-            if (J0 + hl < n) {
-                double2* xo = X + base + (int64_t)(J0 + hl) * kTile + c0 + CPH * hw;
 #pragma unroll
-                for (int q = 0; q < CPH; ++q) xo[q] = v[q];
+            for (int v = 0; v < 4; ++v) {
+                const int r = I0 + (lane >> 4) + 4 * v;
+                if (r >= lo) ring[(r % WS) * CPW + (lane & 15)] = make_double2(cre[v], cim[v]);
             }
-            // the ring slots of rows [J0, J0 + 32) held rows >= J0 + WS, out of reach
-            const int slot = ring_slot(jb, hl, WS) * CPW + CPH * hw;
+            if (tl + NP < ntl) {
 #pragma unroll
-            for (int q = 0; q < CPH; ++q) ring[slot + q] = J0 + hl < n ? v[q] : make_double2(0.0, 0.0);
+                for (int q = 0; q < 8; ++q) av[q] = an[q];
+            }
+        };
+        if (prod) {
+            if (wave < ntl) do_tile(wave);   // tiles 0 .. NP-1: block j - 1's rows among them
+        } else {
+            store_ld(pl);   // L_JJ of block j - 1
+            // rows [J0 - 32 - bw, J0 - bw) come into reach of block j - 1 (for
+            // narrow bands some are block j - 1's own rows, which its solve
+            // below reads); their slots held rows of block j or below, whose
+            // solves are done, and no tile of block j reaches them
+#pragma unroll
+            for (int m = 0; m < kNewPer; ++m) {
+                const int e = ts + NS * m;
+                const int r = J0 - kBlkRows - bw + e / CPW, c = e % CPW;
+                if (r >= 0) ring[(r % WS) * CPW + c] = X[base + (int64_t)r * kTile + c0 + c];
+            }
+        }
+        __syncthreads();   // rows of block j - 1 final; its L_JJ in LDS
+        if (prod) {
+            for (int tl = wave + NP; tl < ntl; tl += NP) do_tile(tl);
+            if (j > 1) {   // first tile of block j - 1 for this wave
+                const int J1 = J0 - kBlkRows, lo1 = max(0, J1 - bw);
+                if (wave < (J1 - lo1 + 15) / 16) load_a(J1, J1 - 16 * (wave + 1), lo1, av);
+            }
+        } else {
+            solve_block(J0 - kBlkRows, (j - 1) & 1);
+            if (j > 1) load_ld(J0 - 2 * kBlkRows, pl);
         }
         __syncthreads();
     }
@@ -1322,10 +1323,10 @@ static hipError_t sweep_reg(const BandSys* sys, const int32_t* colsys, const dou
     if (e != hipSuccess) return e;
     if (CPW == 16 && bwmax <= kBlkMaxBw) {
         const size_t ring = (size_t)blk_ring_rows(bwmax) * 16 * sizeof(double2);
-        e = hipFuncSetAttribute((const void*)k_band_bwd_blocked<kBlkBwdThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        e = hipFuncSetAttribute((const void*)k_band_bwd_pipe<kBlkBwdThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)ring);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_band_bwd_blocked<kBlkBwdThreads>), grid, dim3(kBlkBwdThreads), ring, s, sys, colsys, F,
+        hipLaunchKernelGGL((k_band_bwd_pipe<kBlkBwdThreads>), grid, dim3(kBlkBwdThreads), ring, s, sys, colsys, F,
                            g, X, xcd_map);
     } else {
         hipLaunchKernelGGL((k_band_sweep<K, CPW, CPL, false>), grid, dim3(T), lds, s, sys, colsys, F, g, X, R,
