@@ -69,13 +69,13 @@ TRAFFIC = [
         "workload": "q1_2d_300",
         "precision": "fp64",
         "sources_sha256": {
-            "paper_2511_01927_amd/csrc/band.hip": "d399a5986f430db73643e4a9435d96693daacf2a2a361278f1dc7f4a68f6072b",
+            "paper_2511_01927_amd/csrc/band.hip": "d23c156fb38707c0a675cf0ce2a9d4d7fbc35cde2b5b331e97a059c8129093a3",
             "paper_2511_01927_amd/csrc/internal.h": "4e19dbea0f25f1ead60c00d887ebbd761b83b9432924910ca8ecf490cce52023",
         },
         # bytes per launch (per timed bracket for band_solve: right-hand sides,
         # forward and backward sweep)
-        "per_launch_bytes": {"band_update": 6.794885e+07, "band_update_next": 3.717571e+07,
-                             "band_panel": 2.045747e+07, "band_solve": 8.695659e+10},
+        "per_launch_bytes": {"band_update": 6.794486e+07, "band_update_next": 3.717263e+07,
+                             "band_panel": 2.045747e+07, "band_solve": 8.754036e+10},
         "profile": "profiles/band_q1_300x300_fp64_hbm_traffic.md",
     },
 ]
