@@ -12,6 +12,8 @@ node.  Checked here:
   of 32 (one 64-column seed tile for two circles) and 48 (two seed tiles,
   the second one ragged);
 * agreement with the Jacobi-COCG solver on the same pencil;
+* an iteration cap that stops the seeds early: the unconverged columns are
+  counted and no pair is reported converged above tol;
 * the rejections: a consistent-mass B (off-diagonal entries), a diagonal
   but non-constant B, and a batch.
 """
@@ -94,3 +96,13 @@ def test_multishift_rejects_non_scalar_mass(lib):
         lib.gep_ci_solve(A, sp.diags(d, format="csr"), cont, 16, 4, 8, 1e-8, seed=7, solver="multishift")
     with pytest.raises(lib.GepError, match="single pencils"):
         lib.gep_ci_solve_batch([(A, B, cont), (A, B, cont)], 16, 4, 8, 1e-8, seed=7, solver="multishift")
+
+
+def test_multishift_iteration_cap_reports_unconverged(lib):
+    A, B, cont, _ = _fd7_var(m=8, seed=5, first=11, last=30, k=1)
+    got = lib.gep_ci_solve(A, B, cont, 16, 4, 16, 1e-8, seed=7, solver="multishift", max_iter=3)
+    st = got["stats"]
+    assert st["solver_run"] == "multishift" and st["multishift_iters"] % 3 == 0   # 3 per pass
+    assert st["multishift_unconverged"] > 0
+    assert np.all(got["resid"][got["converged"]] <= 1e-8)
+    assert got["status"] in (0, lib.GEP_WNOCONV, lib.GEP_WSATURATED)

@@ -67,6 +67,7 @@ def test_argument_errors_are_reported(lib):
     assert _solve_status(A, B, good, tol=0.0)[0] == -1
     assert _solve_status(A, B, good, row_group=3)[0] == -1
     assert _solve_status(A, B, good, rows_per_block=-1)[0] == -1
+    assert _solve_status(A, B, good, solver=4)[0] == -1           # no such solver
     bad = np.array([[100.0, 10.0, 60.0, 140.0]])               # window outside the circle
     assert _solve_status(A, B, bad)[0] == -1
     assert _solve_status(A, B, np.array([[100.0, -1.0, 99.0, 100.0]]))[0] == -1
