@@ -149,9 +149,13 @@ typedef struct {
                                ||r|| / |pi| is <= solve_tol ||B v||. */
     int band_kernels;       /* banded factorisation kernels: 0 (default) =
                                register-panel kernels with lookahead for FP64
-                               factors of half bandwidth <= 1024, wide-band
-                               kernels otherwise; 2 = wide-band kernels always
-                               (1 is the same as 0).  Results agree to rounding. */
+                               factors of half bandwidth <= 480 (a panel row
+                               per thread of one work-group), wide-band
+                               kernels otherwise; 1 = the one-work-group
+                               kernels for FP64 factors up to half bandwidth
+                               1024 (panels beyond 480 kept in global
+                               memory); 2 = wide-band kernels always.  Results
+                               agree to rounding. */
     int method;             /* GEP_CIRR (default) or GEP_FEAST */
     int band_group;         /* wide-band kernels: factor at most this many shifted
                                systems at once (0, the default: as many as the

@@ -852,13 +852,20 @@ class Solver {
         return true;
     }
 
-    // The wide-band kernels factor the pass's systems when a band is wider
-    // than the register-panel kernels take, when the factors are FP32 (mixed
-    // precision), or when the caller asks for them (band_kernels = 2).
+    // The wide-band kernels factor the pass's systems when the factors are
+    // FP32 (mixed precision), when the caller asks for them (band_kernels =
+    // 2), when a band is not kept packed (wider than kBandWideBw), and, by
+    // default, when a panel no longer fits one thread per row of one
+    // work-group (kPanel + bw > 512): beyond that the one-work-group panels
+    // keep the panel in global memory and take over ten times as long per
+    // step as the wide-band kernels' multi-work-group panels.  band_kernels
+    // = 1 keeps the one-work-group kernels for every kept band.
     bool use_wide(const std::vector<Job>& jobs) const {
         if (c_.o.precision == GEP_MIXED || c_.o.band_kernels == 2) return true;
-        for (const Job& j : jobs)
+        for (const Job& j : jobs) {
             if (P_->h.prob_boff[j.prob] < 0) return true;
+            if (c_.o.band_kernels == 0 && kPanel + P_->h.prob_bw[j.prob] > 512) return true;
+        }
         return false;
     }
 

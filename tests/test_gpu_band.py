@@ -53,17 +53,18 @@ def test_band_constant_q1_closed_form(lib, nx, ny):
     _check_band_stats(got, len(w.contours) * w.n_nodes // 2)
 
 
-@pytest.mark.parametrize("nx,ny", [(399, 12), (499, 8)])
-def test_band_wide_bands_closed_form(lib, nx, ny):
+@pytest.mark.parametrize("nx,ny,kernels", [(399, 12, "auto"), (499, 8, "auto"), (499, 8, "narrow")])
+def test_band_wide_bands_closed_form(lib, nx, ny, kernels):
     """Half bandwidths 400 and 500: past the blocked sweeps' limit (register
-    window sweeps instead) and, at 500, past the one-thread-per-row panel
-    (1024-thread register panel)."""
+    window sweeps instead) and, at 500, past the one-thread-per-row panel:
+    the automatic choice takes the wide-band kernels there, "narrow" keeps
+    the one-work-group panel in global memory."""
     eig = configs.q1_2d_eigs(nx, ny)
     w = configs.config_q1_2d(nx=nx, ny=ny, first=21, last=60, k=2, n_nodes=16, moments=4, block=16, seed=6)
     lo, hi = w.window
     ref = eig[(eig >= lo) & (eig < hi)]
     got = lib.gep_ci_solve(w.A, w.B, w.contours, w.n_nodes, w.moments, w.block, w.tol, seed=w.seed,
-                           solver="band")
+                           solver="band", band_kernels=kernels)
     assert got["evals"].size == ref.size
     assert np.max(np.abs(got["evals"] - ref) / ref) <= 1e-10
     assert np.max(got["resid"]) <= 1e-8
