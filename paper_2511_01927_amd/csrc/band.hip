@@ -15,8 +15,8 @@
 //   k_band_panel_rows  one work-group per system, one thread per panel row
 //                  (kPanel + bw <= 512): unblocked L D L^T of the panel's
 //                  kPanel columns with each row's entries in registers
-//                  (k_band_panel_reg / k_band_panel: wider bands, the panel
-//                  spread over 1024 threads or in global memory);
+//                  (k_band_panel: wider bands, when asked for, the panel
+//                  in global memory);
 //   k_band_strip   the next panel's columns take the contributions of this
 //                  panel and the one before (critical path of the step);
 //   k_band_update  the rest of the trailing window, from the panel after
@@ -135,70 +135,6 @@ __global__ __launch_bounds__(256) void k_band_panel(const BandSys* __restrict__ 
             cfms(P[(int64_t)(jj + t) * ld + e2], col[t + e2], f);
         }
         __syncthreads();
-    }
-}
-
-// Register-resident panel: the kPanel x (bw + 1) panel entries are spread
-// over the 1024 threads (entry f = jj * (bw + 1) + e held by thread f mod
-// 1024, register f / 1024); each column step publishes the pivot and the
-// scaled column through LDS (two barriers) and every thread updates its own
-// entries.  Used for kPanel * (bw + 1) <= 1024 * Q.
-constexpr int kPanelThreads = 1024;
-
-template <int Q>
-__global__ __launch_bounds__(kPanelThreads) void k_band_panel_reg(const BandSys* __restrict__ sys,
-                                                                  double2* F, int k0,
-                                                                  int32_t* __restrict__ flag) {
-    __shared__ double2 lcol[kPanelThreads * Q / kPanel + 1];
-    __shared__ double2 dsh;
-    const BandSys S = sys[blockIdx.x];
-    if (k0 >= S.n) return;
-    const int ld = S.bw + 1;
-    const int ncols = min(kPanel, S.n - k0);
-    const int total = ncols * ld;
-    double2* P = F + S.off + (int64_t)k0 * ld;
-    double2 v[Q];
-    int cj[Q], ce[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int f = threadIdx.x + kPanelThreads * q;
-        cj[q] = f < total ? f / ld : kPanel;   // kPanel: no entry
-        ce[q] = f < total ? f - cj[q] * ld : 0;
-        v[q] = f < total ? P[f] : make_double2(0.0, 0.0);
-    }
-    for (int jj = 0; jj < ncols; ++jj) {
-        const int j = k0 + jj;
-        const int emax = min(S.bw, S.n - 1 - j);
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-            if (cj[q] == jj && ce[q] == 0) dsh = v[q];
-        __syncthreads();
-        const double2 d = dsh;
-        const double m2 = d.x * d.x + d.y * d.y;
-        if (threadIdx.x == 0 && (!(m2 > 0.0) || !isfinite(m2))) flag[blockIdx.x] = 1;
-        const double2 inv = make_double2(d.x / m2, -d.y / m2);
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-            if (cj[q] == jj && ce[q] >= 1 && ce[q] <= emax) {
-                v[q] = cmul(v[q], inv);
-                lcol[ce[q]] = v[q];
-            }
-        __syncthreads();
-        // entries (jj + t, e2) with 1 <= t <= emax, e2 <= emax - t:
-        // a_{j+t+e2, j+t} -= l_{j+t+e2, j} d l_{j+t, j}
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int t = cj[q] - jj;
-            if (t >= 1 && t <= emax && ce[q] <= emax - t && cj[q] < ncols) {
-                const double2 f = cmul(d, lcol[t]);
-                cfms(v[q], lcol[t + ce[q]], f);
-            }
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int f = threadIdx.x + kPanelThreads * q;
-        if (f < total) P[f] = v[q];
     }
 }
 
@@ -1385,20 +1321,8 @@ hipError_t band_panel(const BandSys* sys, int nsys, int bwmax, double2* F, int k
     } else if (rows <= 512) {
         return launch_ev(k_band_panel_rows<512>, dim3(nsys), dim3(512), s, e0, e1, sys, F, k0, flag);
     }
-    // registers per thread for a kPanel x (bw + 1) panel over 1024 threads
-    const int need = (kPanel * (bwmax + 1) + kPanelThreads - 1) / kPanelThreads;
-    const dim3 b(kPanelThreads);
-    if (need <= 2)
-        return launch_ev(k_band_panel_reg<2>, dim3(nsys), b, s, e0, e1, sys, F, k0, flag);
-    else if (need <= 4)
-        return launch_ev(k_band_panel_reg<4>, dim3(nsys), b, s, e0, e1, sys, F, k0, flag);
-    else if (need <= 6)
-        return launch_ev(k_band_panel_reg<6>, dim3(nsys), b, s, e0, e1, sys, F, k0, flag);
-    else if (need <= 8)
-        return launch_ev(k_band_panel_reg<8>, dim3(nsys), b, s, e0, e1, sys, F, k0, flag);
-    else if (need <= 10)
-        return launch_ev(k_band_panel_reg<10>, dim3(nsys), b, s, e0, e1, sys, F, k0, flag);
-    // wider bands: the panel stays in global memory (more registers would spill)
+    // wider bands (only with band_kernels = 1; by default the wide-band
+    // kernels take them): the panel stays in global memory
     return launch_ev(k_band_panel, dim3(nsys), dim3(256), s, e0, e1, sys, F, k0, flag);
 }
 
