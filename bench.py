@@ -306,7 +306,7 @@ def main_batch(args):
 def main_learned(args):
     """Learned contours + mixed precision + one batched solve against plain FP64
     uniform contours solved pencil by pencil, at equal accuracy, on held-out 3D
-    27-point FEM pencils (the prior trained on 16^3 fields, untimed)."""
+    27-point FEM pencils (the prior trained on coarser fields, untimed)."""
     import math
     from workloads import configs
     first, last = configs.LEARNED_FIRST, configs.LEARNED_LAST
@@ -353,7 +353,7 @@ def main_learned(args):
     prior = learned.SpectralPrior(n_bins=nbins, hidden=256, max_batch=64, seed=11, din=side ** 3)
     hist = prior.train(np.array(feats), np.array(targs), epochs=200, batch=16, lr=1e-3)
     train_s = time.perf_counter() - t0
-    print(f"# prior trained on {len(feats)} solved 16^3 fields in {train_s:.1f} s (loss {hist[0]:.3f} -> "
+    print(f"# prior trained on {len(feats)} solved {configs.LEARNED_TRAIN[0][0]}^3 fields in {train_s:.1f} s (loss {hist[0]:.3f} -> "
           f"{hist[-1]:.3f})", flush=True)
     # held-out instances: learned and uniform contours, block sizes by the same rule
     inst, L_c, L_p, L_b, U_c, U_b = [], [], [], [], [], []
@@ -449,7 +449,8 @@ def main_learned(args):
         "data": "synthetic",
         "config": {"workload": "learned3d: 3D 27-point trilinear-FEM pencils, log-normal coefficients (sigma 1), "
                                "held-out fields on " + ", ".join(f"{m}^3" for m, _ in configs.LEARNED_EVAL)
-                               + f", Weyl indices [{first}, {last}); learned contours (prior trained on 64 16^3 "
+                               + f", Weyl indices [{first}, {last}); learned contours (prior trained on {len(configs.LEARNED_TRAIN)} "
+                               f"{configs.LEARNED_TRAIN[0][0]}^3 "
                                f"fields; KDE with {args.kde_nmin}-{args.kde_nmax} predicted eigenvalues per circle) "
                                "+ FP32 factors with FP64 refinement + one batched solve, against uniform circles "
                                "in FP64 solved pencil by pencil",

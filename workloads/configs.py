@@ -203,8 +203,8 @@ def q1_batch64() -> Batch:
 # 16^3 fields (field seeds 300..363); the comparison runs on held-out fields
 # on finer grids (the prior's transfer to grids it never saw).  Every instance
 # targets the Weyl-law indices [60, 220) of its own coefficient field.
-LEARNED_TRAIN = [(16, s) for s in range(300, 364)]
-LEARNED_EVAL = [(24, 900), (24, 901), (28, 902), (28, 903), (32, 904), (32, 905)]
+LEARNED_TRAIN = [(24, s) for s in range(300, 364)]
+LEARNED_EVAL = [(32, 900), (32, 901), (36, 902), (36, 903), (40, 904), (40, 905)]
 LEARNED_FIRST, LEARNED_LAST = 60, 220
 
 
