@@ -3,6 +3,7 @@ and of the pure helpers of the learned pipeline."""
 import math
 
 import numpy as np
+import pytest
 
 from oracle import density, kde
 
@@ -47,6 +48,51 @@ def test_kde_cuts_in_gaps_and_bounds_counts():
     assert 1.0 < cuts[0] < 2.0 and 3.0 < cuts[1] < 4.0
     assert abs(cuts[0] - 1.5) < 1e-12 and abs(cuts[1] - 3.5) < 1e-12
     assert ivs[0][0] == -0.5 and ivs[-1][1] == 5.5
+
+
+def _g_scan(inside, s, e, w):
+    """Sparsity G(t) = sum_k exp(-w ((t - x_k) / (e - s))^2) at every midpoint
+    between consecutive distinct sorted predictions (the interval's interior
+    candidates), scanned directly."""
+    mids = [0.5 * (a + b) for a, b in zip(inside[:-1], inside[1:]) if b > a]
+    g = [float(np.sum(np.exp(-w * ((t - np.asarray(inside)) / (e - s)) ** 2))) for t in mids]
+    return np.asarray(mids), np.asarray(g)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_kde_cut_is_the_plain_argmin_when_it_leaves_nmin_each_side(seed):
+    """Sec. 4.2, Alg. "Adaptive Contour Construction via KDE": the interval is
+    split at the minimum of G.  The reading here restricts candidates to
+    midpoints that leave N_min predictions on each side; whenever the plain
+    argmin over all interior midpoints already does, the cut is that argmin.
+    One split (N_max = n - 1) exposes the cut as the shared interval end."""
+    r = np.random.default_rng(seed)
+    lam = np.sort(np.concatenate([r.uniform(0.0, 1.0, 40), r.uniform(1.6, 3.0, 50)]))
+    # a kernel narrow against the gap, so G is least inside it and not at the ends
+    s, e, w, nmin = -0.1, 3.1, 200.0, 10
+    mids, g = _g_scan(list(lam), s, e, w)
+    t_star = mids[int(np.argmin(g))]
+    left = int(np.sum(lam < t_star))
+    assert nmin <= left <= lam.size - nmin   # the plain argmin is admissible here
+    ivs = kde.kde_intervals(lam, nmin=nmin, nmax=lam.size - 1, w=w, window=(s, e))
+    assert len(ivs) == 2 and ivs[0][1] == ivs[1][0]
+    assert abs(ivs[0][1] - t_star) <= 1e-15 * max(1.0, abs(t_star))
+
+
+def test_kde_cut_skips_an_argmin_that_leaves_too_few():
+    """The plain argmin of G sits next to the interval's end (a lone
+    prediction far from the rest), leaving fewer than N_min on one side; the
+    cut then goes to the admissible midpoint of least G."""
+    lam = np.sort(np.concatenate([np.linspace(0.0, 1.0, 60), [2.9]]))
+    s, e, w, nmin = -0.05, 3.0, 10.0, 10
+    mids, g = _g_scan(list(lam), s, e, w)
+    t_plain = mids[int(np.argmin(g))]
+    assert np.sum(lam > t_plain) < nmin       # the plain argmin is not admissible
+    ok = np.array([nmin <= np.sum(lam < t) <= lam.size - nmin for t in mids])
+    t_adm = mids[ok][int(np.argmin(g[ok]))]
+    ivs = kde.kde_intervals(lam, nmin=nmin, nmax=lam.size - 1, w=w, window=(s, e))
+    assert len(ivs) == 2
+    assert abs(ivs[0][1] - t_adm) <= 1e-15 * max(1.0, abs(t_adm))
 
 
 def test_kde_default_weight_keeps_counts_in_range():
