@@ -215,8 +215,11 @@ __global__ __launch_bounds__(256) void k_wb_panel(const BandSys* __restrict__ sy
 // LDS in turn with lanes running down band columns; the result registers
 // run down a column of C, so the single read-modify-write per tile is
 // coalesced.  Entries a panel does not reach (past its band) are zero.
-template <typename C>
-__global__ __launch_bounds__(256) void k_wb_update(const BandSys* __restrict__ sys, C* F, int k0, int npan,
+// WPE: waves per SIMD the registers must allow (four work-groups per CU fit
+// the FP32 operands' LDS, two the FP64 ones').
+template <typename C, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
+void k_wb_update(const BandSys* __restrict__ sys, C* F, int k0, int npan,
                                                    int c0, int c1, int strip) {
     using V = typename Mma<C>::V;
     __shared__ C Wi[64][kPanel + 1];
@@ -244,24 +247,39 @@ __global__ __launch_bounds__(256) void k_wb_update(const BandSys* __restrict__ s
         pre[rb] = V{0, 0, 0, 0};
         pim[rb] = V{0, 0, 0, 0};
     }
+    // panel pp's operands go through registers into LDS; the next panel's
+    // are loaded while this one's products run
+    constexpr int kPer = 64 * kPanel / 256;
+    C ri[kPer], rj[kPer];
+    auto fetch = [&](int kp) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int idx = threadIdx.x + 256 * q;
+            const int r = idx & 63, kk = idx >> 6;
+            const int k = kp + kk;
+            const int i = i0 + r, j = j0 + r;
+            ri[q] = czero<C>();
+            rj[q] = czero<C>();
+            if (k < S.n) {
+                if (i < wend && i - k <= S.bw) ri[q] = Fs[(int64_t)k * ld + (i - k)];
+                if (j < cend && j - k <= S.bw) rj[q] = cmulT(Fs[(int64_t)k * ld + (j - k)], Fs[(int64_t)k * ld]);
+            }
+        }
+    };
+    fetch(k0);
     for (int pp = 0; pp < npan; ++pp) {
         const int kp = k0 + kPanel * pp;
         if (kp >= S.n) break;   // uniform
         if (pp > 0) __syncthreads();
-        for (int idx = threadIdx.x; idx < 64 * kPanel; idx += blockDim.x) {
-            const int r = idx & 63, kk = idx >> 6;
-            const int k = kp + kk;
-            const int i = i0 + r, j = j0 + r;
-            C wi = czero<C>(), wj = czero<C>();
-            if (k < S.n) {
-                if (i < wend && i - k <= S.bw) wi = Fs[(int64_t)k * ld + (i - k)];
-                if (j < cend && j - k <= S.bw) wj = cmulT(Fs[(int64_t)k * ld + (j - k)], Fs[(int64_t)k * ld]);
-            }
-            Wi[r][kk] = wi;
-            Wj[r][kk] = wj;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int idx = threadIdx.x + 256 * q;
+            Wi[idx & 63][idx >> 6] = ri[q];
+            Wj[idx & 63][idx >> 6] = rj[q];
         }
         __syncthreads();
-#pragma unroll
+        if (pp + 1 < npan && kp + kPanel < S.n) fetch(kp + kPanel);
+#pragma unroll 2
         for (int st = 0; st < kPanel / 4; ++st) {
             const int kk = 4 * st + (lane >> 4);
             const C a = Wj[wave * 16 + (lane & 15)][kk];
@@ -548,11 +566,11 @@ static hipError_t wb_step_t(const BandSys* sys, int nsys, int bwmax, C* F, int k
     hipLaunchKernelGGL(k_wb_panel<C>, dim3(chunks, nsys), dim3(256), 0, s, sys, F, k0, flag);
     if (k0 + kPanel >= nmax) return hipGetLastError();
     if (bwmax > 0)
-        hipLaunchKernelGGL(k_wb_update<C>, dim3(T + 1, nsys), dim3(256), 0, s, sys, F, k0, 1, k0 + kPanel,
+        hipLaunchKernelGGL((k_wb_update<C, sizeof(C) == 8 ? 4 : 2>), dim3(T + 1, nsys), dim3(256), 0, s, sys, F, k0, 1, k0 + kPanel,
                            k0 + 2 * kPanel, 1);
     hipLaunchKernelGGL(k_wb_panel<C>, dim3(chunks, nsys), dim3(256), 0, s, sys, F, k0 + kPanel, flag);
     if (k0 + 2 * kPanel >= nmax || bwmax == 0) return hipGetLastError();
-    hipLaunchKernelGGL(k_wb_update<C>, dim3(T * (T + 1) / 2, nsys), dim3(256), 0, s, sys, F, k0, 2,
+    hipLaunchKernelGGL((k_wb_update<C, sizeof(C) == 8 ? 4 : 2>), dim3(T * (T + 1) / 2, nsys), dim3(256), 0, s, sys, F, k0, 2,
                        k0 + 2 * kPanel, k0 + 2 * kPanel + bwmax, 0);
     return hipGetLastError();
 }
