@@ -761,6 +761,23 @@ def main():
                        "traffic_unit": "bytes per launch", "avg_launch_us": round(avg_s * 1e6, 2),
                        "alg_bytes_per_launch": per_launch, "launches": launches,
                        "sample": "COCG solve of the same pencil capped at 64 iterations, after the timed steps"}
+        # the practical ceiling beside the 8 TB/s peak: a plain 1 GiB device
+        # copy (1 GiB read + 1 GiB written), median of five
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        times = []
+        for _ in range(6):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            dst.copy_(src)
+            e1.record(stream)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1) / 1e3)
+        copy_gbs = 2.0 * src.numel() * 8 / float(np.median(times[1:])) / 1e9
+        out["spmm"]["copy_ceiling"] = {"gbs": round(copy_gbs, 1), "frac_of_copy": round(rate / copy_gbs, 4),
+                                       "note": "plain 1 GiB device copy (read + write), median of 5"}
+        del src, dst
     if args.stats_out:
         with open(args.stats_out, "w") as f:
             json.dump({"bench": out, "stats": [r["stats"] for r in results]}, f, indent=1)
