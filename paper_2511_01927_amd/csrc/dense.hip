@@ -42,6 +42,8 @@ __device__ inline double block_sum(double v, double* red) {
 constexpr int kBJ = 32;
 constexpr int kBJ2 = 2 * kBJ;
 constexpr int kBJThreads = 256;
+typedef double bj_f64x4 __attribute__((ext_vector_type(4)));
+static_assert(kBJThreads == 256 && kBJ2 == 64, "four waves, one 16-column block each");
 constexpr int kBJMaxSweeps = 60;
 
 __device__ inline void bj_pair(int nbp, int r, int t, int& I, int& J) {
@@ -214,23 +216,34 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_solve(const double* __restric
 // C (64 x 64 per work-group, 4 x 4 per thread) = X^T Y or X Y for LDS tiles.
 template <bool TRANS_X>
 __device__ inline void bj_tile_product(const double (*X)[kBJ2 + 1], const double (*Y)[kBJ2 + 1],
-                                       double (&acc)[4][4], int tr, int tc) {
+                                       double (&acc)[4][4]) {
+    // C = op(X) Y on the FP64 matrix cores: wave w forms columns [16 w, 16 w
+    // + 16) of all four 16-row blocks; v_mfma_f64_16x16x4 lane l holds
+    // A(l % 16, l / 16), B(l / 16, l % 16) and result register v is row
+    // l / 16 + 4 v, column l % 16 of its block (bj_row / bj_col below)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bj_f64x4 c[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int rb = 0; rb < 4; ++rb) c[rb] = bj_f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int q = 0; q < kBJ2 / 4; ++q) {
+        const int u = 4 * q + (lane >> 4);
+        const double yv = Y[u][16 * wave + (lane & 15)];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[a][q] = 0.0;
-    for (int u = 0; u < kBJ2; ++u) {
-        double xv[4], yv[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) xv[a] = TRANS_X ? X[u][tr * 4 + a] : X[tr * 4 + a][u];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) yv[q] = Y[u][tc + 16 * q];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[a][q] = fma(xv[a], yv[q], acc[a][q]);
+        for (int rb = 0; rb < 4; ++rb) {
+            const int i = 16 * rb + (lane & 15);
+            const double xv = TRANS_X ? X[u][i] : X[i][u];
+            c[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, yv, c[rb], 0, 0, 0);
+        }
     }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[rb][v] = c[rb][v];
 }
+// row and column of acc[rb][v] in the 64 x 64 product
+__device__ inline int bj_row(int rb, int v) { return 16 * rb + ((threadIdx.x & 63) >> 4) + 4 * v; }
+__device__ inline int bj_col() { return 16 * (threadIdx.x >> 6) + (threadIdx.x & 15); }
 
 // Apply the round's rotations.  Work-groups [0, nA) take the pair blocks
 // (P <= Q) of A: A[P, Q] <- R_P^T A[P, Q] R_Q and A[Q, P] its transpose, or S
@@ -248,7 +261,6 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_apply(double* __restrict__ Aa
     const int npair = nbp / 2;
     const int nA = npair * (npair + 1) / 2;
     const int t = threadIdx.x;
-    const int tc = t & 15, tr = t >> 4;
     double* A = Aall + (int64_t)b * kmax * kmax;
     const double* Rb = Rall + (int64_t)b * npair * kBJ2 * kBJ2;
     int w = blockIdx.x;
@@ -281,25 +293,25 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_apply(double* __restrict__ Aa
         }
         __syncthreads();
         double acc[4][4];
-        bj_tile_product<true>(X, Y, acc, tr, tc);   // R_P^T A[P, Q]
+        bj_tile_product<true>(X, Y, acc);   // R_P^T A[P, Q]
         __syncthreads();
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) Y[tr * 4 + a][tc + 16 * q] = acc[a][q];
+            for (int q = 0; q < 4; ++q) Y[bj_row(a, q)][bj_col()] = acc[a][q];
         __syncthreads();
-        bj_tile_product<false>(Y, Z, acc, tr, tc);   // (R_P^T A[P, Q]) R_Q
+        bj_tile_product<false>(Y, Z, acc);   // (R_P^T A[P, Q]) R_Q
+        const int g2 = bj_index(I2, J2, bj_col());
+        if (g2 < k) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int g1 = bj_index(I1, J1, tr * 4 + a);
-            if (g1 >= k) continue;
+            for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int g2 = bj_index(I2, J2, tc + 16 * q);
-                if (g2 >= k) continue;
-                A[(int64_t)g1 * k + g2] = acc[a][q];
-                A[(int64_t)g2 * k + g1] = acc[a][q];
-            }
+                for (int q = 0; q < 4; ++q) {
+                    const int g1 = bj_index(I1, J1, bj_row(a, q));
+                    if (g1 >= k) continue;
+                    A[(int64_t)g1 * k + g2] = acc[a][q];
+                    A[(int64_t)g2 * k + g1] = acc[a][q];
+                }
         }
         return;
     }
@@ -319,16 +331,16 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_apply(double* __restrict__ Aa
     }
     __syncthreads();
     double acc[4][4];
-    bj_tile_product<false>(X, Y, acc, tr, tc);
+    bj_tile_product<false>(X, Y, acc);
+    const int g = bj_index(I, J, bj_col());
+    if (g < k) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int i = r0 + tr * 4 + a;
-        if (i >= k) continue;
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int g = bj_index(I, J, tc + 16 * q);
-            if (g < k) V[(int64_t)i * k + g] = acc[a][q];
-        }
+            for (int q = 0; q < 4; ++q) {
+                const int i = r0 + bj_row(a, q);
+                if (i < k) V[(int64_t)i * k + g] = acc[a][q];
+            }
     }
 }
 
