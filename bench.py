@@ -519,7 +519,7 @@ def main():
                          "--max-iter")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "the solver runs on one GPU per process; --gpus must be 1 "
                                    "(multi-GPU sharding is described in the design notes)"}))
         sys.exit(2)
 
