@@ -94,22 +94,52 @@ __global__ __launch_bounds__(kDenseThreads) void k_bj_identity(double* __restric
     for (int e = threadIdx.x; e < k * k; e += blockDim.x) V[e] = (e / k == e % k) ? 1.0 : 0.0;
 }
 
+// Index pair (p < q) of rotation r in step `step` of a sweep on a block
+// pair's subproblem: round robin over all 64 indices when full, else local
+// index r paired with 32 + (r + step) mod 32.
+__device__ inline void bj_step_pair(int full, int step, int r, int& p, int& q) {
+    if (!full) {
+        p = r;
+        q = kBJ + (r + step) % kBJ;
+    } else if (r == 0) {
+        p = kBJ2 - 1;
+        q = step;
+    } else {
+        p = (step + r) % (kBJ2 - 1);
+        q = (step - r + (kBJ2 - 1)) % (kBJ2 - 1);
+    }
+    if (p > q) {
+        const int x = p;
+        p = q;
+        q = x;
+    }
+}
+
 // One rotation sweep on the subproblem of block pair blockIdx.x of round r of
 // matrix blockIdx.y; R and S of the pair go to Rall and Sall.  full != 0:
 // all 64 * 63 / 2 index pairs (63 steps of 32 disjoint pairs, round robin);
 // else only the 32 * 32 pairs that couple I with J (step s pairs local index
 // p with 32 + (p + s) mod 32).  A sweep uses full on its first round, so that
 // every index pair of the matrix is visited at least once per sweep.
+//
+// The 32 rotations of a step are disjoint, so S <- J^T S J splits into 2 x 2
+// blocks: block (a, b) = rows {p_a, q_a} x columns {p_b, q_b} takes rotation
+// a on its rows and then rotation b on its columns (the same operations, in
+// the same order, as rotating all rows first and all columns after), and the
+// diagonal blocks take the 2 x 2 result.  Thread t owns column pair
+// b = t mod 32 (whose rotation every lane computes itself) and the row pairs
+// a = t / 32 + 8m, so each entry of S and R has one owner per step: two
+// barriers per step, one LDS read and write of S and R.
 __global__ __launch_bounds__(kBJThreads) void k_bj_solve(const double* __restrict__ Aall, int kmax,
                                                          const int32_t* __restrict__ ks, int nbp, int r,
                                                          int full, double* __restrict__ Rall,
                                                          double* __restrict__ Sall) {
-    constexpr int kPer = kBJ * kBJ2 / kBJThreads;   // element pairs per thread and phase
-    constexpr int kLanes = kBJThreads / kBJ;        // threads per rotation
+    constexpr int kBlk = kBJ * kBJ / kBJThreads;    // 2 x 2 blocks of S per thread (4)
+    constexpr int kRrow = kBJ2 * kBJ / kBJThreads;  // rows of R per thread (8)
+    constexpr int kStride = kBJThreads / kBJ;       // between a thread's row pairs (8)
     __shared__ double S[kBJ2][kBJ2 + 1];
     __shared__ double Rm[kBJ2][kBJ2 + 1];
-    __shared__ int pp[kBJ], qq[kBJ];
-    __shared__ double cs[kBJ], sn[kBJ], dp[kBJ], dq[kBJ];
+    __shared__ double cs[kBJ], sn[kBJ];
     const int b = blockIdx.y;
     const int k = ks ? ks[b] : kmax;
     const int t = threadIdx.x;
@@ -123,86 +153,58 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_solve(const double* __restric
         Rm[s1][s2] = s1 == s2 ? 1.0 : 0.0;
     }
     __syncthreads();
-    const int pr = t / kLanes, l0 = t % kLanes;   // this thread's rotation and first row / column
+    const int rb = t % kBJ, ra0 = t / kBJ;
     const int nsteps = full ? kBJ2 - 1 : kBJ;
     for (int step = 0; step < nsteps; ++step) {
-        if (t < kBJ) {
-            int p, q;
-            if (!full) {
-                p = t;
-                q = kBJ + (t + step) % kBJ;
-            } else if (t == 0) {
-                p = kBJ2 - 1;
-                q = step;
+        // rotation rb from the step's S (symmetric Schur 2 x 2)
+        int p, q;
+        bj_step_pair(full, step, rb, p, q);
+        double c = 1.0, sv = 0.0, tt = 0.0;
+        const double apq = S[p][q], app = S[p][p], aqq = S[q][q];
+        if (apq != 0.0) {
+            const double diff = aqq - app;
+            if (fabs(diff) > 1e150 * fabs(apq)) {
+                tt = apq / diff;
             } else {
-                p = (step + t) % (kBJ2 - 1);
-                q = (step - t + (kBJ2 - 1)) % (kBJ2 - 1);
+                const double tau = diff / (2.0 * apq);
+                tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             }
-            if (p > q) {
-                const int x = p;
-                p = q;
-                q = x;
-            }
-            double c = 1.0, sv = 0.0, tt = 0.0;
-            const double apq = S[p][q], app = S[p][p], aqq = S[q][q];
-            if (apq != 0.0) {
-                const double diff = aqq - app;
-                if (fabs(diff) > 1e150 * fabs(apq)) {
-                    tt = apq / diff;
-                } else {
-                    const double tau = diff / (2.0 * apq);
-                    tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                }
-                c = 1.0 / sqrt(1.0 + tt * tt);
-                sv = tt * c;
-            }
-            pp[t] = p;
-            qq[t] = q;
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            sv = tt * c;
+        }
+        const double dpp = app - tt * apq, dqq = aqq + tt * apq;
+        if (t < kBJ) {
             cs[t] = c;
             sn[t] = sv;
-            dp[t] = app - tt * apq;
-            dq[t] = aqq + tt * apq;
         }
-        __syncthreads();
-        const int p = pp[pr], q = qq[pr];
-        const double c = cs[pr], sv = sn[pr];
-        {   // rows p, q of S (an unrotated pair has c = 1, sv = 0 and is rewritten unchanged)
-            double ap[kPer], aq[kPer];
+        __syncthreads();   // every rotation has read its entries before any is rewritten
 #pragma unroll
-            for (int m = 0; m < kPer; ++m) {
-                ap[m] = S[p][l0 + kLanes * m];
-                aq[m] = S[q][l0 + kLanes * m];
+        for (int m = 0; m < kBlk; ++m) {
+            const int a = ra0 + kStride * m;
+            int pa, qa;
+            bj_step_pair(full, step, a, pa, qa);
+            const double ca = cs[a], sa = sn[a];
+            const double x00 = S[pa][p], x01 = S[pa][q], x10 = S[qa][p], x11 = S[qa][q];
+            const double y00 = ca * x00 - sa * x10, y10 = sa * x00 + ca * x10;
+            const double y01 = ca * x01 - sa * x11, y11 = sa * x01 + ca * x11;
+            double z00 = c * y00 - sv * y01, z01 = sv * y00 + c * y01;
+            double z10 = c * y10 - sv * y11, z11 = sv * y10 + c * y11;
+            if (a == rb) {
+                z00 = dpp;
+                z01 = z10 = 0.0;
+                z11 = dqq;
             }
-#pragma unroll
-            for (int m = 0; m < kPer; ++m) {
-                S[p][l0 + kLanes * m] = c * ap[m] - sv * aq[m];
-                S[q][l0 + kLanes * m] = sv * ap[m] + c * aq[m];
-            }
+            S[pa][p] = z00;
+            S[pa][q] = z01;
+            S[qa][p] = z10;
+            S[qa][q] = z11;
         }
-        __syncthreads();
-        {   // columns p, q of S and R; entries (p,p), (p,q), (q,p), (q,q) take the 2 x 2 result
-            double sp[kPer], sq[kPer], rp[kPer], rq[kPer];
 #pragma unroll
-            for (int m = 0; m < kPer; ++m) {
-                const int i = l0 + kLanes * m;
-                sp[m] = S[i][p];
-                sq[m] = S[i][q];
-                rp[m] = Rm[i][p];
-                rq[m] = Rm[i][q];
-            }
-            const double dpp = dp[pr], dqq = dq[pr];
-#pragma unroll
-            for (int m = 0; m < kPer; ++m) {
-                const int i = l0 + kLanes * m;
-                double np = c * sp[m] - sv * sq[m];
-                double nq = sv * sp[m] + c * sq[m];
-                np = i == p ? dpp : (i == q ? 0.0 : np);
-                nq = i == q ? dqq : (i == p ? 0.0 : nq);
-                S[i][p] = np;
-                S[i][q] = nq;
-                Rm[i][p] = c * rp[m] - sv * rq[m];
-                Rm[i][q] = sv * rp[m] + c * rq[m];
-            }
+        for (int m = 0; m < kRrow; ++m) {
+            const int i = ra0 + kStride * m;
+            const double rp = Rm[i][p], rq = Rm[i][q];
+            Rm[i][p] = c * rp - sv * rq;
+            Rm[i][q] = sv * rp + c * rq;
         }
         __syncthreads();
     }
