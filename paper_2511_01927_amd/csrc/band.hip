@@ -958,6 +958,18 @@ __global__ __launch_bounds__(NT) void k_band_fwd_pipe(const BandSys* __restrict_
     };
     double2 pl[kLdPer], pd;
     double2 av[8];
+    // rows [J0 + 32 + bw, J0 + 64 + bw) of X, which block J0 brings into
+    // reach, read a block ahead so that their loads overlap the solve
+    double2 nx[kNewPer];
+    auto load_new = [&](int J0) {
+#pragma unroll
+        for (int m = 0; m < kNewPer; ++m) {
+            const int e = ts + NS * m;
+            const int r = J0 + kBlkRows + bw + e / CPW, c = e % CPW;
+            nx[m] = r < n ? X[base + (int64_t)r * kTile + c0 + c] : make_double2(0.0, 0.0);
+        }
+    };
+    if (!prod) load_new(0);
     if (!prod) load_ld(0, pl, pd);
     __syncthreads();   // ring filled
     if (!prod) store_ld(pl, pd);
@@ -1021,8 +1033,7 @@ __global__ __launch_bounds__(NT) void k_band_fwd_pipe(const BandSys* __restrict_
             for (int m = 0; m < kNewPer; ++m) {
                 const int e = ts + NS * m;
                 const int r = J0 + kBlkRows + bw + e / CPW, c = e % CPW;
-                ring[ring_slot(jb, r - J0, WS) * CPW + c] =
-                    r < n ? X[base + (int64_t)r * kTile + c0 + c] : make_double2(0.0, 0.0);
+                ring[ring_slot(jb, r - J0, WS) * CPW + c] = nx[m];
             }
         }
         __syncthreads();   // rows of block j + 1 final; its L_JJ in LDS
@@ -1036,6 +1047,7 @@ __global__ __launch_bounds__(NT) void k_band_fwd_pipe(const BandSys* __restrict_
             if (j + 1 < nblk) {
                 solve_block(J0 + kBlkRows, (j + 1) & 1);
                 if (j + 2 < nblk) load_ld(J0 + 2 * kBlkRows, pl, pd);
+                load_new(J0 + kBlkRows);
             }
         }
         __syncthreads();
@@ -1149,6 +1161,19 @@ __global__ __launch_bounds__(NT) void k_band_bwd_pipe(const BandSys* __restrict_
     };
     double2 pl[kLdPer];
     double2 av[8];
+    // rows [J0 - 32 - bw, J0 - bw) of X, which block J0 brings into reach
+    // (those at or above row 0), read a block ahead so that their loads
+    // overlap the solve
+    double2 nx[kNewPer];
+    auto load_new = [&](int J0) {
+#pragma unroll
+        for (int m = 0; m < kNewPer; ++m) {
+            const int e = ts + NS * m;
+            const int r = J0 - kBlkRows - bw + e / CPW, c = e % CPW;
+            nx[m] = r >= 0 ? X[base + (int64_t)r * kTile + c0 + c] : make_double2(0.0, 0.0);
+        }
+    };
+    if (!prod && nblk > 1) load_new(Jl);
     if (!prod) load_ld(Jl, pl);
     __syncthreads();   // ring filled
     if (!prod) store_ld(pl);
@@ -1209,7 +1234,7 @@ __global__ __launch_bounds__(NT) void k_band_bwd_pipe(const BandSys* __restrict_
             for (int m = 0; m < kNewPer; ++m) {
                 const int e = ts + NS * m;
                 const int r = J0 - kBlkRows - bw + e / CPW, c = e % CPW;
-                if (r >= 0) ring[(r % WS) * CPW + c] = X[base + (int64_t)r * kTile + c0 + c];
+                if (r >= 0) ring[(r % WS) * CPW + c] = nx[m];
             }
         }
         __syncthreads();   // rows of block j - 1 final; its L_JJ in LDS
@@ -1221,7 +1246,10 @@ __global__ __launch_bounds__(NT) void k_band_bwd_pipe(const BandSys* __restrict_
             }
         } else {
             solve_block(J0 - kBlkRows, (j - 1) & 1);
-            if (j > 1) load_ld(J0 - 2 * kBlkRows, pl);
+            if (j > 1) {
+                load_ld(J0 - 2 * kBlkRows, pl);
+                load_new(J0 - kBlkRows);
+            }
         }
         __syncthreads();
     }
