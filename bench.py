@@ -69,13 +69,13 @@ TRAFFIC = [
         "workload": "q1_2d_300",
         "precision": "fp64",
         "sources_sha256": {
-            "paper_2511_01927_amd/csrc/band.hip": "8e96dce78fd13eed33989587919a7eb48724d1ad07f7ff0bf6534d4445769072",
+            "paper_2511_01927_amd/csrc/band.hip": "29b50e4d9924081e0fd016ef5ce1f2c27e3d00568058bc8ab6846117f7fc55cc",
             "paper_2511_01927_amd/csrc/internal.h": "4e19dbea0f25f1ead60c00d887ebbd761b83b9432924910ca8ecf490cce52023",
         },
         # bytes per launch (per timed bracket for band_solve: right-hand sides,
         # forward and backward sweep)
-        "per_launch_bytes": {"band_update": 6.794486e+07, "band_update_next": 3.717263e+07,
-                             "band_panel": 2.045747e+07, "band_solve": 8.754036e+10},
+        "per_launch_bytes": {"band_update": 6.793144e+07, "band_update_next": 3.717571e+07,
+                             "band_panel": 2.045747e+07, "band_solve": 8.755706e+10},
         "profile": "profiles/band_q1_300x300_fp64_hbm_traffic.md",
     },
 ]
