@@ -69,7 +69,7 @@ TRAFFIC = [
         "workload": "q1_2d_300",
         "precision": "fp64",
         "sources_sha256": {
-            "paper_2511_01927_amd/csrc/band.hip": "29b50e4d9924081e0fd016ef5ce1f2c27e3d00568058bc8ab6846117f7fc55cc",
+            "paper_2511_01927_amd/csrc/band.hip": "56908aef7e3a712779915bde8e8163252b5a9ac0c7fb938c40ee75412f820a23",
             "paper_2511_01927_amd/csrc/internal.h": "4e19dbea0f25f1ead60c00d887ebbd761b83b9432924910ca8ecf490cce52023",
         },
         # bytes per launch (per timed bracket for band_solve: right-hand sides,

@@ -519,9 +519,13 @@ __global__ __launch_bounds__(256) void k_band_residual(
     const double2* __restrict__ X, double2* __restrict__ R, int ntiles, int nrb, int rpb,
     double2* __restrict__ part) {
     __shared__ double2 red[4][kTile];
-    const int tile = blockIdx.x / nrb;
-    const int rb = blockIdx.x - tile * nrb;
-    if (tile >= ntiles) return;
+    // consecutive row blocks of a tile on one XCD, so that the rows a block
+    // gathers from its neighbours (a grid row away in a 2D pencil) mostly
+    // come from that XCD's L2
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int tile = lb / nrb;
+    const int rb = lb - tile * nrb;
+    if (tile >= ntiles) return;   // uniform over the work-group
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nt = geom.n[tile];
     const int row0 = geom.row0[tile];
@@ -1437,10 +1441,10 @@ hipError_t band_residual(const DevPencil& P, const TileGeom& g, const double2* s
     const int rpb = (int)std::max<int64_t>(16, (nmax + nrb_cap - 1) / nrb_cap);
     const int nrb = (int)((nmax + rpb - 1) / rpb);
     if (R)
-        hipLaunchKernelGGL(k_band_residual<true>, dim3(ntiles * nrb), dim3(256), 0, s, P.rowptr, P.colind,
+        hipLaunchKernelGGL(k_band_residual<true>, dim3(pad8(ntiles * nrb)), dim3(256), 0, s, P.rowptr, P.colind,
                            P.ab, g, shifts, bsrc, BV, ldbv, X, R, ntiles, nrb, rpb, part);
     else
-        hipLaunchKernelGGL(k_band_residual<false>, dim3(ntiles * nrb), dim3(256), 0, s, P.rowptr, P.colind,
+        hipLaunchKernelGGL(k_band_residual<false>, dim3(pad8(ntiles * nrb)), dim3(256), 0, s, P.rowptr, P.colind,
                            P.ab, g, shifts, bsrc, BV, ldbv, X, R, ntiles, nrb, rpb, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
