@@ -104,9 +104,11 @@ __device__ inline void bj_step_pair(int full, int step, int r, int& p, int& q) {
     } else if (r == 0) {
         p = kBJ2 - 1;
         q = step;
-    } else {
-        p = (step + r) % (kBJ2 - 1);
-        q = (step - r + (kBJ2 - 1)) % (kBJ2 - 1);
+    } else {   // 0 <= step < 63, 1 <= r < 32: one conditional subtraction reduces mod 63
+        p = step + r;
+        p -= p >= kBJ2 - 1 ? kBJ2 - 1 : 0;
+        q = step - r + (kBJ2 - 1);
+        q -= q >= kBJ2 - 1 ? kBJ2 - 1 : 0;
     }
     if (p > q) {
         const int x = p;
